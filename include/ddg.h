@@ -1,0 +1,211 @@
+/*
+ * ddg.h -- C ABI of the MI355X DDG two-level PCG library (libddg.so).
+ *
+ * The library solves A u = f for a sparse symmetric positive definite A with
+ * conjugate gradients preconditioned by two-level symmetric multiplicative
+ * overlapping Schwarz and the Discretely-Discontinuous Galerkin coarse grid of
+ * Edwards and Bridson (arXiv:1504.00907):
+ *   - coarse basis (Section 4): every generating vector restricted to every
+ *     non-overlapping subdomain, orthonormalised per subdomain, rank-deficient
+ *     columns dropped; coarse operator A0 = R0 A R0^T;
+ *   - smoother (Section 6): subdomains expanded to graph distance `overlap`
+ *     in the graph of A, local problems A_i = R~_i A R~_i^T solved exactly,
+ *     multiplicative update u += R~_i^T A_i^{-1} R~_i (f - A u), one pass as
+ *     pre-smoother, the coarse correction, one pass in reverse as post-smoother;
+ *   - Krylov (Sections 1 and 7): CG from x0 = 0.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: DDG_OK (0) or a negative ddg_status.  No C++ exception
+ *     crosses the ABI.  ddg_last_error() gives a thread-local message.
+ *   - "host" pointers are ordinary CPU memory, read during the call only;
+ *     the library copies what it keeps and never retains caller pointers.
+ *   - "device" pointers are HIP device memory on the current device (for
+ *     example torch tensors); they are used on the handle's stream and must
+ *     stay valid until that stream has executed the enqueued work.
+ *   - All floating-point vectors are float64.  Index arrays are int32 except
+ *     CSR row pointers (int64).
+ *   - A handle owns all device memory it allocates; it is bound to one
+ *     stream and is not thread-safe.
+ */
+#ifndef DDG_H
+#define DDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddg_handle_s* ddg_handle;
+
+typedef enum {
+  DDG_OK = 0,
+  DDG_ERR_INVALID_ARG = -1,    /* malformed input (shape, range, symmetry, NaN) */
+  DDG_ERR_NOT_SPD = -2,        /* a local or coarse pivot <= 0 (ddg_last_error names it) */
+  DDG_ERR_RANK = -3,           /* every generating vector vanishes on some subdomain */
+  DDG_ERR_BREAKDOWN = -4,      /* CG: p^T q <= 0 or a non-finite scalar */
+  DDG_ERR_NO_CONVERGENCE = -5, /* max_iter reached; u holds the last iterate */
+  DDG_ERR_HIP = -6,            /* HIP runtime failure */
+  DDG_ERR_OOM = -7,            /* device allocation failed */
+  DDG_ERR_UNSUPPORTED = -8     /* size beyond a documented kernel limit */
+} ddg_status;
+
+typedef enum {
+  DDG_FP64 = 0,        /* everything float64 */
+  DDG_MIXED_FP32 = 1,  /* local factors stored and applied in float32, float32 accumulation */
+  DDG_MIXED_BF16 = 2   /* local factors stored in bfloat16, float32 accumulation */
+} ddg_precision;
+
+typedef struct {
+  int32_t precision;   /* ddg_precision */
+  int32_t max_iter;    /* CG iteration cap (default 1000, Section 7) */
+  double rtol;         /* stop at ||r_k||_2 <= rtol ||f||_2 (recurrence residual) */
+  double rank_tol;     /* drop coarse column j when |R_jj| <= rank_tol |R_11| (default 1e-10) */
+  int32_t tile;        /* factor tile edge 16/32/64; 0 = chosen by the autotuner */
+  int32_t block_target;/* merge local levels up to this many rows; 0 = automatic */
+  int32_t check_every; /* CG iterations enqueued between host convergence checks (0 = 4) */
+  int32_t reserved;
+  void* stream;        /* hipStream_t for all work; NULL = the null stream */
+} ddg_options;
+
+typedef struct {
+  int32_t status;          /* ddg_status of the last solve */
+  int32_t iters;           /* number of products A p of the last solve */
+  double rel_res;          /* recurrence ||r|| / ||f|| at exit */
+  double true_rel_res;     /* ||f - A u|| / ||f|| recomputed on the device at exit */
+  int32_t n_coarse;        /* N_c = sum of kept coarse columns */
+  int32_t n_colours;       /* colour phases per sweep */
+  int32_t n_parts;
+  int32_t n_blocks;        /* total dense diagonal blocks over all local factors */
+  double setup_ms;         /* last ddg_setup / ddg_refactor, device numeric part */
+  double solve_ms;         /* last ddg_solve, wall time on the stream */
+  int64_t factor_bytes;    /* stored local factor bytes */
+  int64_t coarse_bytes;    /* stored coarse inverse bytes */
+  int64_t sweep_bytes;     /* algorithmic HBM bytes of one full preconditioner sweep (both passes) */
+  int64_t iter_bytes;      /* algorithmic HBM bytes of one CG iteration */
+} ddg_info;
+
+/* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */
+void ddg_default_options(ddg_options* opt);
+
+/*
+ * Build the two-level preconditioner (Sections 4 and 6).
+ *   n, row_ptr[n+1], col_idx[nnz], val[nnz]  host; full symmetric CSR, sorted columns,
+ *                                             positive diagonal (checked).
+ *   k, F[n*k]        host; generating vectors, column-major (column j at F + j*n).
+ *                    k = 0 disables the coarse grid.
+ *   part[n]          host; non-overlapping subdomain id of each unknown, in [0, n_parts);
+ *                    every subdomain non-empty.
+ *   overlap          graph distance Delta >= 0 in the stored pattern of A (Section 6).
+ *   opt              may be NULL (defaults).
+ * On success *out owns the handle.  Errors: INVALID_ARG, NOT_SPD, RANK, UNSUPPORTED,
+ * HIP, OOM; *out is left NULL.
+ */
+int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+              const double* val, int32_t k, const double* F, const int32_t* part,
+              int32_t n_parts, int32_t overlap, const ddg_options* opt);
+
+/*
+ * New matrix values with the same pattern (device pointer, nnz float64 in the
+ * CSR order given to ddg_setup).  Recomputes A0 = R0 A R0^T, its inverse and
+ * every local factor; the coarse basis R0 depends only on F and the partition
+ * and is kept (Section 4).  Errors: NOT_SPD, HIP.
+ */
+int ddg_refactor(ddg_handle h, const double* val_dev);
+
+/*
+ * PCG solve (Sections 6-7): u = DDG-PCG(f) from x0 = 0.
+ *   f_dev[n], u_dev[n] device; u_dev is written.  info may be NULL.
+ * Returns DDG_OK, DDG_ERR_NO_CONVERGENCE (u holds the last iterate),
+ * DDG_ERR_BREAKDOWN, DDG_ERR_INVALID_ARG (non-finite f) or DDG_ERR_HIP.
+ */
+int ddg_solve(ddg_handle h, const double* f_dev, double* u_dev, ddg_info* info);
+
+/* z = M^{-1} r, one application of the two-level preconditioner (Section 6). Device vectors. */
+int ddg_apply_precond(ddg_handle h, const double* r_dev, double* z_dev);
+
+/*
+ * The first `stages` steps of M^{-1} r: stages 0..C-1 are the pre-sweep
+ * colour phases, stage C the coarse correction, C+1..2C the post-sweep phases
+ * (so stages = 2C+1 equals ddg_apply_precond).  Writes the partial
+ * correction to e_dev.  For checking properties at full size.
+ */
+int ddg_apply_precond_stages(ddg_handle h, const double* r_dev, double* e_dev, int32_t stages);
+
+/* y = A x on the device (the operator given to ddg_setup / ddg_refactor). */
+int ddg_spmv(ddg_handle h, const double* x_dev, double* y_dev);
+
+/* Fill *info with the handle's sizes and the statistics of the last setup/solve. */
+int ddg_get_info(ddg_handle h, ddg_info* info);
+
+/* Items for ddg_export (host buffers; `bytes` must equal the exact size). */
+typedef enum {
+  DDG_EXPORT_COLOURS = 0,   /* int32[n_parts]: colour of each subdomain */
+  DDG_EXPORT_SET_PTR = 1,   /* int64[n_parts+1]: offsets of the expanded sets */
+  DDG_EXPORT_SET_IDX = 2,   /* int32[sum |expanded set|]: ascending global ids */
+  DDG_EXPORT_KCOUNTS = 3,   /* int32[n_parts]: kept coarse columns per subdomain */
+  DDG_EXPORT_A0 = 4,        /* float64[N_c*N_c]: A0 = R0 A R0^T, row-major */
+  DDG_EXPORT_Q = 5,         /* float64[n*k]: orthonormal coarse basis, node-major (row g: k values) */
+  DDG_EXPORT_BLOCKS = 6     /* int32[n_blocks*3]: (subdomain, first local row, rows) per block */
+} ddg_export_item;
+
+/* Copy an internal structure to a host buffer.  Returns the needed byte count
+ * through *bytes_needed when host_buf is NULL. */
+int ddg_export(ddg_handle h, int32_t what, void* host_buf, int64_t bytes, int64_t* bytes_needed);
+
+/*
+ * Kernel timing for the roofline: when enabled, the library records HIP events
+ * (on the handle's stream) around every local-solve launch and accumulates
+ * their durations.  ddg_profile_read returns total milliseconds, the number
+ * of launches and their algorithmic HBM bytes since the last reset.
+ */
+int ddg_profile_enable(ddg_handle h, int32_t on);
+int ddg_profile_read(ddg_handle h, double* sweep_ms, int64_t* sweep_launches, int64_t* sweep_bytes,
+                     int32_t reset);
+
+/*
+ * Host-only symbolic analysis (no device memory, no GPU calls): validates the
+ * pattern and partition and builds the expanded sets (Section 6), the
+ * conflict colouring and the level blocks of the local factors.  The handle
+ * supports ddg_get_info (n_colours, n_parts, n_blocks, factor_bytes) and
+ * ddg_export of the integer items (COLOURS, SET_PTR, SET_IDX, BLOCKS); every
+ * other call on it returns DDG_ERR_INVALID_ARG.  Free it with ddg_destroy.
+ */
+int ddg_analyze(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                const int32_t* part, int32_t n_parts, int32_t overlap, const ddg_options* opt);
+
+/* Release every device resource of the handle (NULL is ignored). */
+void ddg_destroy(ddg_handle h);
+
+/* Thread-local message describing the last error ("" when none). */
+const char* ddg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Cell-centred variable-coefficient diffusion (the operator family of the
+ * differentiation workload).  dims[3] = (nx, ny, nz), cells x-fastest;
+ * nz = 1 gives 2D.  Face coefficient between cells L, R is the harmonic
+ * mean 2 kL kR / (kL + kR); each boundary face is a zero-Dirichlet ghost face
+ * of coefficient 2 kc.  kappa = exp(theta).
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Write the CSR values of A(exp(theta)) into val_dev, in the sorted-column
+ * CSR order of the same operator (diagonal and its 2*dim face neighbours that
+ * exist).  theta_dev[ncell], val_dev[nnz] device; stream may be NULL.
+ */
+int ddg_stencil_assemble(const int32_t dims[3], const double* theta_dev, double* val_dev,
+                         void* stream);
+
+/*
+ * Per-cell gradient dL/dtheta_c = -kappa_c * lam^T (dA/dkappa_c) u
+ * (adjoint identity for L(u(theta)) with A lam = dL/du).
+ * theta_dev, u_dev, lam_dev, grad_dev: device [ncell].
+ */
+int ddg_stencil_coeff_grad(const int32_t dims[3], const double* theta_dev, const double* u_dev,
+                           const double* lam_dev, double* grad_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDG_H */

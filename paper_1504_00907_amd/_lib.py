@@ -1,0 +1,104 @@
+"""ctypes declarations of libddg.so (the C ABI in include/ddg.h).
+
+The library is loaded from this package directory.  There is no fallback:
+if the shared library is missing or fails to load, every entry point raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddg.so")
+
+DDG_OK = 0
+STATUS = {
+    0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "RANK", -4: "BREAKDOWN",
+    -5: "NO_CONVERGENCE", -6: "HIP", -7: "OOM", -8: "UNSUPPORTED",
+}
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 1, "bf16": 2}
+
+EXPORT_COLOURS, EXPORT_SET_PTR, EXPORT_SET_IDX, EXPORT_KCOUNTS, EXPORT_A0, EXPORT_Q, EXPORT_BLOCKS = range(7)
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
+        ("rank_tol", C.c_double), ("tile", C.c_int32), ("block_target", C.c_int32),
+        ("check_every", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("iters", C.c_int32), ("rel_res", C.c_double),
+        ("true_rel_res", C.c_double), ("n_coarse", C.c_int32), ("n_colours", C.c_int32),
+        ("n_parts", C.c_int32), ("n_blocks", C.c_int32), ("setup_ms", C.c_double),
+        ("solve_ms", C.c_double), ("factor_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
+        ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+class DDGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("ddg_default_options", None, [C.POINTER(Options)]),
+    ("ddg_setup", C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Options)]),
+    ("ddg_refactor", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ddg_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Info)]),
+    ("ddg_apply_precond", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ddg_apply_precond_stages", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("ddg_spmv", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ddg_get_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    ("ddg_export", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    ("ddg_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ddg_profile_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), C.c_int32]),
+    ("ddg_analyze", C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_int32, C.c_int32, C.POINTER(Options)]),
+    ("ddg_destroy", None, [C.c_void_p]),
+    ("ddg_last_error", C.c_char_p, []),
+    ("ddg_stencil_assemble", C.c_int, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ddg_stencil_coeff_grad", C.c_int, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
+]
+
+SYMBOLS = [s[0] for s in _SIGS]
+
+
+def load(path: str = LIB_PATH):
+    """Load libddg.so once; raise if it is absent (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libddg.so not found at {path}; build it with "
+                           "`python -m paper_1504_00907_amd.build` (there is no fallback path)")
+    lib = C.CDLL(path)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int):
+    if rc != DDG_OK:
+        msg = load().ddg_last_error()
+        raise DDGError(rc, msg.decode() if msg else "")

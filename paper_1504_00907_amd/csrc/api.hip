@@ -1,0 +1,516 @@
+// C ABI of libddg: argument checks, device memory plan, setup orchestration
+// and the PCG driver loop.  Every numeric step runs in the HIP kernels of the
+// other translation units; this file only moves integers and pointers.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+
+#include "common.hpp"
+
+namespace ddg {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s);
+
+Handle::~Handle() {
+  for (auto ev : ev_pool) (void)hipEventDestroy(ev);
+  if (h_state) (void)hipHostFree(h_state);
+}
+
+namespace {
+
+int64_t tile_bytes(int32_t b, int32_t T, int es) { return (int64_t)tiles_for(b, T) * T * T * es; }
+
+int storage_size(int precision) {
+  return precision == DDG_MIXED_FP32 ? 4 : (precision == DDG_MIXED_BF16 ? 2 : 8);
+}
+
+void check_values(int64_t n, const int64_t* rp, const int32_t* ci, const double* val) {
+  double amax = 0.0;
+  for (int64_t t = 0; t < rp[n]; ++t) {
+    DDG_REQUIRE(std::isfinite(val[t]), DDG_ERR_INVALID_ARG, "non-finite matrix value");
+    amax = std::max(amax, std::fabs(val[t]));
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+      const int32_t c = ci[t];
+      if (c == i) {
+        DDG_REQUIRE(val[t] > 0.0, DDG_ERR_NOT_SPD, "non-positive diagonal in row " + std::to_string(i));
+        continue;
+      }
+      const int32_t* b = ci + rp[c];
+      const int32_t* e = ci + rp[c + 1];
+      const int64_t u = rp[c] + (std::lower_bound(b, e, (int32_t)i) - b);
+      DDG_REQUIRE(std::fabs(val[t] - val[u]) <= 1e-14 * amax, DDG_ERR_INVALID_ARG,
+                  "matrix not symmetric at (" + std::to_string(i) + "," + std::to_string(c) + ")");
+    }
+  }
+}
+
+// Algorithmic HBM bytes of one local-solve launch per colour (see the design notes):
+// factor tiles read once per substitution; per local row the set index, r,
+// the read-modify-write of e, the two coupling pointers and the coupling
+// entries; for colours that start from a non-zero e also the CSR rows of the
+// gather and one read of e.  colour_bytes[c] is the general case,
+// colour_bytes[C + c] the first phase that starts from e = 0.
+void account_bytes(Handle& h, const int64_t* rp) {
+  const Symbolic& S = h.S;
+  const int es = storage_size(h.opt.precision);
+  const int32_t C = S.n_colours;
+  h.colour_bytes.assign(2 * C, 0);
+  for (int32_t c = 0; c < C; ++c) {
+    int64_t bytes = 0, bytes0 = 0;
+    for (int32_t q = S.colour_ptr[c]; q < S.colour_ptr[c + 1]; ++q) {
+      const int32_t i = S.colour_subs[q];
+      int64_t fb = 0;
+      const int32_t K = S.sub_blk_ptr[i + 1] - S.sub_blk_ptr[i];
+      for (int32_t k = 0; k < K; ++k) {
+        const int64_t tb = tile_bytes(S.blk_size[S.sub_blk_ptr[i] + k], S.tile, es);
+        fb += tb * (k + 1 < K ? 2 : 1);
+      }
+      const int64_t r0 = S.set_ptr[i], r1 = S.set_ptr[i + 1];
+      const int64_t ni = r1 - r0;
+      const int64_t ncpl = (S.lo_ptr[r1] - S.lo_ptr[r0]) + (S.up_ptr[r1] - S.up_ptr[r0]);
+      int64_t nnz_rows = 0;
+      for (int64_t t = r0; t < r1; ++t) nnz_rows += rp[S.set_idx[t] + 1] - rp[S.set_idx[t]];
+      const int64_t common = fb + ni * (4 + 8 + 16) + ni * 16 + ncpl * 12;
+      bytes0 += common;
+      bytes += common + ni * 8 + nnz_rows * 12 + ni * 8;
+    }
+    h.colour_bytes[c] = bytes;
+    h.colour_bytes[C + c] = bytes0;
+  }
+  int64_t sweep = h.colour_bytes[C];  // first pre-sweep phase starts from e = 0
+  for (int32_t c = 1; c < C; ++c) sweep += h.colour_bytes[c];
+  for (int32_t c = 0; c < C; ++c) sweep += h.colour_bytes[c];
+  h.info.sweep_bytes = sweep;
+  const int64_t n = S.n, nnzb = S.nnz * 12 + (n + 1) * 8;
+  const int64_t ntiles = (int64_t)h.nc_tiles_rows * (h.nc_tiles_rows + 1) / 2;
+  // coarse: restrict (residual SpMV + Q), tiled inverse GEMV, prolong (Q, e rmw)
+  const int64_t coarse = h.nc ? (nnzb + 3 * n * 8 + n * h.k * 8 + ntiles * 64 * 64 * 8 + n * h.k * 8 + 16 * n) : 0;
+  // CG: SpMV (p, q), x/r/p/q update, two dots, p update
+  const int64_t cg = nnzb + 2 * n * 8 + 6 * n * 8 + 4 * n * 8 + 3 * n * 8;
+  h.info.iter_bytes = sweep + coarse + cg + n * 8;
+  h.info.factor_bytes = S.fac_elems * es;
+  h.info.coarse_bytes = h.nc ? ntiles * 64 * 64 * 8 : 0;
+}
+
+void check_err_flag(Handle& h, const char* what) {
+  int32_t e[4];
+  DDG_HIP(hipMemcpyAsync(e, h.err_flag.p, sizeof(e), hipMemcpyDeviceToHost, h.stream));
+  DDG_HIP(hipStreamSynchronize(h.stream));
+  if (e[0] != 0) {
+    std::string m = std::string(what) + ": ";
+    if (e[0] == DDG_ERR_RANK) m += "every generating vector vanishes on subdomain " + std::to_string(e[1]);
+    else if (e[1] < 0) m += "coarse pivot " + std::to_string(e[3]) + " not positive (A0 not SPD)";
+    else m += "local pivot not positive in subdomain " + std::to_string(e[1]) + " block " + std::to_string(e[2]) +
+              " row " + std::to_string(e[3]);
+    DDG_HIP(hipMemsetAsync(h.err_flag.p, 0, sizeof(e), h.stream));
+    throw Error{e[0], m};
+  }
+}
+
+void numeric_setup(Handle& h) {
+  hipEvent_t e0, e1;
+  DDG_HIP(hipEventCreate(&e0));
+  DDG_HIP(hipEventCreate(&e1));
+  DDG_HIP(hipEventRecord(e0, h.stream));
+  launch_refresh_couplings(h, h.stream);
+  if (h.nc > 0) {
+    launch_galerkin(h, h.stream);
+    launch_coarse_invert(h, h.stream);
+    check_err_flag(h, "coarse factorisation");
+  }
+  launch_local_factor(h, h.stream);
+  DDG_HIP(hipEventRecord(e1, h.stream));
+  DDG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  DDG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h.info.setup_ms = ms;
+  check_err_flag(h, "local factorisation");
+}
+
+void flush_profile(Handle& h) {
+  if (h.pending.empty()) return;
+  DDG_HIP(hipStreamSynchronize(h.stream));
+  for (auto& pb : h.pending) {
+    float ms = 0.f;
+    DDG_HIP(hipEventElapsedTime(&ms, h.ev_pool[pb.first], h.ev_pool[pb.first + 1]));
+    h.prof_ms += ms;
+    h.prof_launches += 1;
+    h.prof_bytes += pb.second;
+  }
+  h.pending.clear();
+  h.ev_used = 0;
+}
+
+Handle* H(ddg_handle p) { return reinterpret_cast<Handle*>(p); }
+
+template <class Fn>
+int guarded(Fn&& fn) {
+  try {
+    clear_error();
+    fn();
+    return DDG_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DDG_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return DDG_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+}  // namespace ddg
+
+using namespace ddg;
+
+extern "C" {
+
+void ddg_default_options(ddg_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = DDG_FP64;
+  opt->max_iter = 1000;
+  opt->rtol = 1e-8;
+  opt->rank_tol = 1e-10;
+  opt->tile = 0;
+  opt->block_target = 0;
+  opt->check_every = 4;
+  opt->stream = nullptr;
+}
+
+const char* ddg_last_error(void) { return g_last_error.c_str(); }
+
+int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+              int32_t k, const double* F, const int32_t* part, int32_t n_parts, int32_t overlap,
+              const ddg_options* opt) {
+  if (out) *out = nullptr;
+  Handle* hp = nullptr;
+  int rc = guarded([&]() {
+    DDG_REQUIRE(out && row_ptr && col_idx && val && part, DDG_ERR_INVALID_ARG, "null argument");
+    DDG_REQUIRE(k >= 0 && (k == 0 || F), DDG_ERR_INVALID_ARG, "k must be >= 0 and F given when k > 0");
+    auto h = std::make_unique<Handle>();
+    if (opt) h->opt = *opt;
+    else ddg_default_options(&h->opt);
+    DDG_REQUIRE(h->opt.precision >= DDG_FP64 && h->opt.precision <= DDG_MIXED_BF16, DDG_ERR_INVALID_ARG,
+                "unknown precision");
+    if (h->opt.max_iter <= 0) h->opt.max_iter = 1000;
+    if (h->opt.check_every <= 0) h->opt.check_every = 4;
+    DDG_REQUIRE(h->opt.rtol >= 0.0 && h->opt.rank_tol >= 0.0, DDG_ERR_INVALID_ARG, "negative tolerance");
+    h->stream = static_cast<hipStream_t>(h->opt.stream);
+    h->k = k;
+    DDG_REQUIRE(k <= 32, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
+    if (k > 0)
+      for (int64_t t = 0; t < n * (int64_t)k; ++t)
+        DDG_REQUIRE(std::isfinite(F[t]), DDG_ERR_INVALID_ARG, "non-finite generating vectors");
+    build_symbolic(h->S, n, row_ptr, col_idx, part, n_parts, overlap, h->opt.tile, h->opt.block_target);
+    check_values(n, row_ptr, col_idx, val);
+    Symbolic& S = h->S;
+    int dev = 0;
+    DDG_HIP(hipGetDevice(&dev));
+    int lds = 0;
+    DDG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    h->dev_lds_limit = lds;
+    hipStream_t s = h->stream;
+    // integer structure
+    std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
+    std::vector<int32_t> ci(col_idx, col_idx + S.nnz);
+    std::vector<double> vv(val, val + S.nnz);
+    std::vector<int32_t> pp(part, part + n);
+    h->rowptr.upload(rp, s);
+    h->col.upload(ci, s);
+    h->val.upload(vv, s);
+    h->part.upload(pp, s);
+    h->own_ptr.upload(S.own_ptr, s);
+    h->own_idx.upload(S.own_idx, s);
+    h->set_ptr.upload(S.set_ptr, s);
+    h->set_idx.upload(S.set_idx, s);
+    h->colour_subs.upload(S.colour_subs, s);
+    h->nbr_ptr.upload(S.nbr_ptr, s);
+    h->nbr_idx.upload(S.nbr_idx, s);
+    h->sub_blk_ptr.upload(S.sub_blk_ptr, s);
+    h->blk_start.upload(S.blk_start, s);
+    h->blk_size.upload(S.blk_size, s);
+    h->blk_foff.upload(S.blk_foff, s);
+    h->lo_ptr.upload(S.lo_ptr, s);
+    h->lo_col.upload(S.lo_col, s);
+    h->lo_pos.upload(S.lo_pos, s);
+    h->up_ptr.upload(S.up_ptr, s);
+    h->up_col.upload(S.up_col, s);
+    h->up_pos.upload(S.up_pos, s);
+    h->in_ptr.upload(S.in_ptr, s);
+    h->in_col.upload(S.in_col, s);
+    h->in_pos.upload(S.in_pos, s);
+    h->lo_val.alloc(std::max<size_t>(1, S.lo_pos.size()) * sizeof(double));
+    h->up_val.alloc(std::max<size_t>(1, S.up_pos.size()) * sizeof(double));
+    h->err_flag.alloc(4 * sizeof(int32_t));
+    DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 4 * sizeof(int32_t), s));
+    h->fac.alloc((size_t)S.fac_elems * storage_size(h->opt.precision));
+    // coarse basis (depends only on F and the partition)
+    h->kcnt.assign(n_parts, 0);
+    h->koff.assign(n_parts + 1, 0);
+    if (k > 0) {
+      h->F.alloc((size_t)n * k * sizeof(double));
+      DDG_HIP(hipMemcpyAsync(h->F.p, F, (size_t)n * k * sizeof(double), hipMemcpyHostToDevice, s));
+      h->Q.alloc((size_t)n * k * sizeof(double));
+      h->kcnt_d.alloc((size_t)n_parts * sizeof(int32_t));
+      launch_coarse_basis(*h, s);
+      check_err_flag(*h, "coarse basis");
+      DDG_HIP(hipMemcpyAsync(h->kcnt.data(), h->kcnt_d.p, (size_t)n_parts * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      DDG_HIP(hipStreamSynchronize(s));
+      for (int32_t i = 0; i < n_parts; ++i) h->koff[i + 1] = h->koff[i] + h->kcnt[i];
+      h->nc = h->koff[n_parts];
+      h->koff_d.upload(h->koff, s);
+      h->F.release();
+    }
+    if (h->nc > 0) {
+      h->nc_tiles_rows = (int32_t)((h->nc + 63) / 64);
+      const int64_t ntr = h->nc_tiles_rows;
+      const int64_t ntiles = ntr * (ntr + 1) / 2;
+      h->A0.alloc((size_t)h->nc * h->nc * sizeof(double));
+      h->A0inv_t.alloc((size_t)ntiles * 64 * 64 * sizeof(double));
+      h->cy.alloc((size_t)2 * ntr * 64 * sizeof(double));
+      DDG_HIP(hipMemsetAsync(h->cy.p, 0, (size_t)2 * ntr * 64 * sizeof(double), s));
+      h->cpart.alloc((size_t)2 * ntiles * 64 * sizeof(double));
+    }
+    // CG workspace
+    h->r.alloc((size_t)n * sizeof(double));
+    h->p.alloc((size_t)n * sizeof(double));
+    h->q.alloc((size_t)n * sizeof(double));
+    h->z.alloc((size_t)n * sizeof(double));
+    h->n_partials = cg_partials_count(n);
+    h->part_sums.alloc((size_t)h->n_partials * sizeof(double));
+    h->cstate.alloc(sizeof(CgState));
+    DDG_HIP(hipHostMalloc((void**)&h->h_state, sizeof(CgState), hipHostMallocDefault));
+    numeric_setup(*h);
+    account_bytes(*h, row_ptr);
+    h->info.n_coarse = (int32_t)h->nc;
+    h->info.n_colours = S.n_colours;
+    h->info.n_parts = n_parts;
+    h->info.n_blocks = (int32_t)S.blk_size.size();
+    hp = h.release();
+  });
+  if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
+  return rc;
+}
+
+int ddg_analyze(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* part,
+                int32_t n_parts, int32_t overlap, const ddg_options* opt) {
+  if (out) *out = nullptr;
+  Handle* hp = nullptr;
+  int rc = guarded([&]() {
+    DDG_REQUIRE(out && row_ptr && col_idx && part, DDG_ERR_INVALID_ARG, "null argument");
+    auto h = std::make_unique<Handle>();
+    if (opt) h->opt = *opt;
+    else ddg_default_options(&h->opt);
+    h->host_only = true;
+    build_symbolic(h->S, n, row_ptr, col_idx, part, n_parts, overlap, h->opt.tile, h->opt.block_target);
+    h->info.n_colours = h->S.n_colours;
+    h->info.n_parts = n_parts;
+    h->info.n_blocks = (int32_t)h->S.blk_size.size();
+    h->info.factor_bytes = h->S.fac_elems * storage_size(h->opt.precision);
+    hp = h.release();
+  });
+  if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
+  return rc;
+}
+
+int ddg_refactor(ddg_handle hd, const double* val_dev) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && val_dev && !h->host_only, DDG_ERR_INVALID_ARG, "null argument or analysis-only handle");
+    DDG_HIP(hipMemcpyAsync(h->val.p, val_dev, (size_t)h->S.nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                           h->stream));
+    numeric_setup(*h);
+  });
+}
+
+int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info) {
+  Handle* h = H(hd);
+  int rc = guarded([&]() {
+    DDG_REQUIRE(h && f_dev && u_dev && !h->host_only, DDG_ERR_INVALID_ARG, "null argument or analysis-only handle");
+    hipStream_t s = h->stream;
+    hipEvent_t e0, e1;
+    DDG_HIP(hipEventCreate(&e0));
+    DDG_HIP(hipEventCreate(&e1));
+    DDG_HIP(hipEventRecord(e0, s));
+    double* x = u_dev;
+    double* z = h->z.as<double>();
+    launch_cg_init(*h, f_dev, x, s);
+    launch_precond(*h, h->r.as<double>(), z, -1, true, s);
+    launch_cg_start(*h, s);
+    const int chunk = h->opt.check_every;
+    int enqueued = 0;
+    while (true) {
+      for (int t = 0; t < chunk; ++t) {
+        launch_cg_step_a(*h, x, s);
+        launch_precond(*h, h->r.as<double>(), z, -1, true, s);
+        launch_cg_step_b(*h, s);
+      }
+      enqueued += chunk;
+      DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      DDG_HIP(hipStreamSynchronize(s));
+      if (h->profiling) flush_profile(*h);
+      if (h->h_state->done) break;
+      DDG_REQUIRE(enqueued <= h->opt.max_iter + 2 * chunk, DDG_ERR_HIP, "internal: CG loop did not stop");
+    }
+    launch_true_residual(*h, f_dev, x, s);
+    DDG_HIP(hipEventRecord(e1, s));
+    DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    DDG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    DDG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const CgState& st = *h->h_state;
+    h->info.status = st.status;
+    h->info.iters = st.iters;
+    h->info.rel_res = st.fnorm > 0 ? std::sqrt(st.rr) / st.fnorm : 0.0;
+    h->info.true_rel_res = st.fnorm > 0 ? std::sqrt(st.true_rr) / st.fnorm : 0.0;
+    h->info.solve_ms = ms;
+    if (info) *info = h->info;
+    if (st.status != DDG_OK) {
+      const char* what = st.status == DDG_ERR_NO_CONVERGENCE ? "maximum iterations reached"
+                         : st.status == DDG_ERR_BREAKDOWN    ? "CG breakdown (p^T q <= 0 or non-finite)"
+                                                             : "non-finite right-hand side";
+      throw Error{st.status, what};
+    }
+  });
+  if (rc != DDG_OK && info && h) {
+    info->status = rc;
+  }
+  return rc;
+}
+
+int ddg_apply_precond(ddg_handle hd, const double* r_dev, double* z_dev) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && r_dev && z_dev && !h->host_only, DDG_ERR_INVALID_ARG, "null argument or analysis-only handle");
+    launch_precond(*h, r_dev, z_dev, -1, false, h->stream);
+    if (h->profiling) flush_profile(*h);
+  });
+}
+
+int ddg_apply_precond_stages(ddg_handle hd, const double* r_dev, double* e_dev, int32_t stages) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && r_dev && e_dev && !h->host_only, DDG_ERR_INVALID_ARG, "null argument or analysis-only handle");
+    DDG_REQUIRE(stages >= 0 && stages <= 2 * h->S.n_colours + 1, DDG_ERR_INVALID_ARG, "stage count out of range");
+    launch_precond(*h, r_dev, e_dev, stages, false, h->stream);
+    if (h->profiling) flush_profile(*h);
+  });
+}
+
+int ddg_spmv(ddg_handle hd, const double* x_dev, double* y_dev) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && x_dev && y_dev && !h->host_only, DDG_ERR_INVALID_ARG, "null argument or analysis-only handle");
+    launch_spmv(*h, x_dev, y_dev, h->stream);
+    DDG_HIP(hipGetLastError());
+  });
+}
+
+int ddg_get_info(ddg_handle hd, ddg_info* info) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && info, DDG_ERR_INVALID_ARG, "null argument");
+    *info = h->info;
+  });
+}
+
+int ddg_export(ddg_handle hd, int32_t what, void* host_buf, int64_t bytes, int64_t* bytes_needed) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h, DDG_ERR_INVALID_ARG, "null handle");
+    const Symbolic& S = h->S;
+    const void* src = nullptr;
+    int64_t need = 0;
+    bool device = false;
+    std::vector<int32_t> blocks;
+    switch (what) {
+      case DDG_EXPORT_COLOURS: src = S.colour.data(); need = (int64_t)S.colour.size() * 4; break;
+      case DDG_EXPORT_SET_PTR: src = S.set_ptr.data(); need = (int64_t)S.set_ptr.size() * 8; break;
+      case DDG_EXPORT_SET_IDX: src = S.set_idx.data(); need = (int64_t)S.set_idx.size() * 4; break;
+      case DDG_EXPORT_KCOUNTS:
+        DDG_REQUIRE(!h->host_only, DDG_ERR_INVALID_ARG, "analysis-only handle");
+        src = h->kcnt.data(); need = (int64_t)h->kcnt.size() * 4; break;
+      case DDG_EXPORT_A0:
+        DDG_REQUIRE(!h->host_only, DDG_ERR_INVALID_ARG, "analysis-only handle");
+        src = h->A0.p; need = h->nc * h->nc * 8; device = true; break;
+      case DDG_EXPORT_Q:
+        DDG_REQUIRE(!h->host_only, DDG_ERR_INVALID_ARG, "analysis-only handle");
+        src = h->Q.p; need = S.n * h->k * 8; device = true; break;
+      case DDG_EXPORT_BLOCKS:
+        for (int32_t i = 0; i < S.n_parts; ++i)
+          for (int32_t b = S.sub_blk_ptr[i]; b < S.sub_blk_ptr[i + 1]; ++b) {
+            blocks.push_back(i);
+            blocks.push_back(S.blk_start[b]);
+            blocks.push_back(S.blk_size[b]);
+          }
+        src = blocks.data();
+        need = (int64_t)blocks.size() * 4;
+        break;
+      default: throw Error{DDG_ERR_INVALID_ARG, "unknown export item"};
+    }
+    if (bytes_needed) *bytes_needed = need;
+    if (!host_buf) return;
+    DDG_REQUIRE(bytes == need, DDG_ERR_INVALID_ARG, "buffer size mismatch: need " + std::to_string(need));
+    if (need == 0) return;
+    if (device) {
+      DDG_HIP(hipMemcpyAsync(host_buf, src, need, hipMemcpyDeviceToHost, h->stream));
+      DDG_HIP(hipStreamSynchronize(h->stream));
+    } else {
+      std::memcpy(host_buf, src, need);
+    }
+  });
+}
+
+int ddg_profile_enable(ddg_handle hd, int32_t on) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && !h->host_only, DDG_ERR_INVALID_ARG, "null or analysis-only handle");
+    flush_profile(*h);
+    h->profiling = on != 0;
+  });
+}
+
+int ddg_profile_read(ddg_handle hd, double* ms, int64_t* launches, int64_t* bytes, int32_t reset) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && !h->host_only, DDG_ERR_INVALID_ARG, "null or analysis-only handle");
+    flush_profile(*h);
+    if (ms) *ms = h->prof_ms;
+    if (launches) *launches = h->prof_launches;
+    if (bytes) *bytes = h->prof_bytes;
+    if (reset) {
+      h->prof_ms = 0.0;
+      h->prof_launches = 0;
+      h->prof_bytes = 0;
+    }
+  });
+}
+
+void ddg_destroy(ddg_handle hd) {
+  Handle* h = H(hd);
+  if (!h) return;
+  if (!h->host_only) (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+}  // extern "C"

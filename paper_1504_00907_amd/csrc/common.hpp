@@ -1,0 +1,211 @@
+// Internal declarations of libddg: handle layout, error plumbing, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ddg.h"
+
+namespace ddg {
+
+// ---------------------------------------------------------------------------
+// Errors
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+void set_error(const std::string& msg);
+void clear_error();
+
+#define DDG_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t _e = (call);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      throw ::ddg::Error{_e == hipErrorOutOfMemory ? DDG_ERR_OOM : DDG_ERR_HIP,    \
+                         std::string(#call) + ": " + hipGetErrorString(_e)};       \
+    }                                                                              \
+  } while (0)
+
+#define DDG_REQUIRE(cond, code, text)                                              \
+  do {                                                                             \
+    if (!(cond)) throw ::ddg::Error{(code), (text)};                               \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device buffer (owning)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t nbytes) {
+    release();
+    if (nbytes == 0) nbytes = 16;
+    DDG_HIP(hipMalloc(&p, nbytes));
+    bytes = nbytes;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+  template <class T> void upload(const std::vector<T>& v, hipStream_t s) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) DDG_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Host symbolic structure (integers only; no floating-point arithmetic of the method)
+
+struct Symbolic {
+  int64_t n = 0, nnz = 0;
+  int32_t n_parts = 0, overlap = 0;
+  std::vector<int64_t> own_ptr;      // n_parts+1, non-overlapping sets (ascending)
+  std::vector<int32_t> own_idx;      // n
+  std::vector<int64_t> set_ptr;      // n_parts+1, expanded sets
+  std::vector<int32_t> set_idx;      // sum |set|
+  std::vector<int32_t> colour;       // n_parts
+  int32_t n_colours = 0;
+  std::vector<int32_t> colour_ptr;   // n_colours+1 into colour_subs
+  std::vector<int32_t> colour_subs;  // subdomains grouped by colour, ascending id
+  std::vector<int32_t> nbr_ptr;      // n_parts+1, coupled subdomains (incl. self), ascending
+  std::vector<int32_t> nbr_idx;
+  // blocks of the local factors
+  std::vector<int32_t> sub_blk_ptr;  // n_parts+1 into block arrays
+  std::vector<int32_t> blk_start;    // first local row of each block
+  std::vector<int32_t> blk_size;     // rows of each block
+  std::vector<int64_t> blk_foff;     // element offset of each block's tiles in the factor array
+  int64_t fac_elems = 0;
+  int32_t tile = 64;
+  int32_t max_set = 0, max_blk = 0, max_blocks = 0, max_own = 0;
+  // local couplings: per local row (global row id = set_ptr[i] + j)
+  std::vector<int64_t> lo_ptr, up_ptr, in_ptr;   // sum|set|+1 each
+  std::vector<int32_t> lo_col, up_col, in_col;   // local column (within the subdomain)
+  std::vector<int64_t> lo_pos, up_pos, in_pos;   // position in the global CSR value array
+};
+
+// Builds every integer structure; throws Error on malformed input.
+void build_symbolic(Symbolic& S, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                    const int32_t* part, int32_t n_parts, int32_t overlap, int32_t tile,
+                    int32_t block_target);
+
+// Tile layout helpers shared by host and device.
+__host__ __device__ inline int32_t tiles_for(int32_t b, int32_t T) {
+  int32_t nt = (b + T - 1) / T;
+  return nt * (nt + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Device-side CG state (one per handle)
+
+struct CgState {
+  double rho;        // r^T z
+  double alpha, beta;
+  double pq;
+  double rr;         // ||r||^2
+  double fnorm;      // ||f||
+  double tol2;       // (rtol ||f||)^2
+  double true_rr;    // ||f - A x||^2 after the solve
+  int32_t done;      // 1 = converged / stopped
+  int32_t status;    // ddg_status
+  int32_t iters;
+  int32_t max_iter;
+};
+
+// ---------------------------------------------------------------------------
+// Handle
+
+struct Handle {
+  bool host_only = false;   // created by ddg_analyze: symbolic data only
+  ddg_options opt{};
+  hipStream_t stream = nullptr;
+  Symbolic S;
+  int32_t k = 0;          // columns of F
+  int64_t nc = 0;         // coarse dimension
+  int32_t nc_tiles_rows = 0;
+  std::vector<int32_t> kcnt;   // kept columns per subdomain
+  std::vector<int64_t> koff;   // coarse offsets
+  int32_t dev_lds_limit = 65536;
+
+  // device copies
+  DevBuf rowptr, col, val;           // CSR
+  DevBuf part, own_ptr, own_idx;
+  DevBuf set_ptr, set_idx;
+  DevBuf colour_subs;
+  DevBuf nbr_ptr, nbr_idx;
+  DevBuf sub_blk_ptr, blk_start, blk_size, blk_foff;
+  DevBuf lo_ptr, lo_col, lo_pos, lo_val;
+  DevBuf up_ptr, up_col, up_pos, up_val;
+  DevBuf in_ptr, in_col, in_pos;
+  DevBuf F;               // n x k column-major (setup input)
+  DevBuf Q;               // n x k node-major orthonormal basis (zero-padded)
+  DevBuf kcnt_d, koff_d;
+  DevBuf A0;              // nc x nc dense (setup scratch, also kept for export)
+  DevBuf A0inv_t;         // tiled lower inverse, float64, tile 64
+  DevBuf fac;             // local factor tiles (storage precision)
+  DevBuf fac_scratch;     // setup scratch
+  DevBuf err_flag;        // int32[4]: setup error (code, subdomain, block, pivot)
+
+  // CG workspace
+  DevBuf r, p, q, z, part_sums, cstate;
+  DevBuf cy, cpart;       // coarse rhs/solution (nc) and GEMV partials
+  DevBuf pinned_state;    // unused placeholder
+  CgState* h_state = nullptr;   // pinned host mirror
+  int32_t n_partials = 0;
+
+  // info
+  ddg_info info{};
+  int64_t sweep_bytes_colour_fwd[64] = {};
+  std::vector<int64_t> colour_bytes;   // algorithmic bytes of one local-solve launch per colour
+
+  // profiling
+  bool profiling = false;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0, prof_bytes = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int64_t>> pending;  // (event pair index, bytes)
+  int ev_used = 0;
+
+  ~Handle();
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip translation units)
+
+// cg kernels
+void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s);
+// CG: init (x = 0, r = f, ||f||), then rho = r^T z and p = z, then per iteration
+// q = A p / alpha / x,r update / convergence, and after M^{-1}: rho', beta, p = z + beta p.
+void launch_cg_init(Handle& h, const double* f, double* x, hipStream_t s);
+void launch_cg_start(Handle& h, hipStream_t s);
+void launch_cg_step_a(Handle& h, double* x, hipStream_t s);
+void launch_cg_step_b(Handle& h, hipStream_t s);
+void launch_true_residual(Handle& h, const double* f, const double* x, hipStream_t s);
+int32_t cg_partials_count(int64_t n);
+
+// preconditioner
+void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded,
+                    hipStream_t s);
+
+// setup numerics
+void launch_coarse_basis(Handle& h, hipStream_t s);
+void launch_galerkin(Handle& h, hipStream_t s);
+void launch_coarse_invert(Handle& h, hipStream_t s);
+void launch_local_factor(Handle& h, hipStream_t s);
+void launch_refresh_couplings(Handle& h, hipStream_t s);
+
+}  // namespace ddg

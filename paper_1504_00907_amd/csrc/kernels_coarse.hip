@@ -1,0 +1,197 @@
+// Coarse correction of the two-level preconditioner (Section 4 coarse problem,
+// Section 6 multiplicative combination):
+//     e += R0^T A0^{-1} R0 (r - A e)
+// R0^T = blockdiag(Q_i) with Q_i the orthonormal basis of subdomain i, so
+//   b0[off_i + m] = sum_{g in Omega_i} Q[g, m] (r - A e)_g        (restrict)
+//   y = A0^{-1} b0                                                  (tiled symmetric GEMV)
+//   e_g += sum_m Q[g, m] y[off_{part g} + m]                        (prolong)
+// A0^{-1} is the explicit float64 inverse computed at setup; it is stored as
+// lower 64 x 64 tiles and applied with one wave per tile, writing fixed
+// per-tile partials that a second kernel sums in a fixed order.
+#include "common.hpp"
+#include "symv_tile.hpp"
+
+namespace ddg {
+
+namespace {
+
+constexpr int kRThreads = 256;
+constexpr int kMaxK = 32;
+
+__global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
+    const CgState* st, const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
+    const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff, const double* __restrict__ Q,
+    int kq, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const double* __restrict__ val, const double* __restrict__ r, const double* __restrict__ e,
+    double* __restrict__ b0) {
+  if (st && st->done) return;
+  __shared__ double red[kRThreads / 64][kMaxK];
+  const int i = blockIdx.x;
+  const int ki = kcnt[i];
+  double acc[kMaxK];
+#pragma unroll
+  for (int m = 0; m < kMaxK; ++m) acc[m] = 0.0;
+  for (int64_t t = own_ptr[i] + threadIdx.x; t < own_ptr[i + 1]; t += kRThreads) {
+    const int g = own_idx[t];
+    double s = r[g];
+    for (int64_t u = rp[g]; u < rp[g + 1]; ++u) s -= val[u] * e[ci[u]];
+    const double* qg = Q + (int64_t)g * kq;
+#pragma unroll
+    for (int m = 0; m < kMaxK; ++m)
+      if (m < ki) acc[m] += qg[m] * s;
+  }
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m < kMaxK; ++m) {
+    if (m < ki) {
+      double v = wave_sum(acc[m]);
+      if ((threadIdx.x & 63) == 0) red[wv][m] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < ki) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRThreads / 64; ++w) s += red[w][threadIdx.x];
+    b0[koff[i] + threadIdx.x] = s;
+  }
+}
+
+// one wave per 64x64 float64 tile: row and column partials into per-tile slots
+__global__ void __launch_bounds__(256) k_coarse_symv(const CgState* st, const double* __restrict__ tiles,
+                                                     int ntiles, const double* __restrict__ x,
+                                                     double* __restrict__ rowpart,
+                                                     double* __restrict__ colpart) {
+  if (st && st->done) return;
+  constexpr int T = 64;
+  using G = TileGeom<double, T>;
+  constexpr int S = G::S;
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  int I, J;
+  tile_ij(t, I, J);
+  double m[G::SS];
+  load_subtile<double, T>(tiles + (int64_t)t * T * T, lane, m);
+  const int p = lane >> 3, q = lane & 7;
+  double xr[S], xc[S], rowp[S], colp[S];
+#pragma unroll
+  for (int b = 0; b < S; ++b) {
+    xr[b] = x[J * T + q * S + b];
+    xc[b] = x[I * T + p * S + b];
+    rowp[b] = 0.0;
+    colp[b] = 0.0;
+  }
+#pragma unroll
+  for (int a = 0; a < S; ++a)
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      rowp[a] += m[a * S + b] * xr[b];
+      colp[b] += m[a * S + b] * xc[a];
+    }
+  bool w;
+  double rs = group_reduce_scatter<double, S, G::LOGS>(rowp, q, 1, w);
+  rowpart[(int64_t)t * T + p * S + q] = rs;
+  if (I != J) {
+    double cs = group_reduce_scatter<double, S, G::LOGS>(colp, p, 8, w);
+    colpart[(int64_t)t * T + q * S + p] = cs;
+  }
+}
+
+__global__ void k_coarse_sum(const CgState* st, const double* __restrict__ rowpart,
+                             const double* __restrict__ colpart, int ntr, int64_t nc,
+                             double* __restrict__ y) {
+  if (st && st->done) return;
+  constexpr int T = 64;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nc) return;
+  const int I = (int)(row / T), rr = (int)(row % T);
+  double s = 0.0;
+  for (int J = 0; J <= I; ++J) s += rowpart[((int64_t)I * (I + 1) / 2 + J) * T + rr];
+  for (int J = I + 1; J < ntr; ++J) s += colpart[((int64_t)J * (J + 1) / 2 + I) * T + rr];
+  y[row] = s;
+}
+
+__global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ part,
+                                 const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
+                                 const double* __restrict__ Q, int kq, const double* __restrict__ y,
+                                 double* __restrict__ e, int64_t n) {
+  if (st && st->done) return;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int i = part[g];
+  const int ki = kcnt[i];
+  const double* yi = y + koff[i];
+  const double* qg = Q + g * kq;
+  double s = 0.0;
+  for (int m = 0; m < ki; ++m) s += qg[m] * yi[m];
+  e[g] += s;
+}
+
+}  // namespace
+
+void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
+                  const CgState* st, hipStream_t s);
+
+void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s) {
+  if (h.nc == 0) return;
+  const Symbolic& S = h.S;
+  DDG_REQUIRE(h.k <= kMaxK, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
+  double* b0 = h.cy.as<double>();             // padded to whole tiles, zero beyond nc
+  double* y = b0 + (int64_t)h.nc_tiles_rows * 64;
+  hipLaunchKernelGGL(k_coarse_restrict, dim3(S.n_parts), dim3(kRThreads), 0, s, st,
+                     h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
+                     h.koff_d.as<int64_t>(), h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(),
+                     h.col.as<int32_t>(), h.val.as<double>(), r, e, b0);
+  const int ntr = h.nc_tiles_rows;
+  const int ntiles = ntr * (ntr + 1) / 2;
+  double* rowpart = h.cpart.as<double>();
+  double* colpart = rowpart + (int64_t)ntiles * 64;
+  hipLaunchKernelGGL(k_coarse_symv, dim3((ntiles + 3) / 4), dim3(256), 0, s, st,
+                     h.A0inv_t.as<double>(), ntiles, b0, rowpart, colpart);
+  hipLaunchKernelGGL(k_coarse_sum, dim3((unsigned)((h.nc + 255) / 256)), dim3(256), 0, s, st,
+                     rowpart, colpart, ntr, h.nc, y);
+  hipLaunchKernelGGL(k_coarse_prolong, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st,
+                     h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
+                     h.Q.as<double>(), h.k, y, e, S.n);
+  DDG_HIP(hipGetLastError());
+}
+
+// Profiling wrapper: event pair around a local-solve launch.
+static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez, const CgState* st,
+                           hipStream_t s) {
+  if (!h.profiling) {
+    launch_sweep(h, c, r, e, ez, st, s);
+    return;
+  }
+  if (h.ev_used + 2 > (int)h.ev_pool.size()) {
+    for (int t = 0; t < 64; ++t) {
+      hipEvent_t ev;
+      DDG_HIP(hipEventCreate(&ev));
+      h.ev_pool.push_back(ev);
+    }
+  }
+  int idx = h.ev_used;
+  h.ev_used += 2;
+  DDG_HIP(hipEventRecord(h.ev_pool[idx], s));
+  launch_sweep(h, c, r, e, ez, st, s);
+  DDG_HIP(hipEventRecord(h.ev_pool[idx + 1], s));
+  h.pending.push_back({idx, ez ? h.colour_bytes[h.S.n_colours + c] : h.colour_bytes[c]});
+}
+
+void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded, hipStream_t s) {
+  const CgState* st = guarded ? h.cstate.as<CgState>() : nullptr;
+  const int C = h.S.n_colours;
+  const int total = 2 * C + 1;
+  if (stages < 0 || stages > total) stages = total;
+  launch_fill(e, 0.0, h.S.n, s);
+  int done = 0;
+  for (int c = 0; c < C && done < stages; ++c, ++done) sweep_profiled(h, c, r, e, c == 0, st, s);
+  if (done < stages) {
+    launch_coarse(h, r, e, st, s);
+    ++done;
+  }
+  for (int c = C - 1; c >= 0 && done < stages; --c, ++done) sweep_profiled(h, c, r, e, false, st, s);
+}
+
+}  // namespace ddg

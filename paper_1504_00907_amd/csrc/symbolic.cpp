@@ -1,0 +1,341 @@
+// Host symbolic setup: validation of the pattern, non-overlapping and expanded
+// subdomain sets (Section 6: graph distance Delta in the stored pattern of A),
+// conflict colouring of the multiplicative sweep, subdomain adjacency (block
+// pattern of A0, Section 4), and the block-tridiagonal level structure used by
+// the local factors.  Integer work only.
+#include <algorithm>
+#include <numeric>
+#include <thread>
+
+#include "common.hpp"
+
+namespace ddg {
+
+namespace {
+
+void check_pattern(int64_t n, const int64_t* rp, const int32_t* ci) {
+  DDG_REQUIRE(n > 0, DDG_ERR_INVALID_ARG, "n must be positive");
+  DDG_REQUIRE(rp[0] == 0, DDG_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i) {
+    DDG_REQUIRE(rp[i + 1] >= rp[i], DDG_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+    bool diag = false;
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+      int32_t c = ci[t];
+      DDG_REQUIRE(c >= 0 && c < n, DDG_ERR_INVALID_ARG, "column index out of range in row " + std::to_string(i));
+      if (t > rp[i]) DDG_REQUIRE(ci[t - 1] < c, DDG_ERR_INVALID_ARG, "columns must be strictly increasing in row " + std::to_string(i));
+      if (c == i) diag = true;
+    }
+    DDG_REQUIRE(diag, DDG_ERR_INVALID_ARG, "missing diagonal entry in row " + std::to_string(i));
+  }
+  // structural symmetry
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+      int32_t c = ci[t];
+      const int32_t* b = ci + rp[c];
+      const int32_t* e = ci + rp[c + 1];
+      DDG_REQUIRE(std::binary_search(b, e, (int32_t)i), DDG_ERR_INVALID_ARG,
+                  "pattern not symmetric at (" + std::to_string(i) + "," + std::to_string(c) + ")");
+    }
+  }
+}
+
+// Run f(i) for i in [0, count) over a few host threads.
+template <class Fn>
+void parallel_for(int32_t count, Fn&& f) {
+  unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  int32_t nt = (int32_t)std::min<unsigned>(hw, (unsigned)std::max(1, count / 8));
+  if (nt <= 1) {
+    for (int32_t i = 0; i < count; ++i) f(i, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  std::vector<Error> errs(nt);
+  std::vector<int> failed(nt, 0);
+  for (int32_t t = 0; t < nt; ++t) {
+    th.emplace_back([&, t]() {
+      try {
+        for (int32_t i = t; i < count; i += nt) f(i, t);
+      } catch (const Error& e) {
+        errs[t] = e;
+        failed[t] = 1;
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (int32_t t = 0; t < nt; ++t)
+    if (failed[t]) throw errs[t];
+}
+
+}  // namespace
+
+void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci,
+                    const int32_t* part, int32_t n_parts, int32_t overlap, int32_t tile,
+                    int32_t block_target) {
+  check_pattern(n, rp, ci);
+  DDG_REQUIRE(n_parts >= 1, DDG_ERR_INVALID_ARG, "n_parts must be >= 1");
+  DDG_REQUIRE(overlap >= 0, DDG_ERR_INVALID_ARG, "overlap must be >= 0");
+  DDG_REQUIRE(n < (int64_t)1 << 31, DDG_ERR_UNSUPPORTED, "n must fit int32 indices");
+  S.n = n;
+  S.nnz = rp[n];
+  S.n_parts = n_parts;
+  S.overlap = overlap;
+
+  // --- non-overlapping sets (counting sort keeps ascending order)
+  S.own_ptr.assign(n_parts + 1, 0);
+  for (int64_t g = 0; g < n; ++g) {
+    DDG_REQUIRE(part[g] >= 0 && part[g] < n_parts, DDG_ERR_INVALID_ARG, "partition id out of range at " + std::to_string(g));
+    S.own_ptr[part[g] + 1]++;
+  }
+  for (int32_t i = 0; i < n_parts; ++i) {
+    DDG_REQUIRE(S.own_ptr[i + 1] > 0, DDG_ERR_INVALID_ARG, "subdomain " + std::to_string(i) + " is empty");
+    S.own_ptr[i + 1] += S.own_ptr[i];
+  }
+  S.own_idx.resize(n);
+  {
+    std::vector<int64_t> fill(S.own_ptr.begin(), S.own_ptr.end() - 1);
+    for (int64_t g = 0; g < n; ++g) S.own_idx[fill[part[g]]++] = (int32_t)g;
+  }
+  S.max_own = 0;
+  for (int32_t i = 0; i < n_parts; ++i)
+    S.max_own = std::max<int32_t>(S.max_own, (int32_t)(S.own_ptr[i + 1] - S.own_ptr[i]));
+
+  // --- expanded sets: breadth-first Delta levels over stored entries
+  std::vector<std::vector<int32_t>> sets(n_parts);
+  parallel_for(n_parts, [&](int32_t i, int) {
+    std::vector<int32_t> cur(S.own_idx.begin() + S.own_ptr[i], S.own_idx.begin() + S.own_ptr[i + 1]);
+    std::vector<int32_t> front = cur, next;
+    std::vector<int32_t> all = cur;
+    for (int32_t lev = 0; lev < overlap; ++lev) {
+      next.clear();
+      for (int32_t v : front)
+        for (int64_t t = rp[v]; t < rp[v + 1]; ++t) next.push_back(ci[t]);
+      std::sort(next.begin(), next.end());
+      next.erase(std::unique(next.begin(), next.end()), next.end());
+      std::vector<int32_t> fresh;
+      std::set_difference(next.begin(), next.end(), all.begin(), all.end(), std::back_inserter(fresh));
+      std::vector<int32_t> merged;
+      merged.reserve(all.size() + fresh.size());
+      std::merge(all.begin(), all.end(), fresh.begin(), fresh.end(), std::back_inserter(merged));
+      all.swap(merged);
+      front.swap(fresh);
+      if (front.empty()) break;
+    }
+    sets[i].swap(all);
+  });
+  S.set_ptr.assign(n_parts + 1, 0);
+  for (int32_t i = 0; i < n_parts; ++i) S.set_ptr[i + 1] = S.set_ptr[i] + (int64_t)sets[i].size();
+  DDG_REQUIRE(S.set_ptr[n_parts] < ((int64_t)1 << 31), DDG_ERR_UNSUPPORTED, "sum of expanded sets too large");
+  S.set_idx.resize(S.set_ptr[n_parts]);
+  S.max_set = 0;
+  for (int32_t i = 0; i < n_parts; ++i) {
+    std::copy(sets[i].begin(), sets[i].end(), S.set_idx.begin() + S.set_ptr[i]);
+    S.max_set = std::max<int32_t>(S.max_set, (int32_t)sets[i].size());
+  }
+
+  // --- membership (node -> subdomains whose expanded set contains it)
+  std::vector<int64_t> mem_ptr(n + 1, 0);
+  for (int64_t t = 0; t < (int64_t)S.set_idx.size(); ++t) mem_ptr[S.set_idx[t] + 1]++;
+  for (int64_t g = 0; g < n; ++g) mem_ptr[g + 1] += mem_ptr[g];
+  std::vector<int32_t> mem(S.set_idx.size());
+  {
+    std::vector<int64_t> fill(mem_ptr.begin(), mem_ptr.end() - 1);
+    for (int32_t i = 0; i < n_parts; ++i)
+      for (int64_t t = S.set_ptr[i]; t < S.set_ptr[i + 1]; ++t) mem[fill[S.set_idx[t]]++] = i;
+  }
+
+  // --- conflicts: j conflicts with i when set_j meets N[set_i]
+  std::vector<std::vector<int32_t>> conf(n_parts);
+  parallel_for(n_parts, [&](int32_t i, int) {
+    std::vector<int32_t> js;
+    for (int64_t t = S.set_ptr[i]; t < S.set_ptr[i + 1]; ++t) {
+      int32_t v = S.set_idx[t];
+      for (int64_t u = rp[v]; u < rp[v + 1]; ++u) {
+        int32_t w = ci[u];  // w in N[set_i] (includes v itself through the diagonal)
+        for (int64_t m = mem_ptr[w]; m < mem_ptr[w + 1]; ++m)
+          if (mem[m] != i) js.push_back(mem[m]);
+      }
+    }
+    std::sort(js.begin(), js.end());
+    js.erase(std::unique(js.begin(), js.end()), js.end());
+    conf[i].swap(js);
+  });
+  // --- greedy colouring in increasing subdomain id
+  S.colour.assign(n_parts, -1);
+  S.n_colours = 0;
+  {
+    std::vector<int32_t> stamp(n_parts + 1, -1);
+    for (int32_t i = 0; i < n_parts; ++i) {
+      for (int32_t j : conf[i])
+        if (j < i) stamp[S.colour[j]] = i;
+      int32_t c = 0;
+      while (stamp[c] == i) ++c;
+      S.colour[i] = c;
+      S.n_colours = std::max(S.n_colours, c + 1);
+    }
+  }
+  S.colour_ptr.assign(S.n_colours + 1, 0);
+  for (int32_t i = 0; i < n_parts; ++i) S.colour_ptr[S.colour[i] + 1]++;
+  for (int32_t c = 0; c < S.n_colours; ++c) S.colour_ptr[c + 1] += S.colour_ptr[c];
+  S.colour_subs.resize(n_parts);
+  {
+    std::vector<int32_t> fill(S.colour_ptr.begin(), S.colour_ptr.end() - 1);
+    for (int32_t i = 0; i < n_parts; ++i) S.colour_subs[fill[S.colour[i]]++] = i;
+  }
+
+  // --- subdomain adjacency through stored entries (block pattern of A0)
+  S.nbr_ptr.assign(n_parts + 1, 0);
+  std::vector<std::vector<int32_t>> nb(n_parts);
+  parallel_for(n_parts, [&](int32_t i, int) {
+    std::vector<int32_t> js;
+    for (int64_t t = S.own_ptr[i]; t < S.own_ptr[i + 1]; ++t) {
+      int32_t g = S.own_idx[t];
+      for (int64_t u = rp[g]; u < rp[g + 1]; ++u) js.push_back(part[ci[u]]);
+    }
+    std::sort(js.begin(), js.end());
+    js.erase(std::unique(js.begin(), js.end()), js.end());
+    nb[i].swap(js);
+  });
+  for (int32_t i = 0; i < n_parts; ++i) S.nbr_ptr[i + 1] = S.nbr_ptr[i] + (int32_t)nb[i].size();
+  S.nbr_idx.resize(S.nbr_ptr[n_parts]);
+  for (int32_t i = 0; i < n_parts; ++i) std::copy(nb[i].begin(), nb[i].end(), S.nbr_idx.begin() + S.nbr_ptr[i]);
+
+  // --- local structure: block-tridiagonal levels in the ascending local order
+  struct Local {
+    std::vector<int32_t> bstart, bsize;
+    std::vector<int64_t> lo_cnt, up_cnt, in_cnt;  // per local row
+    std::vector<int32_t> lo_col, up_col, in_col;
+    std::vector<int64_t> lo_pos, up_pos, in_pos;
+  };
+  std::vector<Local> loc(n_parts);
+  unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::vector<int32_t>> lmap(hw, std::vector<int32_t>());
+  // choose tile from the typical level width when not given
+  S.tile = tile;
+  parallel_for(n_parts, [&](int32_t i, int tid) {
+    auto& map = lmap[tid];
+    if ((int64_t)map.size() != n) map.assign(n, -1);
+    const int32_t* set = S.set_idx.data() + S.set_ptr[i];
+    int32_t ni = (int32_t)(S.set_ptr[i + 1] - S.set_ptr[i]);
+    for (int32_t j = 0; j < ni; ++j) map[set[j]] = j;
+    std::vector<int32_t> first(ni);
+    for (int32_t j = 0; j < ni; ++j) {
+      int32_t g = set[j];
+      int32_t f = j;
+      for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+        int32_t lc = map[ci[t]];
+        if (lc >= 0) f = std::min(f, lc);
+      }
+      first[j] = f;
+    }
+    std::vector<int32_t> suf(ni + 1, INT32_MAX);
+    for (int32_t j = ni - 1; j >= 0; --j) suf[j] = std::min(suf[j + 1], first[j]);
+    // greedy levels: rows of block m+1 and later may only reach back to block m,
+    // so s_{m+1} = max(s_m + 1, min{j : min_{j' >= j} first(j') >= s_m}).
+    std::vector<int32_t> bnd{0};
+    int32_t j = 0;
+    while (bnd.back() < ni) {
+      int32_t cur = bnd.back();
+      while (j < ni && suf[j] < cur) ++j;  // suf is non-decreasing
+      bnd.push_back(std::min(std::max(cur + 1, j), ni));
+    }
+    // merge consecutive levels: absorb tiny levels, and grow up to the target
+    int32_t target = block_target > 0 ? block_target : 0;
+    const int32_t min_rows = 16;
+    Local& L = loc[i];
+    int32_t s = 0;
+    for (size_t m = 1; m < bnd.size(); ++m) {
+      int32_t e = bnd[m];
+      bool last = (m + 1 == bnd.size());
+      int32_t size = e - s;
+      int32_t next_size = last ? 0 : bnd[m + 1] - e;
+      bool absorb = !last && (size < min_rows || (target > 0 && size + next_size <= target));
+      if (!absorb) {
+        L.bstart.push_back(s);
+        L.bsize.push_back(size);
+        s = e;
+      }
+    }
+    // block id of each local row
+    std::vector<int32_t> blk(ni);
+    for (size_t b = 0; b < L.bstart.size(); ++b)
+      for (int32_t r = L.bstart[b]; r < L.bstart[b] + L.bsize[b]; ++r) blk[r] = (int32_t)b;
+    L.lo_cnt.assign(ni, 0);
+    L.up_cnt.assign(ni, 0);
+    L.in_cnt.assign(ni, 0);
+    for (int32_t jj = 0; jj < ni; ++jj) {
+      int32_t g = set[jj];
+      for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+        int32_t lc = map[ci[t]];
+        if (lc < 0) continue;
+        int32_t d = blk[lc] - blk[jj];
+        DDG_REQUIRE(d >= -1 && d <= 1, DDG_ERR_HIP, "internal: level structure not block tridiagonal");
+        if (d < 0) { L.lo_col.push_back(lc); L.lo_pos.push_back(t); L.lo_cnt[jj]++; }
+        else if (d > 0) { L.up_col.push_back(lc); L.up_pos.push_back(t); L.up_cnt[jj]++; }
+        else { L.in_col.push_back(lc); L.in_pos.push_back(t); L.in_cnt[jj]++; }
+      }
+    }
+    for (int32_t jj = 0; jj < ni; ++jj) map[set[jj]] = -1;
+  });
+
+  // --- concatenate
+  S.sub_blk_ptr.assign(n_parts + 1, 0);
+  for (int32_t i = 0; i < n_parts; ++i) S.sub_blk_ptr[i + 1] = S.sub_blk_ptr[i] + (int32_t)loc[i].bstart.size();
+  int32_t nb_tot = S.sub_blk_ptr[n_parts];
+  S.blk_start.resize(nb_tot);
+  S.blk_size.resize(nb_tot);
+  S.blk_foff.resize(nb_tot + 1);
+  S.max_blk = 0;
+  S.max_blocks = 0;
+  for (int32_t i = 0; i < n_parts; ++i) {
+    std::copy(loc[i].bstart.begin(), loc[i].bstart.end(), S.blk_start.begin() + S.sub_blk_ptr[i]);
+    std::copy(loc[i].bsize.begin(), loc[i].bsize.end(), S.blk_size.begin() + S.sub_blk_ptr[i]);
+    S.max_blocks = std::max<int32_t>(S.max_blocks, (int32_t)loc[i].bstart.size());
+    for (int32_t b : loc[i].bsize) S.max_blk = std::max(S.max_blk, b);
+  }
+  if (S.tile <= 0) {
+    // automatic: the typical level width decides the tile edge
+    std::vector<int32_t> w(S.blk_size);
+    std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
+    int32_t med = w[w.size() / 2];
+    S.tile = med >= 160 ? 64 : (med >= 40 ? 32 : 16);
+  }
+  DDG_REQUIRE(S.tile == 16 || S.tile == 32 || S.tile == 64, DDG_ERR_INVALID_ARG, "tile must be 16, 32 or 64");
+  int64_t off = 0;
+  for (int32_t b = 0; b < nb_tot; ++b) {
+    S.blk_foff[b] = off;
+    off += (int64_t)tiles_for(S.blk_size[b], S.tile) * S.tile * S.tile;
+  }
+  S.blk_foff[nb_tot] = off;
+  S.fac_elems = off;
+
+  int64_t rows = S.set_ptr[n_parts];
+  auto concat = [&](auto getcnt, auto getcol, auto getpos, std::vector<int64_t>& ptr,
+                    std::vector<int32_t>& col, std::vector<int64_t>& pos) {
+    ptr.assign(rows + 1, 0);
+    for (int32_t i = 0; i < n_parts; ++i) {
+      const auto& cnt = getcnt(loc[i]);
+      for (size_t j = 0; j < cnt.size(); ++j) ptr[S.set_ptr[i] + j + 1] = cnt[j];
+    }
+    for (int64_t r = 0; r < rows; ++r) ptr[r + 1] += ptr[r];
+    col.resize(ptr[rows]);
+    pos.resize(ptr[rows]);
+    for (int32_t i = 0; i < n_parts; ++i) {
+      int64_t o = ptr[S.set_ptr[i]];
+      const auto& c = getcol(loc[i]);
+      const auto& p = getpos(loc[i]);
+      std::copy(c.begin(), c.end(), col.begin() + o);
+      std::copy(p.begin(), p.end(), pos.begin() + o);
+    }
+  };
+  concat([](const Local& L) -> const std::vector<int64_t>& { return L.lo_cnt; },
+         [](const Local& L) -> const std::vector<int32_t>& { return L.lo_col; },
+         [](const Local& L) -> const std::vector<int64_t>& { return L.lo_pos; }, S.lo_ptr, S.lo_col, S.lo_pos);
+  concat([](const Local& L) -> const std::vector<int64_t>& { return L.up_cnt; },
+         [](const Local& L) -> const std::vector<int32_t>& { return L.up_col; },
+         [](const Local& L) -> const std::vector<int64_t>& { return L.up_pos; }, S.up_ptr, S.up_col, S.up_pos);
+  concat([](const Local& L) -> const std::vector<int64_t>& { return L.in_cnt; },
+         [](const Local& L) -> const std::vector<int32_t>& { return L.in_col; },
+         [](const Local& L) -> const std::vector<int64_t>& { return L.in_pos; }, S.in_ptr, S.in_col, S.in_pos);
+}
+
+}  // namespace ddg

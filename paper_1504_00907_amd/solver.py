@@ -1,0 +1,187 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Host numpy arrays go to ``ddg_setup``; device vectors are torch float64
+tensors on the current HIP device and all work runs on the handle's stream
+(by default torch's current stream at construction time).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DDGError, Info, Options, check
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t: torch.Tensor, n: int, name: str) -> int:
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of length {n}")
+    return t.data_ptr()
+
+
+class DDGSolver:
+    """DDG two-level PCG handle (see include/ddg.h for the semantics)."""
+
+    def __init__(self, n: int, row_ptr, col_idx, val, F: Optional[np.ndarray], part, n_parts: int,
+                 overlap: int, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000,
+                 rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0, check_every: int = 4,
+                 stream: Optional[torch.cuda.Stream] = None):
+        lib = _lib.load()
+        self._lib = lib
+        self.n = int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        vv = np.ascontiguousarray(val, dtype=np.float64)
+        pp = np.ascontiguousarray(part, dtype=np.int32)
+        if F is None or F.size == 0:
+            k, Fp, Fh = 0, None, None
+        else:
+            Fh = np.asfortranarray(F, dtype=np.float64)
+            k = Fh.shape[1]
+            Fp = _ptr(Fh)
+        if rp.shape != (self.n + 1,) or pp.shape != (self.n,):
+            raise ValueError("row_ptr must have n+1 entries and part n entries")
+        if ci.shape[0] != int(rp[-1]) or vv.shape[0] != int(rp[-1]):
+            raise ValueError("col_idx/val length must equal row_ptr[-1]")
+        if Fh is not None and Fh.shape[0] != self.n:
+            raise ValueError("F must have n rows")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opt = Options()
+        lib.ddg_default_options(C.byref(opt))
+        opt.precision = _lib.PRECISION[precision]
+        opt.rtol = rtol
+        opt.max_iter = max_iter
+        opt.rank_tol = rank_tol
+        opt.tile = tile
+        opt.block_target = block_target
+        opt.check_every = check_every
+        opt.stream = C.c_void_p(self.stream.cuda_stream)
+        self.precision = precision
+        h = C.c_void_p()
+        check(lib.ddg_setup(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
+                            int(n_parts), int(overlap), C.byref(opt)))
+        self._h = h
+        self.nnz = int(rp[-1])
+        self.k = k
+
+    @classmethod
+    def from_problem(cls, P, **kw):
+        """Build from a ``workloads.Problem``."""
+        return cls(P.n, P.A.row_ptr, P.A.col_idx, P.A.val, P.F, P.part, P.n_parts, P.overlap, **kw)
+
+    # -- device operations ------------------------------------------------
+
+    def solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None, raise_on_error: bool = True):
+        if u is None:
+            u = torch.empty_like(f)
+        info = Info()
+        rc = self._lib.ddg_solve(self._h, _dev(f, self.n, "f"), _dev(u, self.n, "u"), C.byref(info))
+        if rc != 0 and raise_on_error:
+            check(rc)
+        return u, info.as_dict()
+
+    def apply_precond(self, r: torch.Tensor, z: Optional[torch.Tensor] = None) -> torch.Tensor:
+        z = torch.empty_like(r) if z is None else z
+        check(self._lib.ddg_apply_precond(self._h, _dev(r, self.n, "r"), _dev(z, self.n, "z")))
+        return z
+
+    def apply_stages(self, r: torch.Tensor, stages: int, e: Optional[torch.Tensor] = None) -> torch.Tensor:
+        e = torch.empty_like(r) if e is None else e
+        check(self._lib.ddg_apply_precond_stages(self._h, _dev(r, self.n, "r"), _dev(e, self.n, "e"), int(stages)))
+        return e
+
+    def spmv(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        y = torch.empty_like(x) if y is None else y
+        check(self._lib.ddg_spmv(self._h, _dev(x, self.n, "x"), _dev(y, self.n, "y")))
+        return y
+
+    def refactor(self, val: torch.Tensor):
+        check(self._lib.ddg_refactor(self._h, _dev(val, self.nnz, "val")))
+
+    # -- host queries -------------------------------------------------------
+
+    def info(self) -> dict:
+        info = Info()
+        check(self._lib.ddg_get_info(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def export(self, what: int) -> np.ndarray:
+        need = C.c_int64()
+        check(self._lib.ddg_export(self._h, what, None, 0, C.byref(need)))
+        dtype = {_lib.EXPORT_COLOURS: np.int32, _lib.EXPORT_SET_PTR: np.int64, _lib.EXPORT_SET_IDX: np.int32,
+                 _lib.EXPORT_KCOUNTS: np.int32, _lib.EXPORT_A0: np.float64, _lib.EXPORT_Q: np.float64,
+                 _lib.EXPORT_BLOCKS: np.int32}[what]
+        out = np.empty(need.value // np.dtype(dtype).itemsize, dtype=dtype)
+        check(self._lib.ddg_export(self._h, what, _ptr(out), need.value, None))
+        return out
+
+    def colours(self) -> np.ndarray:
+        return self.export(_lib.EXPORT_COLOURS)
+
+    def sets(self):
+        ptr = self.export(_lib.EXPORT_SET_PTR)
+        idx = self.export(_lib.EXPORT_SET_IDX)
+        return [idx[ptr[i]:ptr[i + 1]] for i in range(len(ptr) - 1)]
+
+    def kcounts(self) -> np.ndarray:
+        return self.export(_lib.EXPORT_KCOUNTS)
+
+    def A0(self) -> np.ndarray:
+        a = self.export(_lib.EXPORT_A0)
+        m = int(round(np.sqrt(a.size)))
+        return a.reshape(m, m)
+
+    def Q(self) -> np.ndarray:
+        return self.export(_lib.EXPORT_Q).reshape(self.n, self.k)
+
+    def blocks(self) -> np.ndarray:
+        return self.export(_lib.EXPORT_BLOCKS).reshape(-1, 3)
+
+    def profile_enable(self, on: bool = True):
+        check(self._lib.ddg_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True):
+        ms, la, by = C.c_double(), C.c_int64(), C.c_int64()
+        check(self._lib.ddg_profile_read(self._h, C.byref(ms), C.byref(la), C.byref(by), 1 if reset else 0))
+        return {"ms": ms.value, "launches": la.value, "bytes": by.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ddg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stencil_assemble(dims, theta: torch.Tensor, val: torch.Tensor, stream=None):
+    """CSR values of the cell-centred harmonic-mean operator for kappa = exp(theta)."""
+    lib = _lib.load()
+    d = (C.c_int32 * 3)(*[int(x) for x in dims])
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    n = int(np.prod(dims))
+    check(lib.ddg_stencil_assemble(d, _dev(theta, n, "theta"), val.data_ptr(), C.c_void_p(s)))
+    return val
+
+
+def stencil_coeff_grad(dims, theta, u, lam, grad=None, stream=None):
+    """Per-cell dL/dtheta = -kappa lam^T (dA/dkappa) u."""
+    lib = _lib.load()
+    n = int(np.prod(dims))
+    grad = torch.empty_like(theta) if grad is None else grad
+    d = (C.c_int32 * 3)(*[int(x) for x in dims])
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    check(lib.ddg_stencil_coeff_grad(d, _dev(theta, n, "theta"), _dev(u, n, "u"), _dev(lam, n, "lam"),
+                                     _dev(grad, n, "grad"), C.c_void_p(s)))
+    return grad

@@ -1,0 +1,244 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 mode u within 1e-10 relative of the oracle with equal
+iteration counts (+-1); preconditioner applications within 1e-12 relative
+(only rounding differs: explicit Schur-complement inverses vs banded
+Cholesky); mixed modes reach the requested residual (true residual <= 1e-8
+relative) within +-1 iteration of the FP64 oracle.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import DDGOracle
+from workloads import (box_partition, cell_coords, cfg1, diffusion_cc, diffusion_problem, laplace5_nodes,
+                       monomials, node_coords_2d, poisson2d_nodes, seed_rng)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def make_solver(P, **kw):
+    from paper_1504_00907_amd import DDGSolver
+    say(f"[setup] {P.name} n={P.n} parts={P.n_parts} overlap={P.overlap} k={P.k} {kw}")
+    return DDGSolver.from_problem(P, **kw)
+
+
+def small3d(side=20, boxes=2, overlap=1, p=2, sigma=1.0):
+    # ragged: 20/2 = 10-cell boxes, interior level 10*10 + 4*10 = 140 rows -> 3 tiles of 64
+    return diffusion_problem((side,) * 3, (boxes,) * 3, overlap, p, cfg_id=51, rtol=1e-10, ell=4.0,
+                             sigma=sigma, name=f"3d{side}_b{boxes}_o{overlap}_p{p}")
+
+
+CASES = {
+    "cfg1": lambda: cfg1(),
+    "3d20": lambda: small3d(),
+    "3d18_b3": lambda: small3d(side=18, boxes=3, overlap=1, p=1),
+    "2d40_ovl0": lambda: poisson2d_nodes(40, 5, 0, 3, cfg_id=52, rtol=1e-10, name="2d40_ovl0"),
+}
+
+_cache = {}
+
+
+def problem(name):
+    if name not in _cache:
+        P = CASES[name]()
+        _cache[name] = (P, DDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_and_structures(name):
+    P, o = problem(name)
+    s = make_solver(P)
+    x = seed_rng(60, 0).standard_normal(P.n)
+    y = host(s.spmv(dev(x)))
+    ref = P.A.to_scipy() @ x
+    assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
+    assert np.array_equal(s.colours(), o.colours)
+    for i, st in enumerate(s.sets()):
+        assert np.array_equal(st, o.sets[i])
+    assert np.array_equal(s.kcounts(), o.k_counts)
+    info = s.info()
+    assert info["n_coarse"] == o.n_coarse and info["n_colours"] == o.n_colours
+    # coarse basis: orthonormal per subdomain, spans the generating vectors on each subdomain
+    Q = s.Q()
+    for i in range(P.n_parts):
+        m = P.part == i
+        Qi = Q[m][:, :o.k_counts[i]]
+        assert np.abs(Qi.T @ Qi - np.eye(Qi.shape[1])).max() <= 1e-12
+        Fi = P.F[m]
+        assert np.linalg.norm(Fi - Qi @ (Qi.T @ Fi)) <= 1e-10 * np.linalg.norm(Fi)
+    # A0 is basis dependent; its spectrum is not
+    A0 = s.A0()
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (A0 + A0.T)))
+    ev_ref = np.sort(np.linalg.eigvalsh(o.A0))
+    assert np.abs(ev - ev_ref).max() <= 1e-11 * ev_ref.max()
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preconditioner_matches_oracle(name):
+    P, o = problem(name)
+    s = make_solver(P)
+    rng = seed_rng(61, 0)
+    for trial in range(2):
+        r = rng.standard_normal(P.n)
+        say(f"[apply] {name} trial {trial}")
+        z = host(s.apply_precond(dev(r)))
+        ref = o.apply(r)
+        err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+        say(f"   rel err {err:.3e}")
+        assert err <= 1e-12
+    s.close()
+
+
+def test_stage_properties_3d():
+    """Local exactness after every pre-sweep colour and Galerkin orthogonality after the coarse step."""
+    P, o = problem("3d20")
+    s = make_solver(P)
+    As = P.A.to_scipy()
+    r = seed_rng(62, 0).standard_normal(P.n)
+    rd = dev(r)
+    C = o.n_colours
+    Q = s.Q()
+    for stage in range(1, C + 2):
+        say(f"[stages] {stage}")
+        e = host(s.apply_stages(rd, stage))
+        res = r - As @ e
+        if stage <= C:
+            for i in o.order[stage - 1]:
+                assert np.linalg.norm(res[o.sets[i]]) <= 1e-12 * np.linalg.norm(r)
+        else:
+            for i in range(P.n_parts):
+                m = P.part == i
+                assert np.linalg.norm(Q[m].T @ res[m]) <= 1e-12 * np.linalg.norm(r)
+    full = host(s.apply_stages(rd, 2 * C + 1))
+    z = host(s.apply_precond(rd))
+    assert np.array_equal(full, z)
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64_matches_oracle(name):
+    P, o = problem(name)
+    s = make_solver(P, rtol=P.rtol)
+    say(f"[solve] {name} fp64")
+    u, info = s.solve(dev(P.f))
+    u = host(u)
+    x, it, oinfo = o.pcg(P.f, P.rtol)
+    err = np.linalg.norm(u - x) / np.linalg.norm(x)
+    say(f"   iters gpu {info['iters']} oracle {it} rel err {err:.3e} true res {info['true_rel_res']:.3e}")
+    assert info["status"] == 0
+    assert abs(info["iters"] - it) <= 1
+    if info["iters"] == it:
+        assert err <= 1e-10
+    assert info["true_rel_res"] <= 10 * P.rtol
+    true_res = np.linalg.norm(P.f - P.A.to_scipy() @ u) / np.linalg.norm(P.f)
+    assert abs(true_res - info["true_rel_res"]) <= 1e-3 * true_res + 1e-15
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["cfg1", "3d20"])
+def test_solve_mixed(name, precision):
+    P, o = problem(name)
+    tol = 1e-8
+    s = make_solver(P, rtol=tol, precision=precision)
+    say(f"[solve] {name} {precision}")
+    u, info = s.solve(dev(P.f))
+    u = host(u)
+    x, it, _ = o.pcg(P.f, tol)
+    true_res = np.linalg.norm(P.f - P.A.to_scipy() @ u) / np.linalg.norm(P.f)
+    err = np.linalg.norm(u - x) / np.linalg.norm(x)
+    say(f"   iters {info['iters']} (oracle fp64 {it}) true res {true_res:.3e} err vs oracle {err:.3e}")
+    assert info["status"] == 0
+    assert true_res <= 1.5e-8
+    if precision == "fp32":
+        assert abs(info["iters"] - it) <= 1
+    else:
+        assert info["iters"] <= 3 * it + 5
+    s.close()
+
+
+def test_fp64_is_deterministic():
+    P, o = problem("3d20")
+    s = make_solver(P, rtol=1e-10)
+    f = dev(P.f)
+    u1, i1 = s.solve(f)
+    u2, i2 = s.solve(f)
+    assert i1["iters"] == i2["iters"]
+    assert torch.equal(u1, u2)
+    s.close()
+
+
+def test_solve_statuses():
+    from paper_1504_00907_amd import DDGError
+    P, o = problem("cfg1")
+    s = make_solver(P, rtol=1e-10)
+    u, info = s.solve(torch.zeros(P.n, dtype=torch.float64, device="cuda"))
+    assert info["status"] == 0 and info["iters"] == 0 and not torch.any(u)
+    bad = P.f.copy()
+    bad[5] = np.nan
+    with pytest.raises(DDGError) as ei:
+        s.solve(dev(bad))
+    assert ei.value.status == "INVALID_ARG"
+    s.close()
+    s = make_solver(P, rtol=1e-30, max_iter=3)
+    u, info = s.solve(dev(P.f), raise_on_error=False)
+    assert info["status"] == -5 and info["iters"] == 3
+    x, it, _ = o.pcg(P.f, 1e-30, max_iter=3)
+    assert np.linalg.norm(host(u) - x) <= 1e-10 * np.linalg.norm(x)
+    s.close()
+
+
+def test_setup_errors():
+    from paper_1504_00907_amd import DDGError, DDGSolver
+    m = 10
+    A = laplace5_nodes(m)
+    part = box_partition((m, m), (2, 2))
+    F = monomials(node_coords_2d(m), 1)
+    # positive diagonal but indefinite: diag 1, off-diagonal -1
+    val = np.where(A.val == 4.0, 1.0, A.val)
+    with pytest.raises(DDGError) as ei:
+        DDGSolver(A.n, A.row_ptr, A.col_idx, val, F, part, 4, 1)
+    assert ei.value.status == "NOT_SPD"
+    F0 = F.copy()
+    F0[part == 3] = 0.0
+    with pytest.raises(DDGError) as ei:
+        DDGSolver(A.n, A.row_ptr, A.col_idx, A.val, F0, part, 4, 1)
+    assert ei.value.status == "RANK"
+
+
+def test_rank_deficient_strips():
+    """One- and two-node-wide strips keep 3 and 5 of 6 columns, as in the oracle."""
+    m = 12
+    A = laplace5_nodes(m)
+    F = monomials(node_coords_2d(m), 2)
+    xs = np.arange(m * m) % m
+    part = np.where(xs == 0, 0, np.where(xs < 3, 1, 2)).astype(np.int32)
+    from paper_1504_00907_amd import DDGSolver
+    s = DDGSolver(A.n, A.row_ptr, A.col_idx, A.val, F, part, 3, 1, rtol=1e-10)
+    assert list(s.kcounts()) == [3, 5, 6]
+    o = DDGOracle(A, F, part, 3, 1)
+    r = seed_rng(63, 0).standard_normal(A.n)
+    z = host(s.apply_precond(dev(r)))
+    assert np.linalg.norm(z - o.apply(r)) <= 1e-12 * np.linalg.norm(z)
+    s.close()
