@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 
 #include "common.hpp"
@@ -54,19 +55,21 @@ void check_values(int64_t n, const int64_t* rp, const int32_t* ci, const double*
   }
 }
 
-// Algorithmic HBM bytes of one local-solve launch per colour (see the design notes):
-// factor tiles read once per substitution; per local row the set index, r,
-// the read-modify-write of e, the two coupling pointers and the coupling
-// entries; for colours that start from a non-zero e also the CSR rows of the
-// gather and one read of e.  colour_bytes[c] is the general case,
-// colour_bytes[C + c] the first phase that starts from e = 0.
+// Algorithmic HBM bytes of one local-solve kernel launch per colour (see the
+// design notes): factor tiles read once per substitution (the levels of the
+// two chains and the middle level), per local row the residual read, the set
+// index and the read-modify-write of e in the scatter, and the coupling slots.
+// The local-residual kernel that precedes it is counted separately
+// (residual_bytes): set index, r, residual write, and for colours that start
+// from a non-zero e the CSR rows and one read of e.
 void account_bytes(Handle& h, const int64_t* rp) {
   const Symbolic& S = h.S;
   const int es = storage_size(h.opt.precision);
   const int32_t C = S.n_colours;
   h.colour_bytes.assign(2 * C, 0);
+  int64_t resid = 0, resid0 = 0;
   for (int32_t c = 0; c < C; ++c) {
-    int64_t bytes = 0, bytes0 = 0;
+    int64_t bytes = 0;
     for (int32_t q = S.colour_ptr[c]; q < S.colour_ptr[c + 1]; ++q) {
       const int32_t i = S.colour_subs[q];
       int64_t fb = 0;
@@ -77,19 +80,20 @@ void account_bytes(Handle& h, const int64_t* rp) {
       }
       const int64_t r0 = S.set_ptr[i], r1 = S.set_ptr[i + 1];
       const int64_t ni = r1 - r0;
-      const int64_t ncpl = (S.lo_ptr[r1] - S.lo_ptr[r0]) + (S.up_ptr[r1] - S.up_ptr[r0]);
+      const int64_t ncpl = ni * (S.cl + S.cu);  // ELL slots read by the sweep
       int64_t nnz_rows = 0;
       for (int64_t t = r0; t < r1; ++t) nnz_rows += rp[S.set_idx[t] + 1] - rp[S.set_idx[t]];
-      const int64_t common = fb + ni * (4 + 8 + 16) + ni * 16 + ncpl * 12;
-      bytes0 += common;
-      bytes += common + ni * 8 + nnz_rows * 12 + ni * 8;
+      bytes += fb + ni * (8 + 4 + 16) + ncpl * 12;
+      resid0 += ni * (4 + 8 + 8);
+      resid += ni * (4 + 8 + 8 + 16 + 8) + nnz_rows * 12;
     }
     h.colour_bytes[c] = bytes;
-    h.colour_bytes[C + c] = bytes0;
+    h.colour_bytes[C + c] = bytes;
   }
-  int64_t sweep = h.colour_bytes[C];  // first pre-sweep phase starts from e = 0
-  for (int32_t c = 1; c < C; ++c) sweep += h.colour_bytes[c];
-  for (int32_t c = 0; c < C; ++c) sweep += h.colour_bytes[c];
+  h.residual_bytes = resid;
+  int64_t sweep = 0;
+  for (int32_t c = 0; c < C; ++c) sweep += 2 * h.colour_bytes[c];
+  sweep += (2 * C - 1) * (resid / C) + resid0 / C;  // residual kernels (per-colour average)
   h.info.sweep_bytes = sweep;
   const int64_t n = S.n, nnzb = S.nnz * 12 + (n + 1) * 8;
   const int64_t ntiles = (int64_t)h.nc_tiles_rows * (h.nc_tiles_rows + 1) / 2;
@@ -109,6 +113,7 @@ void check_err_flag(Handle& h, const char* what) {
   if (e[0] != 0) {
     std::string m = std::string(what) + ": ";
     if (e[0] == DDG_ERR_RANK) m += "every generating vector vanishes on subdomain " + std::to_string(e[1]);
+    else if (e[0] == DDG_ERR_HIP) m += "workgroup handoff timed out in subdomain " + std::to_string(e[1]);
     else if (e[1] < 0) m += "coarse pivot " + std::to_string(e[3]) + " not positive (A0 not SPD)";
     else m += "local pivot not positive in subdomain " + std::to_string(e[1]) + " block " + std::to_string(e[2]) +
               " row " + std::to_string(e[3]);
@@ -247,10 +252,8 @@ int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t*
     h->blk_start.upload(S.blk_start, s);
     h->blk_size.upload(S.blk_size, s);
     h->blk_foff.upload(S.blk_foff, s);
-    h->lo_ptr.upload(S.lo_ptr, s);
     h->lo_col.upload(S.lo_col, s);
     h->lo_pos.upload(S.lo_pos, s);
-    h->up_ptr.upload(S.up_ptr, s);
     h->up_col.upload(S.up_col, s);
     h->up_pos.upload(S.up_pos, s);
     h->in_ptr.upload(S.in_ptr, s);
@@ -258,6 +261,18 @@ int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t*
     h->in_pos.upload(S.in_pos, s);
     h->lo_val.alloc(std::max<size_t>(1, S.lo_pos.size()) * sizeof(double));
     h->up_val.alloc(std::max<size_t>(1, S.up_pos.size()) * sizeof(double));
+    // two-workgroup sweep: every pair of a colour must be resident at once
+    int ncu = 0;
+    DDG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    h->n_cu = ncu;
+    int max_nsub = 0;
+    for (int32_t c = 0; c < S.n_colours; ++c) max_nsub = std::max(max_nsub, S.colour_ptr[c + 1] - S.colour_ptr[c]);
+    h->twisted_ok = (16 * ((max_nsub + 7) / 8) <= ncu) && std::getenv("DDG_NO_TWIST") == nullptr;
+    h->xch_ld = ((S.max_blk + 63) / 64) * 64;
+    h->xch.alloc((size_t)n_parts * 2 * h->xch_ld * sizeof(double));
+    h->flags.alloc((size_t)n_parts * 2 * sizeof(int32_t));
+    DDG_HIP(hipMemsetAsync(h->flags.p, 0, (size_t)n_parts * 2 * sizeof(int32_t), s));
+    h->bres.alloc((size_t)S.set_ptr[n_parts] * sizeof(double));
     h->err_flag.alloc(4 * sizeof(int32_t));
     DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 4 * sizeof(int32_t), s));
     h->fac.alloc((size_t)S.fac_elems * storage_size(h->opt.precision));
@@ -372,6 +387,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     }
     launch_true_residual(*h, f_dev, x, s);
     DDG_HIP(hipEventRecord(e1, s));
+    check_err_flag(*h, "solve");
     DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
     DDG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;

@@ -90,10 +90,15 @@ struct Symbolic {
   int64_t fac_elems = 0;
   int32_t tile = 64;
   int32_t max_set = 0, max_blk = 0, max_blocks = 0, max_own = 0;
-  // local couplings: per local row (global row id = set_ptr[i] + j)
-  std::vector<int64_t> lo_ptr, up_ptr, in_ptr;   // sum|set|+1 each
-  std::vector<int32_t> lo_col, up_col, in_col;   // local column (within the subdomain)
-  std::vector<int64_t> lo_pos, up_pos, in_pos;   // position in the global CSR value array
+  // local couplings, per local row r (global row id = set_ptr[i] + j):
+  //   lower (to the previous level) and upper (to the next level) in ELL form with
+  //   cl / cu slots per row (col = -1 marks an empty slot), same-level entries in CSR form.
+  int32_t cl = 0, cu = 0;
+  std::vector<int32_t> lo_col, up_col;           // rows * cl, rows * cu: local column or -1
+  std::vector<int64_t> lo_pos, up_pos;           // position in the global CSR value array (or -1)
+  std::vector<int64_t> in_ptr;                   // sum|set|+1
+  std::vector<int32_t> in_col;
+  std::vector<int64_t> in_pos;
 };
 
 // Builds every integer structure; throws Error on malformed input.
@@ -146,9 +151,14 @@ struct Handle {
   DevBuf colour_subs;
   DevBuf nbr_ptr, nbr_idx;
   DevBuf sub_blk_ptr, blk_start, blk_size, blk_foff;
-  DevBuf lo_ptr, lo_col, lo_pos, lo_val;
-  DevBuf up_ptr, up_col, up_pos, up_val;
+  DevBuf lo_col, lo_pos, lo_val;     // ELL lower couplings
+  DevBuf up_col, up_pos, up_val;     // ELL upper couplings
   DevBuf in_ptr, in_col, in_pos;
+  DevBuf xch, flags;                 // two-workgroup handoff buffers of the twisted sweep
+  DevBuf bres;                       // local residuals of one colour's expanded sets
+  int32_t xch_ld = 0;
+  bool twisted_ok = false;
+  int32_t n_cu = 256;
   DevBuf F;               // n x k column-major (setup input)
   DevBuf Q;               // n x k node-major orthonormal basis (zero-padded)
   DevBuf kcnt_d, koff_d;
@@ -167,8 +177,8 @@ struct Handle {
 
   // info
   ddg_info info{};
-  int64_t sweep_bytes_colour_fwd[64] = {};
   std::vector<int64_t> colour_bytes;   // algorithmic bytes of one local-solve launch per colour
+  int64_t residual_bytes = 0;          // all colours' local-residual kernels (non-zero e)
 
   // profiling
   bool profiling = false;

@@ -65,7 +65,6 @@ __global__ void __launch_bounds__(256) k_coarse_symv(const CgState* st, const do
   if (st && st->done) return;
   constexpr int T = 64;
   using G = TileGeom<double, T>;
-  constexpr int S = G::S;
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
@@ -73,29 +72,7 @@ __global__ void __launch_bounds__(256) k_coarse_symv(const CgState* st, const do
   tile_ij(t, I, J);
   double m[G::SS];
   load_subtile<double, T>(tiles + (int64_t)t * T * T, lane, m);
-  const int p = lane >> 3, q = lane & 7;
-  double xr[S], xc[S], rowp[S], colp[S];
-#pragma unroll
-  for (int b = 0; b < S; ++b) {
-    xr[b] = x[J * T + q * S + b];
-    xc[b] = x[I * T + p * S + b];
-    rowp[b] = 0.0;
-    colp[b] = 0.0;
-  }
-#pragma unroll
-  for (int a = 0; a < S; ++a)
-#pragma unroll
-    for (int b = 0; b < S; ++b) {
-      rowp[a] += m[a * S + b] * xr[b];
-      colp[b] += m[a * S + b] * xc[a];
-    }
-  bool w;
-  double rs = group_reduce_scatter<double, S, G::LOGS>(rowp, q, 1, w);
-  rowpart[(int64_t)t * T + p * S + q] = rs;
-  if (I != J) {
-    double cs = group_reduce_scatter<double, S, G::LOGS>(colp, p, 8, w);
-    colpart[(int64_t)t * T + q * S + p] = cs;
-  }
+  symv_tile_slots<double, double, T>(m, I, J, x, rowpart + (int64_t)t * T, colpart + (int64_t)t * T, lane, true);
 }
 
 __global__ void k_coarse_sum(const CgState* st, const double* __restrict__ rowpart,
@@ -131,7 +108,7 @@ __global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ 
 }  // namespace
 
 void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                  const CgState* st, hipStream_t s);
+                  const CgState* st, hipStream_t s, bool residual);
 
 void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s) {
   if (h.nc == 0) return;
@@ -157,11 +134,13 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
   DDG_HIP(hipGetLastError());
 }
 
-// Profiling wrapper: event pair around a local-solve launch.
+// Local residual of one colour, then its local solves; when profiling, an event
+// pair brackets the local-solve kernel alone.
 static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez, const CgState* st,
                            hipStream_t s) {
+  launch_sweep(h, c, r, e, ez, st, s, true);
   if (!h.profiling) {
-    launch_sweep(h, c, r, e, ez, st, s);
+    launch_sweep(h, c, r, e, ez, st, s, false);
     return;
   }
   if (h.ev_used + 2 > (int)h.ev_pool.size()) {
@@ -174,7 +153,7 @@ static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez
   int idx = h.ev_used;
   h.ev_used += 2;
   DDG_HIP(hipEventRecord(h.ev_pool[idx], s));
-  launch_sweep(h, c, r, e, ez, st, s);
+  launch_sweep(h, c, r, e, ez, st, s, false);
   DDG_HIP(hipEventRecord(h.ev_pool[idx + 1], s));
   h.pending.push_back({idx, ez ? h.colour_bytes[h.S.n_colours + c] : h.colour_bytes[c]});
 }

@@ -358,24 +358,20 @@ __device__ void gj_invert_wg(double* __restrict__ A, int b, double* Rp, double* 
   }
 }
 
-// Pack the lower triangle of a symmetric b x b row-major matrix (ld) into T x T tiles.
+// Pack the lower triangle of a symmetric b x b row-major matrix (ld) into T x T tiles
+// (layout of symv_tile.hpp).
 template <class FT, int T, int NT>
 __device__ inline void pack_tiles_wg(const double* __restrict__ A, int64_t ld, int b, FT* __restrict__ out) {
-  using G = TileGeom<FT, T>;
   const int nt = (b + T - 1) / T;
   const int64_t total = (int64_t)nt * (nt + 1) / 2 * T * T;
   for (int64_t idx = threadIdx.x; idx < total; idx += NT) {
     const int t = (int)(idx / (T * T));
-    const int within = (int)(idx % (T * T));
-    // invert tile_elem: within = ((e / E) * 64 + lane) * E + e % E
-    const int chunk = within / G::E;
-    const int lane = chunk % 64;
-    const int e = (chunk / 64) * G::E + within % G::E;
-    const int a = e / G::S, bb = e % G::S;
+    int rr, cc;
+    tile_rc<FT, T>((int)(idx % (T * T)), rr, cc);
     int I, J;
     tile_ij(t, I, J);
-    const int row = I * T + (lane >> 3) * G::S + a;
-    const int col = J * T + (lane & 7) * G::S + bb;
+    const int row = I * T + rr;
+    const int col = J * T + cc;
     double v = 0.0;
     if (row < b && col < b) v = (row >= col) ? A[(int64_t)row * ld + col] : A[(int64_t)col * ld + row];
     out[idx] = Store<FT>::from(v);
@@ -383,7 +379,10 @@ __device__ inline void pack_tiles_wg(const double* __restrict__ A, int64_t ld, i
 }
 
 // ---------------------------------------------------------------------------
-// Local factorisation: one workgroup per subdomain.
+// Local factorisation (twisted block LDL^T, see kernels_sweep.hip): for each
+// subdomain a top chain (levels 0..m-1, couplings to the level below) and a
+// bottom chain (levels K-1..m+1, couplings to the level above) run as two
+// independent workgroups; a second kernel forms and inverts the middle level.
 
 constexpr int kFacThreads = 256;
 constexpr int kFacNB = 16;
@@ -395,9 +394,12 @@ struct FactorArgs {
   const int32_t* blk_start;
   const int32_t* blk_size;
   const int64_t* blk_foff;
-  const int64_t* lo_ptr;
   const int32_t* lo_col;
   const int64_t* lo_pos;
+  int32_t cl;
+  const int32_t* up_col;
+  const int64_t* up_pos;
+  int32_t cu;
   const int64_t* in_ptr;
   const int32_t* in_col;
   const int64_t* in_pos;
@@ -408,54 +410,77 @@ struct FactorArgs {
   int32_t* err;
 };
 
+// Sm = D_k (row-major b x b) from the same-level entries of rows row0..row0+b-1.
+__device__ inline void load_diag_block(double* Sm, int b, int bs, int64_t row0, const FactorArgs& a) {
+  for (int idx = threadIdx.x; idx < b * b; idx += kFacThreads) Sm[idx] = 0.0;
+  __syncthreads();
+  for (int jj = threadIdx.x; jj < b; jj += kFacThreads) {
+    const int64_t row = row0 + jj;
+    for (int64_t t = a.in_ptr[row]; t < a.in_ptr[row + 1]; ++t)
+      Sm[(int64_t)jj * b + (a.in_col[t] - bs)] = a.val[a.in_pos[t]];
+  }
+  __syncthreads();
+}
+
+// Sm -= C X C^T, where C (b x bp) holds the couplings of rows row0.. to the level
+// starting at bsp (ELL slots ccol/cpos, cc per row) and X is bp x bp.
+__device__ inline void schur_update(double* Sm, int b, const double* X, int bp, int bsp, double* Tm,
+                                    const int32_t* ccol, const int64_t* cpos, int cc, int64_t row0,
+                                    const double* val) {
+  for (int idx = threadIdx.x; idx < bp * b; idx += kFacThreads) {
+    const int pp = idx / b, c = idx % b;
+    const int64_t row = row0 + c;
+    double acc = 0.0;
+    for (int q = 0; q < cc; ++q) {
+      const int col = ccol[row * cc + q];
+      if (col >= 0) acc += X[(int64_t)pp * bp + (col - bsp)] * val[cpos[row * cc + q]];
+    }
+    Tm[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < b * b; idx += kFacThreads) {
+    const int r = idx / b, c = idx % b;
+    const int64_t row = row0 + r;
+    double acc = 0.0;
+    for (int q = 0; q < cc; ++q) {
+      const int col = ccol[row * cc + q];
+      if (col >= 0) acc += val[cpos[row * cc + q]] * Tm[(int64_t)(col - bsp) * b + c];
+    }
+    Sm[idx] -= acc;
+  }
+  __syncthreads();
+}
+
 template <class FT, int T>
-__global__ void __launch_bounds__(kFacThreads) k_local_factor(FactorArgs a) {
+__global__ void __launch_bounds__(kFacThreads) k_local_factor_chain(FactorArgs a) {
   extern __shared__ __align__(16) double fsm[];
   double* piv = fsm;                                 // NB*(NB+1)
   double* Rp = fsm + kFacNB * (kFacNB + 1);          // NB * bmax
-  const int sub = a.first_sub + blockIdx.x;
-  double* X = a.scratch + (int64_t)blockIdx.x * 3 * a.bmax2;
-  double* Tm = X + a.bmax2;
-  double* Sm = Tm + a.bmax2;
+  const int slot = blockIdx.x >> 1, chain = blockIdx.x & 1;
+  const int sub = a.first_sub + slot;
+  double* buf = a.scratch + (int64_t)(2 * slot + chain) * 3 * a.bmax2;
+  double* X = buf;
+  double* Tm = buf + a.bmax2;
+  double* Sm = buf + 2 * a.bmax2;
   const int64_t s0 = a.set_ptr[sub];
   const int kb0 = a.sub_blk_ptr[sub];
   const int K = a.sub_blk_ptr[sub + 1] - kb0;
+  const int m = (K - 1) / 2;
+  const int steps = chain == 0 ? m : K - 1 - m;
   FT* fac = static_cast<FT*>(a.fac);
-  const int tid = threadIdx.x;
-  for (int k = 0; k < K; ++k) {
+  for (int j = 0; j < steps; ++j) {
+    const int k = chain == 0 ? j : K - 1 - j;
     const int bs = a.blk_start[kb0 + k];
     const int b = a.blk_size[kb0 + k];
-    for (int idx = tid; idx < b * b; idx += kFacThreads) Sm[idx] = 0.0;
-    __syncthreads();
-    for (int jj = tid; jj < b; jj += kFacThreads) {
-      const int64_t row = s0 + bs + jj;
-      for (int64_t t = a.in_ptr[row]; t < a.in_ptr[row + 1]; ++t)
-        Sm[(int64_t)jj * b + (a.in_col[t] - bs)] = a.val[a.in_pos[t]];
-    }
-    __syncthreads();
-    if (k > 0) {
-      const int bp = a.blk_size[kb0 + k - 1];
-      const int bps = a.blk_start[kb0 + k - 1];
-      // Tm = X_{k-1} L_k^T  (bp x b)
-      for (int idx = tid; idx < bp * b; idx += kFacThreads) {
-        const int p = idx / b, c = idx % b;
-        const int64_t row = s0 + bs + c;
-        double acc = 0.0;
-        for (int64_t t = a.lo_ptr[row]; t < a.lo_ptr[row + 1]; ++t)
-          acc += X[(int64_t)p * bp + (a.lo_col[t] - bps)] * a.val[a.lo_pos[t]];
-        Tm[idx] = acc;
-      }
-      __syncthreads();
-      // Sm -= L_k Tm
-      for (int idx = tid; idx < b * b; idx += kFacThreads) {
-        const int r = idx / b, c = idx % b;
-        const int64_t row = s0 + bs + r;
-        double acc = 0.0;
-        for (int64_t t = a.lo_ptr[row]; t < a.lo_ptr[row + 1]; ++t)
-          acc += a.val[a.lo_pos[t]] * Tm[(int64_t)(a.lo_col[t] - bps) * b + c];
-        Sm[idx] -= acc;
-      }
-      __syncthreads();
+    load_diag_block(Sm, b, bs, s0 + bs, a);
+    if (j > 0) {
+      const int kp = chain == 0 ? k - 1 : k + 1;
+      if (chain == 0)
+        schur_update(Sm, b, X, a.blk_size[kb0 + kp], a.blk_start[kb0 + kp], Tm, a.lo_col, a.lo_pos, a.cl,
+                     s0 + bs, a.val);
+      else
+        schur_update(Sm, b, X, a.blk_size[kb0 + kp], a.blk_start[kb0 + kp], Tm, a.up_col, a.up_pos, a.cu,
+                     s0 + bs, a.val);
     }
     gj_invert_wg<kFacThreads, kFacNB>(Sm, b, Rp, piv, a.err, sub, k);
     pack_tiles_wg<FT, T, kFacThreads>(Sm, b, b, fac + a.blk_foff[kb0 + k]);
@@ -466,10 +491,43 @@ __global__ void __launch_bounds__(kFacThreads) k_local_factor(FactorArgs a) {
   }
 }
 
+template <class FT, int T>
+__global__ void __launch_bounds__(kFacThreads) k_local_factor_mid(FactorArgs a) {
+  extern __shared__ __align__(16) double fsm[];
+  double* piv = fsm;
+  double* Rp = fsm + kFacNB * (kFacNB + 1);
+  const int slot = blockIdx.x;
+  const int sub = a.first_sub + slot;
+  const int64_t s0 = a.set_ptr[sub];
+  const int kb0 = a.sub_blk_ptr[sub];
+  const int K = a.sub_blk_ptr[sub + 1] - kb0;
+  const int m = (K - 1) / 2;
+  const int nB = K - 1 - m;
+  double* bufA = a.scratch + (int64_t)(2 * slot) * 3 * a.bmax2;
+  double* bufB = a.scratch + (int64_t)(2 * slot + 1) * 3 * a.bmax2;
+  // after n chain steps the chain's last inverse sits in slot 0 (n even) or slot 2 (n odd)
+  const double* XA = bufA + ((m & 1) ? 2 : 0) * a.bmax2;
+  const double* XB = bufB + ((nB & 1) ? 2 : 0) * a.bmax2;
+  double* Tm = bufA + a.bmax2;
+  double* Sm = bufA + ((m & 1) ? 0 : 2) * a.bmax2;
+  const int bs = a.blk_start[kb0 + m];
+  const int b = a.blk_size[kb0 + m];
+  load_diag_block(Sm, b, bs, s0 + bs, a);
+  if (m > 0)
+    schur_update(Sm, b, XA, a.blk_size[kb0 + m - 1], a.blk_start[kb0 + m - 1], Tm, a.lo_col, a.lo_pos, a.cl,
+                 s0 + bs, a.val);
+  if (nB > 0)
+    schur_update(Sm, b, XB, a.blk_size[kb0 + m + 1], a.blk_start[kb0 + m + 1], Tm, a.up_col, a.up_pos, a.cu,
+                 s0 + bs, a.val);
+  gj_invert_wg<kFacThreads, kFacNB>(Sm, b, Rp, piv, a.err, sub, m);
+  FT* fac = static_cast<FT*>(a.fac);
+  pack_tiles_wg<FT, T, kFacThreads>(Sm, b, b, fac + a.blk_foff[kb0 + m]);
+}
+
 __global__ void k_gather_vals(const int64_t* __restrict__ pos, const double* __restrict__ val,
                               double* __restrict__ out, int64_t m) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) out[i] = val[pos[i]];
+  if (i < m) out[i] = pos[i] >= 0 ? val[pos[i]] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -605,20 +663,16 @@ __global__ void k_cgj_col(double* __restrict__ A, int64_t N, int P0, int w, cons
 
 __global__ void k_pack_coarse(const double* __restrict__ A, int64_t N, double* __restrict__ out, int ntr) {
   constexpr int T = 64;
-  using G = TileGeom<double, T>;
   const int64_t total = (int64_t)ntr * (ntr + 1) / 2 * T * T;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int t = (int)(idx / (T * T));
-  const int within = (int)(idx % (T * T));
-  const int chunk = within / G::E;
-  const int lane = chunk % 64;
-  const int e = (chunk / 64) * G::E + within % G::E;
-  const int a = e / G::S, bb = e % G::S;
+  int rr, cc;
+  tile_rc<double, T>((int)(idx % (T * T)), rr, cc);
   int I, J;
   tile_ij(t, I, J);
-  const int64_t row = I * T + (lane >> 3) * G::S + a;
-  const int64_t col = J * T + (lane & 7) * G::S + bb;
+  const int64_t row = (int64_t)I * T + rr;
+  const int64_t col = (int64_t)J * T + cc;
   double v = 0.0;
   if (row < N && col < N) v = (row >= col) ? A[row * N + col] : A[col * N + row];
   out[idx] = v;
@@ -629,8 +683,8 @@ void launch_factor_t(Handle& h, hipStream_t s) {
   const Symbolic& S = h.S;
   const int64_t bmax2 = (int64_t)S.max_blk * S.max_blk;
   // bound the scratch: at most `batch` subdomains in flight per launch
-  const int64_t per = 3 * bmax2 * 8;
-  int batch = (int)std::min<int64_t>(S.n_parts, std::max<int64_t>(1, ((int64_t)4 << 30) / per));
+  const int64_t per = 2 * 3 * bmax2 * 8;
+  int batch = (int)std::min<int64_t>(S.n_parts, std::max<int64_t>(1, ((int64_t)6 << 30) / per));
   if ((int64_t)h.fac_scratch.bytes < per * batch) h.fac_scratch.alloc(per * batch);
   FactorArgs a;
   a.set_ptr = h.set_ptr.as<int64_t>();
@@ -638,9 +692,12 @@ void launch_factor_t(Handle& h, hipStream_t s) {
   a.blk_start = h.blk_start.as<int32_t>();
   a.blk_size = h.blk_size.as<int32_t>();
   a.blk_foff = h.blk_foff.as<int64_t>();
-  a.lo_ptr = h.lo_ptr.as<int64_t>();
   a.lo_col = h.lo_col.as<int32_t>();
   a.lo_pos = h.lo_pos.as<int64_t>();
+  a.cl = S.cl;
+  a.up_col = h.up_col.as<int32_t>();
+  a.up_pos = h.up_pos.as<int64_t>();
+  a.cu = S.cu;
   a.in_ptr = h.in_ptr.as<int64_t>();
   a.in_col = h.in_col.as<int32_t>();
   a.in_pos = h.in_pos.as<int64_t>();
@@ -651,12 +708,17 @@ void launch_factor_t(Handle& h, hipStream_t s) {
   a.err = h.err_flag.as<int32_t>();
   size_t lds = sizeof(double) * ((size_t)kFacNB * (kFacNB + 1) + (size_t)kFacNB * S.max_blk);
   DDG_REQUIRE((int64_t)lds <= h.dev_lds_limit, DDG_ERR_UNSUPPORTED, "local level too wide for the factorisation");
-  auto kern = k_local_factor<FT, T>;
-  if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  auto kc = k_local_factor_chain<FT, T>;
+  auto km = k_local_factor_mid<FT, T>;
+  if (lds > 65536) {
+    DDG_HIP(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    DDG_HIP(hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
   for (int first = 0; first < S.n_parts; first += batch) {
     a.first_sub = first;
-    int cnt = std::min(batch, S.n_parts - first);
-    hipLaunchKernelGGL(kern, dim3(cnt), dim3(kFacThreads), lds, s, a);
+    const int cnt = std::min(batch, S.n_parts - first);
+    hipLaunchKernelGGL(kc, dim3(2 * cnt), dim3(kFacThreads), lds, s, a);
+    hipLaunchKernelGGL(km, dim3(cnt), dim3(kFacThreads), lds, s, a);
     DDG_HIP(hipGetLastError());
   }
 }

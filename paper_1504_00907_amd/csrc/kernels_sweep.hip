@@ -4,14 +4,26 @@
 // Same-colour subdomains never touch each other's set or its neighbourhood
 // (conflict colouring), so the phase is race-free and deterministic.
 //
-// Local solve: A_i is block tridiagonal over the levels of its ascending
-// ordering.  The factorisation stores X_k = S_k^{-1} for the Schur complements
-// S_0 = D_0, S_k = D_k - L_k X_{k-1} L_k^T (block LDL^T), so
-//   forward:  t_k = X_k (b_k - L_k t_{k-1})
-//   backward: x_K = t_K,  x_k = t_k - X_k (U_k x_{k+1})
-// where L_k / U_k are the sparse couplings of block k to its lower / upper
-// neighbour taken from A.  Each X_k product is a tiled symmetric GEMV
-// (symv_tile.hpp) that streams the factor from HBM once per substitution.
+// Local solve.  A_i is block tridiagonal over the K levels of its ascending
+// ordering (D_k diagonal blocks, L_k = A_{k,k-1}, U_k = A_{k,k+1}).  The
+// factorisation is "twisted": with m = (K-1)/2 it eliminates levels
+// 0..m-1 from the top (X+_k = S+_k^{-1}, S+_k = D_k - L_k X+_{k-1} L_k^T),
+// levels K-1..m+1 from the bottom (X-_k, S-_k = D_k - U_k X-_{k+1} U_k^T)
+// and stores X_m for the middle level S_m = D_m - L_m X+ L_m^T - U_m X- U_m^T.
+// The exact solve of A_i x = b is then
+//   forward:  t_k = X+_k (b_k - L_k t_{k-1})   k = 0..m-1
+//             t_k = X-_k (b_k - U_k t_{k+1})   k = K-1..m+1
+//   middle:   x_m = X_m (b_m - L_m t_{m-1} - U_m t_{m+1})
+//   backward: x_k = t_k - X+_k U_k x_{k+1}     k = m-1..0
+//             x_k = t_k - X-_k L_k x_{k-1}     k = m+1..K-1
+// Each X product is a tiled symmetric GEMV (symv_tile.hpp) that streams the
+// factor from HBM once per substitution.  The two chains are independent up to
+// the middle level, so a subdomain can be split over two workgroups that hand
+// over one level vector each way (t_{m+1} up, x_m down).
+//
+// Every wave loads all of its tiles of a level at once and, as soon as it has
+// used them, issues the loads of the next level, so the HBM latency overlaps
+// the reductions and barriers between levels.
 #include "common.hpp"
 #include "symv_tile.hpp"
 
@@ -19,195 +31,428 @@ namespace ddg {
 
 struct SweepArgs {
   const int32_t* subs;
+  int32_t nsub;
+  int32_t twisted;
   const int64_t* set_ptr;
   const int32_t* set_idx;
   const int32_t* sub_blk_ptr;
   const int32_t* blk_start;
   const int32_t* blk_size;
   const int64_t* blk_foff;
-  const int64_t* lo_ptr;
   const int32_t* lo_col;
   const double* lo_val;
-  const int64_t* up_ptr;
   const int32_t* up_col;
   const double* up_val;
+  int32_t cl, cu;
   const int64_t* rp;
   const int32_t* ci;
   const double* val;
   const void* fac;
   const double* r;
   double* e;
+  const double* bres;  // local residuals of this colour's sets, indexed like set_idx
   const CgState* st;
   int32_t e_zero;
-  int32_t ldp;  // per-wave partial row length (>= max padded block rows)
+  int32_t ldp;      // per-wave partial row length (>= max padded block rows)
+  double* xch;      // per subdomain: 2 * xch_ld values
+  int32_t* flags;   // per subdomain: 2 flags
+  int32_t xch_ld;
+  int32_t* err;
 };
 
-template <class FT, class AT, int T, int NW>
-__global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
-  if (a.st && a.st->done) return;
-  constexpr int NT = NW * 64;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int sub = a.subs[blockIdx.x];
-  const int64_t s0 = a.set_ptr[sub];
-  const int ni = (int)(a.set_ptr[sub + 1] - s0);
-  AT* w = reinterpret_cast<AT*>(smem_raw);
-  // layout: w[ni_pad] | tv[ldp] | part[NW][ldp]
-  const int ni_pad = (ni + 3) & ~3;
-  AT* tv = w + ni_pad;
-  AT* part = tv + a.ldp;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const FT* fac = static_cast<const FT*>(a.fac);
+namespace {
 
-  // 1. gather the local residual b = (r - A e)[set]
-  for (int j = tid; j < ni; j += NT) {
-    const int g = a.set_idx[s0 + j];
-    double acc = a.r[g];
-    if (!a.e_zero) {
-      for (int64_t t = a.rp[g]; t < a.rp[g + 1]; ++t) acc -= a.val[t] * a.e[a.ci[t]];
+enum StepKind { FWD_LO = 0, FWD_UP = 1, MID = 2, BWD_UP = 3, BWD_LO = 4 };
+
+// Step s of a workgroup's sequence.  role 0: whole subdomain; 1: top chain and
+// middle; 2: bottom chain.
+__device__ inline void decode_step(int role, int s, int K, int m, int& kind, int& k) {
+  const int nB = K - 1 - m;
+  if (role == 1) {
+    if (s < m) { kind = FWD_LO; k = s; }
+    else if (s == m) { kind = MID; k = m; }
+    else { kind = BWD_UP; k = m - 1 - (s - m - 1); }
+    return;
+  }
+  if (role == 2) {
+    if (s < nB) { kind = FWD_UP; k = K - 1 - s; }
+    else { kind = BWD_LO; k = m + 1 + (s - nB); }
+    return;
+  }
+  if (s < m) { kind = FWD_LO; k = s; }
+  else if (s < m + nB) { kind = FWD_UP; k = K - 1 - (s - m); }
+  else if (s == m + nB) { kind = MID; k = m; }
+  else if (s < 2 * m + nB + 1) { kind = BWD_UP; k = m - 1 - (s - m - nB - 1); }
+  else { kind = BWD_LO; k = m + 1 + (s - 2 * m - nB - 1); }
+}
+
+constexpr int kSpinLimit = 1 << 22;
+
+// Bounded wait for the partner workgroup's flag.  Only thread 0 polls and
+// performs the agent-scope acquire (which also invalidates this CU's vector
+// cache); the barrier then orders every wave's reads of the exchange buffer
+// after it.  The reader clears the flag for the next launch.
+__device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        if (atomicCAS(err, 0, DDG_ERR_HIP) == 0) {
+          err[1] = sub;
+          err[2] = -7;
+        }
+        break;
+      }
     }
-    w[j] = (AT)acc;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
+}
 
+// Publish the exchange buffer: every wave waits for its own stores to
+// complete (vmcnt 0), the barrier collects the waves, and thread 0 issues one
+// agent-scope release before raising the flag.
+__device__ inline void handoff_signal(int32_t* flag) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), leave expcnt/lgkmcnt untouched
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+}  // namespace
+
+constexpr int kMaxLevels = 96;   // levels per subdomain staged in LDS
+constexpr int kCplRegs = 2;      // coupling slots per row held in registers (per direction)
+
+template <class FT, class AT, int T, int NW, int TPW>
+__global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
+  if (a.st && a.st->done) return;
+  using G = TileGeom<FT, T>;
+  constexpr int NT = NW * 64;
+  constexpr int TT = T * T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int32_t lv_start[kMaxLevels + 1], lv_size[kMaxLevels];
+  __shared__ int64_t lv_foff[kMaxLevels];
+  int p, role;
+  if (a.twisted) {
+    // pair (bottom, top) = (16g + i, 16g + i + 8): same XCD under round-robin dispatch,
+    // bottom chain dispatched first
+    const int g = blockIdx.x >> 4, w16 = blockIdx.x & 15;
+    p = g * 8 + (w16 & 7);
+    role = (w16 < 8) ? 2 : 1;
+  } else {
+    p = blockIdx.x;
+    role = 0;
+  }
+  if (p >= a.nsub) return;
+  const int sub = a.subs[p];
+  const int64_t s0 = a.set_ptr[sub];
+  const int ni = (int)(a.set_ptr[sub + 1] - s0);
+  const int ni_pad = (ni + 3) & ~3;
+  AT* w = reinterpret_cast<AT*>(smem_raw);
+  AT* tv = w + ni_pad;
+  AT* slots = tv + a.ldp;  // 2 * T per tile of the current level
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const FT* fac = static_cast<const FT*>(a.fac);
   const int kb0 = a.sub_blk_ptr[sub];
-  const int K = a.sub_blk_ptr[sub + 1] - kb0;
+  const int K = a.sub_blk_ptr[sub + 1] - kb0;  // <= kMaxLevels (checked on the host)
+  for (int k = tid; k < K; k += NT) {
+    lv_start[k] = a.blk_start[kb0 + k];
+    lv_size[k] = a.blk_size[kb0 + k];
+    lv_foff[k] = a.blk_foff[kb0 + k];
+  }
+  const int m = (K - 1) / 2;
+  const int nB = K - 1 - m;
+  const int split = (m + 1 < K) ? a.blk_start[kb0 + m + 1] : ni;  // first row of the bottom chain
+  int r0 = 0, r1 = ni;
+  if (role == 1) r1 = split;
+  if (role == 2) r0 = split;
+  const int ns = role == 0 ? 2 * K - 1 : (role == 1 ? 2 * m + 1 : 2 * nB);
 
-  auto block_symv = [&](int k) {
-    const int b = a.blk_size[kb0 + k];
-    const int nt = (b + T - 1) / T;
-    const int ntiles = nt * (nt + 1) / 2;
-    AT* mine = part + wave * a.ldp;
-    for (int r = lane; r < nt * T; r += 64) mine[r] = 0;
-    const FT* tiles = fac + a.blk_foff[kb0 + k];
-    for (int t = wave; t < ntiles; t += NW) {
-      int I, J;
-      tile_ij(t, I, J);
-      symv_one_tile<FT, AT, T>(tiles + (int64_t)t * T * T, I, J, tv, mine, lane);
+  __syncthreads();  // level metadata visible
+
+  FT R[TPW][G::SS];
+  // coupling entries of this thread's row (row tid of the level) for the next step
+  int cpl_col[2 * kCplRegs];
+  AT cpl_val[2 * kCplRegs];
+  const bool cpl_regs = a.cl <= kCplRegs && a.cu <= kCplRegs;
+  auto load_tile = [&](int k, int j) {
+    const int ntl = tiles_for(lv_size[k], T);
+    const int t = j * NW + wave;
+    if (t < ntl) load_subtile<FT, T>(fac + lv_foff[k] + (int64_t)t * TT, lane, R[j]);
+  };
+  auto load_cpl = [&](int kind, int k) {
+    if (!cpl_regs) return;
+    const int b = lv_size[k];
+    const bool use_lo = (kind == FWD_LO || kind == MID || kind == BWD_LO);
+    const bool use_up = (kind == FWD_UP || kind == MID || kind == BWD_UP);
+    const int64_t row = s0 + lv_start[k] + tid;
+#pragma unroll
+    for (int q = 0; q < kCplRegs; ++q) {
+      cpl_col[q] = -1;
+      cpl_col[kCplRegs + q] = -1;
+      cpl_val[q] = 0;
+      cpl_val[kCplRegs + q] = 0;
+      if (tid < b) {
+        if (use_lo && q < a.cl) {
+          cpl_col[q] = a.lo_col[row * a.cl + q];
+          cpl_val[q] = (AT)a.lo_val[row * a.cl + q];
+        }
+        if (use_up && q < a.cu) {
+          cpl_col[kCplRegs + q] = a.up_col[row * a.cu + q];
+          cpl_val[kCplRegs + q] = (AT)a.up_val[row * a.cu + q];
+        }
+      }
     }
   };
+  // the first level's tiles are requested before the residual is read
+  if (ns > 0) {
+    int kind, k;
+    decode_step(role, 0, K, m, kind, k);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) load_tile(k, j);
+    load_cpl(kind, k);
+  }
 
-  // 2. forward elimination
-  for (int k = 0; k < K; ++k) {
-    const int bs = a.blk_start[kb0 + k];
-    const int b = a.blk_size[kb0 + k];
+  // 1. local residual b = (r - A e) on the rows this workgroup owns (computed for
+  //    the whole colour by k_local_residual)
+  for (int j = r0 + tid; j < r1; j += NT) w[j] = (AT)a.bres[s0 + j];
+  __syncthreads();
+
+  double* xch = a.xch + (int64_t)p * 2 * a.xch_ld;
+  int32_t* flags = a.flags + 2 * p;
+  // the wave's first-round tiles are the same at every level
+  int tI[TPW], tJ[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) tile_ij(j * NW + wave, tI[j], tJ[j]);
+
+  for (int s = 0; s < ns; ++s) {
+    int kind, k;
+    decode_step(role, s, K, m, kind, k);
+    const int bs = lv_start[k];
+    const int b = lv_size[k];
     const int nt = (b + T - 1) / T;
+    const int ntl = nt * (nt + 1) / 2;
+    if (role == 1 && kind == MID && nB > 0) {
+      // import t_{m+1} from the bottom chain
+      handoff_wait(flags + 0, a.err, sub);
+      const int bs1 = lv_start[m + 1], b1 = lv_size[m + 1];
+      for (int jj = tid; jj < b1; jj += NT) w[bs1 + jj] = (AT)xch[jj];
+      __syncthreads();
+    }
+    if (role == 2 && kind == BWD_LO && k == m + 1) {
+      // import x_m from the top chain
+      handoff_wait(flags + 1, a.err, sub);
+      const int bsm = lv_start[m], bm = lv_size[m];
+      for (int jj = tid; jj < bm; jj += NT) w[bsm + jj] = (AT)xch[a.xch_ld + jj];
+      __syncthreads();
+    }
+    // input vector of this level
+    const bool fwd = kind <= MID;
+    const bool use_lo = (kind == FWD_LO || kind == MID || kind == BWD_LO);
+    const bool use_up = (kind == FWD_UP || kind == MID || kind == BWD_UP);
     for (int jj = tid; jj < nt * T; jj += NT) {
       AT y = 0;
       if (jj < b) {
-        const int64_t row = s0 + bs + jj;
-        y = w[bs + jj];
-        for (int64_t t = a.lo_ptr[row]; t < a.lo_ptr[row + 1]; ++t)
-          y -= (AT)a.lo_val[t] * w[a.lo_col[t]];
+        AT c = 0;
+        if (cpl_regs && jj == tid) {
+#pragma unroll
+          for (int q = 0; q < 2 * kCplRegs; ++q)
+            if (cpl_col[q] >= 0) c += cpl_val[q] * w[cpl_col[q]];
+        } else {
+          const int64_t row = s0 + bs + jj;
+          if (use_lo)
+            for (int q = 0; q < a.cl; ++q) {
+              const int col = a.lo_col[row * a.cl + q];
+              if (col >= 0) c += (AT)a.lo_val[row * a.cl + q] * w[col];
+            }
+          if (use_up)
+            for (int q = 0; q < a.cu; ++q) {
+              const int col = a.up_col[row * a.cu + q];
+              if (col >= 0) c += (AT)a.up_val[row * a.cu + q] * w[col];
+            }
+        }
+        y = fwd ? w[bs + jj] - c : c;
       }
       tv[jj] = y;
     }
     __syncthreads();
-    block_symv(k);
-    __syncthreads();
-    for (int jj = tid; jj < b; jj += NT) {
-      AT s = 0;
+    // tiles: the first TPW*NW are already in registers; every wave runs all of its
+    // slots (invalid ones on stale registers, without storing) so the tile
+    // computations can interleave.  When a level fits in one round, each register
+    // set is refilled with the next level's tile as soon as it has been used.
+    const int rounds = (ntl + NW * TPW - 1) / (NW * TPW);
+    int kind2 = 0, k2 = 0;
+    const bool has_next = s + 1 < ns;
+    if (has_next) decode_step(role, s + 1, K, m, kind2, k2);
+    for (int round = 0; round < rounds; ++round) {
+      if (round > 0) {
+        const FT* base = fac + lv_foff[k];
 #pragma unroll
-      for (int q = 0; q < NW; ++q) s += part[q * a.ldp + jj];
-      w[bs + jj] = s;
-    }
-    __syncthreads();
-  }
-
-  // 3. backward substitution
-  for (int k = K - 2; k >= 0; --k) {
-    const int bs = a.blk_start[kb0 + k];
-    const int b = a.blk_size[kb0 + k];
-    const int nt = (b + T - 1) / T;
-    for (int jj = tid; jj < nt * T; jj += NT) {
-      AT v = 0;
-      if (jj < b) {
-        const int64_t row = s0 + bs + jj;
-        for (int64_t t = a.up_ptr[row]; t < a.up_ptr[row + 1]; ++t)
-          v += (AT)a.up_val[t] * w[a.up_col[t]];
+        for (int j = 0; j < TPW; ++j) {
+          const int t = (round * TPW + j) * NW + wave;
+          if (t < ntl) load_subtile<FT, T>(base + (int64_t)t * TT, lane, R[j]);
+        }
       }
-      tv[jj] = v;
+      const bool last = round + 1 == rounds;
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) {
+        const int t = (round * TPW + j) * NW + wave;
+        const bool valid = t < ntl;
+        int I = tI[j], J = tJ[j];
+        if (round > 0) tile_ij(t, I, J);
+        if (!valid) I = J = 0;
+        symv_tile_slots<FT, AT, T>(R[j], I, J, tv, slots + (int64_t)(2 * t) * T,
+                                   slots + (int64_t)(2 * t + 1) * T, lane, valid);
+        if (last && has_next) load_tile(k2, j);
+      }
     }
-    __syncthreads();
-    block_symv(k);
+    if (has_next) load_cpl(kind2, k2);
     __syncthreads();
     for (int jj = tid; jj < b; jj += NT) {
-      AT s = 0;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) s += part[q * a.ldp + jj];
-      w[bs + jj] -= s;
+      const AT sum = sum_slots<AT, T>(slots, nt, jj);
+      if (fwd) w[bs + jj] = sum;
+      else w[bs + jj] -= sum;
     }
     __syncthreads();
+    if (role == 2 && kind == FWD_UP && k == m + 1) {
+      for (int jj = tid; jj < b; jj += NT) xch[jj] = (double)w[bs + jj];
+      handoff_signal(flags + 0);
+    }
+    if (role == 1 && kind == MID && nB > 0) {
+      for (int jj = tid; jj < b; jj += NT) xch[a.xch_ld + jj] = (double)w[bs + jj];
+      handoff_signal(flags + 1);
+    }
   }
 
-  // 4. scatter-add the correction
-  for (int j = tid; j < ni; j += NT) {
-    const int g = a.set_idx[s0 + j];
-    a.e[g] += (double)w[j];
+  // scatter-add the correction on the owned rows
+  constexpr int GB = 4;
+  for (int j0 = r0 + tid; j0 < r1; j0 += NT * GB) {
+    int g[GB];
+    double ev[GB];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const int j = j0 + q * NT;
+      g[q] = j < r1 ? a.set_idx[s0 + j] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) ev[q] = g[q] >= 0 ? a.e[g[q]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < GB; ++q)
+      if (g[q] >= 0) a.e[g[q]] = ev[q] + (double)w[j0 + q * NT];
   }
+}
+
+// b = (r - A e) on the expanded sets of one colour, written in set order.
+__global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const int32_t* __restrict__ subs,
+                                                        const int64_t* __restrict__ set_ptr,
+                                                        const int32_t* __restrict__ set_idx,
+                                                        const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                        const double* __restrict__ val, const double* __restrict__ r,
+                                                        const double* __restrict__ e, int e_zero,
+                                                        double* __restrict__ bres) {
+  if (st && st->done) return;
+  const int sub = subs[blockIdx.y];
+  const int64_t s0 = set_ptr[sub];
+  const int ni = (int)(set_ptr[sub + 1] - s0);
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= ni) return;
+  const int g = set_idx[s0 + j];
+  double acc = r[g];
+  if (!e_zero)
+    for (int64_t t = rp[g]; t < rp[g + 1]; ++t) acc -= val[t] * e[ci[t]];
+  bres[s0 + j] = acc;
 }
 
 namespace {
 
-constexpr int kSweepWaves = 8;
-
-template <class FT, class AT, int T>
-void launch_sweep_t(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                    const CgState* st, hipStream_t s) {
+template <class FT, class AT, int T, int NW, int TPW>
+void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, bool e_zero,
+                      const CgState* st, hipStream_t s, bool residual) {
   const Symbolic& S = h.S;
-  int nsub = S.colour_ptr[colour + 1] - S.colour_ptr[colour];
+  const int nsub = S.colour_ptr[colour + 1] - S.colour_ptr[colour];
   if (nsub == 0) return;
   SweepArgs a;
   a.subs = h.colour_subs.as<int32_t>() + S.colour_ptr[colour];
+  a.nsub = nsub;
+  a.twisted = h.twisted_ok ? 1 : 0;
   a.set_ptr = h.set_ptr.as<int64_t>();
   a.set_idx = h.set_idx.as<int32_t>();
   a.sub_blk_ptr = h.sub_blk_ptr.as<int32_t>();
   a.blk_start = h.blk_start.as<int32_t>();
   a.blk_size = h.blk_size.as<int32_t>();
   a.blk_foff = h.blk_foff.as<int64_t>();
-  a.lo_ptr = h.lo_ptr.as<int64_t>();
   a.lo_col = h.lo_col.as<int32_t>();
   a.lo_val = h.lo_val.as<double>();
-  a.up_ptr = h.up_ptr.as<int64_t>();
   a.up_col = h.up_col.as<int32_t>();
   a.up_val = h.up_val.as<double>();
+  a.cl = S.cl;
+  a.cu = S.cu;
   a.rp = h.rowptr.as<int64_t>();
   a.ci = h.col.as<int32_t>();
   a.val = h.val.as<double>();
   a.fac = h.fac.p;
   a.r = r;
   a.e = e;
+  a.bres = h.bres.as<double>();
   a.st = st;
   a.e_zero = e_zero ? 1 : 0;
   const int maxpad = ((S.max_blk + T - 1) / T) * T;
   a.ldp = maxpad;
+  a.xch = h.xch.as<double>();
+  a.flags = h.flags.as<int32_t>();
+  a.xch_ld = h.xch_ld;
+  a.err = h.err_flag.as<int32_t>();
   const int ni_pad = (S.max_set + 3) & ~3;
-  size_t lds = sizeof(AT) * ((size_t)ni_pad + (size_t)maxpad * (1 + kSweepWaves));
-  auto kern = k_sweep<FT, AT, T, kSweepWaves>;
+  DDG_REQUIRE(S.max_blocks <= kMaxLevels, DDG_ERR_UNSUPPORTED, "more than 96 levels in a local problem");
+  const int max_tiles = tiles_for(S.max_blk, T);
+  size_t lds = sizeof(AT) * ((size_t)ni_pad + (size_t)maxpad + 2 * (size_t)max_tiles * T);
+  auto kern = k_sweep<FT, AT, T, NW, TPW>;
   DDG_REQUIRE((int64_t)lds <= h.dev_lds_limit, DDG_ERR_UNSUPPORTED,
               "local problem too large for on-chip storage (" + std::to_string(lds) + " bytes)");
   if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(nsub), dim3(kSweepWaves * 64), lds, s, a);
+  if (residual) {
+    hipLaunchKernelGGL(k_local_residual, dim3((unsigned)((S.max_set + 255) / 256), (unsigned)nsub), dim3(256), 0,
+                       s, st, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e, a.e_zero, h.bres.as<double>());
+    DDG_HIP(hipGetLastError());
+    return;
+  }
+  const unsigned grid = a.twisted ? (unsigned)(16 * ((nsub + 7) / 8)) : (unsigned)nsub;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, s, a);
   DDG_HIP(hipGetLastError());
 }
 
 template <class FT, class AT>
 void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                    const CgState* st, hipStream_t s) {
+                    const CgState* st, hipStream_t s, bool res) {
+  // (waves, tiles per wave per round) keep the register ring within 128 VGPRs at 16 waves
+  // or 256 at 8 waves, without spills
   switch (h.S.tile) {
-    case 16: launch_sweep_t<FT, AT, 16>(h, colour, r, e, e_zero, st, s); break;
-    case 32: launch_sweep_t<FT, AT, 32>(h, colour, r, e, e_zero, st, s); break;
-    default: launch_sweep_t<FT, AT, 64>(h, colour, r, e, e_zero, st, s); break;
+    case 16: launch_sweep_cfg<FT, AT, 16, 4, 4>(h, colour, r, e, e_zero, st, s, res); break;
+    case 32:
+      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4>(h, colour, r, e, e_zero, st, s, res);
+      else launch_sweep_cfg<FT, AT, 32, 8, 9>(h, colour, r, e, e_zero, st, s, res);
+      break;
+    default:
+      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1>(h, colour, r, e, e_zero, st, s, res);
+      else launch_sweep_cfg<FT, AT, 64, 8, 2>(h, colour, r, e, e_zero, st, s, res);
+      break;
   }
 }
 
 }  // namespace
 
+// residual = true: launch only the local-residual kernel of the colour; false: the local solves.
 void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                  const CgState* st, hipStream_t s) {
+                  const CgState* st, hipStream_t s, bool res) {
   switch (h.opt.precision) {
-    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, colour, r, e, e_zero, st, s); break;
-    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, colour, r, e, e_zero, st, s); break;
-    default: launch_sweep_p<double, double>(h, colour, r, e, e_zero, st, s); break;
+    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, colour, r, e, e_zero, st, s, res); break;
+    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, colour, r, e, e_zero, st, s, res); break;
+    default: launch_sweep_p<double, double>(h, colour, r, e, e_zero, st, s, res); break;
   }
 }
 

@@ -297,7 +297,7 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
     std::vector<int32_t> w(S.blk_size);
     std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
     int32_t med = w[w.size() / 2];
-    S.tile = med >= 160 ? 64 : (med >= 40 ? 32 : 16);
+    S.tile = med >= 192 ? 64 : (med >= 48 ? 32 : 16);
   }
   DDG_REQUIRE(S.tile == 16 || S.tile == 32 || S.tile == 64, DDG_ERR_INVALID_ARG, "tile must be 16, 32 or 64");
   int64_t off = 0;
@@ -309,33 +309,50 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
   S.fac_elems = off;
 
   int64_t rows = S.set_ptr[n_parts];
-  auto concat = [&](auto getcnt, auto getcol, auto getpos, std::vector<int64_t>& ptr,
-                    std::vector<int32_t>& col, std::vector<int64_t>& pos) {
-    ptr.assign(rows + 1, 0);
-    for (int32_t i = 0; i < n_parts; ++i) {
-      const auto& cnt = getcnt(loc[i]);
-      for (size_t j = 0; j < cnt.size(); ++j) ptr[S.set_ptr[i] + j + 1] = cnt[j];
+  // ELL couplings
+  S.cl = 0;
+  S.cu = 0;
+  for (int32_t i = 0; i < n_parts; ++i)
+    for (size_t j = 0; j < loc[i].lo_cnt.size(); ++j) {
+      S.cl = std::max<int32_t>(S.cl, (int32_t)loc[i].lo_cnt[j]);
+      S.cu = std::max<int32_t>(S.cu, (int32_t)loc[i].up_cnt[j]);
     }
-    for (int64_t r = 0; r < rows; ++r) ptr[r + 1] += ptr[r];
-    col.resize(ptr[rows]);
-    pos.resize(ptr[rows]);
-    for (int32_t i = 0; i < n_parts; ++i) {
-      int64_t o = ptr[S.set_ptr[i]];
-      const auto& c = getcol(loc[i]);
-      const auto& p = getpos(loc[i]);
-      std::copy(c.begin(), c.end(), col.begin() + o);
-      std::copy(p.begin(), p.end(), pos.begin() + o);
+  const int32_t cl = std::max(1, S.cl), cu = std::max(1, S.cu);
+  S.cl = cl;
+  S.cu = cu;
+  S.lo_col.assign(rows * cl, -1);
+  S.lo_pos.assign(rows * cl, -1);
+  S.up_col.assign(rows * cu, -1);
+  S.up_pos.assign(rows * cu, -1);
+  parallel_for(n_parts, [&](int32_t i, int) {
+    const Local& L = loc[i];
+    int64_t lo_o = 0, up_o = 0;
+    for (size_t j = 0; j < L.lo_cnt.size(); ++j) {
+      const int64_t row = S.set_ptr[i] + (int64_t)j;
+      for (int64_t c = 0; c < L.lo_cnt[j]; ++c) {
+        S.lo_col[row * cl + c] = L.lo_col[lo_o];
+        S.lo_pos[row * cl + c] = L.lo_pos[lo_o];
+        ++lo_o;
+      }
+      for (int64_t c = 0; c < L.up_cnt[j]; ++c) {
+        S.up_col[row * cu + c] = L.up_col[up_o];
+        S.up_pos[row * cu + c] = L.up_pos[up_o];
+        ++up_o;
+      }
     }
-  };
-  concat([](const Local& L) -> const std::vector<int64_t>& { return L.lo_cnt; },
-         [](const Local& L) -> const std::vector<int32_t>& { return L.lo_col; },
-         [](const Local& L) -> const std::vector<int64_t>& { return L.lo_pos; }, S.lo_ptr, S.lo_col, S.lo_pos);
-  concat([](const Local& L) -> const std::vector<int64_t>& { return L.up_cnt; },
-         [](const Local& L) -> const std::vector<int32_t>& { return L.up_col; },
-         [](const Local& L) -> const std::vector<int64_t>& { return L.up_pos; }, S.up_ptr, S.up_col, S.up_pos);
-  concat([](const Local& L) -> const std::vector<int64_t>& { return L.in_cnt; },
-         [](const Local& L) -> const std::vector<int32_t>& { return L.in_col; },
-         [](const Local& L) -> const std::vector<int64_t>& { return L.in_pos; }, S.in_ptr, S.in_col, S.in_pos);
+  });
+  // same-level entries (setup only) in CSR form
+  S.in_ptr.assign(rows + 1, 0);
+  for (int32_t i = 0; i < n_parts; ++i)
+    for (size_t j = 0; j < loc[i].in_cnt.size(); ++j) S.in_ptr[S.set_ptr[i] + j + 1] = loc[i].in_cnt[j];
+  for (int64_t r = 0; r < rows; ++r) S.in_ptr[r + 1] += S.in_ptr[r];
+  S.in_col.resize(S.in_ptr[rows]);
+  S.in_pos.resize(S.in_ptr[rows]);
+  for (int32_t i = 0; i < n_parts; ++i) {
+    const int64_t o = S.in_ptr[S.set_ptr[i]];
+    std::copy(loc[i].in_col.begin(), loc[i].in_col.end(), S.in_col.begin() + o);
+    std::copy(loc[i].in_pos.begin(), loc[i].in_pos.end(), S.in_pos.begin() + o);
+  }
 }
 
 }  // namespace ddg

@@ -3,17 +3,23 @@
 // A symmetric b x b matrix is stored as its lower-triangular T x T tiles
 // (I >= J, row-major tile order I(I+1)/2 + J); diagonal tiles are stored in
 // full (symmetrised), rows and columns beyond b are zero.  Inside a tile the
-// 64 lanes form an 8 x 8 grid: lane (p, q) = p*8 + q owns the S x S sub-tile
-// (S = T/8) with rows p*S.. and columns q*S..  Its S*S values are stored as
-// consecutive 16-byte chunks interleaved across lanes: chunk m of lane L sits
-// at element (m*64 + L)*E (E values per chunk), so each load instruction of a
-// wave reads one contiguous 1 KiB line.
+// 64 lanes form an 8 x 8 grid of S x S sub-tiles (S = T/8): lane L owns the
+// sub-tile with rows lane_p(L)*S.. and columns lane_q(L)*S.., where q is made of
+// lane bits {0,1,3} and p of lane bits {2,4,5}.  Inside its sub-tile the lane's
+// register (i, j) holds row i ^ sq and column j ^ sp, with sq = q >> (3 - log2 S)
+// and sp = p >> (3 - log2 S) (the coordinate bits the butterfly splits on): this
+// lane-dependent order makes every lane keep the same register half at each
+// butterfly step below, so the reduction needs no selects.  The lane's S*S
+// values are stored as consecutive 16-byte chunks interleaved across lanes:
+// chunk m of lane L sits at element (m*64 + L)*E (E values per chunk), so each
+// load instruction of a wave reads one contiguous 1 KiB line.
 //
 // An off-diagonal tile contributes M x_J to rows I and M^T x_I to rows J, so
 // each stored value is read once and used twice.  Row partials are reduced
-// across the 8 lanes that share p (lane bits 0-2), column partials across the
-// 8 lanes that share q (bits 3-5), by butterfly halving: 2*log2(S)+... shuffles
-// per tile instead of a full 64-lane reduction per row.
+// across the 8 lanes that share p, column partials across the 8 lanes that
+// share q, by butterfly halving.  With the bit assignment above the row
+// butterfly only needs lane exchanges xor 8, 2, 1 (DPP moves inside a 16-lane
+// row, no LDS traffic) and the column butterfly xor 32, 16, 4.
 #pragma once
 
 #include "device_util.hpp"
@@ -29,12 +35,28 @@ struct TileGeom {
   static constexpr int LOGS = (S == 8) ? 3 : (S == 4 ? 2 : 1);
 };
 
+// Sub-tile coordinates of a lane.
+__host__ __device__ inline int lane_q(int lane) { return (lane & 3) | ((lane >> 1) & 4); }
+__host__ __device__ inline int lane_p(int lane) { return ((lane >> 2) & 1) | ((lane >> 3) & 6); }
+
 // Element offset (within a tile) of sub-tile value (a, b) of lane L.
 template <class FT, int T>
 __host__ __device__ inline int tile_elem(int lane, int a, int b) {
   using G = TileGeom<FT, T>;
   int e = a * G::S + b;
   return ((e / G::E) * 64 + lane) * G::E + (e % G::E);
+}
+
+// Inverse of tile_elem: element offset within a tile -> (row, col) within the tile.
+template <class FT, int T>
+__host__ __device__ inline void tile_rc(int within, int& row, int& col) {
+  using G = TileGeom<FT, T>;
+  const int chunk = within / G::E;
+  const int lane = chunk % 64;
+  const int e = (chunk / 64) * G::E + within % G::E;
+  const int p = lane_p(lane), q = lane_q(lane);
+  row = p * G::S + ((e / G::S) ^ (q >> (3 - G::LOGS)));
+  col = q * G::S + ((e % G::S) ^ (p >> (3 - G::LOGS)));
 }
 
 // Load the lane's S*S values of one tile.
@@ -62,86 +84,117 @@ __device__ inline void load_subtile(const FT* __restrict__ tile, int lane, FT (&
   }
 }
 
-// Reduce S values held by each of the 8 lanes of a group whose coordinate c
-// (0..7) sits at lane bits with unit stride `unit` (1 or 8).  Afterwards the
-// lane holds the group-total of value index c >> (3 - LOGS); `writer` is true
-// for exactly one lane per index.
-template <class AT, int S, int LOGS>
-__device__ inline AT group_reduce_scatter(AT (&v)[S], int c, int unit, bool& writer) {
-  // halving steps with masks 4u, 2u, u (first LOGS of them)
-  int len = S;
+// Value of the lane `lane ^ MASK` (MASK in {1, 2, 4, 8, 16, 32}).
+template <int MASK>
+__device__ inline int xor_lane_i32(int x) {
+  if constexpr (MASK == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  else if constexpr (MASK == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+  else if constexpr (MASK == 8) return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  else if constexpr (MASK == 4) return __builtin_amdgcn_ds_swizzle(x, 0x1F | (4 << 10));
+  else if constexpr (MASK == 16) return __builtin_amdgcn_ds_swizzle(x, 0x1F | (16 << 10));
+  else return __shfl_xor(x, MASK, 64);
+}
+
+template <int MASK>
+__device__ inline float xor_lane(float x) {
+  return __int_as_float(xor_lane_i32<MASK>(__float_as_int(x)));
+}
+
+template <int MASK>
+__device__ inline double xor_lane(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = xor_lane_i32<MASK>((int)(b & 0xffffffffLL));
+  const int hi = xor_lane_i32<MASK>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One halving step of the butterfly: every lane keeps v[0..H) and adds the
+// partner's v[H..2H), which holds the same rows because of the XOR storage
+// order (see the layout note above).
+template <int MASK, class AT, int H, int N>
+__device__ inline void halve(AT (&v)[N]) {
 #pragma unroll
-  for (int st = 0; st < LOGS; ++st) {
-    const int mask = (4 >> st) * unit;
-    const int hi = (c >> (2 - st)) & 1;
-    const int half = len >> 1;
-#pragma unroll
-    for (int i = 0; i < S / 2; ++i) {
-      if (i < half) {
-        AT mine = hi ? v[i + half] : v[i];
-        AT other = hi ? v[i] : v[i + half];
-        v[i] = mine + __shfl_xor(other, mask, 64);
-      }
-    }
-    len = half;
-  }
+  for (int i = 0; i < H; ++i) v[i] = v[i] + xor_lane<MASK>(v[i + H]);
+}
+
+// Reduce S values held by each of the 8 lanes of a group whose 3-bit
+// coordinate c lives at the lane bits selected by masks (M2, M1, M0), most
+// significant first.  Value i of the lane with coordinate c is logical entry
+// i ^ (c >> (3 - LOGS)).  Afterwards the lane holds the group-total of logical
+// entry c >> (3 - LOGS); `writer` is true for exactly one lane per entry.
+template <class AT, int S, int LOGS, int M2, int M1, int M0>
+__device__ inline AT group_reduce_scatter(AT (&v)[S], int c, bool& writer) {
+  if constexpr (LOGS >= 1) halve<M2, AT, S / 2>(v);
+  if constexpr (LOGS >= 2) halve<M1, AT, S / 4>(v);
+  if constexpr (LOGS >= 3) halve<M0, AT, S / 8>(v);
   AT s = v[0];
-  // remaining all-reduce steps
-#pragma unroll
-  for (int st = LOGS; st < 3; ++st) {
-    const int mask = (4 >> st) * unit;
-    s += __shfl_xor(s, mask, 64);
-  }
+  // remaining all-reduce steps when S < 8
+  if constexpr (LOGS < 2) s += xor_lane<M1>(s);
+  if constexpr (LOGS < 3) s += xor_lane<M0>(s);
   writer = (c & ((1 << (3 - LOGS)) - 1)) == 0;
   return s;
 }
 
-// One wave: contributions of tile (I, J) to out (a per-wave LDS row of partial sums).
-// x is the input vector (LDS), indexed from the block's first row.
+// Contributions of tile (I, J), whose values this lane holds in `m`:
+//   rowslot[0..T) = (M x_J) over the tile's rows,
+//   colslot[0..T) = (M^T x_I) over the tile's columns (off-diagonal tiles only).
+// x is indexed from the block's first row.  The slots are written, not
+// accumulated, so the final sum over tiles has a fixed order.
 template <class FT, class AT, int T>
-__device__ inline void symv_one_tile(const FT* __restrict__ tile, int I, int J, const AT* __restrict__ x,
-                                     AT* __restrict__ out, int lane) {
+__device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I, int J,
+                                       const AT* __restrict__ x, AT* __restrict__ rowslot,
+                                       AT* __restrict__ colslot, int lane, bool valid) {
   using G = TileGeom<FT, T>;
   constexpr int S = G::S;
-  FT m[G::SS];
-  load_subtile<FT, T>(tile, lane, m);
-  const int p = lane >> 3, q = lane & 7;
+  const int p = lane_p(lane), q = lane_q(lane);
+  const int pm = p >> (3 - G::LOGS), qm = q >> (3 - G::LOGS);
+  // register (i, j) holds row p*S + (i ^ qm) and column q*S + (j ^ pm)
   AT xr[S], xc[S];
 #pragma unroll
-  for (int b = 0; b < S; ++b) xr[b] = x[J * T + q * S + b];
+  for (int j = 0; j < S; ++j) xr[j] = x[J * T + q * S + (j ^ pm)];
 #pragma unroll
-  for (int a = 0; a < S; ++a) xc[a] = x[I * T + p * S + a];
+  for (int i = 0; i < S; ++i) xc[i] = x[I * T + p * S + (i ^ qm)];
   AT rowp[S], colp[S];
 #pragma unroll
-  for (int a = 0; a < S; ++a) {
-    rowp[a] = 0;
-    colp[a] = 0;
+  for (int i = 0; i < S; ++i) {
+    rowp[i] = 0;
+    colp[i] = 0;
   }
 #pragma unroll
-  for (int a = 0; a < S; ++a) {
+  for (int i = 0; i < S; ++i) {
 #pragma unroll
-    for (int b = 0; b < S; ++b) {
-      AT mv = Store<FT>::to_acc(m[a * S + b]);
-      rowp[a] += mv * xr[b];
-      colp[b] += mv * xc[a];
+    for (int j = 0; j < S; ++j) {
+      AT mv = Store<FT>::to_acc(m[i * S + j]);
+      rowp[i] += mv * xr[j];
+      colp[j] += mv * xc[i];
     }
   }
   bool w;
-  AT rs = group_reduce_scatter<AT, S, G::LOGS>(rowp, q, 1, w);
-  if (w) out[I * T + p * S + (q >> (3 - G::LOGS))] += rs;
-  if (I != J) {
-    AT cs = group_reduce_scatter<AT, S, G::LOGS>(colp, p, 8, w);
-    if (w) out[J * T + q * S + (p >> (3 - G::LOGS))] += cs;
-  }
+  AT rs = group_reduce_scatter<AT, S, G::LOGS, 8, 2, 1>(rowp, q, w);
+  if (valid && w) rowslot[p * S + (q >> (3 - G::LOGS))] = rs;
+  AT cs = group_reduce_scatter<AT, S, G::LOGS, 32, 16, 4>(colp, p, w);
+  if (valid && I != J && w) colslot[q * S + (p >> (3 - G::LOGS))] = cs;
 }
 
 // Tile (I, J) of linear index t in row-major lower order.
-__device__ inline void tile_ij(int t, int& I, int& J) {
+__host__ __device__ inline void tile_ij(int t, int& I, int& J) {
   int i = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
   while ((i + 1) * (i + 2) / 2 <= t) ++i;
   while (i * (i + 1) / 2 > t) --i;
   I = i;
   J = t - i * (i + 1) / 2;
+}
+
+// Fixed-order sum of the slots of output row r (0 <= r < nt*T) of a block with
+// nt tile rows; slots of tile t sit at [2t][T] (rows) and [2t+1][T] (columns):
+// sum_{J<=I} rowslot(I,J) + sum_{J>I} colslot(J,I), I = r/T.
+template <class AT, int T>
+__device__ inline AT sum_slots(const AT* __restrict__ slots, int nt, int r) {
+  const int I = r / T, rr = r % T;
+  AT s = 0;
+  for (int J = 0; J <= I; ++J) s += slots[(2 * (I * (I + 1) / 2 + J)) * T + rr];
+  for (int J = I + 1; J < nt; ++J) s += slots[(2 * (J * (J + 1) / 2 + I) + 1) * T + rr];
+  return s;
 }
 
 }  // namespace ddg

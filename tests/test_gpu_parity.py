@@ -242,3 +242,34 @@ def test_rank_deficient_strips():
     z = host(s.apply_precond(dev(r)))
     assert np.linalg.norm(z - o.apply(r)) <= 1e-12 * np.linalg.norm(z)
     s.close()
+
+
+@pytest.mark.parametrize("single", [False, True], ids=["two_wg", "one_wg"])
+@pytest.mark.parametrize("name", ["cfg1", "3d20"])
+def test_sweep_paths_match_oracle(name, single, monkeypatch):
+    """Both local-solve schedules (two workgroups per subdomain, or one) agree with the oracle."""
+    if single:
+        monkeypatch.setenv("DDG_NO_TWIST", "1")
+    P, o = problem(name)
+    s = make_solver(P)
+    r = seed_rng(64, 0).standard_normal(P.n)
+    z = host(s.apply_precond(dev(r)))
+    ref = o.apply(r)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+    s.close()
+
+
+@pytest.mark.parametrize("block_target,tile", [(100000, 32), (40, 16), (0, 64)],
+                         ids=["one_level", "merged", "tile64"])
+def test_level_structures_match_oracle(block_target, tile):
+    """K = 1 (whole subdomain in one dense level), merged levels and 64-wide tiles."""
+    P, o = problem("cfg1")
+    s = make_solver(P, block_target=block_target, tile=tile)
+    blocks = s.blocks()
+    if block_target == 100000:
+        assert len(blocks) == P.n_parts
+    r = seed_rng(65, 0).standard_normal(P.n)
+    z = host(s.apply_precond(dev(r)))
+    ref = o.apply(r)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+    s.close()
