@@ -183,15 +183,20 @@ const char* ddg_last_error(void);
 /* ---------------------------------------------------------------------------
  * Cell-centred variable-coefficient diffusion (the operator family of the
  * differentiation workload).  dims[3] = (nx, ny, nz), cells x-fastest;
- * nz = 1 gives 2D.  Face coefficient between cells L, R is the harmonic
+ * the grid is 3D when nz > 1, 2D when nz = 1 < ny, else 1D, and ghost faces
+ * exist only along its own axes.  Face coefficient between cells L, R is the harmonic
  * mean 2 kL kR / (kL + kR); each boundary face is a zero-Dirichlet ghost face
  * of coefficient 2 kc.  kappa = exp(theta).
  * ------------------------------------------------------------------------- */
 
 /*
  * Write the CSR values of A(exp(theta)) into val_dev, in the sorted-column
- * CSR order of the same operator (diagonal and its 2*dim face neighbours that
- * exist).  theta_dev[ncell], val_dev[nnz] device; stream may be NULL.
+ * CSR order of the same operator: row g holds its existing neighbours
+ * g - nx*ny, g - nx, g - 1, the diagonal, g + 1, g + nx, g + nx*ny, in that
+ * order (the pattern is the caller's; it is fixed by dims).  theta_dev[ncell],
+ * val_dev[nnz] device, caller-owned; stream may be NULL (default stream).
+ * Errors: DDG_ERR_INVALID_ARG for non-positive dims or NULL pointers; the
+ * launch is asynchronous and reads no other memory.
  */
 int ddg_stencil_assemble(const int32_t dims[3], const double* theta_dev, double* val_dev,
                          void* stream);

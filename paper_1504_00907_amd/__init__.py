@@ -12,7 +12,10 @@ def __getattr__(name):
     if name in ("DDGSolver", "stencil_assemble", "stencil_coeff_grad"):
         from . import solver
         return getattr(solver, name)
-    if name in ("DDGSolveFunction", "ddg_solve_fn"):
+    if name in ("DDGSolveFunction", "ddg_solve_fn", "DiffusionSolver"):
         from . import autograd
         return getattr(autograd, name)
+    if name == "cc_pattern":
+        from .stencil import cc_pattern
+        return cc_pattern
     raise AttributeError(name)

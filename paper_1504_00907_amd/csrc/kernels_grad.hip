@@ -1,6 +1,8 @@
 // Cell-centred harmonic-mean diffusion operator on an nx x ny x nz grid
 // (x fastest), kappa = exp(theta): assembly of its CSR values and the
-// per-cell coefficient gradient of a solve-based loss.
+// per-cell coefficient gradient of a solve-based loss.  The grid is 3D when
+// nz > 1, 2D when nz = 1 < ny, else 1D; ghost faces exist only along the
+// grid's own axes.
 //
 // Face between cells L and R: a = 2 kL kR / (kL + kR), entries -a off the
 // diagonal, +a on both diagonals; each boundary face adds 2 kc (zero-Dirichlet
@@ -50,7 +52,8 @@ __global__ void k_assemble(Grid G, const double* __restrict__ theta, double* __r
   // order: z-1, y-1, x-1, x+1, y+1, z+1
   const int64_t nb[6] = {g - sz, g - sy, g - sx, g + sx, g + sy, g + sz};
   const bool in[6] = {z > 0, y > 0, x > 0, x < G.nx - 1, y < G.ny - 1, z < G.nz - 1};
-  const bool active[6] = {G.nz > 1, G.ny > 1, true, true, G.ny > 1, G.nz > 1};
+  const bool ay = G.ny > 1 || G.nz > 1, az = G.nz > 1;  // grid dimension: 3 if nz > 1, 2 if ny > 1
+  const bool active[6] = {az, ay, true, true, ay, az};
   for (int d = 0; d < 6; ++d) {
     has[d] = in[d];
     off[d] = 0.0;
@@ -82,7 +85,8 @@ __global__ void k_coeff_grad(Grid G, const double* __restrict__ theta, const dou
   const int64_t sx = 1, sy = G.nx, sz = (int64_t)G.nx * G.ny;
   const int64_t nb[6] = {g - sz, g - sy, g - sx, g + sx, g + sy, g + sz};
   const bool in[6] = {z > 0, y > 0, x > 0, x < G.nx - 1, y < G.ny - 1, z < G.nz - 1};
-  const bool active[6] = {G.nz > 1, G.ny > 1, true, true, G.ny > 1, G.nz > 1};
+  const bool ay = G.ny > 1 || G.nz > 1, az = G.nz > 1;  // grid dimension: 3 if nz > 1, 2 if ny > 1
+  const bool active[6] = {az, ay, true, true, ay, az};
   double acc = 0.0;
   for (int d = 0; d < 6; ++d) {
     if (in[d]) {
