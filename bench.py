@@ -127,6 +127,71 @@ def cpu_baseline(P, iters: int, n_sample: int = 24, seed: int = 5):
     }
 
 
+def fwd_adjoint(side: int, precision: str, steps: int, warmup: int):
+    """Forward + adjoint pairs per second on the differentiation workload.
+
+    side^3 cells (default 96^3), kappa = exp(theta) with theta a GRF (length 8,
+    sigma 1), 12^3-cell boxes, overlap 1, p = 2, rtol 1e-10; L = ||u - u_obs||^2
+    with u_obs solved from a second seeded field.  One pair = device assembly of
+    A(exp(theta)) + numeric refactor (Galerkin product, coarse inverse, local
+    factors) + forward solve + adjoint solve + coefficient-gradient kernel,
+    all through torch.autograd.
+    """
+    import torch
+
+    from paper_1504_00907_amd import DiffusionSolver, ddg_solve_fn
+    from workloads import box_partition, cell_coords, grf, monomials, seed_rng
+
+    shape = (side,) * 3
+    boxes = (side // 12,) * 3
+    theta = grf(shape, 8.0, 1.0, seed_rng(4, 1))
+    theta_obs = grf(shape, 8.0, 1.0, seed_rng(4, 2))
+    fh = seed_rng(4, 0).uniform(-1.0, 1.0, side ** 3)
+    part = box_partition(shape, boxes)
+    F = monomials(cell_coords(shape), 2)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64).ravel()).cuda()
+    log(f"fwd+adjoint workload {side}^3, boxes {boxes}")
+    ds = DiffusionSolver((side,) * 3, F, part, int(np.prod(boxes)), 1, dev(theta_obs), precision=precision,
+                         rtol=1e-10)
+    f = dev(fh)
+    u_obs = ds.solve(f).clone()
+    th = dev(theta)
+
+    def pair():
+        t = th.clone().requires_grad_(True)
+        u = ddg_solve_fn(t, f, ds)
+        fwd = ds.last_info
+        L = ((u - u_obs) ** 2).sum()
+        L.backward()
+        return fwd, ds.last_info, t.grad
+
+    for _ in range(warmup):
+        pair()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fwd, adj, g = pair()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    # refactor alone
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ds.refactor(th)
+    torch.cuda.synchronize()
+    ref_ms = (time.perf_counter() - t1) * 1e3
+    info = ds.solver.info()
+    ds.solver.close()
+    log(f"fwd+adjoint: {ms:.1f} ms/pair (refactor {ref_ms:.1f} ms), iters {fwd['iters']} + {adj['iters']}")
+    return {
+        "workload": f"diffusion3d_{side}^3_exp_theta_L2_loss", "n": side ** 3, "subdomains": int(np.prod(boxes)),
+        "precision": precision, "rtol": 1e-10, "steps": steps,
+        "pairs_per_s": 1e3 / ms, "ms_per_pair": ms, "refactor_ms": ref_ms,
+        "solve_ms_fwd": fwd["solve_ms"], "solve_ms_adj": adj["solve_ms"],
+        "iters_fwd": fwd["iters"], "iters_adj": adj["iters"], "setup_ms_device": info["setup_ms"],
+        "grad_norm": float(torch.linalg.norm(g)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +201,8 @@ def main():
     ap.add_argument("--box", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint (differentiation) leg")
+    ap.add_argument("--adjoint-side", type=int, default=96)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -225,6 +292,11 @@ def main():
         s64.close()
         del s64
 
+    adj = None
+    if not args.no_adjoint:
+        adj = fwd_adjoint(args.adjoint_side, args.precision, max(1, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else 0.0
     roofline = {
         "bound": "hbm", "kernel": "k_sweep (colour-phase local solve)",
@@ -270,6 +342,7 @@ def main():
         "iter_bytes": hinfo["iter_bytes"],
         "whole_solve_GBps": round(whole, 1),
         **out64,
+        "fwd_adjoint": adj,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
