@@ -121,6 +121,52 @@ int ddg_refactor(ddg_handle h, const double* val_dev);
  */
 int ddg_solve(ddg_handle h, const double* f_dev, double* u_dev, ddg_info* info);
 
+/*
+ * Batches of independent systems.  Many systems of uneven sizes share one
+ * handle and advance together: every kernel launch of the solve covers all
+ * systems still iterating (the local solves of a colour, for instance, run
+ * every such system's subdomains of that colour in one launch), while each
+ * system keeps its own CG scalars, stopping test and status (the method of
+ * Sections 4-7 applied to each system separately).  Converged systems drop
+ * out of the launches.  System b is described by a ddg_problem with the
+ * meaning of ddg_setup's arguments (host arrays, copied during the call).
+ */
+typedef struct {
+  int64_t n;
+  const int64_t* row_ptr;   /* n+1 */
+  const int32_t* col_idx;   /* row_ptr[n], local column ids */
+  const double* val;
+  int32_t k;                /* generating vectors (<= 32); may differ between systems */
+  const double* F;          /* n x k column-major */
+  const int32_t* part;      /* n, ids in [0, n_parts) */
+  int32_t n_parts;
+} ddg_problem;
+
+/*
+ * Set up nb systems in one handle (same options and overlap for all).  The
+ * handle's vectors are the concatenation of the systems' vectors in batch
+ * order (system b at rows row_off[b].., see ddg_batch_layout); ddg_solve,
+ * ddg_refactor (values concatenated in the same order), ddg_spmv and
+ * ddg_apply_precond act on all systems at once.  Errors as ddg_setup, with
+ * the message naming the system; UNSUPPORTED beyond 2^31 - 1 total rows.
+ */
+int ddg_setup_batched(ddg_handle* out, int32_t nb, const ddg_problem* probs, int32_t overlap,
+                      const ddg_options* opt);
+
+/*
+ * Solve every system of the batch: f_dev, u_dev are the concatenated
+ * right-hand sides and solutions (device).  infos (nb entries, may be NULL)
+ * receives per system: status, iters, rel_res, true_rel_res, n_coarse,
+ * n_parts, and solve_ms = device time from the start of the batch solve to
+ * the iteration at which that system stopped.  The return code is DDG_OK
+ * when every system converged, else the first failing system's status.
+ */
+int ddg_solve_batched(ddg_handle h, const double* f_dev, double* u_dev, ddg_info* infos);
+
+/* Batch layout: *nb, row_off[nb+1] (first row of each system), sub_off[nb+1]
+ * (first subdomain).  Any output pointer may be NULL. */
+int ddg_batch_layout(ddg_handle h, int32_t* nb, int64_t* row_off, int32_t* sub_off);
+
 /* z = M^{-1} r, one application of the two-level preconditioner (Section 6). Device vectors. */
 int ddg_apply_precond(ddg_handle h, const double* r_dev, double* z_dev);
 
@@ -144,7 +190,7 @@ typedef enum {
   DDG_EXPORT_SET_PTR = 1,   /* int64[n_parts+1]: offsets of the expanded sets */
   DDG_EXPORT_SET_IDX = 2,   /* int32[sum |expanded set|]: ascending global ids */
   DDG_EXPORT_KCOUNTS = 3,   /* int32[n_parts]: kept coarse columns per subdomain */
-  DDG_EXPORT_A0 = 4,        /* float64[N_c*N_c]: A0 = R0 A R0^T, row-major */
+  DDG_EXPORT_A0 = 4,        /* float64[sum_b N_c(b)^2]: A0 = R0 A R0^T, row-major, one block per system */
   DDG_EXPORT_Q = 5,         /* float64[n*k]: orthonormal coarse basis, node-major (row g: k values) */
   DDG_EXPORT_BLOCKS = 6     /* int32[n_blocks*3]: (subdomain, first local row, rows) per block */
 } ddg_export_item;

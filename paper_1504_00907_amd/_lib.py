@@ -45,6 +45,13 @@ class Info(C.Structure):
         return d
 
 
+class Problem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+        ("k", C.c_int32), ("F", C.c_void_p), ("part", C.c_void_p), ("n_parts", C.c_int32),
+    ]
+
+
 class DDGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -61,6 +68,10 @@ _SIGS = [
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Options)]),
     ("ddg_refactor", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ddg_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Info)]),
+    ("ddg_setup_batched", C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Problem), C.c_int32,
+                                    C.POINTER(Options)]),
+    ("ddg_solve_batched", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Info)]),
+    ("ddg_batch_layout", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]),
     ("ddg_apply_precond", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ddg_apply_precond_stages", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("ddg_spmv", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

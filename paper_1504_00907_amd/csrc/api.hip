@@ -96,7 +96,7 @@ void account_bytes(Handle& h, const int64_t* rp) {
   sweep += (2 * C - 1) * (resid / C) + resid0 / C;  // residual kernels (per-colour average)
   h.info.sweep_bytes = sweep;
   const int64_t n = S.n, nnzb = S.nnz * 12 + (n + 1) * 8;
-  const int64_t ntiles = (int64_t)h.nc_tiles_rows * (h.nc_tiles_rows + 1) / 2;
+  const int64_t ntiles = h.ntiles;
   // coarse: restrict (residual SpMV + Q), tiled inverse GEMV, prolong (Q, e rmw)
   const int64_t coarse = h.nc ? (nnzb + 3 * n * 8 + n * h.k * 8 + ntiles * 64 * 64 * 8 + n * h.k * 8 + 16 * n) : 0;
   // CG: SpMV (p, q), x/r/p/q update, two dots, p update
@@ -158,6 +158,165 @@ void flush_profile(Handle& h) {
   h.ev_used = 0;
 }
 
+// Setup of one handle holding nb independent systems: system b owns rows
+// [seg_off[b], seg_off[b+1]) and subdomains [sub_off[b], sub_off[b+1]); the
+// matrix has no entries between systems.
+void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                int32_t k, const double* F, const int32_t* part, int32_t n_parts, int32_t overlap,
+                const std::vector<int64_t>& seg_off, const std::vector<int32_t>& sub_off) {
+  Handle* h = &hh;
+  if (h->opt.max_iter <= 0) h->opt.max_iter = 1000;
+  if (h->opt.check_every <= 0) h->opt.check_every = 4;
+  DDG_REQUIRE(h->opt.precision >= DDG_FP64 && h->opt.precision <= DDG_MIXED_BF16, DDG_ERR_INVALID_ARG,
+              "unknown precision");
+  DDG_REQUIRE(h->opt.rtol >= 0.0 && h->opt.rank_tol >= 0.0, DDG_ERR_INVALID_ARG, "negative tolerance");
+  h->stream = static_cast<hipStream_t>(h->opt.stream);
+  h->k = k;
+  h->nb = (int32_t)seg_off.size() - 1;
+  h->seg_off = seg_off;
+  h->sub_off = sub_off;
+  DDG_REQUIRE(k <= 32, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
+  if (k > 0)
+    for (int64_t t = 0; t < n * (int64_t)k; ++t)
+      DDG_REQUIRE(std::isfinite(F[t]), DDG_ERR_INVALID_ARG, "non-finite generating vectors");
+  build_symbolic(h->S, n, row_ptr, col_idx, part, n_parts, overlap, h->opt.tile, h->opt.block_target);
+  check_values(n, row_ptr, col_idx, val);
+  Symbolic& S = h->S;
+  int dev = 0;
+  DDG_HIP(hipGetDevice(&dev));
+  int lds = 0;
+  DDG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  h->dev_lds_limit = lds;
+  int clk = 0;
+  DDG_HIP(hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, dev));
+  h->clock_khz = clk > 0 ? clk : 100000;
+  hipStream_t s = h->stream;
+  // system of each subdomain
+  std::vector<int32_t> si(n_parts, 0);
+  for (int32_t b = 0; b < h->nb; ++b)
+    for (int32_t i = sub_off[b]; i < sub_off[b + 1]; ++i) si[i] = b;
+  h->sub_inst.upload(si, s);
+  // integer structure
+  std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
+  std::vector<int32_t> ci(col_idx, col_idx + S.nnz);
+  std::vector<double> vv(val, val + S.nnz);
+  std::vector<int32_t> pp(part, part + n);
+  h->rowptr.upload(rp, s);
+  h->col.upload(ci, s);
+  h->val.upload(vv, s);
+  h->part.upload(pp, s);
+  h->own_ptr.upload(S.own_ptr, s);
+  h->own_idx.upload(S.own_idx, s);
+  h->set_ptr.upload(S.set_ptr, s);
+  h->set_idx.upload(S.set_idx, s);
+  h->colour_subs.upload(S.colour_subs, s);
+  h->nbr_ptr.upload(S.nbr_ptr, s);
+  h->nbr_idx.upload(S.nbr_idx, s);
+  h->sub_blk_ptr.upload(S.sub_blk_ptr, s);
+  h->blk_start.upload(S.blk_start, s);
+  h->blk_size.upload(S.blk_size, s);
+  h->blk_foff.upload(S.blk_foff, s);
+  h->lo_col.upload(S.lo_col, s);
+  h->lo_pos.upload(S.lo_pos, s);
+  h->up_col.upload(S.up_col, s);
+  h->up_pos.upload(S.up_pos, s);
+  h->in_ptr.upload(S.in_ptr, s);
+  h->in_col.upload(S.in_col, s);
+  h->in_pos.upload(S.in_pos, s);
+  h->lo_val.alloc(std::max<size_t>(1, S.lo_pos.size()) * sizeof(double));
+  h->up_val.alloc(std::max<size_t>(1, S.up_pos.size()) * sizeof(double));
+  // two-workgroup sweep: every pair of a colour must be resident at once
+  int ncu = 0;
+  DDG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  h->n_cu = ncu;
+  int max_nsub = 0;
+  for (int32_t c = 0; c < S.n_colours; ++c) max_nsub = std::max(max_nsub, S.colour_ptr[c + 1] - S.colour_ptr[c]);
+  h->twisted_ok = (16 * ((max_nsub + 7) / 8) <= ncu) && std::getenv("DDG_NO_TWIST") == nullptr;
+  h->xch_ld = ((S.max_blk + 63) / 64) * 64;
+  if (h->twisted_ok) {
+    h->xch.alloc((size_t)n_parts * 2 * h->xch_ld * sizeof(double));
+    h->flags.alloc((size_t)n_parts * 2 * sizeof(int32_t));
+    DDG_HIP(hipMemsetAsync(h->flags.p, 0, (size_t)n_parts * 2 * sizeof(int32_t), s));
+  }
+  h->bres.alloc((size_t)S.set_ptr[n_parts] * sizeof(double));
+  h->err_flag.alloc(4 * sizeof(int32_t));
+  DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 4 * sizeof(int32_t), s));
+  h->fac.alloc((size_t)S.fac_elems * storage_size(h->opt.precision));
+  // coarse basis (depends only on F and the partition)
+  h->kcnt.assign(n_parts, 0);
+  h->koff.assign(n_parts + 1, 0);
+  h->cblk_off.assign(h->nb + 1, 0);
+  h->cblk_n.assign(h->nb, 0);
+  if (k > 0) {
+    h->F.alloc((size_t)n * k * sizeof(double));
+    DDG_HIP(hipMemcpyAsync(h->F.p, F, (size_t)n * k * sizeof(double), hipMemcpyHostToDevice, s));
+    h->Q.alloc((size_t)n * k * sizeof(double));
+    h->kcnt_d.alloc((size_t)n_parts * sizeof(int32_t));
+    launch_coarse_basis(*h, s);
+    check_err_flag(*h, "coarse basis");
+    DDG_HIP(hipMemcpyAsync(h->kcnt.data(), h->kcnt_d.p, (size_t)n_parts * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    DDG_HIP(hipStreamSynchronize(s));
+    // coarse numbering: subdomain order, each system's block padded to a multiple of 64
+    int64_t run = 0;
+    for (int32_t b = 0; b < h->nb; ++b) {
+      h->cblk_off[b] = run;
+      for (int32_t i = sub_off[b]; i < sub_off[b + 1]; ++i) {
+        h->koff[i] = run;
+        run += h->kcnt[i];
+      }
+      h->cblk_n[b] = (int32_t)(run - h->cblk_off[b]);
+      h->nc += h->cblk_n[b];
+      run = (run + 63) / 64 * 64;
+    }
+    h->koff[n_parts] = run;
+    h->cblk_off[h->nb] = run;
+    h->koff_d.upload(h->koff, s);
+    h->F.release();
+  }
+  h->nc_pad = h->cblk_off[h->nb];
+  if (h->nc > 0) {
+    h->a0_off.assign(h->nb + 1, 0);
+    h->tile_base.assign(h->nb + 1, 0);
+    std::vector<int32_t> tinst, rinst;
+    for (int32_t b = 0; b < h->nb; ++b) {
+      const int64_t nbk = h->cblk_n[b];
+      const int64_t ntr = (h->cblk_off[b + 1] - h->cblk_off[b]) / 64;
+      h->a0_off[b + 1] = h->a0_off[b] + nbk * nbk;
+      h->tile_base[b + 1] = h->tile_base[b] + ntr * (ntr + 1) / 2;
+      tinst.insert(tinst.end(), (size_t)(ntr * (ntr + 1) / 2), b);
+      rinst.insert(rinst.end(), (size_t)ntr, b);
+    }
+    h->ntiles = h->tile_base[h->nb];
+    h->cblk_off_d.upload(h->cblk_off, s);
+    h->cblk_n_d.upload(h->cblk_n, s);
+    h->a0_off_d.upload(h->a0_off, s);
+    h->tile_base_d.upload(h->tile_base, s);
+    h->tile_inst.upload(tinst, s);
+    h->trow_inst.upload(rinst, s);
+    h->A0.alloc((size_t)h->a0_off[h->nb] * sizeof(double));
+    h->A0inv_t.alloc((size_t)h->ntiles * 64 * 64 * sizeof(double));
+    h->cy.alloc((size_t)2 * h->nc_pad * sizeof(double));
+    DDG_HIP(hipMemsetAsync(h->cy.p, 0, (size_t)2 * h->nc_pad * sizeof(double), s));
+    h->cpart.alloc((size_t)2 * h->ntiles * 64 * sizeof(double));
+  }
+  // CG workspace
+  h->r.alloc((size_t)n * sizeof(double));
+  h->p.alloc((size_t)n * sizeof(double));
+  h->q.alloc((size_t)n * sizeof(double));
+  h->z.alloc((size_t)n * sizeof(double));
+  build_cg_map(*h, s);
+  h->cstate.alloc((size_t)h->nb * sizeof(CgState));
+  DDG_HIP(hipHostMalloc((void**)&h->h_state, (size_t)h->nb * sizeof(CgState), hipHostMallocDefault));
+  h->sys_info.assign(h->nb, ddg_info{});
+  numeric_setup(*h);
+  account_bytes(*h, row_ptr);
+  h->info.n_coarse = (int32_t)h->nc;
+  h->info.n_colours = S.n_colours;
+  h->info.n_parts = n_parts;
+  h->info.n_blocks = (int32_t)S.blk_size.size();
+}
+
 Handle* H(ddg_handle p) { return reinterpret_cast<Handle*>(p); }
 
 template <class Fn>
@@ -212,113 +371,70 @@ int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t*
     auto h = std::make_unique<Handle>();
     if (opt) h->opt = *opt;
     else ddg_default_options(&h->opt);
-    DDG_REQUIRE(h->opt.precision >= DDG_FP64 && h->opt.precision <= DDG_MIXED_BF16, DDG_ERR_INVALID_ARG,
-                "unknown precision");
-    if (h->opt.max_iter <= 0) h->opt.max_iter = 1000;
-    if (h->opt.check_every <= 0) h->opt.check_every = 4;
-    DDG_REQUIRE(h->opt.rtol >= 0.0 && h->opt.rank_tol >= 0.0, DDG_ERR_INVALID_ARG, "negative tolerance");
-    h->stream = static_cast<hipStream_t>(h->opt.stream);
-    h->k = k;
-    DDG_REQUIRE(k <= 32, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
-    if (k > 0)
-      for (int64_t t = 0; t < n * (int64_t)k; ++t)
-        DDG_REQUIRE(std::isfinite(F[t]), DDG_ERR_INVALID_ARG, "non-finite generating vectors");
-    build_symbolic(h->S, n, row_ptr, col_idx, part, n_parts, overlap, h->opt.tile, h->opt.block_target);
-    check_values(n, row_ptr, col_idx, val);
-    Symbolic& S = h->S;
-    int dev = 0;
-    DDG_HIP(hipGetDevice(&dev));
-    int lds = 0;
-    DDG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    h->dev_lds_limit = lds;
-    hipStream_t s = h->stream;
-    // integer structure
-    std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
-    std::vector<int32_t> ci(col_idx, col_idx + S.nnz);
-    std::vector<double> vv(val, val + S.nnz);
-    std::vector<int32_t> pp(part, part + n);
-    h->rowptr.upload(rp, s);
-    h->col.upload(ci, s);
-    h->val.upload(vv, s);
-    h->part.upload(pp, s);
-    h->own_ptr.upload(S.own_ptr, s);
-    h->own_idx.upload(S.own_idx, s);
-    h->set_ptr.upload(S.set_ptr, s);
-    h->set_idx.upload(S.set_idx, s);
-    h->colour_subs.upload(S.colour_subs, s);
-    h->nbr_ptr.upload(S.nbr_ptr, s);
-    h->nbr_idx.upload(S.nbr_idx, s);
-    h->sub_blk_ptr.upload(S.sub_blk_ptr, s);
-    h->blk_start.upload(S.blk_start, s);
-    h->blk_size.upload(S.blk_size, s);
-    h->blk_foff.upload(S.blk_foff, s);
-    h->lo_col.upload(S.lo_col, s);
-    h->lo_pos.upload(S.lo_pos, s);
-    h->up_col.upload(S.up_col, s);
-    h->up_pos.upload(S.up_pos, s);
-    h->in_ptr.upload(S.in_ptr, s);
-    h->in_col.upload(S.in_col, s);
-    h->in_pos.upload(S.in_pos, s);
-    h->lo_val.alloc(std::max<size_t>(1, S.lo_pos.size()) * sizeof(double));
-    h->up_val.alloc(std::max<size_t>(1, S.up_pos.size()) * sizeof(double));
-    // two-workgroup sweep: every pair of a colour must be resident at once
-    int ncu = 0;
-    DDG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    h->n_cu = ncu;
-    int max_nsub = 0;
-    for (int32_t c = 0; c < S.n_colours; ++c) max_nsub = std::max(max_nsub, S.colour_ptr[c + 1] - S.colour_ptr[c]);
-    h->twisted_ok = (16 * ((max_nsub + 7) / 8) <= ncu) && std::getenv("DDG_NO_TWIST") == nullptr;
-    h->xch_ld = ((S.max_blk + 63) / 64) * 64;
-    h->xch.alloc((size_t)n_parts * 2 * h->xch_ld * sizeof(double));
-    h->flags.alloc((size_t)n_parts * 2 * sizeof(int32_t));
-    DDG_HIP(hipMemsetAsync(h->flags.p, 0, (size_t)n_parts * 2 * sizeof(int32_t), s));
-    h->bres.alloc((size_t)S.set_ptr[n_parts] * sizeof(double));
-    h->err_flag.alloc(4 * sizeof(int32_t));
-    DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 4 * sizeof(int32_t), s));
-    h->fac.alloc((size_t)S.fac_elems * storage_size(h->opt.precision));
-    // coarse basis (depends only on F and the partition)
-    h->kcnt.assign(n_parts, 0);
-    h->koff.assign(n_parts + 1, 0);
-    if (k > 0) {
-      h->F.alloc((size_t)n * k * sizeof(double));
-      DDG_HIP(hipMemcpyAsync(h->F.p, F, (size_t)n * k * sizeof(double), hipMemcpyHostToDevice, s));
-      h->Q.alloc((size_t)n * k * sizeof(double));
-      h->kcnt_d.alloc((size_t)n_parts * sizeof(int32_t));
-      launch_coarse_basis(*h, s);
-      check_err_flag(*h, "coarse basis");
-      DDG_HIP(hipMemcpyAsync(h->kcnt.data(), h->kcnt_d.p, (size_t)n_parts * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
-      DDG_HIP(hipStreamSynchronize(s));
-      for (int32_t i = 0; i < n_parts; ++i) h->koff[i + 1] = h->koff[i] + h->kcnt[i];
-      h->nc = h->koff[n_parts];
-      h->koff_d.upload(h->koff, s);
-      h->F.release();
+    setup_impl(*h, n, row_ptr, col_idx, val, k, F, part, n_parts, overlap, {0, n}, {0, n_parts});
+    hp = h.release();
+  });
+  if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
+  return rc;
+}
+
+int ddg_setup_batched(ddg_handle* out, int32_t nb, const ddg_problem* probs, int32_t overlap,
+                      const ddg_options* opt) {
+  if (out) *out = nullptr;
+  Handle* hp = nullptr;
+  int rc = guarded([&]() {
+    DDG_REQUIRE(out && probs && nb >= 1, DDG_ERR_INVALID_ARG, "null argument or empty batch");
+    std::vector<int64_t> seg_off(nb + 1, 0);
+    std::vector<int32_t> sub_off(nb + 1, 0);
+    int64_t nnz = 0;
+    int32_t kmax = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+      const ddg_problem& P = probs[b];
+      DDG_REQUIRE(P.n > 0 && P.row_ptr && P.col_idx && P.val && P.part && P.n_parts > 0, DDG_ERR_INVALID_ARG,
+                  "system " + std::to_string(b) + ": null argument or empty");
+      DDG_REQUIRE(P.k >= 0 && (P.k == 0 || P.F), DDG_ERR_INVALID_ARG,
+                  "system " + std::to_string(b) + ": k must be >= 0 and F given when k > 0");
+      DDG_REQUIRE(P.row_ptr[0] == 0 && P.row_ptr[P.n] >= P.n, DDG_ERR_INVALID_ARG,
+                  "system " + std::to_string(b) + ": bad row pointers");
+      seg_off[b + 1] = seg_off[b] + P.n;
+      sub_off[b + 1] = sub_off[b] + P.n_parts;
+      nnz += P.row_ptr[P.n];
+      kmax = std::max(kmax, P.k);
     }
-    if (h->nc > 0) {
-      h->nc_tiles_rows = (int32_t)((h->nc + 63) / 64);
-      const int64_t ntr = h->nc_tiles_rows;
-      const int64_t ntiles = ntr * (ntr + 1) / 2;
-      h->A0.alloc((size_t)h->nc * h->nc * sizeof(double));
-      h->A0inv_t.alloc((size_t)ntiles * 64 * 64 * sizeof(double));
-      h->cy.alloc((size_t)2 * ntr * 64 * sizeof(double));
-      DDG_HIP(hipMemsetAsync(h->cy.p, 0, (size_t)2 * ntr * 64 * sizeof(double), s));
-      h->cpart.alloc((size_t)2 * ntiles * 64 * sizeof(double));
+    const int64_t n = seg_off[nb];
+    DDG_REQUIRE(n < INT32_MAX, DDG_ERR_UNSUPPORTED, "batch exceeds 2^31 rows");
+    // one block-diagonal system: rows, columns and subdomain ids shifted per system;
+    // generating vectors padded with zero columns up to the largest k (dropped by the rank rule)
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> ci((size_t)nnz);
+    std::vector<double> vv((size_t)nnz);
+    std::vector<int32_t> pp((size_t)n);
+    std::vector<double> Fc((size_t)n * kmax, 0.0);
+    for (int32_t b = 0; b < nb; ++b) {
+      const ddg_problem& P = probs[b];
+      const int64_t r0 = seg_off[b], e0 = rp[r0];
+      for (int64_t i = 0; i < P.n; ++i) {
+        rp[r0 + i + 1] = e0 + P.row_ptr[i + 1];
+        const int32_t pi = P.part[i];
+        DDG_REQUIRE(pi >= 0 && pi < P.n_parts, DDG_ERR_INVALID_ARG,
+                    "system " + std::to_string(b) + ": partition id out of range");
+        pp[r0 + i] = pi + sub_off[b];
+      }
+      for (int64_t t = 0; t < P.row_ptr[P.n]; ++t) {
+        const int32_t c = P.col_idx[t];
+        DDG_REQUIRE(c >= 0 && c < P.n, DDG_ERR_INVALID_ARG, "system " + std::to_string(b) + ": column out of range");
+        ci[e0 + t] = (int32_t)(c + r0);
+        vv[e0 + t] = P.val[t];
+      }
+      for (int32_t m = 0; m < P.k; ++m)
+        for (int64_t i = 0; i < P.n; ++i) Fc[(size_t)m * n + r0 + i] = P.F[(size_t)m * P.n + i];
     }
-    // CG workspace
-    h->r.alloc((size_t)n * sizeof(double));
-    h->p.alloc((size_t)n * sizeof(double));
-    h->q.alloc((size_t)n * sizeof(double));
-    h->z.alloc((size_t)n * sizeof(double));
-    h->n_partials = cg_partials_count(n);
-    h->part_sums.alloc((size_t)h->n_partials * sizeof(double));
-    h->cstate.alloc(sizeof(CgState));
-    DDG_HIP(hipHostMalloc((void**)&h->h_state, sizeof(CgState), hipHostMallocDefault));
-    numeric_setup(*h);
-    account_bytes(*h, row_ptr);
-    h->info.n_coarse = (int32_t)h->nc;
-    h->info.n_colours = S.n_colours;
-    h->info.n_parts = n_parts;
-    h->info.n_blocks = (int32_t)S.blk_size.size();
+    auto h = std::make_unique<Handle>();
+    if (opt) h->opt = *opt;
+    else ddg_default_options(&h->opt);
+    int32_t parts = sub_off[nb];
+    setup_impl(*h, n, rp.data(), ci.data(), vv.data(), kmax, kmax ? Fc.data() : nullptr, pp.data(), parts, overlap,
+               seg_off, sub_off);
     hp = h.release();
   });
   if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
@@ -367,6 +483,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     DDG_HIP(hipEventRecord(e0, s));
     double* x = u_dev;
     double* z = h->z.as<double>();
+    const size_t sb = (size_t)h->nb * sizeof(CgState);
     launch_cg_init(*h, f_dev, x, s);
     launch_precond(*h, h->r.as<double>(), z, -1, true, s);
     launch_cg_start(*h, s);
@@ -379,39 +496,77 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
         launch_cg_step_b(*h, s);
       }
       enqueued += chunk;
-      DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sb, hipMemcpyDeviceToHost, s));
       DDG_HIP(hipStreamSynchronize(s));
       if (h->profiling) flush_profile(*h);
-      if (h->h_state->done) break;
+      bool all = true;
+      for (int32_t b = 0; b < h->nb && all; ++b) all = h->h_state[b].done != 0;
+      if (all) break;
       DDG_REQUIRE(enqueued <= h->opt.max_iter + 2 * chunk, DDG_ERR_HIP, "internal: CG loop did not stop");
     }
     launch_true_residual(*h, f_dev, x, s);
     DDG_HIP(hipEventRecord(e1, s));
     check_err_flag(*h, "solve");
-    DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sb, hipMemcpyDeviceToHost, s));
     DDG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     DDG_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const CgState& st = *h->h_state;
-    h->info.status = st.status;
-    h->info.iters = st.iters;
-    h->info.rel_res = st.fnorm > 0 ? std::sqrt(st.rr) / st.fnorm : 0.0;
-    h->info.true_rel_res = st.fnorm > 0 ? std::sqrt(st.true_rr) / st.fnorm : 0.0;
+    // per system, then the aggregate: the worst of every figure, first failing status
+    int32_t status = DDG_OK, iters = 0;
+    double rel = 0.0, trel = 0.0;
+    for (int32_t b = 0; b < h->nb; ++b) {
+      const CgState& st = h->h_state[b];
+      ddg_info& si = h->sys_info[b];
+      si = h->info;
+      si.status = st.status;
+      si.iters = st.iters;
+      si.rel_res = st.fnorm > 0 ? std::sqrt(st.rr) / st.fnorm : 0.0;
+      si.true_rel_res = st.fnorm > 0 ? std::sqrt(st.true_rr) / st.fnorm : 0.0;
+      si.n_coarse = h->cblk_n[b];
+      si.n_parts = h->sub_off[b + 1] - h->sub_off[b];
+      si.solve_ms = st.t_done >= st.t_start ? (double)(st.t_done - st.t_start) / h->clock_khz : 0.0;
+      if (status == DDG_OK && st.status != DDG_OK) status = st.status;
+      iters = std::max(iters, st.iters);
+      rel = std::max(rel, si.rel_res);
+      trel = std::max(trel, si.true_rel_res);
+    }
+    h->info.status = status;
+    h->info.iters = iters;
+    h->info.rel_res = rel;
+    h->info.true_rel_res = trel;
     h->info.solve_ms = ms;
     if (info) *info = h->info;
-    if (st.status != DDG_OK) {
-      const char* what = st.status == DDG_ERR_NO_CONVERGENCE ? "maximum iterations reached"
-                         : st.status == DDG_ERR_BREAKDOWN    ? "CG breakdown (p^T q <= 0 or non-finite)"
-                                                             : "non-finite right-hand side";
-      throw Error{st.status, what};
+    if (status != DDG_OK) {
+      const char* what = status == DDG_ERR_NO_CONVERGENCE ? "maximum iterations reached"
+                         : status == DDG_ERR_BREAKDOWN    ? "CG breakdown (p^T q <= 0 or non-finite)"
+                                                          : "non-finite right-hand side";
+      throw Error{status, what};
     }
   });
   if (rc != DDG_OK && info && h) {
     info->status = rc;
   }
   return rc;
+}
+
+int ddg_solve_batched(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* infos) {
+  Handle* h = H(hd);
+  const int rc = ddg_solve(hd, f_dev, u_dev, nullptr);
+  if (h && infos && !h->host_only && (int32_t)h->sys_info.size() == h->nb)
+    for (int32_t b = 0; b < h->nb; ++b) infos[b] = h->sys_info[b];
+  return rc;
+}
+
+int ddg_batch_layout(ddg_handle hd, int32_t* nb, int64_t* row_off, int32_t* sub_off) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && !h->host_only, DDG_ERR_INVALID_ARG, "null or analysis-only handle");
+    if (nb) *nb = h->nb;
+    if (row_off) std::copy(h->seg_off.begin(), h->seg_off.end(), row_off);
+    if (sub_off) std::copy(h->sub_off.begin(), h->sub_off.end(), sub_off);
+  });
 }
 
 int ddg_apply_precond(ddg_handle hd, const double* r_dev, double* z_dev) {
@@ -468,7 +623,7 @@ int ddg_export(ddg_handle hd, int32_t what, void* host_buf, int64_t bytes, int64
         src = h->kcnt.data(); need = (int64_t)h->kcnt.size() * 4; break;
       case DDG_EXPORT_A0:
         DDG_REQUIRE(!h->host_only, DDG_ERR_INVALID_ARG, "analysis-only handle");
-        src = h->A0.p; need = h->nc * h->nc * 8; device = true; break;
+        src = h->A0.p; need = (h->nc > 0 ? h->a0_off[h->nb] : 0) * 8; device = true; break;
       case DDG_EXPORT_Q:
         DDG_REQUIRE(!h->host_only, DDG_ERR_INVALID_ARG, "analysis-only handle");
         src = h->Q.p; need = S.n * h->k * 8; device = true; break;

@@ -113,7 +113,7 @@ __host__ __device__ inline int32_t tiles_for(int32_t b, int32_t T) {
 }
 
 // ---------------------------------------------------------------------------
-// Device-side CG state (one per handle)
+// Device-side CG state (one per independent system of the handle)
 
 struct CgState {
   double rho;        // r^T z
@@ -127,6 +127,8 @@ struct CgState {
   int32_t status;    // ddg_status
   int32_t iters;
   int32_t max_iter;
+  uint64_t t_start;  // device real-time counter at the start of the solve
+  uint64_t t_done;   // ... when this system stopped
 };
 
 // ---------------------------------------------------------------------------
@@ -138,10 +140,28 @@ struct Handle {
   hipStream_t stream = nullptr;
   Symbolic S;
   int32_t k = 0;          // columns of F
-  int64_t nc = 0;         // coarse dimension
-  int32_t nc_tiles_rows = 0;
+  int64_t nc = 0;         // coarse dimension (sum over systems, without padding)
   std::vector<int32_t> kcnt;   // kept columns per subdomain
-  std::vector<int64_t> koff;   // coarse offsets
+  std::vector<int64_t> koff;   // coarse offsets (each system's block starts on a multiple of 64)
+
+  // independent systems (a batch): system b owns rows [seg_off[b], seg_off[b+1]) and
+  // subdomains [sub_off[b], sub_off[b+1]); its coarse block is rows
+  // [cblk_off[b], cblk_off[b] + cblk_n[b]) of the padded coarse vector
+  int32_t nb = 1;
+  std::vector<int64_t> seg_off;
+  std::vector<int32_t> sub_off;
+  std::vector<int64_t> cblk_off;     // nb+1, multiples of 64
+  std::vector<int32_t> cblk_n;       // nb
+  std::vector<int64_t> a0_off;       // nb+1, element offsets of the dense A0 blocks
+  std::vector<int64_t> tile_base;    // nb+1, first 64x64 tile of each inverse block
+  int64_t nc_pad = 0;                // cblk_off[nb]
+  int64_t ntiles = 0;                // tile_base[nb]
+  DevBuf sub_inst;                   // int32 per subdomain
+  DevBuf cblk_off_d, cblk_n_d, a0_off_d, tile_base_d, tile_inst, trow_inst;
+  // CG reduction map: workgroup g covers rows [wg_lo[g], wg_hi[g]) of system wg_seg[g];
+  // the partials of system b are [seg_wg_ptr[b], seg_wg_ptr[b+1])
+  DevBuf wg_seg, wg_lo, wg_hi, seg_wg_ptr_d;
+  std::vector<int32_t> seg_wg_ptr;
   int32_t dev_lds_limit = 65536;
 
   // device copies
@@ -162,21 +182,23 @@ struct Handle {
   DevBuf F;               // n x k column-major (setup input)
   DevBuf Q;               // n x k node-major orthonormal basis (zero-padded)
   DevBuf kcnt_d, koff_d;
-  DevBuf A0;              // nc x nc dense (setup scratch, also kept for export)
-  DevBuf A0inv_t;         // tiled lower inverse, float64, tile 64
+  DevBuf A0;              // dense coarse blocks, one per system (kept for export)
+  DevBuf A0inv_t;         // tiled lower inverses, float64, tile 64
   DevBuf fac;             // local factor tiles (storage precision)
   DevBuf fac_scratch;     // setup scratch
   DevBuf err_flag;        // int32[4]: setup error (code, subdomain, block, pivot)
 
   // CG workspace
   DevBuf r, p, q, z, part_sums, cstate;
-  DevBuf cy, cpart;       // coarse rhs/solution (nc) and GEMV partials
+  DevBuf cy, cpart;       // coarse rhs/solution (nc_pad each) and GEMV partials
   DevBuf pinned_state;    // unused placeholder
-  CgState* h_state = nullptr;   // pinned host mirror
+  CgState* h_state = nullptr;   // pinned host mirror (nb entries)
   int32_t n_partials = 0;
 
   // info
   ddg_info info{};
+  std::vector<ddg_info> sys_info;      // per system, last solve
+  int32_t clock_khz = 100000;          // device real-time counter rate
   std::vector<int64_t> colour_bytes;   // algorithmic bytes of one local-solve launch per colour
   int64_t residual_bytes = 0;          // all colours' local-residual kernels (non-zero e)
 
@@ -205,7 +227,7 @@ void launch_cg_start(Handle& h, hipStream_t s);
 void launch_cg_step_a(Handle& h, double* x, hipStream_t s);
 void launch_cg_step_b(Handle& h, hipStream_t s);
 void launch_true_residual(Handle& h, const double* f, const double* x, hipStream_t s);
-int32_t cg_partials_count(int64_t n);
+void build_cg_map(Handle& h, hipStream_t s);
 
 // preconditioner
 void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded,

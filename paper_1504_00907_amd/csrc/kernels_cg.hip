@@ -1,10 +1,14 @@
 // CG kernels (Sections 1 and 7: CG from x0 = 0, stop at ||r|| <= rtol ||f||).
-// All vectors float64.  Reductions are two-stage and fixed-order: each
-// workgroup writes one partial (wave butterfly, then waves in order) and a
-// one-workgroup scalar kernel sums the partials in a fixed tree, so results
-// are bitwise reproducible.  Every kernel first reads the device CG state and
-// returns when the solve has stopped, so whole iterations can be enqueued
-// ahead of the host's convergence checks.
+// All vectors float64.  A handle may hold several independent systems (a
+// batch); each has its own CG state and its own scalars, and its rows form one
+// contiguous segment of every vector.  Reductions are two-stage and
+// fixed-order: workgroup g covers a contiguous row range of one system and
+// writes one partial (wave butterfly, then waves in order); a scalar kernel
+// with one workgroup per system sums that system's partials in a fixed tree,
+// so results are bitwise reproducible.  Every kernel first reads its system's
+// CG state and returns when that system has stopped, so whole iterations can
+// be enqueued ahead of the host's convergence checks and converged systems of
+// a batch drop out of every launch.
 #include "common.hpp"
 #include "device_util.hpp"
 
@@ -26,6 +30,13 @@ __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, int
   for (; i < n; i += stride) d[i] = s[i];
 }
 
+struct SegMap {
+  const int32_t* seg;   // system of each workgroup
+  const int64_t* lo;    // first row
+  const int64_t* hi;    // end row
+  const int32_t* ptr;   // nb+1: partials of system b are [ptr[b], ptr[b+1])
+};
+
 __device__ inline double row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                  const double* __restrict__ v, const double* __restrict__ x,
                                  int64_t g) {
@@ -43,12 +54,12 @@ __global__ void k_spmv(const int64_t* __restrict__ rp, const int32_t* __restrict
 }
 
 // x = 0, r = f, partial f.f
-__global__ void k_cg_init(const double* __restrict__ f, double* __restrict__ x,
-                          double* __restrict__ r, double* __restrict__ part, int64_t n) {
+__global__ void k_cg_init(SegMap m, const double* __restrict__ f, double* __restrict__ x,
+                          double* __restrict__ r, double* __restrict__ part) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
     double fi = f[i];
     x[i] = 0.0;
     r[i] = fi;
@@ -58,10 +69,14 @@ __global__ void k_cg_init(const double* __restrict__ f, double* __restrict__ x,
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_cg_init_scalar(CgState* st, const double* __restrict__ part, int np, double rtol,
+__device__ inline uint64_t device_clock() { return wall_clock64(); }
+
+__global__ void k_cg_init_scalar(CgState* stb, SegMap m, const double* __restrict__ part, double rtol,
                                  int max_iter) {
   __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part, np, red);
+  const int b = blockIdx.x;
+  CgState* st = stb + b;
+  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
   if (threadIdx.x == 0) {
     st->iters = 0;
     st->max_iter = max_iter;
@@ -72,24 +87,27 @@ __global__ void k_cg_init_scalar(CgState* st, const double* __restrict__ part, i
     st->tol2 = rtol * rtol * s;
     st->rho = st->alpha = st->beta = st->pq = 0.0;
     st->true_rr = 0.0;
+    st->t_start = device_clock();
+    st->t_done = 0;
     if (!isfinite(s)) {
       st->status = DDG_ERR_INVALID_ARG;
       st->done = 1;
     } else if (s == 0.0) {
       st->done = 1;
     }
+    if (st->done) st->t_done = st->t_start;
   }
 }
 
 // p = z, partial r.z
-__global__ void k_copy_dot(const CgState* st, const double* __restrict__ r,
+__global__ void k_copy_dot(const CgState* stb, SegMap m, const double* __restrict__ r,
                            const double* __restrict__ z, double* __restrict__ p,
-                           double* __restrict__ part, int64_t n) {
-  if (st->done) return;
+                           double* __restrict__ part) {
+  if (stb[m.seg[blockIdx.x]].done) return;
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
     double zi = z[i];
     p[i] = zi;
     acc += r[i] * zi;
@@ -98,14 +116,21 @@ __global__ void k_copy_dot(const CgState* st, const double* __restrict__ r,
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_rho_scalar(CgState* st, const double* __restrict__ part, int np, int first) {
+__device__ inline void stop(CgState* st, int32_t status) {
+  st->status = status;
+  st->done = 1;
+  st->t_done = device_clock();
+}
+
+__global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ part, int first) {
+  const int b = blockIdx.x;
+  CgState* st = stb + b;
   if (st->done) return;
   __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part, np, red);
+  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
   if (threadIdx.x == 0) {
     if (!(s > 0.0) || !isfinite(s)) {
-      st->status = DDG_ERR_BREAKDOWN;
-      st->done = 1;
+      stop(st, DDG_ERR_BREAKDOWN);
       return;
     }
     if (first) {
@@ -118,15 +143,15 @@ __global__ void k_rho_scalar(CgState* st, const double* __restrict__ part, int n
 }
 
 // q = A p, partial p.q
-__global__ void k_spmv_dot(const CgState* st, const int64_t* __restrict__ rp,
+__global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restrict__ rp,
                            const int32_t* __restrict__ ci, const double* __restrict__ v,
                            const double* __restrict__ p, double* __restrict__ q,
-                           double* __restrict__ part, int64_t n) {
-  if (st->done) return;
+                           double* __restrict__ part) {
+  if (stb[m.seg[blockIdx.x]].done) return;
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
     double qi = row_dot(rp, ci, v, p, i);
     q[i] = qi;
     acc += p[i] * qi;
@@ -135,15 +160,16 @@ __global__ void k_spmv_dot(const CgState* st, const int64_t* __restrict__ rp,
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_alpha_scalar(CgState* st, const double* __restrict__ part, int np) {
+__global__ void k_alpha_scalar(CgState* stb, SegMap m, const double* __restrict__ part) {
+  const int b = blockIdx.x;
+  CgState* st = stb + b;
   if (st->done) return;
   __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part, np, red);
+  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
   if (threadIdx.x == 0) {
     st->pq = s;
     if (!(s > 0.0) || !isfinite(s)) {
-      st->status = DDG_ERR_BREAKDOWN;
-      st->done = 1;
+      stop(st, DDG_ERR_BREAKDOWN);
       return;
     }
     st->alpha = st->rho / s;
@@ -151,15 +177,16 @@ __global__ void k_alpha_scalar(CgState* st, const double* __restrict__ part, int
 }
 
 // x += alpha p, r -= alpha q, partial r.r
-__global__ void k_axpy2_dot(const CgState* st, double* __restrict__ x, double* __restrict__ r,
+__global__ void k_axpy2_dot(const CgState* stb, SegMap m, double* __restrict__ x, double* __restrict__ r,
                             const double* __restrict__ p, const double* __restrict__ q,
-                            double* __restrict__ part, int64_t n) {
+                            double* __restrict__ part) {
+  const CgState* st = stb + m.seg[blockIdx.x];
   if (st->done) return;
   __shared__ double red[kThreads / 64];
   const double a = st->alpha;
   double acc = 0.0;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
     x[i] += a * p[i];
     double ri = r[i] - a * q[i];
     r[i] = ri;
@@ -169,57 +196,50 @@ __global__ void k_axpy2_dot(const CgState* st, double* __restrict__ x, double* _
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_conv_scalar(CgState* st, const double* __restrict__ part, int np) {
+__global__ void k_conv_scalar(CgState* stb, SegMap m, const double* __restrict__ part) {
+  const int b = blockIdx.x;
+  CgState* st = stb + b;
   if (st->done) return;
   __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part, np, red);
+  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
   if (threadIdx.x == 0) {
     st->rr = s;
     st->iters += 1;
-    if (!isfinite(s)) {
-      st->status = DDG_ERR_BREAKDOWN;
-      st->done = 1;
-    } else if (s <= st->tol2) {
-      st->status = DDG_OK;
-      st->done = 1;
-    } else if (st->iters >= st->max_iter) {
-      st->status = DDG_ERR_NO_CONVERGENCE;
-      st->done = 1;
-    }
+    if (!isfinite(s)) stop(st, DDG_ERR_BREAKDOWN);
+    else if (s <= st->tol2) stop(st, DDG_OK);
+    else if (st->iters >= st->max_iter) stop(st, DDG_ERR_NO_CONVERGENCE);
   }
 }
 
 // partial r.z (after the preconditioner)
-__global__ void k_dot(const CgState* st, const double* __restrict__ a, const double* __restrict__ b,
-                      double* __restrict__ part, int64_t n) {
-  if (st->done) return;
+__global__ void k_dot(const CgState* stb, SegMap m, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ part) {
+  if (stb[m.seg[blockIdx.x]].done) return;
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    acc += a[i] * b[i];
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) acc += a[i] * b[i];
   double s = block_sum<kThreads>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // p = z + beta p
-__global__ void k_xpby(const CgState* st, const double* __restrict__ z, double* __restrict__ p,
-                       int64_t n) {
+__global__ void k_xpby(const CgState* stb, SegMap m, const double* __restrict__ z, double* __restrict__ p) {
+  const CgState* st = stb + m.seg[blockIdx.x];
   if (st->done) return;
   const double b = st->beta;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    p[i] = z[i] + b * p[i];
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) p[i] = z[i] + b * p[i];
 }
 
 // partial ||f - A x||^2 (always runs)
-__global__ void k_resid_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+__global__ void k_resid_dot(SegMap m, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                             const double* __restrict__ v, const double* __restrict__ f,
-                            const double* __restrict__ x, double* __restrict__ part, int64_t n) {
+                            const double* __restrict__ x, double* __restrict__ part) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
     double d = f[i] - row_dot(rp, ci, v, x, i);
     acc += d * d;
   }
@@ -227,10 +247,11 @@ __global__ void k_resid_dot(const int64_t* __restrict__ rp, const int32_t* __res
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_true_scalar(CgState* st, const double* __restrict__ part, int np) {
+__global__ void k_true_scalar(CgState* stb, SegMap m, const double* __restrict__ part) {
   __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part, np, red);
-  if (threadIdx.x == 0) st->true_rr = s;
+  const int b = blockIdx.x;
+  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
+  if (threadIdx.x == 0) stb[b].true_rr = s;
 }
 
 int grid_for(int64_t n) {
@@ -238,11 +259,36 @@ int grid_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
 }
 
+SegMap segmap(const Handle& h) {
+  return SegMap{h.wg_seg.as<int32_t>(), h.wg_lo.as<int64_t>(), h.wg_hi.as<int64_t>(), h.seg_wg_ptr_d.as<int32_t>()};
+}
+
 }  // namespace
 
-int32_t cg_partials_count(int64_t n) {
-  int64_t g = (n + kThreads * 4 - 1) / (kThreads * 4);
-  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
+// Row ranges of the reduction workgroups: each system is cut into at most 1024
+// contiguous chunks of at least 2048 rows (a multiple of 256).
+void build_cg_map(Handle& h, hipStream_t s) {
+  std::vector<int32_t> seg;
+  std::vector<int64_t> lo, hi;
+  h.seg_wg_ptr.assign(h.nb + 1, 0);
+  for (int32_t b = 0; b < h.nb; ++b) {
+    const int64_t a0 = h.seg_off[b], a1 = h.seg_off[b + 1], nb = a1 - a0;
+    int64_t chunk = std::max<int64_t>(2048, (nb + 1023) / 1024);
+    chunk = (chunk + kThreads - 1) / kThreads * kThreads;
+    int64_t cnt = std::max<int64_t>(1, (nb + chunk - 1) / chunk);
+    for (int64_t c = 0; c < cnt; ++c) {
+      seg.push_back(b);
+      lo.push_back(a0 + std::min(nb, c * chunk));
+      hi.push_back(a0 + std::min(nb, (c + 1) * chunk));
+    }
+    h.seg_wg_ptr[b + 1] = (int32_t)seg.size();
+  }
+  h.n_partials = (int32_t)seg.size();
+  h.wg_seg.upload(seg, s);
+  h.wg_lo.upload(lo, s);
+  h.wg_hi.upload(hi, s);
+  h.seg_wg_ptr_d.upload(h.seg_wg_ptr, s);
+  h.part_sums.alloc((size_t)h.n_partials * sizeof(double));
 }
 
 void launch_fill(double* x, double v, int64_t n, hipStream_t s) {
@@ -259,49 +305,48 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
 }
 
 void launch_cg_init(Handle& h, const double* f, double* x, hipStream_t s) {
-  int np = h.n_partials;
-  hipLaunchKernelGGL(k_cg_init, dim3(np), dim3(kThreads), 0, s, f, x, h.r.as<double>(),
-                     h.part_sums.as<double>(), h.S.n);
-  hipLaunchKernelGGL(k_cg_init_scalar, dim3(1), dim3(kThreads), 0, s, h.cstate.as<CgState>(),
-                     h.part_sums.as<double>(), np, h.opt.rtol, h.opt.max_iter);
+  const SegMap m = segmap(h);
+  hipLaunchKernelGGL(k_cg_init, dim3(h.n_partials), dim3(kThreads), 0, s, m, f, x, h.r.as<double>(),
+                     h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_cg_init_scalar, dim3(h.nb), dim3(kThreads), 0, s, h.cstate.as<CgState>(), m,
+                     h.part_sums.as<double>(), h.opt.rtol, h.opt.max_iter);
 }
 
 void launch_cg_start(Handle& h, hipStream_t s) {
-  int np = h.n_partials;
+  const SegMap m = segmap(h);
   CgState* st = h.cstate.as<CgState>();
-  hipLaunchKernelGGL(k_copy_dot, dim3(np), dim3(kThreads), 0, s, st, h.r.as<double>(),
-                     h.z.as<double>(), h.p.as<double>(), h.part_sums.as<double>(), h.S.n);
-  hipLaunchKernelGGL(k_rho_scalar, dim3(1), dim3(kThreads), 0, s, st, h.part_sums.as<double>(), np, 1);
+  hipLaunchKernelGGL(k_copy_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.r.as<double>(),
+                     h.z.as<double>(), h.p.as<double>(), h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_rho_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), 1);
 }
 
 void launch_cg_step_a(Handle& h, double* x, hipStream_t s) {
-  int np = h.n_partials;
+  const SegMap m = segmap(h);
   CgState* st = h.cstate.as<CgState>();
-  hipLaunchKernelGGL(k_spmv_dot, dim3(np), dim3(kThreads), 0, s, st, h.rowptr.as<int64_t>(),
+  hipLaunchKernelGGL(k_spmv_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.rowptr.as<int64_t>(),
                      h.col.as<int32_t>(), h.val.as<double>(), h.p.as<double>(), h.q.as<double>(),
-                     h.part_sums.as<double>(), h.S.n);
-  hipLaunchKernelGGL(k_alpha_scalar, dim3(1), dim3(kThreads), 0, s, st, h.part_sums.as<double>(), np);
-  hipLaunchKernelGGL(k_axpy2_dot, dim3(np), dim3(kThreads), 0, s, st, x, h.r.as<double>(),
-                     h.p.as<double>(), h.q.as<double>(), h.part_sums.as<double>(), h.S.n);
-  hipLaunchKernelGGL(k_conv_scalar, dim3(1), dim3(kThreads), 0, s, st, h.part_sums.as<double>(), np);
+                     h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_alpha_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_axpy2_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, x, h.r.as<double>(),
+                     h.p.as<double>(), h.q.as<double>(), h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_conv_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>());
 }
 
 void launch_cg_step_b(Handle& h, hipStream_t s) {
-  int np = h.n_partials;
+  const SegMap m = segmap(h);
   CgState* st = h.cstate.as<CgState>();
-  hipLaunchKernelGGL(k_dot, dim3(np), dim3(kThreads), 0, s, st, h.r.as<double>(), h.z.as<double>(),
-                     h.part_sums.as<double>(), h.S.n);
-  hipLaunchKernelGGL(k_rho_scalar, dim3(1), dim3(kThreads), 0, s, st, h.part_sums.as<double>(), np, 0);
-  hipLaunchKernelGGL(k_xpby, dim3(grid_for(h.S.n)), dim3(kThreads), 0, s, st, h.z.as<double>(),
-                     h.p.as<double>(), h.S.n);
+  hipLaunchKernelGGL(k_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.r.as<double>(), h.z.as<double>(),
+                     h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_rho_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), 0);
+  hipLaunchKernelGGL(k_xpby, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.z.as<double>(), h.p.as<double>());
 }
 
 void launch_true_residual(Handle& h, const double* f, const double* x, hipStream_t s) {
-  int np = h.n_partials;
-  hipLaunchKernelGGL(k_resid_dot, dim3(np), dim3(kThreads), 0, s, h.rowptr.as<int64_t>(),
-                     h.col.as<int32_t>(), h.val.as<double>(), f, x, h.part_sums.as<double>(), h.S.n);
-  hipLaunchKernelGGL(k_true_scalar, dim3(1), dim3(kThreads), 0, s, h.cstate.as<CgState>(),
-                     h.part_sums.as<double>(), np);
+  const SegMap m = segmap(h);
+  hipLaunchKernelGGL(k_resid_dot, dim3(h.n_partials), dim3(kThreads), 0, s, m, h.rowptr.as<int64_t>(),
+                     h.col.as<int32_t>(), h.val.as<double>(), f, x, h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_true_scalar, dim3(h.nb), dim3(kThreads), 0, s, h.cstate.as<CgState>(), m,
+                     h.part_sums.as<double>());
 }
 
 }  // namespace ddg

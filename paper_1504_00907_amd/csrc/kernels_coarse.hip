@@ -7,7 +7,10 @@
 //   e_g += sum_m Q[g, m] y[off_{part g} + m]                        (prolong)
 // A0^{-1} is the explicit float64 inverse computed at setup; it is stored as
 // lower 64 x 64 tiles and applied with one wave per tile, writing fixed
-// per-tile partials that a second kernel sums in a fixed order.
+// per-tile partials that a second kernel sums in a fixed order.  With several
+// independent systems A0 is block diagonal: system b owns the padded coarse
+// rows [cblk_off[b], cblk_off[b+1]) and the tiles [tile_base[b], tile_base[b+1])
+// of its own inverse; kernels skip the work of systems that have stopped.
 #include "common.hpp"
 #include "symv_tile.hpp"
 
@@ -19,14 +22,14 @@ constexpr int kRThreads = 256;
 constexpr int kMaxK = 32;
 
 __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
-    const CgState* st, const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
+    const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
     const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff, const double* __restrict__ Q,
     int kq, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
     const double* __restrict__ val, const double* __restrict__ r, const double* __restrict__ e,
     double* __restrict__ b0) {
-  if (st && st->done) return;
-  __shared__ double red[kRThreads / 64][kMaxK];
   const int i = blockIdx.x;
+  if (st && st[sub_inst[i]].done) return;
+  __shared__ double red[kRThreads / 64][kMaxK];
   const int ki = kcnt[i];
   double acc[kMaxK];
 #pragma unroll
@@ -58,45 +61,57 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
 }
 
 // one wave per 64x64 float64 tile: row and column partials into per-tile slots
-__global__ void __launch_bounds__(256) k_coarse_symv(const CgState* st, const double* __restrict__ tiles,
-                                                     int ntiles, const double* __restrict__ x,
+__global__ void __launch_bounds__(256) k_coarse_symv(const CgState* st, const int32_t* __restrict__ tile_inst,
+                                                     const int64_t* __restrict__ tile_base,
+                                                     const int64_t* __restrict__ cblk_off,
+                                                     const double* __restrict__ tiles, int64_t ntiles,
+                                                     const double* __restrict__ x,
                                                      double* __restrict__ rowpart,
                                                      double* __restrict__ colpart) {
-  if (st && st->done) return;
   constexpr int T = 64;
   using G = TileGeom<double, T>;
   const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
+  const int b = tile_inst[t];
+  if (st && st[b].done) return;
   int I, J;
-  tile_ij(t, I, J);
+  tile_ij((int)(t - tile_base[b]), I, J);
   double m[G::SS];
-  load_subtile<double, T>(tiles + (int64_t)t * T * T, lane, m);
-  symv_tile_slots<double, double, T>(m, I, J, x, rowpart + (int64_t)t * T, colpart + (int64_t)t * T, lane, true);
+  load_subtile<double, T>(tiles + t * T * T, lane, m);
+  symv_tile_slots<double, double, T>(m, I, J, x + cblk_off[b], rowpart + t * T, colpart + t * T, lane, true);
 }
 
-__global__ void k_coarse_sum(const CgState* st, const double* __restrict__ rowpart,
-                             const double* __restrict__ colpart, int ntr, int64_t nc,
-                             double* __restrict__ y) {
-  if (st && st->done) return;
+// y over the padded coarse rows; trow_inst gives the system of each 64-row tile row
+__global__ void k_coarse_sum(const CgState* st, const int32_t* __restrict__ trow_inst,
+                             const int64_t* __restrict__ tile_base, const int64_t* __restrict__ cblk_off,
+                             const double* __restrict__ rowpart, const double* __restrict__ colpart,
+                             int64_t nc_pad, double* __restrict__ y) {
   constexpr int T = 64;
-  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nc) return;
-  const int I = (int)(row / T), rr = (int)(row % T);
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nc_pad) return;
+  const int b = trow_inst[row / T];
+  if (st && st[b].done) return;
+  const int64_t lr = row - cblk_off[b];
+  const int I = (int)(lr / T), rr = (int)(lr % T);
+  const int ntr = (int)((cblk_off[b + 1] - cblk_off[b]) / T);
+  const double* rp = rowpart + tile_base[b] * T;
+  const double* cp = colpart + tile_base[b] * T;
   double s = 0.0;
-  for (int J = 0; J <= I; ++J) s += rowpart[((int64_t)I * (I + 1) / 2 + J) * T + rr];
-  for (int J = I + 1; J < ntr; ++J) s += colpart[((int64_t)J * (J + 1) / 2 + I) * T + rr];
+  for (int J = 0; J <= I; ++J) s += rp[((int64_t)I * (I + 1) / 2 + J) * T + rr];
+  for (int J = I + 1; J < ntr; ++J) s += cp[((int64_t)J * (J + 1) / 2 + I) * T + rr];
   y[row] = s;
 }
 
-__global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ part,
+__global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ sub_inst,
+                                 const int32_t* __restrict__ part,
                                  const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
                                  const double* __restrict__ Q, int kq, const double* __restrict__ y,
                                  double* __restrict__ e, int64_t n) {
-  if (st && st->done) return;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int i = part[g];
+  if (st && st[sub_inst[i]].done) return;
   const int ki = kcnt[i];
   const double* yi = y + koff[i];
   const double* qg = Q + g * kq;
@@ -114,21 +129,22 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
   if (h.nc == 0) return;
   const Symbolic& S = h.S;
   DDG_REQUIRE(h.k <= kMaxK, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
-  double* b0 = h.cy.as<double>();             // padded to whole tiles, zero beyond nc
-  double* y = b0 + (int64_t)h.nc_tiles_rows * 64;
-  hipLaunchKernelGGL(k_coarse_restrict, dim3(S.n_parts), dim3(kRThreads), 0, s, st,
+  double* b0 = h.cy.as<double>();             // padded to whole tiles, zero beyond each block
+  double* y = b0 + h.nc_pad;
+  const int32_t* sub_inst = h.sub_inst.as<int32_t>();
+  hipLaunchKernelGGL(k_coarse_restrict, dim3(S.n_parts), dim3(kRThreads), 0, s, st, sub_inst,
                      h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
                      h.koff_d.as<int64_t>(), h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(),
                      h.col.as<int32_t>(), h.val.as<double>(), r, e, b0);
-  const int ntr = h.nc_tiles_rows;
-  const int ntiles = ntr * (ntr + 1) / 2;
   double* rowpart = h.cpart.as<double>();
-  double* colpart = rowpart + (int64_t)ntiles * 64;
-  hipLaunchKernelGGL(k_coarse_symv, dim3((ntiles + 3) / 4), dim3(256), 0, s, st,
-                     h.A0inv_t.as<double>(), ntiles, b0, rowpart, colpart);
-  hipLaunchKernelGGL(k_coarse_sum, dim3((unsigned)((h.nc + 255) / 256)), dim3(256), 0, s, st,
-                     rowpart, colpart, ntr, h.nc, y);
-  hipLaunchKernelGGL(k_coarse_prolong, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st,
+  double* colpart = rowpart + h.ntiles * 64;
+  hipLaunchKernelGGL(k_coarse_symv, dim3((unsigned)((h.ntiles + 3) / 4)), dim3(256), 0, s, st,
+                     h.tile_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
+                     h.A0inv_t.as<double>(), h.ntiles, b0, rowpart, colpart);
+  hipLaunchKernelGGL(k_coarse_sum, dim3((unsigned)((h.nc_pad + 255) / 256)), dim3(256), 0, s, st,
+                     h.trow_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
+                     rowpart, colpart, h.nc_pad, y);
+  hipLaunchKernelGGL(k_coarse_prolong, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st, sub_inst,
                      h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
                      h.Q.as<double>(), h.k, y, e, S.n);
   DDG_HIP(hipGetLastError());

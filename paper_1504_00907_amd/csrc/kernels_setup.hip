@@ -179,9 +179,14 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
     const int32_t* __restrict__ part, const int32_t* __restrict__ kcnt,
     const int64_t* __restrict__ koff, const double* __restrict__ Q, int kq,
     const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ val,
-    double* __restrict__ A0, int64_t nc) {
+    const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ cblk_off,
+    const int32_t* __restrict__ cblk_n, const int64_t* __restrict__ a0_off, double* __restrict__ A0) {
   __shared__ double lds[kGalLds / 8];
   const int i = blockIdx.x;
+  // the block row of subdomain i lies in the dense coarse block of its system
+  const int sys = sub_inst[i];
+  const int64_t c0 = cblk_off[sys], nc = cblk_n[sys];
+  double* A0b = A0 + a0_off[sys];
   const int64_t base = own_ptr[i];
   const int ni = (int)(own_ptr[i + 1] - base);
   const int nb0 = nbr_ptr[i];
@@ -244,7 +249,7 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
         const int a = (e / kq) % kq;
         const int b = e % kq;
         const int j = nbr_idx[nb0 + g0 + s];
-        if (a < ki && b < kcnt[j]) A0[(koff[i] + a) * nc + koff[j] + b] = acc[u];
+        if (a < ki && b < kcnt[j]) A0b[(koff[i] + a - c0) * nc + koff[j] + b - c0] = acc[u];
       }
     }
   }
@@ -531,12 +536,27 @@ __global__ void k_gather_vals(const int64_t* __restrict__ pos, const double* __r
 }
 
 // ---------------------------------------------------------------------------
-// Coarse inverse: blocked Gauss-Jordan over the whole device.
+// Coarse inverse: blocked Gauss-Jordan over the whole device, one dense block
+// per independent system (the last grid dimension selects the system).
 
 constexpr int kCNB = 64;
 
-__global__ void __launch_bounds__(256) k_cgj_pivot(double* __restrict__ A, int64_t N, int P0, int w,
-                                                   double* __restrict__ pinv, int32_t* err) {
+struct CoarseBlocks {
+  double* A;               // dense blocks
+  const int64_t* a0_off;   // element offset of each block
+  const int32_t* n;        // order of each block
+  double* pinv;            // per system kCNB x kCNB
+  double* Rbuf;            // per system kCNB x (order), at kCNB * cblk_off
+  const int64_t* cblk_off;
+};
+
+__global__ void __launch_bounds__(256) k_cgj_pivot(CoarseBlocks cb, int P0, int32_t* err) {
+  const int sys = blockIdx.x;
+  const int64_t N = cb.n[sys];
+  if (P0 >= N) return;
+  const int w = (int)min<int64_t>(kCNB, N - P0);
+  double* A = cb.A + cb.a0_off[sys];
+  double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
   __shared__ double piv[kCNB * (kCNB + 1)];
   for (int idx = threadIdx.x; idx < w * w; idx += 256)
     piv[(idx / w) * (kCNB + 1) + idx % w] = A[(int64_t)(P0 + idx / w) * N + P0 + idx % w];
@@ -544,7 +564,7 @@ __global__ void __launch_bounds__(256) k_cgj_pivot(double* __restrict__ A, int64
   for (int t = 0; t < w; ++t) {
     double d = piv[t * (kCNB + 1) + t];
     if (!(d > 0.0) || !isfinite(d)) {
-      if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, -1, -1, P0 + t);
+      if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, -1, sys, P0 + t);
       d = 1.0;
     }
     double nv[16];
@@ -571,8 +591,14 @@ __global__ void __launch_bounds__(256) k_cgj_pivot(double* __restrict__ A, int64
 }
 
 // row panel R = Pinv A[P, :] for columns outside P; written to Rbuf and in place
-__global__ void k_cgj_row(double* __restrict__ A, int64_t N, int P0, int w,
-                          const double* __restrict__ pinv, double* __restrict__ Rbuf) {
+__global__ void k_cgj_row(CoarseBlocks cb, int P0) {
+  const int sys = blockIdx.y;
+  const int64_t N = cb.n[sys];
+  if (P0 >= N) return;
+  const int w = (int)min<int64_t>(kCNB, N - P0);
+  double* A = cb.A + cb.a0_off[sys];
+  const double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
+  double* Rbuf = cb.Rbuf + kCNB * cb.cblk_off[sys];
   __shared__ double pv[kCNB * kCNB];
   for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) pv[idx] = pinv[idx];
   __syncthreads();
@@ -592,12 +618,17 @@ __global__ void k_cgj_row(double* __restrict__ A, int64_t N, int P0, int w,
 }
 
 // trailing update on 64 x 64 output tiles: A[i, c] -= A[i, P] R[P, c]
-__global__ void __launch_bounds__(256) k_cgj_update(double* __restrict__ A, int64_t N, int P0, int w,
-                                                    const double* __restrict__ Rbuf) {
+__global__ void __launch_bounds__(256) k_cgj_update(CoarseBlocks cb, int P0) {
+  const int sys = blockIdx.z;
+  const int64_t N = cb.n[sys];
+  const int64_t i0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  if (P0 >= N || i0 >= N || c0 >= N) return;
+  const int w = (int)min<int64_t>(kCNB, N - P0);
+  double* A = cb.A + cb.a0_off[sys];
+  const double* Rbuf = cb.Rbuf + kCNB * cb.cblk_off[sys];
   constexpr int UC = 32;
   __shared__ double cp[64][UC + 1];   // column panel rows of this tile
   __shared__ double rp[UC][64 + 1];   // row panel columns of this tile
-  const int64_t i0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
   const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
   double acc[4][4] = {};
   for (int u0 = 0; u0 < w; u0 += UC) {
@@ -639,7 +670,13 @@ __global__ void __launch_bounds__(256) k_cgj_update(double* __restrict__ A, int6
 }
 
 // column panel A[i, P] = -A[i, P] Pinv (rows outside P) and the pivot block itself
-__global__ void k_cgj_col(double* __restrict__ A, int64_t N, int P0, int w, const double* __restrict__ pinv) {
+__global__ void k_cgj_col(CoarseBlocks cb, int P0) {
+  const int sys = blockIdx.y;
+  const int64_t N = cb.n[sys];
+  if (P0 >= N) return;
+  const int w = (int)min<int64_t>(kCNB, N - P0);
+  double* A = cb.A + cb.a0_off[sys];
+  const double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
   __shared__ double pv[kCNB * kCNB];
   for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) pv[idx] = pinv[idx];
   __syncthreads();
@@ -661,20 +698,25 @@ __global__ void k_cgj_col(double* __restrict__ A, int64_t N, int P0, int w, cons
   }
 }
 
-__global__ void k_pack_coarse(const double* __restrict__ A, int64_t N, double* __restrict__ out, int ntr) {
+// tile t of the packed inverses (system tile_inst[t]); zero beyond the block's order
+__global__ void k_pack_coarse(const double* __restrict__ A, const int64_t* __restrict__ a0_off,
+                              const int32_t* __restrict__ nblk, const int32_t* __restrict__ tile_inst,
+                              const int64_t* __restrict__ tile_base, int64_t ntiles, double* __restrict__ out) {
   constexpr int T = 64;
-  const int64_t total = (int64_t)ntr * (ntr + 1) / 2 * T * T;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int t = (int)(idx / (T * T));
+  if (idx >= ntiles * T * T) return;
+  const int64_t t = idx / (T * T);
+  const int sys = tile_inst[t];
+  const int64_t N = nblk[sys];
+  const double* Ab = A + a0_off[sys];
   int rr, cc;
   tile_rc<double, T>((int)(idx % (T * T)), rr, cc);
   int I, J;
-  tile_ij(t, I, J);
+  tile_ij((int)(t - tile_base[sys]), I, J);
   const int64_t row = (int64_t)I * T + rr;
   const int64_t col = (int64_t)J * T + cc;
   double v = 0.0;
-  if (row < N && col < N) v = (row >= col) ? A[row * N + col] : A[col * N + row];
+  if (row < N && col < N) v = (row >= col) ? Ab[row * N + col] : Ab[col * N + row];
   out[idx] = v;
 }
 
@@ -748,38 +790,45 @@ void launch_coarse_basis(Handle& h, hipStream_t s) {
 
 void launch_galerkin(Handle& h, hipStream_t s) {
   const Symbolic& S = h.S;
-  DDG_HIP(hipMemsetAsync(h.A0.p, 0, (size_t)h.nc * h.nc * sizeof(double), s));
+  DDG_HIP(hipMemsetAsync(h.A0.p, 0, (size_t)h.a0_off[h.nb] * sizeof(double), s));
   hipLaunchKernelGGL(k_galerkin, dim3(S.n_parts), dim3(kGalThreads), 0, s, h.own_ptr.as<int64_t>(),
                      h.own_idx.as<int32_t>(), h.nbr_ptr.as<int32_t>(), h.nbr_idx.as<int32_t>(),
                      h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
                      h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(),
-                     h.val.as<double>(), h.A0.as<double>(), h.nc);
+                     h.val.as<double>(), h.sub_inst.as<int32_t>(), h.cblk_off_d.as<int64_t>(),
+                     h.cblk_n_d.as<int32_t>(), h.a0_off_d.as<int64_t>(), h.A0.as<double>());
   DDG_HIP(hipGetLastError());
 }
 
 void launch_coarse_invert(Handle& h, hipStream_t s) {
-  const int64_t N = h.nc;
+  const int64_t total = h.a0_off[h.nb];
+  int64_t nmax = 0;
+  for (int32_t b = 0; b < h.nb; ++b) nmax = std::max<int64_t>(nmax, h.cblk_n[b]);
   DevBuf work;
-  work.alloc(((size_t)kCNB * kCNB + (size_t)kCNB * N) * sizeof(double));
+  work.alloc(((size_t)kCNB * kCNB * h.nb + (size_t)kCNB * h.nc_pad) * sizeof(double));
   // the inverse is formed in a copy so that A0 stays available for export
   DevBuf inv;
-  inv.alloc((size_t)N * N * sizeof(double));
-  DDG_HIP(hipMemcpyAsync(inv.p, h.A0.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
-  double* A = inv.as<double>();
-  double* pinv = work.as<double>();
-  double* Rbuf = pinv + kCNB * kCNB;
-  const unsigned tiles = (unsigned)((N + 63) / 64);
-  for (int P0 = 0; P0 < N; P0 += kCNB) {
-    const int w = (int)std::min<int64_t>(kCNB, N - P0);
-    hipLaunchKernelGGL(k_cgj_pivot, dim3(1), dim3(256), 0, s, A, N, P0, w, pinv, h.err_flag.as<int32_t>());
-    hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((N + 127) / 128)), dim3(128), 0, s, A, N, P0, w, pinv, Rbuf);
-    hipLaunchKernelGGL(k_cgj_update, dim3(tiles, tiles), dim3(256), 0, s, A, N, P0, w, Rbuf);
-    hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((N + 127) / 128)), dim3(128), 0, s, A, N, P0, w, pinv);
+  inv.alloc((size_t)total * sizeof(double));
+  DDG_HIP(hipMemcpyAsync(inv.p, h.A0.p, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CoarseBlocks cb;
+  cb.A = inv.as<double>();
+  cb.a0_off = h.a0_off_d.as<int64_t>();
+  cb.n = h.cblk_n_d.as<int32_t>();
+  cb.pinv = work.as<double>();
+  cb.Rbuf = cb.pinv + (int64_t)kCNB * kCNB * h.nb;
+  cb.cblk_off = h.cblk_off_d.as<int64_t>();
+  const unsigned tiles = (unsigned)((nmax + 63) / 64);
+  const unsigned nb = (unsigned)h.nb;
+  for (int P0 = 0; P0 < nmax; P0 += kCNB) {
+    hipLaunchKernelGGL(k_cgj_pivot, dim3(nb), dim3(256), 0, s, cb, P0, h.err_flag.as<int32_t>());
+    hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((nmax + 127) / 128), nb), dim3(128), 0, s, cb, P0);
+    hipLaunchKernelGGL(k_cgj_update, dim3(tiles, tiles, nb), dim3(256), 0, s, cb, P0);
+    hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((nmax + 127) / 128), nb), dim3(128), 0, s, cb, P0);
   }
-  const int ntr = h.nc_tiles_rows;
-  const int64_t total = (int64_t)ntr * (ntr + 1) / 2 * 64 * 64;
-  hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, N,
-                     h.A0inv_t.as<double>(), ntr);
+  const int64_t elems = h.ntiles * 64 * 64;
+  hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, cb.A,
+                     h.a0_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.tile_inst.as<int32_t>(),
+                     h.tile_base_d.as<int64_t>(), h.ntiles, h.A0inv_t.as<double>());
   DDG_HIP(hipGetLastError());
   DDG_HIP(hipStreamSynchronize(s));
 }

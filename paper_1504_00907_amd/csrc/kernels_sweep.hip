@@ -51,7 +51,8 @@ struct SweepArgs {
   const double* r;
   double* e;
   const double* bres;  // local residuals of this colour's sets, indexed like set_idx
-  const CgState* st;
+  const CgState* st;         // per system; a subdomain is skipped once its system has stopped
+  const int32_t* sub_inst;   // system of each subdomain
   int32_t e_zero;
   int32_t ldp;      // per-wave partial row length (>= max padded block rows)
   double* xch;      // per subdomain: 2 * xch_ld values
@@ -130,7 +131,6 @@ constexpr int kCplRegs = 2;      // coupling slots per row held in registers (pe
 
 template <class FT, class AT, int T, int NW, int TPW>
 __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
-  if (a.st && a.st->done) return;
   using G = TileGeom<FT, T>;
   constexpr int NT = NW * 64;
   constexpr int TT = T * T;
@@ -150,6 +150,9 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   }
   if (p >= a.nsub) return;
   const int sub = a.subs[p];
+  // both workgroups of a pair read the same flag (stable during the launch), so
+  // they skip together and no handoff is left waiting
+  if (a.st && a.st[a.sub_inst[sub]].done) return;
   const int64_t s0 = a.set_ptr[sub];
   const int ni = (int)(a.set_ptr[sub + 1] - s0);
   const int ni_pad = (ni + 3) & ~3;
@@ -348,15 +351,16 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
 }
 
 // b = (r - A e) on the expanded sets of one colour, written in set order.
-__global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const int32_t* __restrict__ subs,
+__global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const int32_t* __restrict__ sub_inst,
+                                                        const int32_t* __restrict__ subs,
                                                         const int64_t* __restrict__ set_ptr,
                                                         const int32_t* __restrict__ set_idx,
                                                         const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                         const double* __restrict__ val, const double* __restrict__ r,
                                                         const double* __restrict__ e, int e_zero,
                                                         double* __restrict__ bres) {
-  if (st && st->done) return;
   const int sub = subs[blockIdx.y];
+  if (st && st[sub_inst[sub]].done) return;
   const int64_t s0 = set_ptr[sub];
   const int ni = (int)(set_ptr[sub + 1] - s0);
   const int j = blockIdx.x * 256 + threadIdx.x;
@@ -400,6 +404,7 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   a.e = e;
   a.bres = h.bres.as<double>();
   a.st = st;
+  a.sub_inst = h.sub_inst.as<int32_t>();
   a.e_zero = e_zero ? 1 : 0;
   const int maxpad = ((S.max_blk + T - 1) / T) * T;
   a.ldp = maxpad;
@@ -417,7 +422,7 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (residual) {
     hipLaunchKernelGGL(k_local_residual, dim3((unsigned)((S.max_set + 255) / 256), (unsigned)nsub), dim3(256), 0,
-                       s, st, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e, a.e_zero, h.bres.as<double>());
+                       s, st, a.sub_inst, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e, a.e_zero, h.bres.as<double>());
     DDG_HIP(hipGetLastError());
     return;
   }

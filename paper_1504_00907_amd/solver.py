@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DDGError, Info, Options, check
+from ._lib import DDGError, Info, Options, Problem, check
 
 
 def _ptr(a: np.ndarray):
@@ -25,6 +25,20 @@ def _dev(t: torch.Tensor, n: int, name: str) -> int:
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
         raise ValueError(f"{name} must be a contiguous float64 device tensor of length {n}")
     return t.data_ptr()
+
+
+def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream):
+    opt = Options()
+    lib.ddg_default_options(C.byref(opt))
+    opt.precision = _lib.PRECISION[precision]
+    opt.rtol = rtol
+    opt.max_iter = max_iter
+    opt.rank_tol = rank_tol
+    opt.tile = tile
+    opt.block_target = block_target
+    opt.check_every = check_every
+    opt.stream = C.c_void_p(stream.cuda_stream)
+    return opt
 
 
 class DDGSolver:
@@ -54,16 +68,7 @@ class DDGSolver:
         if Fh is not None and Fh.shape[0] != self.n:
             raise ValueError("F must have n rows")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opt = Options()
-        lib.ddg_default_options(C.byref(opt))
-        opt.precision = _lib.PRECISION[precision]
-        opt.rtol = rtol
-        opt.max_iter = max_iter
-        opt.rank_tol = rank_tol
-        opt.tile = tile
-        opt.block_target = block_target
-        opt.check_every = check_every
-        opt.stream = C.c_void_p(self.stream.cuda_stream)
+        opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
@@ -140,7 +145,7 @@ class DDGSolver:
         return a.reshape(m, m)
 
     def Q(self) -> np.ndarray:
-        return self.export(_lib.EXPORT_Q).reshape(self.n, self.k)
+        return self.export(_lib.EXPORT_Q).reshape(self.n, -1)
 
     def blocks(self) -> np.ndarray:
         return self.export(_lib.EXPORT_BLOCKS).reshape(-1, 3)
@@ -163,6 +168,72 @@ class DDGSolver:
             self.close()
         except Exception:
             pass
+
+
+class DDGBatchSolver(DDGSolver):
+    """Many independent systems in one handle (``ddg_setup_batched``).
+
+    ``problems`` is a sequence of (row_ptr, col_idx, val, F, part, n_parts)
+    with host arrays; device vectors are the concatenation of the systems'
+    vectors (``row_off`` gives the offsets).
+    """
+
+    def __init__(self, problems, overlap: int, precision: str = "fp64", rtol: float = 1e-8,
+                 max_iter: int = 1000, rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0,
+                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None):
+        lib = _lib.load()
+        self._lib = lib
+        keep = []
+        arr = (Problem * len(problems))()
+        for b, (rp, ci, vv, F, pp, nparts) in enumerate(problems):
+            rp = np.ascontiguousarray(rp, dtype=np.int64)
+            ci = np.ascontiguousarray(ci, dtype=np.int32)
+            vv = np.ascontiguousarray(vv, dtype=np.float64)
+            pp = np.ascontiguousarray(pp, dtype=np.int32)
+            Fh = np.asfortranarray(F, dtype=np.float64) if F is not None and F.size else None
+            n = rp.shape[0] - 1
+            if ci.shape[0] != rp[-1] or vv.shape[0] != rp[-1] or pp.shape[0] != n:
+                raise ValueError(f"system {b}: inconsistent array lengths")
+            if Fh is not None and Fh.shape[0] != n:
+                raise ValueError(f"system {b}: F must have n rows")
+            keep += [rp, ci, vv, pp, Fh]
+            arr[b].n = n
+            arr[b].row_ptr = rp.ctypes.data
+            arr[b].col_idx = ci.ctypes.data
+            arr[b].val = vv.ctypes.data
+            arr[b].k = 0 if Fh is None else Fh.shape[1]
+            arr[b].F = None if Fh is None else Fh.ctypes.data
+            arr[b].part = pp.ctypes.data
+            arr[b].n_parts = int(nparts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream)
+        self.precision = precision
+        h = C.c_void_p()
+        check(lib.ddg_setup_batched(C.byref(h), len(problems), arr, int(overlap), C.byref(opt)))
+        del keep
+        self._h = h
+        nb = C.c_int32()
+        check(lib.ddg_batch_layout(h, C.byref(nb), None, None))
+        self.nb = nb.value
+        self.row_off = np.zeros(self.nb + 1, dtype=np.int64)
+        self.sub_off = np.zeros(self.nb + 1, dtype=np.int32)
+        check(lib.ddg_batch_layout(h, None, _ptr(self.row_off), _ptr(self.sub_off)))
+        self.n = int(self.row_off[-1])
+        self.nnz = int(sum(int(np.asarray(p[0])[-1]) for p in problems))
+        self.k = max((0 if p[3] is None else np.asarray(p[3]).shape[1]) for p in problems)
+
+    def solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None, raise_on_error: bool = True):
+        """Solve all systems; returns (u, [info per system])."""
+        if u is None:
+            u = torch.empty_like(f)
+        infos = (Info * self.nb)()
+        rc = self._lib.ddg_solve_batched(self._h, _dev(f, self.n, "f"), _dev(u, self.n, "u"), infos)
+        if rc != 0 and raise_on_error:
+            check(rc)
+        return u, [i.as_dict() for i in infos]
+
+    def split(self, x: torch.Tensor):
+        return [x[self.row_off[b]:self.row_off[b + 1]] for b in range(self.nb)]
 
 
 def stencil_assemble(dims, theta: torch.Tensor, val: torch.Tensor, stream=None):
