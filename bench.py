@@ -127,6 +127,93 @@ def cpu_baseline(P, iters: int, n_sample: int = 24, seed: int = 5):
     }
 
 
+def _batch_instance(arg):
+    """Host arrays of one system of the batched workload (runs in a worker process)."""
+    from workloads import cfg4_instance
+    i, L = arg
+    P = cfg4_instance(i, int(L))
+    return (P.A.row_ptr, P.A.col_idx, P.A.val, np.asfortranarray(P.F), P.part, P.n_parts), P.f
+
+
+def batched(count: int, precision: str, steps: int, warmup: int):
+    """Batched leg: `count` independent 2D diffusion systems in one handle.
+
+    Side lengths L ~ U{128..512} (seeded), L x L cells, kappa = exp(z) with z
+    iid N(0, 1) per cell, f ~ U(-1, 1); near-equal boxes of about 32^2 cells
+    (m = round(L/32) per axis), overlap 2, p = 3 (10 monomials), rtol 1e-8.
+    The launch shape (tile edge, level merge target) comes from the library's
+    autotuner on a sample of the batch.  Reports solves/s over the whole batch
+    and the per-system device time to convergence (p50/p99).
+    """
+    import multiprocessing as mp
+
+    import torch
+
+    from paper_1504_00907_amd import DDGBatchSolver, tune_batched
+    from workloads import cfg4_sides
+
+    sides = cfg4_sides(count)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        res = pool.map(_batch_instance, list(enumerate(sides)), chunksize=4)
+    probs = [r[0] for r in res]
+    f = torch.from_numpy(np.concatenate([r[1] for r in res])).cuda()
+    del res
+    gen_s = time.perf_counter() - t0
+    log(f"batched: {count} systems, n = {f.numel()}, generated in {gen_s:.1f} s")
+    t0 = time.perf_counter()
+    tile, bt, cands = tune_batched(probs, 2, precision, max_sample=0)
+    tune_s = time.perf_counter() - t0
+    log(f"batched: autotuner chose tile {tile}, block_target {bt} in {tune_s:.1f} s")
+    t0 = time.perf_counter()
+    b = DDGBatchSolver(probs, 2, precision=precision, rtol=1e-8, tile=tile, block_target=bt)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = b.info()
+    del probs
+    log(f"batched: setup {setup_s:.1f} s (device numeric {info['setup_ms']:.0f} ms)")
+    u = torch.empty_like(f)
+    for _ in range(warmup):
+        b.solve(f, u)
+    torch.cuda.synchronize()
+    b.profile_enable(True)
+    b.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, infos = b.solve(f, u)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = b.profile_read(reset=True)
+    b.profile_enable(False)
+    sweep_gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    per = np.array([i["solve_ms"] for i in infos])
+    its = np.array([i["iters"] for i in infos])
+    tres = np.array([i["true_rel_res"] for i in infos])
+    ok = all(i["status"] == 0 for i in infos)
+    b.close()
+    log(f"batched: {ms:.1f} ms per batch solve, {count * 1e3 / ms:.1f} solves/s, iters {its.min()}..{its.max()}, "
+        f"sweep kernel {sweep_gbs:.0f} GB/s")
+    return {
+        "workload": f"batch{count}_diffusion2d_L128-512_kappa_lognormal",
+        "systems": count, "n_total": int(f.numel()), "subdomains": int(info["n_parts"]), "overlap": 2, "p": 3,
+        "precision": precision, "rtol": 1e-8, "steps": steps,
+        "ms_per_batch": ms, "solves_per_s": count * 1e3 / ms,
+        "solves_per_s_incl_setup": count / (ms * 1e-3 + setup_s),
+        "system_ms_p50": float(np.percentile(per, 50)), "system_ms_p99": float(np.percentile(per, 99)),
+        "iters_min": int(its.min()), "iters_median": float(np.median(its)), "iters_max": int(its.max()),
+        "max_true_rel_res": float(tres.max()), "all_converged": ok,
+        "setup_s": setup_s, "setup_ms_device": info["setup_ms"], "generate_s": gen_s,
+        "tuned": {"tile": tile, "block_target": bt, "tune_s": tune_s,
+                  "candidates": [{"tile": c[0], "block_target": c[1], "precond_ms": c[2], "factor_bytes": c[3]}
+                                 for c in cands]},
+        "factor_bytes": info["factor_bytes"], "iter_bytes": info["iter_bytes"],
+        "sweep_kernel": {"achieved_GBps": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
+                         "launches": prof["launches"],
+                         "avg_launch_us": prof["ms"] * 1e3 / prof["launches"] if prof["launches"] else None,
+                         "share_of_solve": prof["ms"] / (ms * steps)},
+    }
+
+
 def fwd_adjoint(side: int, precision: str, steps: int, warmup: int):
     """Forward + adjoint pairs per second on the differentiation workload.
 
@@ -203,6 +290,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint (differentiation) leg")
     ap.add_argument("--adjoint-side", type=int, default=96)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg (256 uneven 2D systems)")
+    ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -292,6 +381,11 @@ def main():
         s64.close()
         del s64
 
+    bat = None
+    if not args.no_batch:
+        bat = batched(args.batch_count, args.precision, max(1, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+
     adj = None
     if not args.no_adjoint:
         adj = fwd_adjoint(args.adjoint_side, args.precision, max(1, args.steps // 2), 1)
@@ -343,6 +437,7 @@ def main():
         "whole_solve_GBps": round(whole, 1),
         **out64,
         "fwd_adjoint": adj,
+        "batched": bat,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

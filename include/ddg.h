@@ -163,6 +163,33 @@ int ddg_setup_batched(ddg_handle* out, int32_t nb, const ddg_problem* probs, int
  */
 int ddg_solve_batched(ddg_handle h, const double* f_dev, double* u_dev, ddg_info* infos);
 
+/* One measured candidate of ddg_tune_batched. */
+typedef struct {
+  int32_t tile;           /* tile edge of the local factors (16, 32, 64) */
+  int32_t block_target;   /* level merge target (0 = merge only levels under 16 rows) */
+  double precond_ms;      /* mean preconditioner application on the sample; -1 if the shape does not fit */
+  int64_t factor_bytes;   /* local factor storage on the sample */
+} ddg_tune_entry;
+
+/*
+ * Autotuner for the launch shape of the local solves (an implementation
+ * choice; the method is unchanged).  Sets up a sample of the batch
+ * (max_sample systems spread evenly over the size order; 0 = enough systems
+ * for about 4096 subdomains, or all of them) for every
+ * candidate tile edge {16, 32, 64} x level merge target {0, 64, 128}, times
+ * preconditioner applications with HIP events, and writes *best = *base
+ * (NULL = defaults) with the fastest tile and block_target.  report (may be
+ * NULL) receives up to report_cap candidates, *n_report their count.
+ * cache_path (may be NULL) is a text file of "key tile block_target ms" lines
+ * keyed by the batch's shape, precision and device: a hit returns without
+ * measuring (report then stays empty), a miss appends the result.
+ * Uses the device and the default stream of base.  Errors: INVALID_ARG,
+ * UNSUPPORTED (no candidate fits), and those of ddg_setup_batched.
+ */
+int ddg_tune_batched(int32_t nb, const ddg_problem* probs, int32_t overlap, const ddg_options* base,
+                     int32_t max_sample, const char* cache_path, ddg_options* best, ddg_tune_entry* report,
+                     int32_t report_cap, int32_t* n_report);
+
 /* Batch layout: *nb, row_off[nb+1] (first row of each system), sub_off[nb+1]
  * (first subdomain).  Any output pointer may be NULL. */
 int ddg_batch_layout(ddg_handle h, int32_t* nb, int64_t* row_off, int32_t* sub_off);

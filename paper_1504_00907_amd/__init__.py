@@ -9,7 +9,7 @@ from ._lib import DDGError  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("DDGSolver", "DDGBatchSolver", "stencil_assemble", "stencil_coeff_grad"):
+    if name in ("DDGSolver", "DDGBatchSolver", "tune_batched", "stencil_assemble", "stencil_coeff_grad"):
         from . import solver
         return getattr(solver, name)
     if name in ("DDGSolveFunction", "ddg_solve_fn", "DiffusionSolver"):

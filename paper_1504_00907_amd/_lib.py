@@ -52,6 +52,11 @@ class Problem(C.Structure):
     ]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("block_target", C.c_int32), ("precond_ms", C.c_double),
+                ("factor_bytes", C.c_int64)]
+
+
 class DDGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -71,6 +76,9 @@ _SIGS = [
     ("ddg_setup_batched", C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Problem), C.c_int32,
                                     C.POINTER(Options)]),
     ("ddg_solve_batched", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Info)]),
+    ("ddg_tune_batched", C.c_int, [C.c_int32, C.POINTER(Problem), C.c_int32, C.POINTER(Options), C.c_int32,
+                                   C.c_char_p, C.POINTER(Options), C.POINTER(TuneEntry), C.c_int32,
+                                   C.POINTER(C.c_int32)]),
     ("ddg_batch_layout", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]),
     ("ddg_apply_precond", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ddg_apply_precond_stages", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),

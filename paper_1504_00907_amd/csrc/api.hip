@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <fstream>
 #include <memory>
 
 #include "common.hpp"
@@ -317,6 +319,185 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->info.n_blocks = (int32_t)S.blk_size.size();
 }
 
+// One block-diagonal system from the listed systems: rows, columns and
+// subdomain ids shifted per system; generating vectors padded with zero
+// columns up to the largest k (the rank rule drops them).
+void setup_batch(Handle& h, const std::vector<const ddg_problem*>& probs, int32_t overlap) {
+  const int32_t nb = (int32_t)probs.size();
+  std::vector<int64_t> seg_off(nb + 1, 0);
+  std::vector<int32_t> sub_off(nb + 1, 0);
+  int64_t nnz = 0;
+  int32_t kmax = 0;
+  for (int32_t b = 0; b < nb; ++b) {
+    const ddg_problem& P = *probs[b];
+    DDG_REQUIRE(P.n > 0 && P.row_ptr && P.col_idx && P.val && P.part && P.n_parts > 0, DDG_ERR_INVALID_ARG,
+                "system " + std::to_string(b) + ": null argument or empty");
+    DDG_REQUIRE(P.k >= 0 && (P.k == 0 || P.F), DDG_ERR_INVALID_ARG,
+                "system " + std::to_string(b) + ": k must be >= 0 and F given when k > 0");
+    DDG_REQUIRE(P.row_ptr[0] == 0 && P.row_ptr[P.n] >= P.n, DDG_ERR_INVALID_ARG,
+                "system " + std::to_string(b) + ": bad row pointers");
+    seg_off[b + 1] = seg_off[b] + P.n;
+    sub_off[b + 1] = sub_off[b] + P.n_parts;
+    nnz += P.row_ptr[P.n];
+    kmax = std::max(kmax, P.k);
+  }
+  const int64_t n = seg_off[nb];
+  DDG_REQUIRE(n < INT32_MAX, DDG_ERR_UNSUPPORTED, "batch exceeds 2^31 - 1 rows");
+  std::vector<int64_t> rp(n + 1, 0);
+  std::vector<int32_t> ci((size_t)nnz);
+  std::vector<double> vv((size_t)nnz);
+  std::vector<int32_t> pp((size_t)n);
+  std::vector<double> Fc((size_t)n * kmax, 0.0);
+  for (int32_t b = 0; b < nb; ++b) {
+    const ddg_problem& P = *probs[b];
+    const int64_t r0 = seg_off[b], e0 = rp[r0];
+    for (int64_t i = 0; i < P.n; ++i) {
+      rp[r0 + i + 1] = e0 + P.row_ptr[i + 1];
+      const int32_t pi = P.part[i];
+      DDG_REQUIRE(pi >= 0 && pi < P.n_parts, DDG_ERR_INVALID_ARG,
+                  "system " + std::to_string(b) + ": partition id out of range");
+      pp[r0 + i] = pi + sub_off[b];
+    }
+    for (int64_t t = 0; t < P.row_ptr[P.n]; ++t) {
+      const int32_t c = P.col_idx[t];
+      DDG_REQUIRE(c >= 0 && c < P.n, DDG_ERR_INVALID_ARG, "system " + std::to_string(b) + ": column out of range");
+      ci[e0 + t] = (int32_t)(c + r0);
+      vv[e0 + t] = P.val[t];
+    }
+    for (int32_t m = 0; m < P.k; ++m)
+      for (int64_t i = 0; i < P.n; ++i) Fc[(size_t)m * n + r0 + i] = P.F[(size_t)m * P.n + i];
+  }
+  setup_impl(h, n, rp.data(), ci.data(), vv.data(), kmax, kmax ? Fc.data() : nullptr, pp.data(), sub_off[nb],
+             overlap, seg_off, sub_off);
+}
+
+// Autotuner of the local-solve launch shape.  Candidates: tile edge T in
+// {16, 32, 64} x level merge target in {0 (merge only levels under 16 rows),
+// 64, 128}.  Each candidate is set up on a sample of the batch (max_sample
+// systems spread evenly over the size order; by default enough for about 4096
+// subdomains, so that the launches are as full as the whole batch's) and
+// timed over preconditioner applications with HIP events; the fastest is
+// returned.  Results are cached by a key of the batch's shape in a text file.
+std::string tune_key(int32_t nb, const ddg_problem* probs, int32_t overlap, const ddg_options& o) {
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      hsh ^= (v >> (8 * i)) & 0xff;
+      hsh *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)nb);
+  for (int32_t b = 0; b < nb; ++b) {
+    mix((uint64_t)probs[b].n);
+    mix((uint64_t)probs[b].row_ptr[probs[b].n]);
+    mix((uint64_t)probs[b].k);
+    mix((uint64_t)probs[b].n_parts);
+  }
+  mix((uint64_t)overlap);
+  mix((uint64_t)o.precision);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    for (const char* c = prop.gcnArchName; *c; ++c) mix((uint64_t)(unsigned char)*c);
+  char buf[17];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)hsh);
+  return buf;
+}
+
+void tune_batch(int32_t nb, const ddg_problem* probs, int32_t overlap, const ddg_options& base, int32_t max_sample,
+                const char* cache_path, ddg_options& best, ddg_tune_entry* report, int32_t report_cap,
+                int32_t* n_report) {
+  best = base;
+  const std::string key = tune_key(nb, probs, overlap, base);
+  if (n_report) *n_report = 0;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string k;
+    int32_t t, bt;
+    double ms;
+    while (in >> k >> t >> bt >> ms) {
+      if (k == key) {
+        best.tile = t;
+        best.block_target = bt;
+        return;
+      }
+    }
+  }
+  // sample: systems at evenly spaced positions of the size order
+  std::vector<int32_t> order(nb);
+  for (int32_t b = 0; b < nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return probs[a].n < probs[c].n; });
+  // default sample size: enough systems for about 4096 subdomains (a colour's launch then
+  // has as many workgroups as the full batch would keep resident), all if fewer
+  int32_t ns = max_sample;
+  if (ns <= 0) {
+    int64_t parts = 0;
+    for (int32_t b = 0; b < nb; ++b) parts += probs[b].n_parts;
+    const double avg = (double)parts / nb;
+    ns = (int32_t)std::ceil(4096.0 / std::max(1.0, avg));
+  }
+  ns = std::max(1, std::min(ns, nb));
+  std::vector<const ddg_problem*> sample;
+  for (int32_t q = 0; q < ns; ++q) {
+    const int32_t pos = ns == 1 ? nb - 1 : (int32_t)((int64_t)q * (nb - 1) / (ns - 1));
+    if (sample.empty() || sample.back() != probs + order[pos]) sample.push_back(probs + order[pos]);
+  }
+  const int32_t tiles[3] = {16, 32, 64};
+  const int32_t targets[3] = {0, 64, 128};
+  double best_ms = -1.0;
+  int32_t cnt = 0;
+  for (int32_t T : tiles) {
+    for (int32_t bt : targets) {
+      double ms = -1.0;
+      int64_t fbytes = 0;
+      try {
+        Handle h;
+        h.opt = base;
+        h.opt.tile = T;
+        h.opt.block_target = bt;
+        setup_batch(h, sample, overlap);
+        fbytes = h.info.factor_bytes;
+        const int64_t n = h.S.n;
+        DevBuf r, z;
+        r.alloc((size_t)n * sizeof(double));
+        z.alloc((size_t)n * sizeof(double));
+        launch_fill(r.as<double>(), 1.0, n, h.stream);
+        launch_precond(h, r.as<double>(), z.as<double>(), -1, false, h.stream);
+        hipEvent_t e0, e1;
+        DDG_HIP(hipEventCreate(&e0));
+        DDG_HIP(hipEventCreate(&e1));
+        const int reps = 5;
+        DDG_HIP(hipEventRecord(e0, h.stream));
+        for (int t = 0; t < reps; ++t) launch_precond(h, r.as<double>(), z.as<double>(), -1, false, h.stream);
+        DDG_HIP(hipEventRecord(e1, h.stream));
+        DDG_HIP(hipEventSynchronize(e1));
+        float f = 0.f;
+        DDG_HIP(hipEventElapsedTime(&f, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        check_err_flag(h, "tuning");
+        ms = f / reps;
+        DDG_HIP(hipStreamSynchronize(h.stream));
+      } catch (const Error& e) {
+        if (e.code != DDG_ERR_UNSUPPORTED) throw;  // a candidate the shapes cannot use is skipped
+      }
+      if (report && cnt < report_cap) report[cnt] = ddg_tune_entry{T, bt, ms, fbytes};
+      ++cnt;
+      if (ms >= 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+        best_ms = ms;
+        best.tile = T;
+        best.block_target = bt;
+      }
+    }
+  }
+  if (n_report) *n_report = std::min(cnt, report_cap);
+  DDG_REQUIRE(best_ms >= 0.0, DDG_ERR_UNSUPPORTED, "no launch shape fits the local problems");
+  if (cache_path) {
+    std::ofstream outf(cache_path, std::ios::app);
+    outf << key << ' ' << best.tile << ' ' << best.block_target << ' ' << best_ms << '\n';
+  }
+}
+
 Handle* H(ddg_handle p) { return reinterpret_cast<Handle*>(p); }
 
 template <class Fn>
@@ -384,61 +565,28 @@ int ddg_setup_batched(ddg_handle* out, int32_t nb, const ddg_problem* probs, int
   Handle* hp = nullptr;
   int rc = guarded([&]() {
     DDG_REQUIRE(out && probs && nb >= 1, DDG_ERR_INVALID_ARG, "null argument or empty batch");
-    std::vector<int64_t> seg_off(nb + 1, 0);
-    std::vector<int32_t> sub_off(nb + 1, 0);
-    int64_t nnz = 0;
-    int32_t kmax = 0;
-    for (int32_t b = 0; b < nb; ++b) {
-      const ddg_problem& P = probs[b];
-      DDG_REQUIRE(P.n > 0 && P.row_ptr && P.col_idx && P.val && P.part && P.n_parts > 0, DDG_ERR_INVALID_ARG,
-                  "system " + std::to_string(b) + ": null argument or empty");
-      DDG_REQUIRE(P.k >= 0 && (P.k == 0 || P.F), DDG_ERR_INVALID_ARG,
-                  "system " + std::to_string(b) + ": k must be >= 0 and F given when k > 0");
-      DDG_REQUIRE(P.row_ptr[0] == 0 && P.row_ptr[P.n] >= P.n, DDG_ERR_INVALID_ARG,
-                  "system " + std::to_string(b) + ": bad row pointers");
-      seg_off[b + 1] = seg_off[b] + P.n;
-      sub_off[b + 1] = sub_off[b] + P.n_parts;
-      nnz += P.row_ptr[P.n];
-      kmax = std::max(kmax, P.k);
-    }
-    const int64_t n = seg_off[nb];
-    DDG_REQUIRE(n < INT32_MAX, DDG_ERR_UNSUPPORTED, "batch exceeds 2^31 rows");
-    // one block-diagonal system: rows, columns and subdomain ids shifted per system;
-    // generating vectors padded with zero columns up to the largest k (dropped by the rank rule)
-    std::vector<int64_t> rp(n + 1, 0);
-    std::vector<int32_t> ci((size_t)nnz);
-    std::vector<double> vv((size_t)nnz);
-    std::vector<int32_t> pp((size_t)n);
-    std::vector<double> Fc((size_t)n * kmax, 0.0);
-    for (int32_t b = 0; b < nb; ++b) {
-      const ddg_problem& P = probs[b];
-      const int64_t r0 = seg_off[b], e0 = rp[r0];
-      for (int64_t i = 0; i < P.n; ++i) {
-        rp[r0 + i + 1] = e0 + P.row_ptr[i + 1];
-        const int32_t pi = P.part[i];
-        DDG_REQUIRE(pi >= 0 && pi < P.n_parts, DDG_ERR_INVALID_ARG,
-                    "system " + std::to_string(b) + ": partition id out of range");
-        pp[r0 + i] = pi + sub_off[b];
-      }
-      for (int64_t t = 0; t < P.row_ptr[P.n]; ++t) {
-        const int32_t c = P.col_idx[t];
-        DDG_REQUIRE(c >= 0 && c < P.n, DDG_ERR_INVALID_ARG, "system " + std::to_string(b) + ": column out of range");
-        ci[e0 + t] = (int32_t)(c + r0);
-        vv[e0 + t] = P.val[t];
-      }
-      for (int32_t m = 0; m < P.k; ++m)
-        for (int64_t i = 0; i < P.n; ++i) Fc[(size_t)m * n + r0 + i] = P.F[(size_t)m * P.n + i];
-    }
+    std::vector<const ddg_problem*> list(nb);
+    for (int32_t b = 0; b < nb; ++b) list[b] = probs + b;
     auto h = std::make_unique<Handle>();
     if (opt) h->opt = *opt;
     else ddg_default_options(&h->opt);
-    int32_t parts = sub_off[nb];
-    setup_impl(*h, n, rp.data(), ci.data(), vv.data(), kmax, kmax ? Fc.data() : nullptr, pp.data(), parts, overlap,
-               seg_off, sub_off);
+    setup_batch(*h, list, overlap);
     hp = h.release();
   });
   if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
   return rc;
+}
+
+int ddg_tune_batched(int32_t nb, const ddg_problem* probs, int32_t overlap, const ddg_options* base,
+                     int32_t max_sample, const char* cache_path, ddg_options* best, ddg_tune_entry* report,
+                     int32_t report_cap, int32_t* n_report) {
+  return guarded([&]() {
+    DDG_REQUIRE(probs && nb >= 1 && best, DDG_ERR_INVALID_ARG, "null argument or empty batch");
+    ddg_options b0;
+    if (base) b0 = *base;
+    else ddg_default_options(&b0);
+    tune_batch(nb, probs, overlap, b0, max_sample, cache_path, *best, report, report_cap, n_report);
+  });
 }
 
 int ddg_analyze(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* part,

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DDGError, Info, Options, Problem, check
+from ._lib import DDGError, Info, Options, Problem, TuneEntry, check
 
 
 def _ptr(a: np.ndarray):
@@ -170,6 +170,56 @@ class DDGSolver:
             pass
 
 
+def _problem_array(problems):
+    """ctypes array of ddg_problem plus the host arrays it points into (keep them alive)."""
+    keep = []
+    arr = (Problem * len(problems))()
+    for b, (rp, ci, vv, F, pp, nparts) in enumerate(problems):
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        ci = np.ascontiguousarray(ci, dtype=np.int32)
+        vv = np.ascontiguousarray(vv, dtype=np.float64)
+        pp = np.ascontiguousarray(pp, dtype=np.int32)
+        Fh = np.asfortranarray(F, dtype=np.float64) if F is not None and F.size else None
+        n = rp.shape[0] - 1
+        if ci.shape[0] != rp[-1] or vv.shape[0] != rp[-1] or pp.shape[0] != n:
+            raise ValueError(f"system {b}: inconsistent array lengths")
+        if Fh is not None and Fh.shape[0] != n:
+            raise ValueError(f"system {b}: F must have n rows")
+        keep += [rp, ci, vv, pp, Fh]
+        arr[b].n = n
+        arr[b].row_ptr = rp.ctypes.data
+        arr[b].col_idx = ci.ctypes.data
+        arr[b].val = vv.ctypes.data
+        arr[b].k = 0 if Fh is None else Fh.shape[1]
+        arr[b].F = None if Fh is None else Fh.ctypes.data
+        arr[b].part = pp.ctypes.data
+        arr[b].n_parts = int(nparts)
+    return arr, keep
+
+
+def tune_batched(problems, overlap: int, precision: str = "fp64", max_sample: int = 8,
+                 cache: Optional[str] = None, stream: Optional[torch.cuda.Stream] = None):
+    """Pick (tile, block_target) for a batch with the library's autotuner.
+
+    Returns (tile, block_target, candidates) where candidates lists the
+    measured (tile, block_target, precond_ms, factor_bytes) -- empty on a
+    cache hit.
+    """
+    lib = _lib.load()
+    arr, keep = _problem_array(problems)
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    base = _options(lib, precision, 1e-8, 1000, 1e-10, 0, 0, 4, stream)
+    best = Options()
+    rep = (TuneEntry * 16)()
+    nrep = C.c_int32()
+    path = cache.encode() if cache else None
+    check(lib.ddg_tune_batched(len(problems), arr, int(overlap), C.byref(base), int(max_sample), path,
+                               C.byref(best), rep, 16, C.byref(nrep)))
+    del keep
+    cands = [(rep[i].tile, rep[i].block_target, rep[i].precond_ms, rep[i].factor_bytes) for i in range(nrep.value)]
+    return best.tile, best.block_target, cands
+
+
 class DDGBatchSolver(DDGSolver):
     """Many independent systems in one handle (``ddg_setup_batched``).
 
@@ -183,28 +233,7 @@ class DDGBatchSolver(DDGSolver):
                  check_every: int = 4, stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
         self._lib = lib
-        keep = []
-        arr = (Problem * len(problems))()
-        for b, (rp, ci, vv, F, pp, nparts) in enumerate(problems):
-            rp = np.ascontiguousarray(rp, dtype=np.int64)
-            ci = np.ascontiguousarray(ci, dtype=np.int32)
-            vv = np.ascontiguousarray(vv, dtype=np.float64)
-            pp = np.ascontiguousarray(pp, dtype=np.int32)
-            Fh = np.asfortranarray(F, dtype=np.float64) if F is not None and F.size else None
-            n = rp.shape[0] - 1
-            if ci.shape[0] != rp[-1] or vv.shape[0] != rp[-1] or pp.shape[0] != n:
-                raise ValueError(f"system {b}: inconsistent array lengths")
-            if Fh is not None and Fh.shape[0] != n:
-                raise ValueError(f"system {b}: F must have n rows")
-            keep += [rp, ci, vv, pp, Fh]
-            arr[b].n = n
-            arr[b].row_ptr = rp.ctypes.data
-            arr[b].col_idx = ci.ctypes.data
-            arr[b].val = vv.ctypes.data
-            arr[b].k = 0 if Fh is None else Fh.shape[1]
-            arr[b].F = None if Fh is None else Fh.ctypes.data
-            arr[b].part = pp.ctypes.data
-            arr[b].n_parts = int(nparts)
+        arr, keep = _problem_array(problems)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream)
         self.precision = precision

@@ -173,3 +173,26 @@ def test_systems_stop_independently():
     with pytest.raises(DDGError):
         b.solve(dev(np.concatenate([P.f for P in Ps])))
     b.close()
+
+
+def test_autotuner_picks_a_measured_shape(tmp_path):
+    from paper_1504_00907_amd import DDGBatchSolver, tune_batched
+    Ps, Os = systems()
+    probs = [(P.A.row_ptr, P.A.col_idx, P.A.val, P.F, P.part, P.n_parts) for P in Ps]
+    cache = str(tmp_path / "tune.txt")
+    tile, bt, cands = tune_batched(probs, 2, "fp32", max_sample=4, cache=cache)
+    say(f"   tuner: tile {tile} block_target {bt}; candidates {cands}")
+    assert len(cands) == 9
+    timed = [c for c in cands if c[2] >= 0]
+    assert timed and min(timed, key=lambda c: c[2])[:2] == (tile, bt)
+    # a cache hit returns the same choice without measuring
+    tile2, bt2, cands2 = tune_batched(probs, 2, "fp32", max_sample=4, cache=cache)
+    assert (tile2, bt2) == (tile, bt) and cands2 == []
+    # the chosen shape solves the batch like the default one
+    b = DDGBatchSolver(probs, 2, precision="fp32", rtol=1e-8, tile=tile, block_target=bt)
+    u, infos = b.solve(dev(np.concatenate([P.f for P in Ps])))
+    u = host(u)
+    for i, P in enumerate(Ps):
+        ui = u[b.row_off[i]:b.row_off[i + 1]]
+        assert np.linalg.norm(P.f - P.A.to_scipy() @ ui) <= 1.5e-8 * np.linalg.norm(P.f)
+    b.close()

@@ -166,9 +166,7 @@ def diffusion_cc(kappa: np.ndarray) -> CSR:
     kappa = np.asarray(kappa, dtype=np.float64)
     shape = kappa.shape
     n = kappa.size
-    idx = np.arange(n).reshape(shape)
     diag = np.zeros(shape)
-    rows, cols, vals = [], [], []
     for ax in range(kappa.ndim):
         m = shape[ax]
         sl_l = [slice(None)] * kappa.ndim
@@ -180,10 +178,6 @@ def diffusion_cc(kappa: np.ndarray) -> CSR:
         a = 2.0 * kl * kr / (kl + kr)
         diag[tuple(sl_l)] += a
         diag[tuple(sl_r)] += a
-        il = idx[tuple(sl_l)].ravel()
-        ir = idx[tuple(sl_r)].ravel()
-        av = a.ravel()
-        rows += [il, ir]; cols += [ir, il]; vals += [-av, -av]
         # ghost faces on both ends of this axis
         lo = [slice(None)] * kappa.ndim
         hi = [slice(None)] * kappa.ndim
@@ -191,10 +185,44 @@ def diffusion_cc(kappa: np.ndarray) -> CSR:
         hi[ax] = m - 1
         diag[tuple(lo)] += 2.0 * kappa[tuple(lo)]
         diag[tuple(hi)] += 2.0 * kappa[tuple(hi)]
-    rows.append(idx.ravel()); cols.append(idx.ravel()); vals.append(diag.ravel())
-    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                      shape=(n, n))
-    return CSR.from_scipy(A)
+    # CSR rows directly, columns ascending: minus-neighbours along axes 0..d-1
+    # (largest stride first), the diagonal, then plus-neighbours along d-1..0
+    d = kappa.ndim
+    strides = [int(np.prod(shape[ax + 1:])) for ax in range(d)]
+    slots = []
+    for ax in range(d):
+        m = shape[ax]
+        sl_l = [slice(None)] * d
+        sl_r = [slice(None)] * d
+        sl_l[ax] = slice(0, m - 1)
+        sl_r[ax] = slice(1, m)
+        a = 2.0 * kappa[tuple(sl_l)] * kappa[tuple(sl_r)] / (kappa[tuple(sl_l)] + kappa[tuple(sl_r)])
+        minus = np.zeros(shape, dtype=bool)
+        minus[tuple(sl_r)] = True
+        mval = np.zeros(shape)
+        mval[tuple(sl_r)] = -a
+        plus = np.zeros(shape, dtype=bool)
+        plus[tuple(sl_l)] = True
+        pval = np.zeros(shape)
+        pval[tuple(sl_l)] = -a
+        slots.append(((-strides[ax], minus.ravel(), mval.ravel()), (strides[ax], plus.ravel(), pval.ravel())))
+    order = [slots[ax][0] for ax in range(d)] + [(0, np.ones(n, dtype=bool), diag.ravel())] + \
+            [slots[ax][1] for ax in reversed(range(d))]
+    counts = np.zeros(n, dtype=np.int64)
+    for _, msk, _ in order:
+        counts += msk
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = np.empty(row_ptr[-1], dtype=np.int32)
+    val = np.empty(row_ptr[-1], dtype=np.float64)
+    pos = row_ptr[:-1].copy()
+    g = np.arange(n, dtype=np.int64)
+    for off, msk, v in order:
+        rows_ = np.flatnonzero(msk)
+        col[pos[rows_]] = g[rows_] + off
+        val[pos[rows_]] = v[rows_]
+        pos[rows_] += 1
+    return CSR(n=n, row_ptr=row_ptr, col_idx=col, val=val)
 
 
 # ---------------------------------------------------------------------------
