@@ -215,7 +215,7 @@ int ddg_get_info(ddg_handle h, ddg_info* info);
 typedef enum {
   DDG_EXPORT_COLOURS = 0,   /* int32[n_parts]: colour of each subdomain */
   DDG_EXPORT_SET_PTR = 1,   /* int64[n_parts+1]: offsets of the expanded sets */
-  DDG_EXPORT_SET_IDX = 2,   /* int32[sum |expanded set|]: ascending global ids */
+  DDG_EXPORT_SET_IDX = 2,   /* int32[sum |expanded set|]: global ids, in the local order of the factors */
   DDG_EXPORT_KCOUNTS = 3,   /* int32[n_parts]: kept coarse columns per subdomain */
   DDG_EXPORT_A0 = 4,        /* float64[sum_b N_c(b)^2]: A0 = R0 A R0^T, row-major, one block per system */
   DDG_EXPORT_Q = 5,         /* float64[n*k]: orthonormal coarse basis, node-major (row g: k values) */

@@ -456,11 +456,11 @@ __device__ inline void schur_update(double* Sm, int b, const double* X, int bp, 
   __syncthreads();
 }
 
-template <class FT, int T>
+template <class FT, int T, int NB>
 __global__ void __launch_bounds__(kFacThreads) k_local_factor_chain(FactorArgs a) {
   extern __shared__ __align__(16) double fsm[];
   double* piv = fsm;                                 // NB*(NB+1)
-  double* Rp = fsm + kFacNB * (kFacNB + 1);          // NB * bmax
+  double* Rp = fsm + NB * (NB + 1);                  // NB * bmax
   const int slot = blockIdx.x >> 1, chain = blockIdx.x & 1;
   const int sub = a.first_sub + slot;
   double* buf = a.scratch + (int64_t)(2 * slot + chain) * 3 * a.bmax2;
@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(kFacThreads) k_local_factor_chain(FactorArgs a
         schur_update(Sm, b, X, a.blk_size[kb0 + kp], a.blk_start[kb0 + kp], Tm, a.up_col, a.up_pos, a.cu,
                      s0 + bs, a.val);
     }
-    gj_invert_wg<kFacThreads, kFacNB>(Sm, b, Rp, piv, a.err, sub, k);
+    gj_invert_wg<kFacThreads, NB>(Sm, b, Rp, piv, a.err, sub, k);
     pack_tiles_wg<FT, T, kFacThreads>(Sm, b, b, fac + a.blk_foff[kb0 + k]);
     __syncthreads();
     double* tmp = X;
@@ -496,11 +496,11 @@ __global__ void __launch_bounds__(kFacThreads) k_local_factor_chain(FactorArgs a
   }
 }
 
-template <class FT, int T>
+template <class FT, int T, int NB>
 __global__ void __launch_bounds__(kFacThreads) k_local_factor_mid(FactorArgs a) {
   extern __shared__ __align__(16) double fsm[];
   double* piv = fsm;
-  double* Rp = fsm + kFacNB * (kFacNB + 1);
+  double* Rp = fsm + NB * (NB + 1);
   const int slot = blockIdx.x;
   const int sub = a.first_sub + slot;
   const int64_t s0 = a.set_ptr[sub];
@@ -524,7 +524,7 @@ __global__ void __launch_bounds__(kFacThreads) k_local_factor_mid(FactorArgs a) 
   if (nB > 0)
     schur_update(Sm, b, XB, a.blk_size[kb0 + m + 1], a.blk_start[kb0 + m + 1], Tm, a.up_col, a.up_pos, a.cu,
                  s0 + bs, a.val);
-  gj_invert_wg<kFacThreads, kFacNB>(Sm, b, Rp, piv, a.err, sub, m);
+  gj_invert_wg<kFacThreads, NB>(Sm, b, Rp, piv, a.err, sub, m);
   FT* fac = static_cast<FT*>(a.fac);
   pack_tiles_wg<FT, T, kFacThreads>(Sm, b, b, fac + a.blk_foff[kb0 + m]);
 }
@@ -748,10 +748,13 @@ void launch_factor_t(Handle& h, hipStream_t s) {
   a.bmax2 = bmax2;
   a.fac = h.fac.p;
   a.err = h.err_flag.as<int32_t>();
-  size_t lds = sizeof(double) * ((size_t)kFacNB * (kFacNB + 1) + (size_t)kFacNB * S.max_blk);
-  DDG_REQUIRE((int64_t)lds <= h.dev_lds_limit, DDG_ERR_UNSUPPORTED, "local level too wide for the factorisation");
-  auto kc = k_local_factor_chain<FT, T>;
-  auto km = k_local_factor_mid<FT, T>;
+  // panel width 16 when its row panel fits on chip, else 8 (wide levels)
+  auto lds_for = [&](int nb) { return sizeof(double) * ((size_t)nb * (nb + 1) + (size_t)nb * S.max_blk); };
+  const bool wide = (int64_t)lds_for(kFacNB) > h.dev_lds_limit - 1024;
+  const size_t lds = wide ? lds_for(8) : lds_for(kFacNB);
+  DDG_REQUIRE((int64_t)lds <= h.dev_lds_limit - 1024, DDG_ERR_UNSUPPORTED, "local level too wide for the factorisation");
+  auto kc = wide ? k_local_factor_chain<FT, T, 8> : k_local_factor_chain<FT, T, kFacNB>;
+  auto km = wide ? k_local_factor_mid<FT, T, 8> : k_local_factor_mid<FT, T, kFacNB>;
   if (lds > 65536) {
     DDG_HIP(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     DDG_HIP(hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -24,6 +24,8 @@
 // Every wave loads all of its tiles of a level at once and, as soon as it has
 // used them, issues the loads of the next level, so the HBM latency overlaps
 // the reductions and barriers between levels.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "symv_tile.hpp"
 
@@ -59,6 +61,8 @@ struct SweepArgs {
   int32_t* flags;   // per subdomain: 2 flags
   int32_t xch_ld;
   int32_t* err;
+  int32_t slot_tiles;   // tiles whose partial slots fit on chip (a multiple of one round); wider
+                        // levels are reduced in phases of this many tiles into an accumulator
 };
 
 namespace {
@@ -158,7 +162,8 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   const int ni_pad = (ni + 3) & ~3;
   AT* w = reinterpret_cast<AT*>(smem_raw);
   AT* tv = w + ni_pad;
-  AT* slots = tv + a.ldp;  // 2 * T per tile of the current level
+  AT* acc = tv + a.ldp;     // phase accumulator (levels wider than slot_tiles only)
+  AT* slots = acc + a.ldp;  // 2 * T per tile of the current phase
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const FT* fac = static_cast<const FT*>(a.fac);
   const int kb0 = a.sub_blk_ptr[sub];
@@ -289,10 +294,13 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
     // computations can interleave.  When a level fits in one round, each register
     // set is refilled with the next level's tile as soon as it has been used.
     const int rounds = (ntl + NW * TPW - 1) / (NW * TPW);
+    const int phase_rounds = a.slot_tiles / (NW * TPW);
+    const bool phased = ntl > a.slot_tiles;
     int kind2 = 0, k2 = 0;
     const bool has_next = s + 1 < ns;
     if (has_next) decode_step(role, s + 1, K, m, kind2, k2);
     for (int round = 0; round < rounds; ++round) {
+      const int t_phase = (round / phase_rounds) * phase_rounds * NW * TPW;  // first tile of the phase
       if (round > 0) {
         const FT* base = fac + lv_foff[k];
 #pragma unroll
@@ -309,15 +317,25 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
         int I = tI[j], J = tJ[j];
         if (round > 0) tile_ij(t, I, J);
         if (!valid) I = J = 0;
-        symv_tile_slots<FT, AT, T>(R[j], I, J, tv, slots + (int64_t)(2 * t) * T,
-                                   slots + (int64_t)(2 * t + 1) * T, lane, valid);
+        symv_tile_slots<FT, AT, T>(R[j], I, J, tv, slots + (int64_t)(2 * (t - t_phase)) * T,
+                                   slots + (int64_t)(2 * (t - t_phase) + 1) * T, lane, valid);
         if (last && has_next) load_tile(k2, j);
+      }
+      if (phased && ((round + 1) % phase_rounds == 0 || last)) {
+        // fold this phase's slots into the accumulator, rows in a fixed tile order
+        __syncthreads();
+        const int t_end = min(ntl, t_phase + phase_rounds * NW * TPW);
+        for (int jj = tid; jj < b; jj += NT) {
+          const AT part = sum_slots_range<AT, T>(slots, nt, jj, t_phase, t_end);
+          acc[jj] = t_phase == 0 ? part : acc[jj] + part;
+        }
+        __syncthreads();
       }
     }
     if (has_next) load_cpl(kind2, k2);
     __syncthreads();
     for (int jj = tid; jj < b; jj += NT) {
-      const AT sum = sum_slots<AT, T>(slots, nt, jj);
+      const AT sum = phased ? acc[jj] : sum_slots<AT, T>(slots, nt, jj);
       if (fwd) w[bs + jj] = sum;
       else w[bs + jj] -= sum;
     }
@@ -415,10 +433,21 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   const int ni_pad = (S.max_set + 3) & ~3;
   DDG_REQUIRE(S.max_blocks <= kMaxLevels, DDG_ERR_UNSUPPORTED, "more than 96 levels in a local problem");
   const int max_tiles = tiles_for(S.max_blk, T);
-  size_t lds = sizeof(AT) * ((size_t)ni_pad + (size_t)maxpad + 2 * (size_t)max_tiles * T);
+  // on-chip plan: w (set), tv and the phase accumulator (one level each), then the
+  // per-tile slots of up to slot_tiles tiles (whole rounds of NW * TPW tiles)
+  const int round_tiles = NW * TPW;
+  const int64_t fixed = sizeof(AT) * ((int64_t)ni_pad + 2 * (int64_t)maxpad);
+  const int64_t per_tile = sizeof(AT) * 2 * (int64_t)T;
+  // (the kernel's static level metadata takes about 1.5 KiB of the same LDS)
+  int64_t cap = (h.dev_lds_limit - 2048 - fixed) / per_tile;
+  cap = cap / round_tiles * round_tiles;
+  if (const char* env = std::getenv("DDG_SWEEP_SLOT_TILES")) cap = std::min<int64_t>(cap, std::max(1, std::atoi(env)) * (int64_t)round_tiles);
+  const int64_t need_tiles = (int64_t)(max_tiles + round_tiles - 1) / round_tiles * round_tiles;
+  a.slot_tiles = (int32_t)std::min<int64_t>(cap, need_tiles);
+  DDG_REQUIRE(a.slot_tiles >= round_tiles, DDG_ERR_UNSUPPORTED,
+              "local problem too large for on-chip storage (" + std::to_string(fixed) + " bytes before slots)");
+  const size_t lds = (size_t)(fixed + per_tile * a.slot_tiles);
   auto kern = k_sweep<FT, AT, T, NW, TPW>;
-  DDG_REQUIRE((int64_t)lds <= h.dev_lds_limit, DDG_ERR_UNSUPPORTED,
-              "local problem too large for on-chip storage (" + std::to_string(lds) + " bytes)");
   if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (residual) {
     hipLaunchKernelGGL(k_local_residual, dim3((unsigned)((S.max_set + 255) / 256), (unsigned)nsub), dim3(256), 0,

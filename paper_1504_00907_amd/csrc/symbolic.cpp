@@ -214,47 +214,134 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
   parallel_for(n_parts, [&](int32_t i, int tid) {
     auto& map = lmap[tid];
     if ((int64_t)map.size() != n) map.assign(n, -1);
-    const int32_t* set = S.set_idx.data() + S.set_ptr[i];
+    int32_t* set = S.set_idx.data() + S.set_ptr[i];
     int32_t ni = (int32_t)(S.set_ptr[i + 1] - S.set_ptr[i]);
-    for (int32_t j = 0; j < ni; ++j) map[set[j]] = j;
-    std::vector<int32_t> first(ni);
-    for (int32_t j = 0; j < ni; ++j) {
-      int32_t g = set[j];
-      int32_t f = j;
-      for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
-        int32_t lc = map[ci[t]];
-        if (lc >= 0) f = std::min(f, lc);
-      }
-      first[j] = f;
-    }
-    std::vector<int32_t> suf(ni + 1, INT32_MAX);
-    for (int32_t j = ni - 1; j >= 0; --j) suf[j] = std::min(suf[j + 1], first[j]);
-    // greedy levels: rows of block m+1 and later may only reach back to block m,
-    // so s_{m+1} = max(s_m + 1, min{j : min_{j' >= j} first(j') >= s_m}).
-    std::vector<int32_t> bnd{0};
-    int32_t j = 0;
-    while (bnd.back() < ni) {
-      int32_t cur = bnd.back();
-      while (j < ni && suf[j] < cur) ++j;  // suf is non-decreasing
-      bnd.push_back(std::min(std::max(cur + 1, j), ni));
-    }
-    // merge consecutive levels: absorb tiny levels, and grow up to the target
-    int32_t target = block_target > 0 ? block_target : 0;
+    // Level structure of the local rows taken in the order `ord` (global ids):
+    // greedy boundaries (rows of level m+1 and later may only reach back to
+    // level m, so s_{m+1} = max(s_m + 1, min{j : min_{j' >= j} first(j') >= s_m})),
+    // then consecutive levels merged (tiny ones absorbed, grown up to the target).
+    const int32_t target = block_target > 0 ? block_target : 0;
     const int32_t min_rows = 16;
+    auto levels_of = [&](const int32_t* ord, std::vector<int32_t>& bstart, std::vector<int32_t>& bsize) {
+      for (int32_t j = 0; j < ni; ++j) map[ord[j]] = j;
+      std::vector<int32_t> first(ni);
+      for (int32_t j = 0; j < ni; ++j) {
+        int32_t g = ord[j];
+        int32_t f = j;
+        for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+          int32_t lc = map[ci[t]];
+          if (lc >= 0) f = std::min(f, lc);
+        }
+        first[j] = f;
+      }
+      std::vector<int32_t> suf(ni + 1, INT32_MAX);
+      for (int32_t j = ni - 1; j >= 0; --j) suf[j] = std::min(suf[j + 1], first[j]);
+      std::vector<int32_t> bnd{0};
+      int32_t j = 0;
+      while (bnd.back() < ni) {
+        int32_t cur = bnd.back();
+        while (j < ni && suf[j] < cur) ++j;  // suf is non-decreasing
+        bnd.push_back(std::min(std::max(cur + 1, j), ni));
+      }
+      bstart.clear();
+      bsize.clear();
+      int32_t s0 = 0;
+      for (size_t m = 1; m < bnd.size(); ++m) {
+        int32_t e = bnd[m];
+        bool last = (m + 1 == bnd.size());
+        int32_t size = e - s0;
+        int32_t next_size = last ? 0 : bnd[m + 1] - e;
+        bool absorb = !last && (size < min_rows || (target > 0 && size + next_size <= target));
+        if (!absorb) {
+          bstart.push_back(s0);
+          bsize.push_back(size);
+          s0 = e;
+        }
+      }
+      for (int32_t jj = 0; jj < ni; ++jj) map[ord[jj]] = -1;
+      double cost = 0.0;  // factor entries ~ sum of squared level sizes
+      for (int32_t b : bsize) cost += (double)b * b;
+      return cost;
+    };
     Local& L = loc[i];
-    int32_t s = 0;
-    for (size_t m = 1; m < bnd.size(); ++m) {
-      int32_t e = bnd[m];
-      bool last = (m + 1 == bnd.size());
-      int32_t size = e - s;
-      int32_t next_size = last ? 0 : bnd[m + 1] - e;
-      bool absorb = !last && (size < min_rows || (target > 0 && size + next_size <= target));
-      if (!absorb) {
-        L.bstart.push_back(s);
-        L.bsize.push_back(size);
-        s = e;
+    // candidate 1: ascending global order
+    levels_of(set, L.bstart, L.bsize);
+    // candidate 2, only for subdomains whose natural levels are very wide (irregular
+    // shapes): breadth-first levels of the local graph from a pseudo-peripheral row
+    // (rows sorted by distance, then global id), kept when it narrows the widest level.
+    // Narrow natural levels are kept even when the breadth-first ones store fewer
+    // entries: the sweep's cost per level is mostly latency, so more levels cost more.
+    const int32_t wide_level = 1024;
+    int32_t max_nat = 0;
+    for (int32_t b : L.bsize) max_nat = std::max(max_nat, b);
+    if (max_nat > wide_level && ni > 2 * min_rows) {
+      for (int32_t j = 0; j < ni; ++j) map[set[j]] = j;
+      std::vector<int32_t> dist(ni), queue(ni);
+      auto bfs = [&](int32_t src) {
+        std::fill(dist.begin(), dist.end(), -1);
+        int32_t head = 0, tail = 0;
+        dist[src] = 0;
+        queue[tail++] = src;
+        while (head < tail) {
+          int32_t v = queue[head++];
+          int32_t g = set[v];
+          for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+            int32_t w = map[ci[t]];
+            if (w >= 0 && dist[w] < 0) {
+              dist[w] = dist[v] + 1;
+              queue[tail++] = w;
+            }
+          }
+        }
+        return tail;  // rows reached
+      };
+      auto degree = [&](int32_t v) {
+        int32_t g = set[v], d = 0;
+        for (int64_t t = rp[g]; t < rp[g + 1]; ++t) d += map[ci[t]] >= 0;
+        return d;
+      };
+      int32_t src = 0;
+      for (int32_t v = 1; v < ni; ++v)
+        if (degree(v) < degree(src)) src = v;
+      int32_t ecc = -1;
+      bool connected = true;
+      for (int it = 0; it < 6; ++it) {
+        if (bfs(src) != ni) {
+          connected = false;
+          break;
+        }
+        int32_t e = *std::max_element(dist.begin(), dist.end());
+        if (e <= ecc) break;
+        ecc = e;
+        int32_t best = -1;
+        for (int32_t v = 0; v < ni; ++v)
+          if (dist[v] == e && (best < 0 || degree(v) < degree(best))) best = v;
+        if (best == src) break;
+        src = best;
+      }
+      if (connected && bfs(src) == ni) {
+        std::vector<int32_t> ord(set, set + ni);
+        std::vector<int32_t> key(ni);
+        for (int32_t v = 0; v < ni; ++v) key[v] = dist[v];
+        std::vector<int32_t> idx(ni);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        for (int32_t v = 0; v < ni; ++v) ord[v] = set[idx[v]];
+        for (int32_t jj = 0; jj < ni; ++jj) map[set[jj]] = -1;
+        std::vector<int32_t> bs2, sz2;
+        levels_of(ord.data(), bs2, sz2);
+        int32_t max_bfs = 0;
+        for (int32_t b : sz2) max_bfs = std::max(max_bfs, b);
+        if (max_bfs < max_nat) {
+          std::copy(ord.begin(), ord.end(), set);
+          L.bstart.swap(bs2);
+          L.bsize.swap(sz2);
+        }
+      } else {
+        for (int32_t jj = 0; jj < ni; ++jj) map[set[jj]] = -1;
       }
     }
+    for (int32_t j = 0; j < ni; ++j) map[set[j]] = j;
     // block id of each local row
     std::vector<int32_t> blk(ni);
     for (size_t b = 0; b < L.bstart.size(); ++b)

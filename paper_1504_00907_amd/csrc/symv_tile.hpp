@@ -197,4 +197,22 @@ __device__ inline AT sum_slots(const AT* __restrict__ slots, int nt, int r) {
   return s;
 }
 
+// As sum_slots, restricted to the tiles t0 <= t < t1 whose slots sit at
+// [2(t - t0)][T] (rows) and [2(t - t0) + 1][T] (columns); same tile order.
+template <class AT, int T>
+__device__ inline AT sum_slots_range(const AT* __restrict__ slots, int nt, int r, int t0, int t1) {
+  const int I = r / T, rr = r % T;
+  AT s = 0;
+  const int a0 = I * (I + 1) / 2;
+  for (int J = 0; J <= I; ++J) {
+    const int t = a0 + J;
+    if (t >= t0 && t < t1) s += slots[(2 * (t - t0)) * T + rr];
+  }
+  for (int J = I + 1; J < nt; ++J) {
+    const int t = J * (J + 1) / 2 + I;
+    if (t >= t0 && t < t1) s += slots[(2 * (t - t0) + 1) * T + rr];
+  }
+  return s;
+}
+
 }  // namespace ddg

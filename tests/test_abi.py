@@ -88,6 +88,9 @@ def _problems():
     part = rng.integers(0, 9, size=A2.n).astype(np.int32)
     part[:9] = np.arange(9)
     yield "2d23_random9_ovl1", A2, part, 9, 1
+    # elongated subdomains: breadth-first local ordering gives narrower levels than grid lines
+    kap = np.exp(seed_rng(43, 1).standard_normal((6, 2400)))
+    yield "2d_strips_6x2400_ovl1", diffusion_cc(kap), box_partition((6, 2400), (1, 2)), 2, 1
 
 
 @pytest.mark.parametrize("case", list(_problems()), ids=lambda c: c[0])
@@ -100,7 +103,7 @@ def test_symbolic_matches_oracle(case):
         ptr = an.export(_lib.EXPORT_SET_PTR, np.int64)
         idx = an.export(_lib.EXPORT_SET_IDX, np.int32)
         for i in range(n_parts):
-            assert np.array_equal(idx[ptr[i]:ptr[i + 1]], o.sets[i]), i
+            assert np.array_equal(np.sort(idx[ptr[i]:ptr[i + 1]]), o.sets[i]), i
         colours = an.export(_lib.EXPORT_COLOURS, np.int32)
         assert np.array_equal(colours, o.colours)
         info = an.info()
@@ -115,8 +118,25 @@ def test_symbolic_matches_oracle(case):
             ni = len(o.sets[i])
             assert bl[-1, 1] + bl[-1, 2] == ni
             lab = np.repeat(np.arange(len(bl)), bl[:, 2])
-            Ai = As[o.sets[i]][:, o.sets[i]].tocoo()
+            loc = idx[ptr[i]:ptr[i + 1]]          # local order of the factors
+            Ai = As[loc][:, loc].tocoo()
             assert np.abs(lab[Ai.row] - lab[Ai.col]).max() <= 1
+    finally:
+        an.close()
+
+
+def test_elongated_subdomains_use_narrow_levels():
+    """A 6 x 1200 strip (x fastest) has grid-line levels of 1200+ rows, too wide
+    to be kept; the breadth-first ordering's levels are far narrower."""
+    kap = np.exp(seed_rng(43, 1).standard_normal((6, 2400)))
+    A = diffusion_cc(kap)
+    an = Analysis(A, box_partition((6, 2400), (1, 2)), 2, 1)
+    try:
+        blocks = an.export(_lib.EXPORT_BLOCKS, np.int32).reshape(-1, 3)
+        assert blocks[:, 2].max() <= 32
+        ptr = an.export(_lib.EXPORT_SET_PTR, np.int64)
+        idx = an.export(_lib.EXPORT_SET_IDX, np.int32)
+        assert not np.all(np.diff(idx[ptr[0]:ptr[1]]) > 0)   # not the ascending order
     finally:
         an.close()
 
