@@ -185,7 +185,15 @@ struct Handle {
   DevBuf A0;              // dense coarse blocks, one per system (kept for export)
   DevBuf A0inv_t;         // tiled lower inverses, float64, tile 64
   DevBuf fac;             // local factor tiles (storage precision)
-  DevBuf fac_scratch;     // setup scratch
+  // batched local factorisation: item schedule (built once per handle) and scratch
+  struct FacStage {
+    int32_t first, count, gj, bmax;
+  };
+  bool fac_plan_ready = false;
+  std::vector<FacStage> fac_stages;
+  DevBuf fac_items, fac_off, fac_n, fac_rb, fac_esub, fac_eblk;
+  int32_t fac_max_items = 0;
+  DevBuf fac_scratch, fac_tm, fac_work;
   DevBuf err_flag;        // int32[4]: setup error (code, subdomain, block, pivot)
 
   // CG workspace

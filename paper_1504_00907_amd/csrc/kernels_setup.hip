@@ -256,277 +256,140 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
 }
 
 // ---------------------------------------------------------------------------
-// In-workgroup helpers for Gauss-Jordan inversion of a small SPD block in LDS.
-// piv is w x w with leading dimension ldp; on return it holds the inverse.
-template <int NT>
-__device__ inline void gj_small(double* piv, int w, int ldp, int32_t* err, int sub, int blk, int row0) {
-  for (int t = 0; t < w; ++t) {
-    double d = piv[t * ldp + t];
-    const bool bad = !(d > 0.0) || !isfinite(d);
-    if (bad) {
-      if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, sub, blk, row0 + t);
-      d = 1.0;
-    }
-    double nv[4];
-    int cnt = 0;
-    for (int idx = threadIdx.x; idx < w * w; idx += NT, ++cnt) {
-      const int i = idx / w, c = idx % w;
-      const double aic = piv[i * ldp + c];
-      const double ait = piv[i * ldp + t];
-      const double atc = piv[t * ldp + c];
-      double v;
-      if (i == t && c == t) v = 1.0 / d;
-      else if (i == t) v = atc / d;
-      else if (c == t) v = -ait / d;
-      else v = aic - ait * atc / d;
-      nv[cnt] = v;
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int idx = threadIdx.x; idx < w * w; idx += NT, ++cnt) piv[(idx / w) * ldp + idx % w] = nv[cnt];
-    __syncthreads();
-  }
-}
-
-// In-place blocked Gauss-Jordan inverse of the SPD b x b row-major matrix A (ld = b)
-// by one workgroup.  Rp is an LDS buffer of nb * b doubles, piv nb*(nb+1).
-template <int NT, int NB>
-__device__ void gj_invert_wg(double* __restrict__ A, int b, double* Rp, double* piv, int32_t* err,
-                             int sub, int blk) {
-  constexpr int LDP = NB + 1;
-  for (int P0 = 0; P0 < b; P0 += NB) {
-    const int w = min(NB, b - P0);
-    for (int idx = threadIdx.x; idx < w * w; idx += NT)
-      piv[(idx / w) * LDP + idx % w] = A[(int64_t)(P0 + idx / w) * b + P0 + idx % w];
-    __syncthreads();
-    gj_small<NT>(piv, w, LDP, err, sub, blk, P0);
-    // new row panel: R = Pinv * A[P, c] for c outside P (written in place and kept in LDS)
-    for (int c = threadIdx.x; c < b; c += NT) {
-      if (c >= P0 && c < P0 + w) continue;
-      double old[NB];
-#pragma unroll
-      for (int u = 0; u < NB; ++u) old[u] = (u < w) ? A[(int64_t)(P0 + u) * b + c] : 0.0;
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < w) {
-          double s = 0.0;
-#pragma unroll
-          for (int u = 0; u < NB; ++u)
-            if (u < w) s += piv[t * LDP + u] * old[u];
-          Rp[t * b + c] = s;
-          A[(int64_t)(P0 + t) * b + c] = s;
-        }
-      }
-    }
-    __syncthreads();
-    // trailing update, 4 columns per thread: A[i, c] -= A[i, P] R[P, c]
-    const int c4n = (b + 3) / 4;
-    for (int idx = threadIdx.x; idx < b * c4n; idx += NT) {
-      const int i = idx / c4n;
-      if (i >= P0 && i < P0 + w) continue;
-      const int c0 = (idx % c4n) * 4;
-      double colp[NB];
-#pragma unroll
-      for (int u = 0; u < NB; ++u) colp[u] = (u < w) ? A[(int64_t)i * b + P0 + u] : 0.0;
-      for (int cc = 0; cc < 4; ++cc) {
-        const int c = c0 + cc;
-        if (c >= b || (c >= P0 && c < P0 + w)) continue;
-        double s = 0.0;
-#pragma unroll
-        for (int u = 0; u < NB; ++u)
-          if (u < w) s += colp[u] * Rp[u * b + c];
-        A[(int64_t)i * b + c] -= s;
-      }
-    }
-    __syncthreads();
-    // new column panel: A[i, P] = -A[i, P] Pinv, and the pivot block itself
-    for (int i = threadIdx.x; i < b; i += NT) {
-      if (i >= P0 && i < P0 + w) {
-        for (int t = 0; t < w; ++t) A[(int64_t)i * b + P0 + t] = piv[(i - P0) * LDP + t];
-        continue;
-      }
-      double old[NB];
-#pragma unroll
-      for (int u = 0; u < NB; ++u) old[u] = (u < w) ? A[(int64_t)i * b + P0 + u] : 0.0;
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < w) {
-          double s = 0.0;
-#pragma unroll
-          for (int u = 0; u < NB; ++u)
-            if (u < w) s += old[u] * piv[u * LDP + t];
-          A[(int64_t)i * b + P0 + t] = -s;
-        }
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Pack the lower triangle of a symmetric b x b row-major matrix (ld) into T x T tiles
-// (layout of symv_tile.hpp).
-template <class FT, int T, int NT>
-__device__ inline void pack_tiles_wg(const double* __restrict__ A, int64_t ld, int b, FT* __restrict__ out) {
-  const int nt = (b + T - 1) / T;
-  const int64_t total = (int64_t)nt * (nt + 1) / 2 * T * T;
-  for (int64_t idx = threadIdx.x; idx < total; idx += NT) {
-    const int t = (int)(idx / (T * T));
-    int rr, cc;
-    tile_rc<FT, T>((int)(idx % (T * T)), rr, cc);
-    int I, J;
-    tile_ij(t, I, J);
-    const int row = I * T + rr;
-    const int col = J * T + cc;
-    double v = 0.0;
-    if (row < b && col < b) v = (row >= col) ? A[(int64_t)row * ld + col] : A[(int64_t)col * ld + row];
-    out[idx] = Store<FT>::from(v);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Local factorisation (twisted block LDL^T, see kernels_sweep.hip): for each
 // subdomain a top chain (levels 0..m-1, couplings to the level below) and a
-// bottom chain (levels K-1..m+1, couplings to the level above) run as two
-// independent workgroups; a second kernel forms and inverts the middle level.
+// bottom chain (levels K-1..m+1, couplings to the level above), then the
+// middle level m with both.  Chain step j of every chain of a group runs in
+// the same launches ("items", one per active chain):
+//   Tm = X_prev C^T            (k_fac_tm)
+//   S  = D_k - C Tm            (k_fac_form; the middle level subtracts both sides)
+//   S  <- S^{-1}               (the blocked Gauss-Jordan kernels of the coarse
+//                               inverse, over all items at once)
+//   tiles of S^{-1} -> factor  (k_fac_pack)
+// so each panel update of the inversion is spread over thousands of
+// workgroups instead of one workgroup per chain.
 
-constexpr int kFacThreads = 256;
-constexpr int kFacNB = 16;
+struct FacItem {
+  int32_t cur;     // global block id of the level being factored
+  int32_t prev;    // global block id of the coupled level already inverted (-1: none)
+  int32_t sub;     // subdomain
+  int32_t use_up;  // 0: couplings to the lower level (lo ELL), 1: to the upper level (up ELL)
+  int32_t add_d;   // 1: start from the level's diagonal block D_k
+  int32_t pad;
+  int64_t s_off;   // element offset of S (n x n, row-major) in the scratch
+  int64_t x_off;   // element offset of X_prev (bp x bp)
+  int64_t t_off;   // element offset of Tm (bp x n)
+};
 
-struct FactorArgs {
-  int32_t first_sub;
+struct FacArgs {
+  const FacItem* items;
   const int64_t* set_ptr;
   const int32_t* sub_blk_ptr;
   const int32_t* blk_start;
   const int32_t* blk_size;
   const int64_t* blk_foff;
   const int32_t* lo_col;
-  const int64_t* lo_pos;
+  const double* lo_val;
   int32_t cl;
   const int32_t* up_col;
-  const int64_t* up_pos;
+  const double* up_val;
   int32_t cu;
   const int64_t* in_ptr;
   const int32_t* in_col;
   const int64_t* in_pos;
   const double* val;
   double* scratch;
-  int64_t bmax2;
+  double* tm;
   void* fac;
-  int32_t* err;
 };
 
-// Sm = D_k (row-major b x b) from the same-level entries of rows row0..row0+b-1.
-__device__ inline void load_diag_block(double* Sm, int b, int bs, int64_t row0, const FactorArgs& a) {
-  for (int idx = threadIdx.x; idx < b * b; idx += kFacThreads) Sm[idx] = 0.0;
-  __syncthreads();
-  for (int jj = threadIdx.x; jj < b; jj += kFacThreads) {
-    const int64_t row = row0 + jj;
-    for (int64_t t = a.in_ptr[row]; t < a.in_ptr[row + 1]; ++t)
-      Sm[(int64_t)jj * b + (a.in_col[t] - bs)] = a.val[a.in_pos[t]];
-  }
-  __syncthreads();
-}
+constexpr int kFacRows = 8;   // rows of the level per workgroup in the formation kernels
 
-// Sm -= C X C^T, where C (b x bp) holds the couplings of rows row0.. to the level
-// starting at bsp (ELL slots ccol/cpos, cc per row) and X is bp x bp.
-__device__ inline void schur_update(double* Sm, int b, const double* X, int bp, int bsp, double* Tm,
-                                    const int32_t* ccol, const int64_t* cpos, int cc, int64_t row0,
-                                    const double* val) {
-  for (int idx = threadIdx.x; idx < bp * b; idx += kFacThreads) {
-    const int pp = idx / b, c = idx % b;
-    const int64_t row = row0 + c;
-    double acc = 0.0;
-    for (int q = 0; q < cc; ++q) {
-      const int col = ccol[row * cc + q];
-      if (col >= 0) acc += X[(int64_t)pp * bp + (col - bsp)] * val[cpos[row * cc + q]];
-    }
-    Tm[idx] = acc;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < b * b; idx += kFacThreads) {
-    const int r = idx / b, c = idx % b;
+// Tm[pp, r] = sum_q X_prev[pp, col_q - bsp] * c_q over the couplings (col_q, c_q) of row r
+__global__ void __launch_bounds__(256) k_fac_tm(FacArgs a) {
+  const FacItem it = a.items[blockIdx.x];
+  if (it.prev < 0) return;
+  const int b = a.blk_size[it.cur];
+  const int r0 = blockIdx.y * kFacRows;
+  if (r0 >= b) return;
+  const int bp = a.blk_size[it.prev], bsp = a.blk_start[it.prev];
+  const int64_t row0 = a.set_ptr[it.sub] + a.blk_start[it.cur];
+  const int cc = it.use_up ? a.cu : a.cl;
+  const int32_t* ccol = it.use_up ? a.up_col : a.lo_col;
+  const double* cval = it.use_up ? a.up_val : a.lo_val;
+  const double* X = a.scratch + it.x_off;
+  double* Tm = a.tm + it.t_off;
+  const int rows = min(kFacRows, b - r0);
+  for (int idx = threadIdx.x; idx < bp * rows; idx += 256) {
+    const int pp = idx / rows, r = r0 + idx % rows;
     const int64_t row = row0 + r;
     double acc = 0.0;
     for (int q = 0; q < cc; ++q) {
       const int col = ccol[row * cc + q];
-      if (col >= 0) acc += val[cpos[row * cc + q]] * Tm[(int64_t)(col - bsp) * b + c];
+      if (col >= 0) acc += X[(int64_t)pp * bp + (col - bsp)] * cval[row * cc + q];
     }
-    Sm[idx] -= acc;
+    Tm[(int64_t)pp * b + r] = acc;
   }
-  __syncthreads();
 }
 
-template <class FT, int T, int NB>
-__global__ void __launch_bounds__(kFacThreads) k_local_factor_chain(FactorArgs a) {
-  extern __shared__ __align__(16) double fsm[];
-  double* piv = fsm;                                 // NB*(NB+1)
-  double* Rp = fsm + NB * (NB + 1);                  // NB * bmax
-  const int slot = blockIdx.x >> 1, chain = blockIdx.x & 1;
-  const int sub = a.first_sub + slot;
-  double* buf = a.scratch + (int64_t)(2 * slot + chain) * 3 * a.bmax2;
-  double* X = buf;
-  double* Tm = buf + a.bmax2;
-  double* Sm = buf + 2 * a.bmax2;
-  const int64_t s0 = a.set_ptr[sub];
-  const int kb0 = a.sub_blk_ptr[sub];
-  const int K = a.sub_blk_ptr[sub + 1] - kb0;
-  const int m = (K - 1) / 2;
-  const int steps = chain == 0 ? m : K - 1 - m;
-  FT* fac = static_cast<FT*>(a.fac);
-  for (int j = 0; j < steps; ++j) {
-    const int k = chain == 0 ? j : K - 1 - j;
-    const int bs = a.blk_start[kb0 + k];
-    const int b = a.blk_size[kb0 + k];
-    load_diag_block(Sm, b, bs, s0 + bs, a);
-    if (j > 0) {
-      const int kp = chain == 0 ? k - 1 : k + 1;
-      if (chain == 0)
-        schur_update(Sm, b, X, a.blk_size[kb0 + kp], a.blk_start[kb0 + kp], Tm, a.lo_col, a.lo_pos, a.cl,
-                     s0 + bs, a.val);
-      else
-        schur_update(Sm, b, X, a.blk_size[kb0 + kp], a.blk_start[kb0 + kp], Tm, a.up_col, a.up_pos, a.cu,
-                     s0 + bs, a.val);
-    }
-    gj_invert_wg<kFacThreads, NB>(Sm, b, Rp, piv, a.err, sub, k);
-    pack_tiles_wg<FT, T, kFacThreads>(Sm, b, b, fac + a.blk_foff[kb0 + k]);
+// S[r, :] = (add_d ? D_k[r, :] : S[r, :]) - sum_q c_q Tm[col_q - bsp, :]
+__global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
+  const FacItem it = a.items[blockIdx.x];
+  const int b = a.blk_size[it.cur];
+  const int r0 = blockIdx.y * kFacRows;
+  if (r0 >= b) return;
+  const int rows = min(kFacRows, b - r0);
+  const int bs = a.blk_start[it.cur];
+  const int64_t row0 = a.set_ptr[it.sub] + bs;
+  double* S = a.scratch + it.s_off;
+  if (it.add_d) {
+    for (int idx = threadIdx.x; idx < rows * b; idx += 256) S[(int64_t)(r0 + idx / b) * b + idx % b] = 0.0;
     __syncthreads();
-    double* tmp = X;
-    X = Sm;
-    Sm = tmp;
+    for (int r = threadIdx.x; r < rows; r += 256) {
+      const int64_t row = row0 + r0 + r;
+      for (int64_t t = a.in_ptr[row]; t < a.in_ptr[row + 1]; ++t)
+        S[(int64_t)(r0 + r) * b + (a.in_col[t] - bs)] = a.val[a.in_pos[t]];
+    }
+    __syncthreads();
+  }
+  if (it.prev < 0) return;
+  const int bsp = a.blk_start[it.prev];
+  const int cc = it.use_up ? a.cu : a.cl;
+  const int32_t* ccol = it.use_up ? a.up_col : a.lo_col;
+  const double* cval = it.use_up ? a.up_val : a.lo_val;
+  const double* Tm = a.tm + it.t_off;
+  for (int idx = threadIdx.x; idx < rows * b; idx += 256) {
+    const int r = r0 + idx / b, c = idx % b;
+    const int64_t row = row0 + r;
+    double acc = 0.0;
+    for (int q = 0; q < cc; ++q) {
+      const int col = ccol[row * cc + q];
+      if (col >= 0) acc += cval[row * cc + q] * Tm[(int64_t)(col - bsp) * b + c];
+    }
+    S[(int64_t)r * b + c] -= acc;
   }
 }
 
-template <class FT, int T, int NB>
-__global__ void __launch_bounds__(kFacThreads) k_local_factor_mid(FactorArgs a) {
-  extern __shared__ __align__(16) double fsm[];
-  double* piv = fsm;
-  double* Rp = fsm + NB * (NB + 1);
-  const int slot = blockIdx.x;
-  const int sub = a.first_sub + slot;
-  const int64_t s0 = a.set_ptr[sub];
-  const int kb0 = a.sub_blk_ptr[sub];
-  const int K = a.sub_blk_ptr[sub + 1] - kb0;
-  const int m = (K - 1) / 2;
-  const int nB = K - 1 - m;
-  double* bufA = a.scratch + (int64_t)(2 * slot) * 3 * a.bmax2;
-  double* bufB = a.scratch + (int64_t)(2 * slot + 1) * 3 * a.bmax2;
-  // after n chain steps the chain's last inverse sits in slot 0 (n even) or slot 2 (n odd)
-  const double* XA = bufA + ((m & 1) ? 2 : 0) * a.bmax2;
-  const double* XB = bufB + ((nB & 1) ? 2 : 0) * a.bmax2;
-  double* Tm = bufA + a.bmax2;
-  double* Sm = bufA + ((m & 1) ? 0 : 2) * a.bmax2;
-  const int bs = a.blk_start[kb0 + m];
-  const int b = a.blk_size[kb0 + m];
-  load_diag_block(Sm, b, bs, s0 + bs, a);
-  if (m > 0)
-    schur_update(Sm, b, XA, a.blk_size[kb0 + m - 1], a.blk_start[kb0 + m - 1], Tm, a.lo_col, a.lo_pos, a.cl,
-                 s0 + bs, a.val);
-  if (nB > 0)
-    schur_update(Sm, b, XB, a.blk_size[kb0 + m + 1], a.blk_start[kb0 + m + 1], Tm, a.up_col, a.up_pos, a.cu,
-                 s0 + bs, a.val);
-  gj_invert_wg<kFacThreads, NB>(Sm, b, Rp, piv, a.err, sub, m);
-  FT* fac = static_cast<FT*>(a.fac);
-  pack_tiles_wg<FT, T, kFacThreads>(Sm, b, b, fac + a.blk_foff[kb0 + m]);
+// lower T x T tiles of the symmetric n x n matrix S (layout of symv_tile.hpp), converted to FT
+template <class FT, int T>
+__global__ void __launch_bounds__(256) k_fac_pack(FacArgs a) {
+  const FacItem it = a.items[blockIdx.x];
+  const int b = a.blk_size[it.cur];
+  const int nt = (b + T - 1) / T;
+  const int64_t total = (int64_t)nt * (nt + 1) / 2 * T * T;
+  const double* S = a.scratch + it.s_off;
+  FT* out = static_cast<FT*>(a.fac) + a.blk_foff[it.cur];
+  for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
+    const int t = (int)(idx / (T * T));
+    int rr, cc;
+    tile_rc<FT, T>((int)(idx % (T * T)), rr, cc);
+    int I, J;
+    tile_ij(t, I, J);
+    const int row = I * T + rr, col = J * T + cc;
+    double v = 0.0;
+    if (row < b && col < b) v = (row >= col) ? S[(int64_t)row * b + col] : S[(int64_t)col * b + row];
+    out[idx] = Store<FT>::from(v);
+  }
 }
 
 __global__ void k_gather_vals(const int64_t* __restrict__ pos, const double* __restrict__ val,
@@ -548,9 +411,16 @@ struct CoarseBlocks {
   double* pinv;            // per system kCNB x kCNB
   double* Rbuf;            // per system kCNB x (order), at kCNB * cblk_off
   const int64_t* cblk_off;
+  const int32_t* err_sub;  // when set (local levels): subdomain and level reported on a bad pivot
+  const int32_t* err_blk;
 };
 
-__global__ void __launch_bounds__(256) k_cgj_pivot(CoarseBlocks cb, int P0, int32_t* err) {
+constexpr int kPivThreads = 256;
+constexpr int kPivPer = kCNB * kCNB / kPivThreads;   // pivot-block entries per thread
+
+// Gauss-Jordan inverse of the kCNB x kCNB pivot block in LDS; thread x owns the
+// fixed entries x + q * kPivThreads, so its values stay in registers.
+__global__ void __launch_bounds__(kPivThreads) k_cgj_pivot(CoarseBlocks cb, int P0, int32_t* err) {
   const int sys = blockIdx.x;
   const int64_t N = cb.n[sys];
   if (P0 >= N) return;
@@ -558,40 +428,58 @@ __global__ void __launch_bounds__(256) k_cgj_pivot(CoarseBlocks cb, int P0, int3
   double* A = cb.A + cb.a0_off[sys];
   double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
   __shared__ double piv[kCNB * (kCNB + 1)];
-  for (int idx = threadIdx.x; idx < w * w; idx += 256)
+  for (int idx = threadIdx.x; idx < w * w; idx += kPivThreads)
     piv[(idx / w) * (kCNB + 1) + idx % w] = A[(int64_t)(P0 + idx / w) * N + P0 + idx % w];
   __syncthreads();
+  int ii[kPivPer], cc[kPivPer];
+#pragma unroll
+  for (int q = 0; q < kPivPer; ++q) {
+    const int idx = threadIdx.x + q * kPivThreads;
+    ii[q] = idx < w * w ? idx / w : -1;
+    cc[q] = idx < w * w ? idx % w : 0;
+  }
   for (int t = 0; t < w; ++t) {
     double d = piv[t * (kCNB + 1) + t];
     if (!(d > 0.0) || !isfinite(d)) {
-      if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, -1, sys, P0 + t);
+      if (threadIdx.x == 0) {
+        if (cb.err_sub) record_error(err, DDG_ERR_NOT_SPD, cb.err_sub[sys], cb.err_blk[sys], P0 + t);
+        else record_error(err, DDG_ERR_NOT_SPD, -1, sys, P0 + t);
+      }
       d = 1.0;
     }
-    double nv[16];
-    int cnt = 0;
-    for (int idx = threadIdx.x; idx < w * w; idx += 256, ++cnt) {
-      const int i = idx / w, c = idx % w;
-      const double aic = piv[i * (kCNB + 1) + c];
-      const double ait = piv[i * (kCNB + 1) + t];
-      const double atc = piv[t * (kCNB + 1) + c];
-      double v;
-      if (i == t && c == t) v = 1.0 / d;
-      else if (i == t) v = atc / d;
-      else if (c == t) v = -ait / d;
-      else v = aic - ait * atc / d;
-      nv[cnt] = v;
+    const double rd = 1.0 / d;
+    double nv[kPivPer];
+#pragma unroll
+    for (int q = 0; q < kPivPer; ++q) {
+      const int i = ii[q], c = cc[q];
+      double v = 0.0;
+      if (i >= 0) {
+        const double aic = piv[i * (kCNB + 1) + c];
+        const double ait = piv[i * (kCNB + 1) + t];
+        const double atc = piv[t * (kCNB + 1) + c];
+        if (i == t && c == t) v = rd;
+        else if (i == t) v = atc * rd;
+        else if (c == t) v = -ait * rd;
+        else v = aic - ait * atc * rd;
+      }
+      nv[q] = v;
     }
     __syncthreads();
-    cnt = 0;
-    for (int idx = threadIdx.x; idx < w * w; idx += 256, ++cnt)
-      piv[(idx / w) * (kCNB + 1) + idx % w] = nv[cnt];
+#pragma unroll
+    for (int q = 0; q < kPivPer; ++q)
+      if (ii[q] >= 0) piv[ii[q] * (kCNB + 1) + cc[q]] = nv[q];
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < w * w; idx += 256) pinv[idx] = piv[(idx / w) * (kCNB + 1) + idx % w];
+  for (int idx = threadIdx.x; idx < w * w; idx += kPivThreads) pinv[idx] = piv[(idx / w) * (kCNB + 1) + idx % w];
 }
 
+// Row and column panels: a workgroup covers 32 columns (rows) of the panel with
+// 8 threads each, every thread producing 8 of the (up to) 64 panel entries; all
+// old values are read before any is overwritten.
+constexpr int kPanLines = 32, kPanSplit = 8, kPanOut = kCNB / kPanSplit;
+
 // row panel R = Pinv A[P, :] for columns outside P; written to Rbuf and in place
-__global__ void k_cgj_row(CoarseBlocks cb, int P0) {
+__global__ void __launch_bounds__(256) k_cgj_row(CoarseBlocks cb, int P0) {
   const int sys = blockIdx.y;
   const int64_t N = cb.n[sys];
   if (P0 >= N) return;
@@ -601,23 +489,35 @@ __global__ void k_cgj_row(CoarseBlocks cb, int P0) {
   double* Rbuf = cb.Rbuf + kCNB * cb.cblk_off[sys];
   __shared__ double pv[kCNB * kCNB];
   for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) pv[idx] = pinv[idx];
-  __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N || (c >= P0 && c < P0 + w)) return;
+  const int64_t c = (int64_t)blockIdx.x * kPanLines + threadIdx.x % kPanLines;
+  const int t0 = (threadIdx.x / kPanLines) * kPanOut;
+  const bool active = c < N && !(c >= P0 && c < P0 + w);
   double old[kCNB];
 #pragma unroll
-  for (int u = 0; u < kCNB; ++u) old[u] = (u < w) ? A[(int64_t)(P0 + u) * N + c] : 0.0;
-  for (int t = 0; t < w; ++t) {
-    double s = 0.0;
+  for (int u = 0; u < kCNB; ++u) old[u] = (active && u < w) ? A[(int64_t)(P0 + u) * N + c] : 0.0;
+  __syncthreads();  // pv loaded; every old value of this workgroup's columns read
+  if (!active) return;
 #pragma unroll
-    for (int u = 0; u < kCNB; ++u)
-      if (u < w) s += pv[t * w + u] * old[u];
-    Rbuf[(int64_t)t * N + c] = s;
-    A[(int64_t)(P0 + t) * N + c] = s;
+  for (int q = 0; q < kPanOut; ++q) {
+    const int t = t0 + q;
+    if (t < w) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < kCNB; ++u)
+        if (u < w) s += pv[t * w + u] * old[u];
+      Rbuf[(int64_t)t * N + c] = s;
+      A[(int64_t)(P0 + t) * N + c] = s;
+    }
   }
 }
 
-// trailing update on 64 x 64 output tiles: A[i, c] -= A[i, P] R[P, c]
+// trailing update on 64 x 64 output tiles: A[i, c] -= A[i, P] R[P, c], on the
+// FP64 matrix cores.  Each of the 4 waves computes a 32 x 32 quadrant as 2 x 2
+// products of 16 x 16 tiles (v_mfma_f64_16x16x4: lane l feeds A[l%16][l/16] and
+// B[l/16][l%16] and receives D[4r + l/16][l%16] in result register r), the
+// panels staged through LDS in 32-wide chunks.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256) k_cgj_update(CoarseBlocks cb, int P0) {
   const int sys = blockIdx.z;
   const int64_t N = cb.n[sys];
@@ -629,8 +529,14 @@ __global__ void __launch_bounds__(256) k_cgj_update(CoarseBlocks cb, int P0) {
   constexpr int UC = 32;
   __shared__ double cp[64][UC + 1];   // column panel rows of this tile
   __shared__ double rp[UC][64 + 1];   // row panel columns of this tile
-  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-  double acc[4][4] = {};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  mfma_d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = mfma_d4{0.0, 0.0, 0.0, 0.0};
   for (int u0 = 0; u0 < w; u0 += UC) {
     for (int idx = threadIdx.x; idx < 64 * UC; idx += 256) {
       const int r = idx / UC, u = idx % UC;
@@ -641,36 +547,35 @@ __global__ void __launch_bounds__(256) k_cgj_update(CoarseBlocks cb, int P0) {
       rp[uu][cc] = (u0 + uu < w && c < N) ? Rbuf[(int64_t)(u0 + uu) * N + c] : 0.0;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int u = 0; u < UC; ++u) {
-      double av[4], bv[4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        av[x] = cp[tr * 4 + x][u];
-        bv[x] = rp[u][tc * 4 + x];
-      }
+    for (int k0 = 0; k0 < UC; k0 += 4) {
+      double af[2], bf[2];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 2; ++x) af[x] = cp[wr + x * 16 + li][k0 + lk];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+      for (int y = 0; y < 2; ++y) bf[y] = rp[k0 + lk][wc + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int64_t i = i0 + tr * 4 + x;
-    if (i >= N || (i >= P0 && i < P0 + w)) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int64_t c = c0 + tc * 4 + y;
-      if (c >= N || (c >= P0 && c < P0 + w)) continue;
-      A[i * N + c] -= acc[x][y];
-    }
-  }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wr + x * 16 + 4 * r + lk;
+        const int64_t c = c0 + wc + y * 16 + li;
+        if (i >= N || c >= N || (i >= P0 && i < P0 + w) || (c >= P0 && c < P0 + w)) continue;
+        A[i * N + c] -= acc[x][y][r];
+      }
 }
 
 // column panel A[i, P] = -A[i, P] Pinv (rows outside P) and the pivot block itself
-__global__ void k_cgj_col(CoarseBlocks cb, int P0) {
+__global__ void __launch_bounds__(256) k_cgj_col(CoarseBlocks cb, int P0) {
   const int sys = blockIdx.y;
   const int64_t N = cb.n[sys];
   if (P0 >= N) return;
@@ -679,17 +584,23 @@ __global__ void k_cgj_col(CoarseBlocks cb, int P0) {
   const double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
   __shared__ double pv[kCNB * kCNB];
   for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) pv[idx] = pinv[idx];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  if (i >= P0 && i < P0 + w) {
-    for (int t = 0; t < w; ++t) A[i * N + P0 + t] = pv[(i - P0) * w + t];
-    return;
-  }
+  const int64_t i = (int64_t)blockIdx.x * kPanLines + threadIdx.x % kPanLines;
+  const int t0 = (threadIdx.x / kPanLines) * kPanOut;
+  const bool pivot_row = i >= P0 && i < P0 + w;
+  const bool active = i < N;
   double old[kCNB];
 #pragma unroll
-  for (int u = 0; u < kCNB; ++u) old[u] = (u < w) ? A[i * N + P0 + u] : 0.0;
-  for (int t = 0; t < w; ++t) {
+  for (int u = 0; u < kCNB; ++u) old[u] = (active && !pivot_row && u < w) ? A[i * N + P0 + u] : 0.0;
+  __syncthreads();  // pv loaded; every old value of this workgroup's rows read
+  if (!active) return;
+#pragma unroll
+  for (int q = 0; q < kPanOut; ++q) {
+    const int t = t0 + q;
+    if (t >= w) continue;
+    if (pivot_row) {
+      A[i * N + P0 + t] = pv[(i - P0) * w + t];
+      continue;
+    }
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < kCNB; ++u)
@@ -720,52 +631,186 @@ __global__ void k_pack_coarse(const double* __restrict__ A, const int64_t* __res
   out[idx] = v;
 }
 
+// Schedule of the batched factorisation: groups of subdomains whose scratch
+// fits the budget; per group, the chain steps, then the middle level.
+struct FacPlanHost {
+  struct Stage {
+    int32_t first, count;    // items [first, first + count) of the item array
+    int32_t gj;              // 1: invert and pack after forming (0: a form-only pass)
+    int32_t bmax;            // widest level of the stage
+  };
+  std::vector<FacItem> items;
+  std::vector<Stage> stages;
+  std::vector<int32_t> group_first;   // stage index where each group starts
+  int64_t scratch_elems = 0, tm_elems = 0, rb_elems = 0;
+  int32_t max_items = 0;
+};
+
+void build_fac_plan(const Symbolic& S, FacPlanHost& P) {
+  const int64_t bmax = std::max<int32_t>(1, S.max_blk);
+  const int64_t per_chain = 2 * bmax * bmax;            // X and S buffers
+  const int64_t budget = ((int64_t)5 << 30) / 8;        // scratch elements (+ Tm of the same order)
+  // (at most 30000 subdomains per group: item counts stay within a grid dimension)
+  const int32_t gsub = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>(std::min<int64_t>(S.n_parts, 30000), budget / (2 * per_chain)));
+  P.scratch_elems = (int64_t)gsub * 2 * per_chain;
+  P.tm_elems = (int64_t)gsub * 2 * bmax * bmax;
+  for (int32_t g0 = 0; g0 < S.n_parts; g0 += gsub) {
+    const int32_t g1 = std::min(S.n_parts, g0 + gsub);
+    P.group_first.push_back((int32_t)P.stages.size());
+    int32_t steps = 0;
+    for (int32_t i = g0; i < g1; ++i) {
+      const int32_t K = S.sub_blk_ptr[i + 1] - S.sub_blk_ptr[i];
+      const int32_t m = (K - 1) / 2;
+      steps = std::max(steps, std::max(m, K - 1 - m));
+    }
+    // chain (i, dir) uses buffers at ((i - g0) * 2 + dir) * per_chain + {0, bmax^2}; after
+    // step j its inverse sits in buffer j & 1
+    auto buf = [&](int32_t i, int dir, int par) {
+      return ((int64_t)(i - g0) * 2 + dir) * per_chain + (par & 1) * bmax * bmax;
+    };
+    for (int32_t j = 0; j < steps; ++j) {
+      FacPlanHost::Stage st{(int32_t)P.items.size(), 0, 1, 0};
+      for (int32_t i = g0; i < g1; ++i) {
+        const int32_t kb0 = S.sub_blk_ptr[i], K = S.sub_blk_ptr[i + 1] - kb0;
+        const int32_t m = (K - 1) / 2, nB = K - 1 - m;
+        for (int dir = 0; dir < 2; ++dir) {
+          const int32_t len = dir == 0 ? m : nB;
+          if (j >= len) continue;
+          const int32_t k = dir == 0 ? j : K - 1 - j;
+          const int32_t kp = dir == 0 ? k - 1 : k + 1;
+          FacItem it{};
+          it.cur = kb0 + k;
+          it.prev = j > 0 ? kb0 + kp : -1;
+          it.sub = i;
+          it.use_up = dir;
+          it.add_d = 1;
+          it.s_off = buf(i, dir, j);
+          it.x_off = buf(i, dir, j - 1);
+          it.t_off = (int64_t)(P.items.size() - st.first) * bmax * bmax;
+          st.bmax = std::max(st.bmax, S.blk_size[it.cur]);
+          P.items.push_back(it);
+        }
+      }
+      st.count = (int32_t)P.items.size() - st.first;
+      if (st.count) P.stages.push_back(st);
+    }
+    // middle level: formed in the top chain's free buffer from both chains' last inverses
+    for (int pass = 0; pass < 2; ++pass) {
+      FacPlanHost::Stage st{(int32_t)P.items.size(), 0, pass == 1, 0};
+      for (int32_t i = g0; i < g1; ++i) {
+        const int32_t kb0 = S.sub_blk_ptr[i], K = S.sub_blk_ptr[i + 1] - kb0;
+        const int32_t m = (K - 1) / 2, nB = K - 1 - m;
+        FacItem it{};
+        it.cur = kb0 + m;
+        it.sub = i;
+        it.s_off = buf(i, 0, m);
+        it.t_off = (int64_t)(P.items.size() - st.first) * bmax * bmax;
+        if (pass == 0) {
+          it.prev = m > 0 ? kb0 + m - 1 : -1;
+          it.use_up = 0;
+          it.add_d = 1;
+          it.x_off = buf(i, 0, m - 1);
+        } else {
+          it.prev = nB > 0 ? kb0 + m + 1 : -1;
+          it.use_up = 1;
+          it.add_d = 0;
+          it.x_off = buf(i, 1, nB - 1);
+        }
+        st.bmax = std::max(st.bmax, S.blk_size[it.cur]);
+        P.items.push_back(it);
+      }
+      st.count = (int32_t)P.items.size() - st.first;
+      P.stages.push_back(st);
+    }
+  }
+  for (auto& st : P.stages) P.max_items = std::max(P.max_items, st.count);
+  P.rb_elems = (int64_t)P.max_items * kCNB * bmax;
+}
+
 template <class FT, int T>
 void launch_factor_t(Handle& h, hipStream_t s) {
   const Symbolic& S = h.S;
-  const int64_t bmax2 = (int64_t)S.max_blk * S.max_blk;
-  // bound the scratch: at most `batch` subdomains in flight per launch
-  const int64_t per = 2 * 3 * bmax2 * 8;
-  int batch = (int)std::min<int64_t>(S.n_parts, std::max<int64_t>(1, ((int64_t)6 << 30) / per));
-  if ((int64_t)h.fac_scratch.bytes < per * batch) h.fac_scratch.alloc(per * batch);
-  FactorArgs a;
+  if (!h.fac_plan_ready) {
+    FacPlanHost P;
+    build_fac_plan(S, P);
+    h.fac_items.upload(P.items, s);
+    h.fac_stages.clear();
+    for (auto& st : P.stages) h.fac_stages.push_back({st.first, st.count, st.gj, st.bmax});
+    // per-item arrays for the Gauss-Jordan kernels, one block per stage (same item order)
+    std::vector<int64_t> off(P.items.size()), rb(P.items.size());
+    std::vector<int32_t> n(P.items.size()), esub(P.items.size()), eblk(P.items.size());
+    const int64_t bmax = std::max<int32_t>(1, S.max_blk);
+    for (auto& st : P.stages)
+      for (int32_t q = 0; q < st.count; ++q) {
+        const FacItem& it = P.items[st.first + q];
+        off[st.first + q] = it.s_off;
+        n[st.first + q] = S.blk_size[it.cur];
+        rb[st.first + q] = (int64_t)q * bmax;
+        esub[st.first + q] = it.sub;
+        eblk[st.first + q] = it.cur - S.sub_blk_ptr[it.sub];
+      }
+    h.fac_off.upload(off, s);
+    h.fac_n.upload(n, s);
+    h.fac_rb.upload(rb, s);
+    h.fac_esub.upload(esub, s);
+    h.fac_eblk.upload(eblk, s);
+    h.fac_scratch.alloc((size_t)P.scratch_elems * sizeof(double));
+    h.fac_tm.alloc((size_t)P.tm_elems * sizeof(double));
+    h.fac_work.alloc(((size_t)kCNB * kCNB * P.max_items + (size_t)P.rb_elems) * sizeof(double));
+    h.fac_max_items = P.max_items;
+    h.fac_plan_ready = true;
+  }
+  FacArgs a;
   a.set_ptr = h.set_ptr.as<int64_t>();
   a.sub_blk_ptr = h.sub_blk_ptr.as<int32_t>();
   a.blk_start = h.blk_start.as<int32_t>();
   a.blk_size = h.blk_size.as<int32_t>();
   a.blk_foff = h.blk_foff.as<int64_t>();
   a.lo_col = h.lo_col.as<int32_t>();
-  a.lo_pos = h.lo_pos.as<int64_t>();
+  a.lo_val = h.lo_val.as<double>();
   a.cl = S.cl;
   a.up_col = h.up_col.as<int32_t>();
-  a.up_pos = h.up_pos.as<int64_t>();
+  a.up_val = h.up_val.as<double>();
   a.cu = S.cu;
   a.in_ptr = h.in_ptr.as<int64_t>();
   a.in_col = h.in_col.as<int32_t>();
   a.in_pos = h.in_pos.as<int64_t>();
   a.val = h.val.as<double>();
   a.scratch = h.fac_scratch.as<double>();
-  a.bmax2 = bmax2;
+  a.tm = h.fac_tm.as<double>();
   a.fac = h.fac.p;
-  a.err = h.err_flag.as<int32_t>();
-  // panel width 16 when its row panel fits on chip, else 8 (wide levels)
-  auto lds_for = [&](int nb) { return sizeof(double) * ((size_t)nb * (nb + 1) + (size_t)nb * S.max_blk); };
-  const bool wide = (int64_t)lds_for(kFacNB) > h.dev_lds_limit - 1024;
-  const size_t lds = wide ? lds_for(8) : lds_for(kFacNB);
-  DDG_REQUIRE((int64_t)lds <= h.dev_lds_limit - 1024, DDG_ERR_UNSUPPORTED, "local level too wide for the factorisation");
-  auto kc = wide ? k_local_factor_chain<FT, T, 8> : k_local_factor_chain<FT, T, kFacNB>;
-  auto km = wide ? k_local_factor_mid<FT, T, 8> : k_local_factor_mid<FT, T, kFacNB>;
-  if (lds > 65536) {
-    DDG_HIP(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    DDG_HIP(hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const FacItem* items = h.fac_items.as<FacItem>();
+  for (const auto& st : h.fac_stages) {
+    a.items = items + st.first;
+    const unsigned ny = (unsigned)((st.bmax + kFacRows - 1) / kFacRows);
+    hipLaunchKernelGGL(k_fac_tm, dim3((unsigned)st.count, ny), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_fac_form, dim3((unsigned)st.count, ny), dim3(256), 0, s, a);
+    if (!st.gj) continue;
+    CoarseBlocks cb;
+    cb.A = a.scratch;
+    cb.a0_off = h.fac_off.as<int64_t>() + st.first;
+    cb.n = h.fac_n.as<int32_t>() + st.first;
+    cb.pinv = h.fac_work.as<double>();
+    cb.Rbuf = cb.pinv + (int64_t)kCNB * kCNB * h.fac_max_items;
+    cb.cblk_off = h.fac_rb.as<int64_t>() + st.first;
+    cb.err_sub = h.fac_esub.as<int32_t>() + st.first;
+    cb.err_blk = h.fac_eblk.as<int32_t>() + st.first;
+    const unsigned tiles = (unsigned)((st.bmax + 63) / 64);
+    const unsigned cnt = (unsigned)st.count;
+    for (int P0 = 0; P0 < st.bmax; P0 += kCNB) {
+      hipLaunchKernelGGL(k_cgj_pivot, dim3(cnt), dim3(kPivThreads), 0, s, cb, P0, h.err_flag.as<int32_t>());
+      hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((st.bmax + kPanLines - 1) / kPanLines), cnt), dim3(256), 0, s,
+                         cb, P0);
+      hipLaunchKernelGGL(k_cgj_update, dim3(tiles, tiles, cnt), dim3(256), 0, s, cb, P0);
+      hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((st.bmax + kPanLines - 1) / kPanLines), cnt), dim3(256), 0, s,
+                         cb, P0);
+    }
+    const int64_t nt = (st.bmax + T - 1) / T;
+    const unsigned py = (unsigned)std::min<int64_t>(64, (nt * (nt + 1) / 2 * T * T + 255) / 256);
+    hipLaunchKernelGGL((k_fac_pack<FT, T>), dim3(cnt, py), dim3(256), 0, s, a);
   }
-  for (int first = 0; first < S.n_parts; first += batch) {
-    a.first_sub = first;
-    const int cnt = std::min(batch, S.n_parts - first);
-    hipLaunchKernelGGL(kc, dim3(2 * cnt), dim3(kFacThreads), lds, s, a);
-    hipLaunchKernelGGL(km, dim3(cnt), dim3(kFacThreads), lds, s, a);
-    DDG_HIP(hipGetLastError());
-  }
+  DDG_HIP(hipGetLastError());
 }
 
 template <class FT>
@@ -820,13 +865,15 @@ void launch_coarse_invert(Handle& h, hipStream_t s) {
   cb.pinv = work.as<double>();
   cb.Rbuf = cb.pinv + (int64_t)kCNB * kCNB * h.nb;
   cb.cblk_off = h.cblk_off_d.as<int64_t>();
+  cb.err_sub = nullptr;
+  cb.err_blk = nullptr;
   const unsigned tiles = (unsigned)((nmax + 63) / 64);
   const unsigned nb = (unsigned)h.nb;
   for (int P0 = 0; P0 < nmax; P0 += kCNB) {
-    hipLaunchKernelGGL(k_cgj_pivot, dim3(nb), dim3(256), 0, s, cb, P0, h.err_flag.as<int32_t>());
-    hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((nmax + 127) / 128), nb), dim3(128), 0, s, cb, P0);
+    hipLaunchKernelGGL(k_cgj_pivot, dim3(nb), dim3(kPivThreads), 0, s, cb, P0, h.err_flag.as<int32_t>());
+    hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((nmax + kPanLines - 1) / kPanLines), nb), dim3(256), 0, s, cb, P0);
     hipLaunchKernelGGL(k_cgj_update, dim3(tiles, tiles, nb), dim3(256), 0, s, cb, P0);
-    hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((nmax + 127) / 128), nb), dim3(128), 0, s, cb, P0);
+    hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((nmax + kPanLines - 1) / kPanLines), nb), dim3(256), 0, s, cb, P0);
   }
   const int64_t elems = h.ntiles * 64 * 64;
   hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, cb.A,
