@@ -39,7 +39,7 @@ SWEEP_SOURCES = ["paper_1504_00907_amd/csrc/kernels_sweep.hip", "paper_1504_0090
                  "paper_1504_00907_amd/csrc/device_util.hpp"]
 
 
-def profiled_traffic(precision: str):
+def profiled_traffic(precision: str, tile: int):
     """HBM bytes per k_sweep dispatch from the committed rocprofv3 counter summary.
 
     Returns None when no summary exists for this precision or when the kernel
@@ -58,7 +58,7 @@ def profiled_traffic(precision: str):
     h = hashlib.sha256()
     for src in SWEEP_SOURCES:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    if kv.get("src_sha256_16") != h.hexdigest()[:16]:
+    if kv.get("src_sha256_16") != h.hexdigest()[:16] or kv.get("tile") != str(tile):
         return None
     try:
         return float(kv["traffic_bytes_per_dispatch"])
@@ -351,6 +351,9 @@ def main():
     ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D Q1 elasticity leg")
     ap.add_argument("--elasticity-nel", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--tile", type=int, default=0, help="tile edge of the local factors (0: automatic)")
+    ap.add_argument("--block-target", type=int, default=0, help="level merge target (0: merge only tiny levels)")
+    ap.add_argument("--tune", action="store_true", help="choose tile and merge target with the library's autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -387,9 +390,21 @@ def main():
     f = torch.from_numpy(P.f).cuda()
     A = P.A.to_scipy()
 
+    tile_bt = (args.tile, args.block_target)
+    tuned = None
+    if args.tune:
+        from paper_1504_00907_amd import tune_batched
+        t0 = time.perf_counter()
+        tt, bt, cands = tune_batched([(P.A.row_ptr, P.A.col_idx, P.A.val, P.F, P.part, P.n_parts)], P.overlap,
+                                     args.precision, max_sample=1)
+        tile_bt = (tt, bt)
+        tuned = {"tile": tt, "block_target": bt, "tune_s": time.perf_counter() - t0,
+                 "candidates": [{"tile": c[0], "block_target": c[1], "precond_ms": c[2]} for c in cands]}
+        log(f"autotuner: tile {tt}, block_target {bt} ({tuned['tune_s']:.1f} s): {cands}")
+
     def setup(precision):
         t0 = time.perf_counter()
-        s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol)
+        s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol, tile=tile_bt[0], block_target=tile_bt[1])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         log(f"setup {precision}: wall {wall:.2f} s, device numeric {s.info()['setup_ms']:.1f} ms")
@@ -459,7 +474,7 @@ def main():
         "bound": "hbm", "kernel": "k_sweep (colour-phase local solve)",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": profiled_traffic(args.precision) if args.side == 128 and args.box == 16 else None,
+        "traffic": profiled_traffic(args.precision, hinfo["tile"]) if args.side == 128 and args.box == 16 else None,
         "launches": prof["launches"] if prof else 0,
         "avg_launch_us": (prof["ms"] * 1e3 / prof["launches"]) if prof and prof["launches"] else None,
         "bytes_per_launch": (prof["bytes"] / prof["launches"]) if prof and prof["launches"] else None,
@@ -502,6 +517,7 @@ def main():
         "fwd_adjoint": adj,
         "batched": bat,
         "elasticity": ela,
+        "tuned": tuned,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -83,6 +83,8 @@ typedef struct {
   int64_t coarse_bytes;    /* stored coarse inverse bytes */
   int64_t sweep_bytes;     /* algorithmic HBM bytes of one full preconditioner sweep (both passes) */
   int64_t iter_bytes;      /* algorithmic HBM bytes of one CG iteration */
+  int32_t tile;            /* tile edge of the local factors (16, 32 or 64) */
+  int32_t reserved2;
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */

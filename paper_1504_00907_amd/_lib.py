@@ -36,7 +36,7 @@ class Info(C.Structure):
         ("true_rel_res", C.c_double), ("n_coarse", C.c_int32), ("n_colours", C.c_int32),
         ("n_parts", C.c_int32), ("n_blocks", C.c_int32), ("setup_ms", C.c_double),
         ("solve_ms", C.c_double), ("factor_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
-        ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64),
+        ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("reserved2", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

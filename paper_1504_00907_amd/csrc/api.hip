@@ -104,6 +104,7 @@ void account_bytes(Handle& h, const int64_t* rp) {
   // CG: SpMV (p, q), x/r/p/q update, two dots, p update
   const int64_t cg = nnzb + 2 * n * 8 + 6 * n * 8 + 4 * n * 8 + 3 * n * 8;
   h.info.iter_bytes = sweep + coarse + cg + n * 8;
+  h.info.tile = S.tile;
   h.info.factor_bytes = S.fac_elems * es;
   h.info.coarse_bytes = h.nc ? ntiles * 64 * 64 * 8 : 0;
 }
@@ -604,6 +605,7 @@ int ddg_analyze(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_
     h->info.n_parts = n_parts;
     h->info.n_blocks = (int32_t)h->S.blk_size.size();
     h->info.factor_bytes = h->S.fac_elems * storage_size(h->opt.precision);
+    h->info.tile = h->S.tile;
     hp = h.release();
   });
   if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
