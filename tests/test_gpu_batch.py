@@ -196,3 +196,41 @@ def test_autotuner_picks_a_measured_shape(tmp_path):
         ui = u[b.row_off[i]:b.row_off[i + 1]]
         assert np.linalg.norm(P.f - P.A.to_scipy() @ ui) <= 1.5e-8 * np.linalg.norm(P.f)
     b.close()
+
+
+@pytest.mark.slow
+def test_full_batch_sampled():
+    """The 256-system batch of the benchmark (FP32 factors, rtol 1e-8): every system
+    reaches the residual; sampled systems (smallest, largest, two seeded) match a
+    standalone handle's iteration count and the FP64 oracle's (+-1)."""
+    import multiprocessing as mp
+    from paper_1504_00907_amd import DDGBatchSolver, DDGSolver
+    from workloads import cfg4_sides
+    sides = cfg4_sides()
+    with mp.get_context("spawn").Pool(16) as pool:
+        Ps = pool.starmap(cfg4_instance, [(i, int(L)) for i, L in enumerate(sides)], chunksize=4)
+    probs = [(P.A.row_ptr, P.A.col_idx, P.A.val, P.F, P.part, P.n_parts) for P in Ps]
+    say(f"[batch] {len(Ps)} systems, n = {sum(P.n for P in Ps)}")
+    b = DDGBatchSolver(probs, 2, precision="fp32", rtol=1e-8)
+    u, infos = b.solve(dev(np.concatenate([P.f for P in Ps])))
+    u = host(u)
+    assert all(i["status"] == 0 for i in infos)
+    assert max(i["true_rel_res"] for i in infos) <= 1e-8
+    b.close()
+    order = np.argsort(sides)
+    rng = seed_rng(81, 0)
+    picks = [int(order[0]), int(order[-1])] + [int(x) for x in rng.choice(len(Ps), 2, replace=False)]
+    for i in picks:
+        P = Ps[i]
+        ui = u[b.row_off[i]:b.row_off[i + 1]]
+        true_res = np.linalg.norm(P.f - P.A.to_scipy() @ ui) / np.linalg.norm(P.f)
+        s = DDGSolver.from_problem(P, precision="fp32", rtol=1e-8)
+        us, info_s = s.solve(dev(P.f))
+        s.close()
+        o = DDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap)
+        x, it, _ = o.pcg(P.f, 1e-8)
+        say(f"   system {i} (L={sides[i]}, n={P.n}): iters batch {infos[i]['iters']} alone {info_s['iters']} "
+            f"oracle {it}, true res {true_res:.2e}")
+        assert true_res <= 1.5e-8
+        assert infos[i]["iters"] == info_s["iters"] and abs(infos[i]["iters"] - it) <= 1
+        assert np.linalg.norm(ui - host(us)) <= 1e-8 * np.linalg.norm(ui)

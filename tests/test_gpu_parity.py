@@ -297,3 +297,41 @@ def test_phased_slot_reduction_matches_oracle(name, tile, block_target, precisio
     say(f"   phased {name} {precision}: rel err {err:.2e}")
     assert err <= (1e-12 if precision == "fp64" else 1e-5)
     s.close()
+
+
+@pytest.mark.slow
+def test_full_size_128_against_oracle():
+    """The timed workload at full size (128^3 cells, 512 subdomains, N_c = 5120):
+    one FP64 preconditioner application and the FP64 solve against the oracle,
+    and the mixed FP32 solve in the launch configuration bench.py times."""
+    import time
+    from workloads import cfg2
+    P = cfg2()
+    t0 = time.time()
+    o = DDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap)
+    say(f"[oracle] setup {time.time() - t0:.1f} s")
+    s = make_solver(P, rtol=P.rtol)
+    r = seed_rng(67, 0).standard_normal(P.n)
+    z = host(s.apply_precond(dev(r)))
+    t0 = time.time()
+    ref = o.apply(r)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say(f"   precond rel err {err:.2e} (oracle apply {time.time() - t0:.1f} s)")
+    assert err <= 1e-12
+    u, info = s.solve(dev(P.f))
+    u = host(u)
+    s.close()
+    x, it, _ = o.pcg(P.f, P.rtol)
+    err = np.linalg.norm(u - x) / np.linalg.norm(x)
+    say(f"   fp64 solve: iters {info['iters']} oracle {it} rel err {err:.2e}")
+    assert abs(info["iters"] - it) <= 1
+    if info["iters"] == it:
+        assert err <= 1e-10
+    s = make_solver(P, rtol=P.rtol, precision="fp32")
+    um, im = s.solve(dev(P.f))
+    um = host(um)
+    s.close()
+    true_res = np.linalg.norm(P.f - P.A.to_scipy() @ um) / np.linalg.norm(P.f)
+    say(f"   mixed fp32: iters {im['iters']} true res {true_res:.2e} err vs oracle "
+        f"{np.linalg.norm(um - x) / np.linalg.norm(x):.2e}")
+    assert true_res <= 1.5e-8 and abs(im["iters"] - it) <= 1
