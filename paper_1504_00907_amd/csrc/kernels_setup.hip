@@ -416,61 +416,71 @@ struct CoarseBlocks {
 };
 
 constexpr int kPivThreads = 256;
-constexpr int kPivPer = kCNB * kCNB / kPivThreads;   // pivot-block entries per thread
 
-// Gauss-Jordan inverse of the kCNB x kCNB pivot block in LDS; thread x owns the
-// fixed entries x + q * kPivThreads, so its values stay in registers.
+// Gauss-Jordan inverse of a w x w (w <= 64) block held in registers: thread x
+// owns the 4 x 4 sub-block at rows 4 (x / 16).., columns 4 (x % 16)..; each
+// step publishes only the pivot row and column through LDS (double-buffered,
+// one barrier per step).  On return m holds the inverse (zeros outside w x w).
+__device__ inline void gj_regs(double (&m)[4][4], int w, int32_t* err, int sub, int blk, int row0) {
+  __shared__ double prow[2][kCNB], pcol[2][kCNB];
+  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+  for (int t = 0; t < w; ++t) {
+    const int buf = t & 1;
+    if (t >= r0 && t < r0 + 4)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) prow[buf][c0 + j] = m[t - r0][j];
+    if (t >= c0 && t < c0 + 4)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) pcol[buf][r0 + i] = m[i][t - c0];
+    __syncthreads();
+    double d = prow[buf][t];
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, sub, blk, row0 + t);
+      d = 1.0;
+    }
+    const double rd = 1.0 / d;
+    double ait[4], atc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ait[i] = pcol[buf][r0 + i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) atc[j] = prow[buf][c0 + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int gi = r0 + i, gj = c0 + j;
+        double v;
+        if (gi == t && gj == t) v = rd;
+        else if (gi == t) v = atc[j] * rd;
+        else if (gj == t) v = -ait[i] * rd;
+        else v = m[i][j] - ait[i] * atc[j] * rd;
+        m[i][j] = v;
+      }
+    // a buffer is rewritten two steps later, after the next step's barrier
+  }
+}
+
 __global__ void __launch_bounds__(kPivThreads) k_cgj_pivot(CoarseBlocks cb, int P0, int32_t* err) {
   const int sys = blockIdx.x;
   const int64_t N = cb.n[sys];
   if (P0 >= N) return;
   const int w = (int)min<int64_t>(kCNB, N - P0);
-  double* A = cb.A + cb.a0_off[sys];
+  const double* A = cb.A + cb.a0_off[sys];
   double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
-  __shared__ double piv[kCNB * (kCNB + 1)];
-  for (int idx = threadIdx.x; idx < w * w; idx += kPivThreads)
-    piv[(idx / w) * (kCNB + 1) + idx % w] = A[(int64_t)(P0 + idx / w) * N + P0 + idx % w];
-  __syncthreads();
-  int ii[kPivPer], cc[kPivPer];
+  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+  double m[4][4];
 #pragma unroll
-  for (int q = 0; q < kPivPer; ++q) {
-    const int idx = threadIdx.x + q * kPivThreads;
-    ii[q] = idx < w * w ? idx / w : -1;
-    cc[q] = idx < w * w ? idx % w : 0;
-  }
-  for (int t = 0; t < w; ++t) {
-    double d = piv[t * (kCNB + 1) + t];
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (threadIdx.x == 0) {
-        if (cb.err_sub) record_error(err, DDG_ERR_NOT_SPD, cb.err_sub[sys], cb.err_blk[sys], P0 + t);
-        else record_error(err, DDG_ERR_NOT_SPD, -1, sys, P0 + t);
-      }
-      d = 1.0;
-    }
-    const double rd = 1.0 / d;
-    double nv[kPivPer];
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int q = 0; q < kPivPer; ++q) {
-      const int i = ii[q], c = cc[q];
-      double v = 0.0;
-      if (i >= 0) {
-        const double aic = piv[i * (kCNB + 1) + c];
-        const double ait = piv[i * (kCNB + 1) + t];
-        const double atc = piv[t * (kCNB + 1) + c];
-        if (i == t && c == t) v = rd;
-        else if (i == t) v = atc * rd;
-        else if (c == t) v = -ait * rd;
-        else v = aic - ait * atc * rd;
-      }
-      nv[q] = v;
-    }
-    __syncthreads();
+    for (int j = 0; j < 4; ++j)
+      m[i][j] = (r0 + i < w && c0 + j < w) ? A[(int64_t)(P0 + r0 + i) * N + P0 + c0 + j] : 0.0;
+  const int esub = cb.err_sub ? cb.err_sub[sys] : -1, eblk = cb.err_sub ? cb.err_blk[sys] : sys;
+  gj_regs(m, w, err, esub, eblk, P0);
 #pragma unroll
-    for (int q = 0; q < kPivPer; ++q)
-      if (ii[q] >= 0) piv[ii[q] * (kCNB + 1) + cc[q]] = nv[q];
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < w * w; idx += kPivThreads) pinv[idx] = piv[(idx / w) * (kCNB + 1) + idx % w];
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r0 + i < w && c0 + j < w) pinv[(r0 + i) * w + c0 + j] = m[i][j];
 }
 
 // Row and column panels: a workgroup covers 32 columns (rows) of the panel with
@@ -607,6 +617,142 @@ __global__ void __launch_bounds__(256) k_cgj_col(CoarseBlocks cb, int P0) {
       if (u < w) s += old[u] * pv[u * w + t];
     A[i * N + P0 + t] = -s;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Recursive inverse of one dense SPD block (the coarse matrix of a single
+// system).  With A = [[A11, A12], [A21, A22]], W = A11^{-1} A12 and the Schur
+// complement S = A22 - A21 W:
+//   A^{-1} = [[A11^{-1} + W S^{-1} W^T, -W S^{-1}], [-S^{-1} W^T, S^{-1}]],
+// so the work is two half-size inverses and four GEMMs; the GEMMs run on the
+// FP64 matrix cores and carry almost all of the N^3 flops, which keeps the
+// inversion compute-bound instead of making N/64 passes over the matrix.
+// Leaves (at most 64 rows) are inverted by Gauss-Jordan in LDS.
+
+struct GemmArgs {
+  const double* A;  // M x K, row-major, lda
+  int64_t lda;
+  const double* B;  // K x N row-major (ldb), or N x K row-major when tb
+  int64_t ldb;
+  int32_t tb;
+  double* C;        // M x N, row-major, ldc
+  int64_t ldc;
+  int32_t M, N, K;
+  double alpha, beta;
+};
+
+// C = beta C + alpha A op(B) on 64 x 64 output tiles (same wave/lane layout as k_cgj_update)
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  if (i0 >= g.M || j0 >= g.N) return;
+  constexpr int UC = 32;
+  __shared__ double As[64][UC + 1];
+  __shared__ double Bs[UC][64 + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  mfma_d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < g.K; k0 += UC) {
+    for (int idx = threadIdx.x; idx < 64 * UC; idx += 256) {
+      const int r = idx / UC, u = idx % UC;
+      As[r][u] = (i0 + r < g.M && k0 + u < g.K) ? g.A[(i0 + r) * g.lda + k0 + u] : 0.0;
+      if (g.tb) {
+        const int c = idx / UC, uu = idx % UC;
+        Bs[uu][c] = (j0 + c < g.N && k0 + uu < g.K) ? g.B[(j0 + c) * g.ldb + k0 + uu] : 0.0;
+      } else {
+        const int uu = idx / 64, c = idx % 64;
+        Bs[uu][c] = (j0 + c < g.N && k0 + uu < g.K) ? g.B[(int64_t)(k0 + uu) * g.ldb + j0 + c] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < UC; kk += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) af[x] = As[wr + x * 16 + li][kk + lk];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bf[y] = Bs[kk + lk][wc + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wr + x * 16 + 4 * r + lk;
+        const int64_t j = j0 + wc + y * 16 + li;
+        if (i >= g.M || j >= g.N) continue;
+        double* c = g.C + i * g.ldc + j;
+        *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * acc[x][y][r];
+      }
+}
+
+// dst[j, i] = src[i, j] for i < M, j < N (row-major, leading dimension ld for both)
+__global__ void k_transpose_f64(const double* __restrict__ src, double* __restrict__ dst, int64_t ld, int M, int N) {
+  __shared__ double t[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+  for (int r = ty; r < 32; r += 8)
+    if (bi + r < M && bj + tx < N) t[r][tx] = src[(int64_t)(bi + r) * ld + bj + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8)
+    if (bj + r < N && bi + tx < M) dst[(int64_t)(bj + r) * ld + bi + tx] = t[tx][r];
+}
+
+// in-place Gauss-Jordan inverse of the w x w (w <= 64) SPD block at X (leading dimension ld)
+__global__ void __launch_bounds__(kPivThreads) k_leaf_inv(double* X, int64_t ld, int w, int row0, int32_t* err) {
+  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+  double m[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m[i][j] = (r0 + i < w && c0 + j < w) ? X[(int64_t)(r0 + i) * ld + c0 + j] : 0.0;
+  gj_regs(m, w, err, -1, 0, row0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r0 + i < w && c0 + j < w) X[(int64_t)(r0 + i) * ld + c0 + j] = m[i][j];
+}
+
+void gemm(hipStream_t s, const double* A, int64_t lda, const double* B, int64_t ldb, bool tb, double* C,
+          int64_t ldc, int M, int N, int K, double alpha, double beta) {
+  GemmArgs g{A, lda, B, ldb, tb ? 1 : 0, C, ldc, M, N, K, alpha, beta};
+  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64)), dim3(256), 0, s, g);
+}
+
+// X[lo:hi, lo:hi] (leading dimension ld) <- its inverse; T: workspace stack
+void recursive_inverse(hipStream_t s, double* X, int64_t ld, int lo, int hi, double* T, int32_t* err) {
+  const int n = hi - lo;
+  if (n <= kCNB) {
+    hipLaunchKernelGGL(k_leaf_inv, dim3(1), dim3(kPivThreads), 0, s, X + (int64_t)lo * ld + lo, ld, n, lo, err);
+    return;
+  }
+  const int m = lo + kCNB * ((n + 2 * kCNB - 1) / (2 * kCNB));
+  const int n1 = m - lo, n2 = hi - m;
+  double* X11 = X + (int64_t)lo * ld + lo;
+  double* X12 = X + (int64_t)lo * ld + m;
+  double* X21 = X + (int64_t)m * ld + lo;
+  double* X22 = X + (int64_t)m * ld + m;
+  double* W = T;                                    // n1 x n2, leading dimension n2
+  recursive_inverse(s, X, ld, lo, m, T + (int64_t)n1 * n2, err);        // X11 <- A11^{-1}
+  gemm(s, X11, ld, X12, ld, false, W, n2, n1, n2, n1, 1.0, 0.0);        // W = A11^{-1} A12
+  gemm(s, X21, ld, W, n2, false, X22, ld, n2, n2, n1, -1.0, 1.0);       // X22 = A22 - A21 W
+  recursive_inverse(s, X, ld, m, hi, T + (int64_t)n1 * n2, err);        // X22 <- S^{-1}
+  gemm(s, W, n2, X22, ld, false, X12, ld, n1, n2, n2, -1.0, 0.0);       // X12 = -W S^{-1}
+  gemm(s, X12, ld, W, n2, true, X11, ld, n1, n1, n2, -1.0, 1.0);        // X11 -= X12 W^T
+  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)((n2 + 31) / 32), (unsigned)((n1 + 31) / 32)), dim3(256), 0,
+                     s, X12, X21, ld, n1, n2);                          // X21 = X12^T
 }
 
 // tile t of the packed inverses (system tile_inst[t]); zero beyond the block's order
@@ -858,6 +1004,19 @@ void launch_coarse_invert(Handle& h, hipStream_t s) {
   DevBuf inv;
   inv.alloc((size_t)total * sizeof(double));
   DDG_HIP(hipMemcpyAsync(inv.p, h.A0.p, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (h.nb == 1 && nmax > 2 * kCNB) {
+    // one system: recursive inverse on the matrix cores
+    DevBuf T;
+    T.alloc((size_t)(nmax * nmax / 2 + 1) * sizeof(double));
+    recursive_inverse(s, inv.as<double>(), nmax, 0, (int)nmax, T.as<double>(), h.err_flag.as<int32_t>());
+    const int64_t elems = h.ntiles * 64 * 64;
+    hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, inv.as<double>(),
+                       h.a0_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.tile_inst.as<int32_t>(),
+                       h.tile_base_d.as<int64_t>(), h.ntiles, h.A0inv_t.as<double>());
+    DDG_HIP(hipGetLastError());
+    DDG_HIP(hipStreamSynchronize(s));
+    return;
+  }
   CoarseBlocks cb;
   cb.A = inv.as<double>();
   cb.a0_off = h.a0_off_d.as<int64_t>();
