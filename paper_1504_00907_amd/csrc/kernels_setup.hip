@@ -439,22 +439,19 @@ __device__ inline void gj_regs(double (&m)[4][4], int w, int32_t* err, int sub, 
       d = 1.0;
     }
     const double rd = 1.0 / d;
-    double ait[4], atc[4];
+    // branch-free step: with P_i = rd on the pivot row (else -a_it rd) and Q_j = 1 on the
+    // pivot column (else a_tj), every entry becomes (row t or column t ? 0 : a_ij) + P_i Q_j
+    double P[4], Q[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ait[i] = pcol[buf][r0 + i];
+    for (int i = 0; i < 4; ++i) P[i] = (r0 + i == t) ? rd : -pcol[buf][r0 + i] * rd;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) atc[j] = prow[buf][c0 + j];
+    for (int j = 0; j < 4; ++j) Q[j] = (c0 + j == t) ? 1.0 : prow[buf][c0 + j];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int gi = r0 + i, gj = c0 + j;
-        double v;
-        if (gi == t && gj == t) v = rd;
-        else if (gi == t) v = atc[j] * rd;
-        else if (gj == t) v = -ait[i] * rd;
-        else v = m[i][j] - ait[i] * atc[j] * rd;
-        m[i][j] = v;
+        const double base = (r0 + i == t || c0 + j == t) ? 0.0 : m[i][j];
+        m[i][j] = __builtin_fma(P[i], Q[j], base);
       }
     // a buffer is rewritten two steps later, after the next step's barrier
   }
