@@ -170,9 +170,18 @@ __global__ void __launch_bounds__(kQrThreads) k_coarse_qr(
 // Galerkin product
 
 constexpr int kGalThreads = 256;
-constexpr int kGalAcc = 16;
 constexpr int kGalLds = 48 * 1024;
 
+typedef double gal_d4 __attribute__((ext_vector_type(4)));
+
+// Block row i of A0 = R0 A R0^T (Section 4): for every coupled subdomain j,
+//   A0[koff_i + a, koff_j + b] = sum_{g in Omega_i} Q[g, a] (A Q_j)[g, b].
+// The rows of Omega_i are taken in chunks: W[r, (s, b)] = (A Q_j)[g_r, b] for a
+// group of neighbours s is formed in LDS from the sparse rows, then the dense
+// contraction Q_i^T W runs on the FP64 matrix cores (v_mfma_f64_16x16x4: the
+// k <= 32 coarse columns of subdomain i are one or two 16-row tiles, each wave
+// owns 16-column slabs of the group's (s, b) columns, the chunk rows are the
+// reduction dimension).
 __global__ void __launch_bounds__(kGalThreads) k_galerkin(
     const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
     const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr_idx,
@@ -182,6 +191,7 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
     const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ cblk_off,
     const int32_t* __restrict__ cblk_n, const int64_t* __restrict__ a0_off, double* __restrict__ A0) {
   __shared__ double lds[kGalLds / 8];
+  constexpr int SL = 4;                     // slabs per wave (per row tile)
   const int i = blockIdx.x;
   // the block row of subdomain i lies in the dense coarse block of its system
   const int sys = sub_inst[i];
@@ -192,64 +202,84 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
   const int nb0 = nbr_ptr[i];
   const int nnb = nbr_ptr[i + 1] - nb0;
   const int ki = kcnt[i];
-  const int tid = threadIdx.x;
-  // slots per group so that every thread holds at most kGalAcc accumulators
-  const int per_slot = kq * kq;
-  int gslots = (kGalThreads * kGalAcc) / per_slot;
-  if (gslots < 1) gslots = 1;
-  for (int g0 = 0; g0 < nnb; g0 += gslots) {
-    const int gs = min(gslots, nnb - g0);
-    const int entries = gs * per_slot;
-    int ch = kGalLds / (8 * (gs * kq + kq));
-    if (ch > 64) ch = 64;
-    double* Wc = lds;               // [ch][gs][kq]
-    double* Qc = lds + ch * gs * kq;  // [ch][kq]
-    double acc[kGalAcc];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt_n = kq > 16 ? 2 : 1;         // row tiles of the k coarse columns of i
+  const int slabs_max = 4 * (mt_n == 1 ? SL : SL / 2);
+  const int gmax = max(1, (slabs_max * 16) / kq);
+  for (int g0 = 0; g0 < nnb; g0 += gmax) {
+    const int gs = min(gmax, nnb - g0);
+    const int ncol = gs * kq;
+    int ch = kGalLds / (8 * (ncol + kq));
+    ch = min(64, ch) & ~3;
+    double* Wc = lds;               // [ch][ncol]
+    double* Qc = lds + ch * ncol;   // [ch][kq]
+    gal_d4 acc[2][SL];
 #pragma unroll
-    for (int u = 0; u < kGalAcc; ++u) acc[u] = 0.0;
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int q = 0; q < SL; ++q) acc[m][q] = gal_d4{0.0, 0.0, 0.0, 0.0};
     for (int r0 = 0; r0 < ni; r0 += ch) {
       const int rows = min(ch, ni - r0);
-      for (int idx = tid; idx < rows * gs * kq; idx += kGalThreads) {
-        const int r = idx / (gs * kq);
-        const int s = (idx / kq) % gs;
-        const int b = idx % kq;
+      const int rows4 = (rows + 3) & ~3;
+      for (int idx = tid; idx < rows4 * ncol; idx += kGalThreads) Wc[idx] = 0.0;
+      __syncthreads();
+      // thread (r, b) adds every stored entry of row r into column b of its neighbour's slot
+      // (neighbour ids ascending: binary search within the group)
+      const int32_t* grp = nbr_idx + nb0 + g0;
+      for (int idx = tid; idx < rows * kq; idx += kGalThreads) {
+        const int r = idx / kq, b = idx % kq;
         const int g = own_idx[base + r0 + r];
-        const int j = nbr_idx[nb0 + g0 + s];
-        double w = 0.0;
         for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
           const int c = ci[t];
-          if (part[c] == j) w += val[t] * Q[(int64_t)c * kq + b];
+          const int j = part[c];
+          int lo = 0, hi = gs;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (grp[mid] < j) lo = mid + 1;
+            else hi = mid;
+          }
+          if (lo < gs && grp[lo] == j) Wc[r * ncol + lo * kq + b] += val[t] * Q[(int64_t)c * kq + b];
         }
-        Wc[idx] = w;
       }
-      for (int idx = tid; idx < rows * kq; idx += kGalThreads) {
+      for (int idx = tid; idx < rows4 * kq; idx += kGalThreads) {
         const int r = idx / kq, a = idx % kq;
-        Qc[idx] = Q[(int64_t)own_idx[base + r0 + r] * kq + a];
+        Qc[idx] = r < rows ? Q[(int64_t)own_idx[base + r0 + r] * kq + a] : 0.0;
       }
       __syncthreads();
+      for (int k0 = 0; k0 < rows4; k0 += 4) {
+        const int r = k0 + lk;
+        double af[2];
 #pragma unroll
-      for (int u = 0; u < kGalAcc; ++u) {
-        const int e = tid + u * kGalThreads;
-        if (e < entries) {
-          const int s = e / per_slot;
-          const int a = (e / kq) % kq;
-          const int b = e % kq;
-          double v = acc[u];
-          for (int r = 0; r < rows; ++r) v += Qc[r * kq + a] * Wc[(r * gs + s) * kq + b];
-          acc[u] = v;
+        for (int m = 0; m < 2; ++m) {
+          const int a = m * 16 + li;
+          af[m] = (m < mt_n && a < kq) ? Qc[r * kq + a] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+          const int col = (q * 4 + wave) * 16 + li;
+          const double bf = col < ncol ? Wc[r * ncol + col] : 0.0;
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+            if (m < mt_n) acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m], bf, acc[m][q], 0, 0, 0);
         }
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < kGalAcc; ++u) {
-      const int e = tid + u * kGalThreads;
-      if (e < entries) {
-        const int s = e / per_slot;
-        const int a = (e / kq) % kq;
-        const int b = e % kq;
-        const int j = nbr_idx[nb0 + g0 + s];
-        if (a < ki && b < kcnt[j]) A0b[(koff[i] + a - c0) * nc + koff[j] + b - c0] = acc[u];
+    for (int m = 0; m < 2; ++m) {
+      if (m >= mt_n) continue;
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        const int col = (q * 4 + wave) * 16 + li;
+        if (col >= ncol) continue;
+        const int sj = col / kq, b = col % kq;
+        const int j = nbr_idx[nb0 + g0 + sj];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int a = m * 16 + 4 * e + lk;
+          if (a < ki && b < kcnt[j]) A0b[(koff[i] + a - c0) * nc + koff[j] + b - c0] = acc[m][q][e];
+        }
       }
     }
   }
