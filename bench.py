@@ -349,6 +349,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg (256 uneven 2D systems)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D Q1 elasticity leg")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the forward+adjoint leg and print its record (for profiling the refactor)")
     ap.add_argument("--elasticity-nel", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--tile", type=int, default=0, help="tile edge of the local factors (0: automatic)")
@@ -384,6 +386,10 @@ def main():
         ms = ev0.elapsed_time(ev1) / 10
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
                           "copy_ms": ms, "copy_GBps": 2 * a.numel() * 8 / ms / 1e6}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"fwd_adjoint": fwd_adjoint(args.adjoint_side, args.precision, max(1, args.steps), 1)}),
+              flush=True)
         return
     log(f"generating workload {args.side}^3, boxes {args.box}^3")
     P = cfg2(side=args.side, box=args.box)
