@@ -193,6 +193,7 @@ struct Handle {
   std::vector<FacStage> fac_stages;
   DevBuf fac_items, fac_off, fac_n, fac_rb, fac_esub, fac_eblk;
   int32_t fac_max_items = 0;
+  int64_t fac_wstride = 0;   // per-item workspace of the recursive level inverse
   DevBuf fac_scratch, fac_tm, fac_work;
   DevBuf err_flag;        // int32[4]: setup error (code, subdomain, block, pivot)
 

@@ -669,9 +669,7 @@ struct GemmArgs {
 };
 
 // C = beta C + alpha A op(B) on 64 x 64 output tiles (same wave/lane layout as k_cgj_update)
-__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  if (i0 >= g.M || j0 >= g.N) return;
+__device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
   constexpr int UC = 32;
   __shared__ double As[64][UC + 1];
   __shared__ double Bs[UC][64 + 1];
@@ -722,6 +720,12 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
         double* c = g.C + i * g.ldc + j;
         *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * acc[x][y][r];
       }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  if (i0 >= g.M || j0 >= g.N) return;
+  gemm_tile(g, i0, j0);
 }
 
 // dst[j, i] = src[i, j] for i < M, j < N (row-major, leading dimension ld for both)
@@ -802,6 +806,107 @@ __global__ void k_pack_coarse(const double* __restrict__ A, const int64_t* __res
   double v = 0.0;
   if (row < N && col < N) v = (row >= col) ? Ab[row * N + col] : Ab[col * N + row];
   out[idx] = v;
+}
+
+// Batched recursive inverse of the level matrices of one stage (item q: S at
+// scratch + off[q], n[q] x n[q], leading dimension n[q]).  The recursion tree is
+// built on the stage's widest level; an item takes each node [lo, hi) with split
+// m clipped to its own size, so one launch per node serves every item.
+struct BInv {
+  double* scratch;
+  const int64_t* off;
+  const int32_t* n;
+  double* W;          // per item workspace of wstride elements
+  int64_t wstride;
+  const int32_t* err_sub;
+  const int32_t* err_blk;
+};
+
+__global__ void __launch_bounds__(kPivThreads) k_bleaf(BInv bi, int lo, int hi, int32_t* err) {
+  const int q = blockIdx.x;
+  const int b = bi.n[q];
+  if (lo >= b) return;
+  const int w = min(hi, b) - lo;
+  double* X = bi.scratch + bi.off[q] + (int64_t)lo * b + lo;
+  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+  double m[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m[i][j] = (r0 + i < w && c0 + j < w) ? X[(int64_t)(r0 + i) * b + c0 + j] : 0.0;
+  gj_regs(m, w, err, bi.err_sub[q], bi.err_blk[q], lo);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r0 + i < w && c0 + j < w) X[(int64_t)(r0 + i) * b + c0 + j] = m[i][j];
+}
+
+// op 0: W = X11 X12; 1: X22 -= X21 W; 2: X12 = -W X22; 3: X11 -= X12 W^T
+__global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid, int hi, int64_t woff, int ldw) {
+  const int q = blockIdx.z;
+  const int b = bi.n[q];
+  if (lo >= b) return;
+  const int m = min(mid, b), h = min(hi, b);
+  const int n1 = m - lo, n2 = h - m;
+  if (n2 <= 0) return;
+  double* X = bi.scratch + bi.off[q];
+  double* W = bi.W + (int64_t)q * bi.wstride + woff;
+  double* X11 = X + (int64_t)lo * b + lo;
+  double* X12 = X + (int64_t)lo * b + m;
+  double* X21 = X + (int64_t)m * b + lo;
+  double* X22 = X + (int64_t)m * b + m;
+  GemmArgs g;
+  switch (op) {
+    case 0: g = GemmArgs{X11, b, X12, b, 0, W, ldw, n1, n2, n1, 1.0, 0.0}; break;
+    case 1: g = GemmArgs{X21, b, W, ldw, 0, X22, b, n2, n2, n1, -1.0, 1.0}; break;
+    case 2: g = GemmArgs{W, ldw, X22, b, 0, X12, b, n1, n2, n2, -1.0, 0.0}; break;
+    default: g = GemmArgs{X12, b, W, ldw, 1, X11, b, n1, n1, n2, -1.0, 1.0}; break;
+  }
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  if (i0 >= g.M || j0 >= g.N) return;
+  gemm_tile(g, i0, j0);
+}
+
+// X21 = X12^T for every item
+__global__ void k_btranspose(BInv bi, int lo, int mid, int hi) {
+  const int q = blockIdx.z;
+  const int b = bi.n[q];
+  if (lo >= b) return;
+  const int m = min(mid, b), h = min(hi, b);
+  const int n1 = m - lo, n2 = h - m;
+  if (n2 <= 0) return;
+  double* X = bi.scratch + bi.off[q];
+  const double* src = X + (int64_t)lo * b + m;
+  double* dst = X + (int64_t)m * b + lo;
+  __shared__ double t[32][33];
+  const int bi0 = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8)
+    if (bi0 + r < n1 && bj + tx < n2) t[r][tx] = src[(int64_t)(bi0 + r) * b + bj + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8)
+    if (bj + r < n2 && bi0 + tx < n1) dst[(int64_t)(bj + r) * b + bi0 + tx] = t[tx][r];
+}
+
+void binv_node(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi, int64_t woff, int32_t* err) {
+  const int n = hi - lo;
+  if (n <= kCNB) {
+    hipLaunchKernelGGL(k_bleaf, dim3(cnt), dim3(kPivThreads), 0, s, bi, lo, hi, err);
+    return;
+  }
+  const int m = lo + kCNB * ((n + 2 * kCNB - 1) / (2 * kCNB));
+  const int n1 = m - lo, n2 = hi - m;
+  const int64_t next = woff + (int64_t)n1 * n2;
+  auto gemm_grid = [&](int M, int N) { return dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), cnt); };
+  binv_node(s, bi, cnt, lo, m, next, err);
+  hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n2), dim3(256), 0, s, bi, 0, lo, m, hi, woff, n2);
+  hipLaunchKernelGGL(k_bgemm, gemm_grid(n2, n2), dim3(256), 0, s, bi, 1, lo, m, hi, woff, n2);
+  binv_node(s, bi, cnt, m, hi, next, err);
+  hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n2), dim3(256), 0, s, bi, 2, lo, m, hi, woff, n2);
+  hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n1), dim3(256), 0, s, bi, 3, lo, m, hi, woff, n2);
+  hipLaunchKernelGGL(k_btranspose, dim3((unsigned)((n2 + 31) / 32), (unsigned)((n1 + 31) / 32), cnt), dim3(256), 0,
+                     s, bi, lo, m, hi);
 }
 
 // Schedule of the batched factorisation: groups of subdomains whose scratch
@@ -930,7 +1035,8 @@ void launch_factor_t(Handle& h, hipStream_t s) {
     h.fac_eblk.upload(eblk, s);
     h.fac_scratch.alloc((size_t)P.scratch_elems * sizeof(double));
     h.fac_tm.alloc((size_t)P.tm_elems * sizeof(double));
-    h.fac_work.alloc(((size_t)kCNB * kCNB * P.max_items + (size_t)P.rb_elems) * sizeof(double));
+    h.fac_wstride = bmax * bmax / 2 + 64;
+    h.fac_work.alloc((size_t)h.fac_wstride * P.max_items * sizeof(double));
     h.fac_max_items = P.max_items;
     h.fac_plan_ready = true;
   }
@@ -960,25 +1066,16 @@ void launch_factor_t(Handle& h, hipStream_t s) {
     hipLaunchKernelGGL(k_fac_tm, dim3((unsigned)st.count, ny), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_fac_form, dim3((unsigned)st.count, ny), dim3(256), 0, s, a);
     if (!st.gj) continue;
-    CoarseBlocks cb;
-    cb.A = a.scratch;
-    cb.a0_off = h.fac_off.as<int64_t>() + st.first;
-    cb.n = h.fac_n.as<int32_t>() + st.first;
-    cb.pinv = h.fac_work.as<double>();
-    cb.Rbuf = cb.pinv + (int64_t)kCNB * kCNB * h.fac_max_items;
-    cb.cblk_off = h.fac_rb.as<int64_t>() + st.first;
-    cb.err_sub = h.fac_esub.as<int32_t>() + st.first;
-    cb.err_blk = h.fac_eblk.as<int32_t>() + st.first;
-    const unsigned tiles = (unsigned)((st.bmax + 63) / 64);
+    BInv bi;
+    bi.scratch = a.scratch;
+    bi.off = h.fac_off.as<int64_t>() + st.first;
+    bi.n = h.fac_n.as<int32_t>() + st.first;
+    bi.W = h.fac_work.as<double>();
+    bi.wstride = h.fac_wstride;
+    bi.err_sub = h.fac_esub.as<int32_t>() + st.first;
+    bi.err_blk = h.fac_eblk.as<int32_t>() + st.first;
     const unsigned cnt = (unsigned)st.count;
-    for (int P0 = 0; P0 < st.bmax; P0 += kCNB) {
-      hipLaunchKernelGGL(k_cgj_pivot, dim3(cnt), dim3(kPivThreads), 0, s, cb, P0, h.err_flag.as<int32_t>());
-      hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((st.bmax + kPanLines - 1) / kPanLines), cnt), dim3(256), 0, s,
-                         cb, P0);
-      hipLaunchKernelGGL(k_cgj_update, dim3(tiles, tiles, cnt), dim3(256), 0, s, cb, P0);
-      hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((st.bmax + kPanLines - 1) / kPanLines), cnt), dim3(256), 0, s,
-                         cb, P0);
-    }
+    binv_node(s, bi, cnt, 0, st.bmax, 0, h.err_flag.as<int32_t>());
     const int64_t nt = (st.bmax + T - 1) / T;
     const unsigned py = (unsigned)std::min<int64_t>(64, (nt * (nt + 1) / 2 * T * T + 255) / 256);
     hipLaunchKernelGGL((k_fac_pack<FT, T>), dim3(cnt, py), dim3(256), 0, s, a);
