@@ -191,7 +191,7 @@ struct Handle {
   };
   bool fac_plan_ready = false;
   std::vector<FacStage> fac_stages;
-  DevBuf fac_items, fac_off, fac_n, fac_rb, fac_esub, fac_eblk;
+  DevBuf fac_items, fac_off, fac_n, fac_esub, fac_eblk;
   int32_t fac_max_items = 0;
   int64_t fac_wstride = 0;   // per-item workspace of the recursive level inverse
   DevBuf fac_scratch, fac_tm, fac_work;

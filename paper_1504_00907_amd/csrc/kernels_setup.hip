@@ -429,21 +429,10 @@ __global__ void k_gather_vals(const int64_t* __restrict__ pos, const double* __r
 }
 
 // ---------------------------------------------------------------------------
-// Coarse inverse: blocked Gauss-Jordan over the whole device, one dense block
-// per independent system (the last grid dimension selects the system).
+// Dense SPD inverses (coarse blocks and local levels): Gauss-Jordan on blocks
+// of at most kCNB rows, recursive Schur complements above.
 
 constexpr int kCNB = 64;
-
-struct CoarseBlocks {
-  double* A;               // dense blocks
-  const int64_t* a0_off;   // element offset of each block
-  const int32_t* n;        // order of each block
-  double* pinv;            // per system kCNB x kCNB
-  double* Rbuf;            // per system kCNB x (order), at kCNB * cblk_off
-  const int64_t* cblk_off;
-  const int32_t* err_sub;  // when set (local levels): subdomain and level reported on a bad pivot
-  const int32_t* err_blk;
-};
 
 constexpr int kPivThreads = 256;
 
@@ -487,164 +476,7 @@ __device__ inline void gj_regs(double (&m)[4][4], int w, int32_t* err, int sub, 
   }
 }
 
-__global__ void __launch_bounds__(kPivThreads) k_cgj_pivot(CoarseBlocks cb, int P0, int32_t* err) {
-  const int sys = blockIdx.x;
-  const int64_t N = cb.n[sys];
-  if (P0 >= N) return;
-  const int w = (int)min<int64_t>(kCNB, N - P0);
-  const double* A = cb.A + cb.a0_off[sys];
-  double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
-  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
-  double m[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      m[i][j] = (r0 + i < w && c0 + j < w) ? A[(int64_t)(P0 + r0 + i) * N + P0 + c0 + j] : 0.0;
-  const int esub = cb.err_sub ? cb.err_sub[sys] : -1, eblk = cb.err_sub ? cb.err_blk[sys] : sys;
-  gj_regs(m, w, err, esub, eblk, P0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (r0 + i < w && c0 + j < w) pinv[(r0 + i) * w + c0 + j] = m[i][j];
-}
-
-// Row and column panels: a workgroup covers 32 columns (rows) of the panel with
-// 8 threads each, every thread producing 8 of the (up to) 64 panel entries; all
-// old values are read before any is overwritten.
-constexpr int kPanLines = 32, kPanSplit = 8, kPanOut = kCNB / kPanSplit;
-
-// row panel R = Pinv A[P, :] for columns outside P; written to Rbuf and in place
-__global__ void __launch_bounds__(256) k_cgj_row(CoarseBlocks cb, int P0) {
-  const int sys = blockIdx.y;
-  const int64_t N = cb.n[sys];
-  if (P0 >= N) return;
-  const int w = (int)min<int64_t>(kCNB, N - P0);
-  double* A = cb.A + cb.a0_off[sys];
-  const double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
-  double* Rbuf = cb.Rbuf + kCNB * cb.cblk_off[sys];
-  __shared__ double pv[kCNB * kCNB];
-  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) pv[idx] = pinv[idx];
-  const int64_t c = (int64_t)blockIdx.x * kPanLines + threadIdx.x % kPanLines;
-  const int t0 = (threadIdx.x / kPanLines) * kPanOut;
-  const bool active = c < N && !(c >= P0 && c < P0 + w);
-  double old[kCNB];
-#pragma unroll
-  for (int u = 0; u < kCNB; ++u) old[u] = (active && u < w) ? A[(int64_t)(P0 + u) * N + c] : 0.0;
-  __syncthreads();  // pv loaded; every old value of this workgroup's columns read
-  if (!active) return;
-#pragma unroll
-  for (int q = 0; q < kPanOut; ++q) {
-    const int t = t0 + q;
-    if (t < w) {
-      double s = 0.0;
-#pragma unroll
-      for (int u = 0; u < kCNB; ++u)
-        if (u < w) s += pv[t * w + u] * old[u];
-      Rbuf[(int64_t)t * N + c] = s;
-      A[(int64_t)(P0 + t) * N + c] = s;
-    }
-  }
-}
-
-// trailing update on 64 x 64 output tiles: A[i, c] -= A[i, P] R[P, c], on the
-// FP64 matrix cores.  Each of the 4 waves computes a 32 x 32 quadrant as 2 x 2
-// products of 16 x 16 tiles (v_mfma_f64_16x16x4: lane l feeds A[l%16][l/16] and
-// B[l/16][l%16] and receives D[4r + l/16][l%16] in result register r), the
-// panels staged through LDS in 32-wide chunks.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
-
-__global__ void __launch_bounds__(256) k_cgj_update(CoarseBlocks cb, int P0) {
-  const int sys = blockIdx.z;
-  const int64_t N = cb.n[sys];
-  const int64_t i0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-  if (P0 >= N || i0 >= N || c0 >= N) return;
-  const int w = (int)min<int64_t>(kCNB, N - P0);
-  double* A = cb.A + cb.a0_off[sys];
-  const double* Rbuf = cb.Rbuf + kCNB * cb.cblk_off[sys];
-  constexpr int UC = 32;
-  __shared__ double cp[64][UC + 1];   // column panel rows of this tile
-  __shared__ double rp[UC][64 + 1];   // row panel columns of this tile
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int li = lane & 15, lk = lane >> 4;
-  mfma_d4 acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-  for (int u0 = 0; u0 < w; u0 += UC) {
-    for (int idx = threadIdx.x; idx < 64 * UC; idx += 256) {
-      const int r = idx / UC, u = idx % UC;
-      const int64_t i = i0 + r;
-      cp[r][u] = (u0 + u < w && i < N) ? A[i * N + P0 + u0 + u] : 0.0;
-      const int uu = idx / 64, cc = idx % 64;
-      const int64_t c = c0 + cc;
-      rp[uu][cc] = (u0 + uu < w && c < N) ? Rbuf[(int64_t)(u0 + uu) * N + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k0 = 0; k0 < UC; k0 += 4) {
-      double af[2], bf[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) af[x] = cp[wr + x * 16 + li][k0 + lk];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) bf[y] = rp[k0 + lk][wc + y * 16 + li];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + wr + x * 16 + 4 * r + lk;
-        const int64_t c = c0 + wc + y * 16 + li;
-        if (i >= N || c >= N || (i >= P0 && i < P0 + w) || (c >= P0 && c < P0 + w)) continue;
-        A[i * N + c] -= acc[x][y][r];
-      }
-}
-
-// column panel A[i, P] = -A[i, P] Pinv (rows outside P) and the pivot block itself
-__global__ void __launch_bounds__(256) k_cgj_col(CoarseBlocks cb, int P0) {
-  const int sys = blockIdx.y;
-  const int64_t N = cb.n[sys];
-  if (P0 >= N) return;
-  const int w = (int)min<int64_t>(kCNB, N - P0);
-  double* A = cb.A + cb.a0_off[sys];
-  const double* pinv = cb.pinv + (int64_t)sys * kCNB * kCNB;
-  __shared__ double pv[kCNB * kCNB];
-  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) pv[idx] = pinv[idx];
-  const int64_t i = (int64_t)blockIdx.x * kPanLines + threadIdx.x % kPanLines;
-  const int t0 = (threadIdx.x / kPanLines) * kPanOut;
-  const bool pivot_row = i >= P0 && i < P0 + w;
-  const bool active = i < N;
-  double old[kCNB];
-#pragma unroll
-  for (int u = 0; u < kCNB; ++u) old[u] = (active && !pivot_row && u < w) ? A[i * N + P0 + u] : 0.0;
-  __syncthreads();  // pv loaded; every old value of this workgroup's rows read
-  if (!active) return;
-#pragma unroll
-  for (int q = 0; q < kPanOut; ++q) {
-    const int t = t0 + q;
-    if (t >= w) continue;
-    if (pivot_row) {
-      A[i * N + P0 + t] = pv[(i - P0) * w + t];
-      continue;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < kCNB; ++u)
-      if (u < w) s += old[u] * pv[u * w + t];
-    A[i * N + P0 + t] = -s;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Recursive inverse of one dense SPD block (the coarse matrix of a single
@@ -668,7 +500,11 @@ struct GemmArgs {
   double alpha, beta;
 };
 
-// C = beta C + alpha A op(B) on 64 x 64 output tiles (same wave/lane layout as k_cgj_update)
+// C = beta C + alpha A op(B) on 64 x 64 output tiles on the FP64 matrix cores: each of
+// the 4 waves computes a 32 x 32 quadrant as 2 x 2 products of 16 x 16 tiles
+// (v_mfma_f64_16x16x4: lane l feeds A[l%16][l/16] and B[l/16][l%16] and receives
+// D[4r + l/16][l%16] in result register r), the operands staged through LDS in
+// 32-wide chunks of the reduction dimension.
 __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
   constexpr int UC = 32;
   __shared__ double As[64][UC + 1];
@@ -722,70 +558,6 @@ __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
       }
 }
 
-__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  if (i0 >= g.M || j0 >= g.N) return;
-  gemm_tile(g, i0, j0);
-}
-
-// dst[j, i] = src[i, j] for i < M, j < N (row-major, leading dimension ld for both)
-__global__ void k_transpose_f64(const double* __restrict__ src, double* __restrict__ dst, int64_t ld, int M, int N) {
-  __shared__ double t[32][33];
-  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
-  for (int r = ty; r < 32; r += 8)
-    if (bi + r < M && bj + tx < N) t[r][tx] = src[(int64_t)(bi + r) * ld + bj + tx];
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8)
-    if (bj + r < N && bi + tx < M) dst[(int64_t)(bj + r) * ld + bi + tx] = t[tx][r];
-}
-
-// in-place Gauss-Jordan inverse of the w x w (w <= 64) SPD block at X (leading dimension ld)
-__global__ void __launch_bounds__(kPivThreads) k_leaf_inv(double* X, int64_t ld, int w, int row0, int32_t* err) {
-  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
-  double m[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) m[i][j] = (r0 + i < w && c0 + j < w) ? X[(int64_t)(r0 + i) * ld + c0 + j] : 0.0;
-  gj_regs(m, w, err, -1, 0, row0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (r0 + i < w && c0 + j < w) X[(int64_t)(r0 + i) * ld + c0 + j] = m[i][j];
-}
-
-void gemm(hipStream_t s, const double* A, int64_t lda, const double* B, int64_t ldb, bool tb, double* C,
-          int64_t ldc, int M, int N, int K, double alpha, double beta) {
-  GemmArgs g{A, lda, B, ldb, tb ? 1 : 0, C, ldc, M, N, K, alpha, beta};
-  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64)), dim3(256), 0, s, g);
-}
-
-// X[lo:hi, lo:hi] (leading dimension ld) <- its inverse; T: workspace stack
-void recursive_inverse(hipStream_t s, double* X, int64_t ld, int lo, int hi, double* T, int32_t* err) {
-  const int n = hi - lo;
-  if (n <= kCNB) {
-    hipLaunchKernelGGL(k_leaf_inv, dim3(1), dim3(kPivThreads), 0, s, X + (int64_t)lo * ld + lo, ld, n, lo, err);
-    return;
-  }
-  const int m = lo + kCNB * ((n + 2 * kCNB - 1) / (2 * kCNB));
-  const int n1 = m - lo, n2 = hi - m;
-  double* X11 = X + (int64_t)lo * ld + lo;
-  double* X12 = X + (int64_t)lo * ld + m;
-  double* X21 = X + (int64_t)m * ld + lo;
-  double* X22 = X + (int64_t)m * ld + m;
-  double* W = T;                                    // n1 x n2, leading dimension n2
-  recursive_inverse(s, X, ld, lo, m, T + (int64_t)n1 * n2, err);        // X11 <- A11^{-1}
-  gemm(s, X11, ld, X12, ld, false, W, n2, n1, n2, n1, 1.0, 0.0);        // W = A11^{-1} A12
-  gemm(s, X21, ld, W, n2, false, X22, ld, n2, n2, n1, -1.0, 1.0);       // X22 = A22 - A21 W
-  recursive_inverse(s, X, ld, m, hi, T + (int64_t)n1 * n2, err);        // X22 <- S^{-1}
-  gemm(s, W, n2, X22, ld, false, X12, ld, n1, n2, n2, -1.0, 0.0);       // X12 = -W S^{-1}
-  gemm(s, X12, ld, W, n2, true, X11, ld, n1, n1, n2, -1.0, 1.0);        // X11 -= X12 W^T
-  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)((n2 + 31) / 32), (unsigned)((n1 + 31) / 32)), dim3(256), 0,
-                     s, X12, X21, ld, n1, n2);                          // X21 = X12^T
-}
-
 // tile t of the packed inverses (system tile_inst[t]); zero beyond the block's order
 __global__ void k_pack_coarse(const double* __restrict__ A, const int64_t* __restrict__ a0_off,
                               const int32_t* __restrict__ nblk, const int32_t* __restrict__ tile_inst,
@@ -816,11 +588,16 @@ struct BInv {
   double* scratch;
   const int64_t* off;
   const int32_t* n;
-  double* W;          // per item workspace of wstride elements
+  double* W;          // per item workspace: wstride elements each, or at woffs[q] when given
   int64_t wstride;
-  const int32_t* err_sub;
+  const int64_t* woffs;
+  const int32_t* err_sub;   // NULL: a coarse block (reported as coarse row)
   const int32_t* err_blk;
 };
+
+__device__ inline double* binv_work(const BInv& bi, int q) {
+  return bi.W + (bi.woffs ? bi.woffs[q] : (int64_t)q * bi.wstride);
+}
 
 __global__ void __launch_bounds__(kPivThreads) k_bleaf(BInv bi, int lo, int hi, int32_t* err) {
   const int q = blockIdx.x;
@@ -834,7 +611,8 @@ __global__ void __launch_bounds__(kPivThreads) k_bleaf(BInv bi, int lo, int hi, 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) m[i][j] = (r0 + i < w && c0 + j < w) ? X[(int64_t)(r0 + i) * b + c0 + j] : 0.0;
-  gj_regs(m, w, err, bi.err_sub[q], bi.err_blk[q], lo);
+  if (bi.err_sub) gj_regs(m, w, err, bi.err_sub[q], bi.err_blk[q], lo);
+  else gj_regs(m, w, err, -1, bi.err_blk ? bi.err_blk[q] : q, lo);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -851,7 +629,7 @@ __global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid,
   const int n1 = m - lo, n2 = h - m;
   if (n2 <= 0) return;
   double* X = bi.scratch + bi.off[q];
-  double* W = bi.W + (int64_t)q * bi.wstride + woff;
+  double* W = binv_work(bi, q) + woff;
   double* X11 = X + (int64_t)lo * b + lo;
   double* X12 = X + (int64_t)lo * b + m;
   double* X21 = X + (int64_t)m * b + lo;
@@ -889,6 +667,16 @@ __global__ void k_btranspose(BInv bi, int lo, int mid, int hi) {
     if (bj + r < n2 && bi0 + tx < n1) dst[(int64_t)(bj + r) * b + bi0 + tx] = t[tx][r];
 }
 
+// Workspace elements per item that binv_node(lo = 0, hi = n) touches: W of a node
+// sits at the node's stack offset and spans n1 x n2 (leading dimension n2).
+int64_t binv_work_need(int lo, int hi, int64_t woff) {
+  const int n = hi - lo;
+  if (n <= kCNB) return woff;
+  const int m = lo + kCNB * ((n + 2 * kCNB - 1) / (2 * kCNB));
+  const int64_t next = woff + (int64_t)(m - lo) * (hi - m);
+  return std::max(next, std::max(binv_work_need(lo, m, next), binv_work_need(m, hi, next)));
+}
+
 void binv_node(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi, int64_t woff, int32_t* err) {
   const int n = hi - lo;
   if (n <= kCNB) {
@@ -920,7 +708,7 @@ struct FacPlanHost {
   std::vector<FacItem> items;
   std::vector<Stage> stages;
   std::vector<int32_t> group_first;   // stage index where each group starts
-  int64_t scratch_elems = 0, tm_elems = 0, rb_elems = 0;
+  int64_t scratch_elems = 0, tm_elems = 0;
   int32_t max_items = 0;
 };
 
@@ -1003,7 +791,6 @@ void build_fac_plan(const Symbolic& S, FacPlanHost& P) {
     }
   }
   for (auto& st : P.stages) P.max_items = std::max(P.max_items, st.count);
-  P.rb_elems = (int64_t)P.max_items * kCNB * bmax;
 }
 
 template <class FT, int T>
@@ -1015,8 +802,8 @@ void launch_factor_t(Handle& h, hipStream_t s) {
     h.fac_items.upload(P.items, s);
     h.fac_stages.clear();
     for (auto& st : P.stages) h.fac_stages.push_back({st.first, st.count, st.gj, st.bmax});
-    // per-item arrays for the Gauss-Jordan kernels, one block per stage (same item order)
-    std::vector<int64_t> off(P.items.size()), rb(P.items.size());
+    // per-item arrays of the inversion kernels, one block per stage (same item order)
+    std::vector<int64_t> off(P.items.size());
     std::vector<int32_t> n(P.items.size()), esub(P.items.size()), eblk(P.items.size());
     const int64_t bmax = std::max<int32_t>(1, S.max_blk);
     for (auto& st : P.stages)
@@ -1024,18 +811,16 @@ void launch_factor_t(Handle& h, hipStream_t s) {
         const FacItem& it = P.items[st.first + q];
         off[st.first + q] = it.s_off;
         n[st.first + q] = S.blk_size[it.cur];
-        rb[st.first + q] = (int64_t)q * bmax;
         esub[st.first + q] = it.sub;
         eblk[st.first + q] = it.cur - S.sub_blk_ptr[it.sub];
       }
     h.fac_off.upload(off, s);
     h.fac_n.upload(n, s);
-    h.fac_rb.upload(rb, s);
     h.fac_esub.upload(esub, s);
     h.fac_eblk.upload(eblk, s);
     h.fac_scratch.alloc((size_t)P.scratch_elems * sizeof(double));
     h.fac_tm.alloc((size_t)P.tm_elems * sizeof(double));
-    h.fac_wstride = bmax * bmax / 2 + 64;
+    h.fac_wstride = binv_work_need(0, (int)bmax, 0) + 64;
     h.fac_work.alloc((size_t)h.fac_wstride * P.max_items * sizeof(double));
     h.fac_max_items = P.max_items;
     h.fac_plan_ready = true;
@@ -1072,6 +857,7 @@ void launch_factor_t(Handle& h, hipStream_t s) {
     bi.n = h.fac_n.as<int32_t>() + st.first;
     bi.W = h.fac_work.as<double>();
     bi.wstride = h.fac_wstride;
+    bi.woffs = nullptr;
     bi.err_sub = h.fac_esub.as<int32_t>() + st.first;
     bi.err_blk = h.fac_eblk.as<int32_t>() + st.first;
     const unsigned cnt = (unsigned)st.count;
@@ -1122,44 +908,58 @@ void launch_coarse_invert(Handle& h, hipStream_t s) {
   const int64_t total = h.a0_off[h.nb];
   int64_t nmax = 0;
   for (int32_t b = 0; b < h.nb; ++b) nmax = std::max<int64_t>(nmax, h.cblk_n[b]);
-  DevBuf work;
-  work.alloc(((size_t)kCNB * kCNB * h.nb + (size_t)kCNB * h.nc_pad) * sizeof(double));
   // the inverse is formed in a copy so that A0 stays available for export
   DevBuf inv;
   inv.alloc((size_t)total * sizeof(double));
   DDG_HIP(hipMemcpyAsync(inv.p, h.A0.p, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (h.nb == 1 && nmax > 2 * kCNB) {
-    // one system: recursive inverse on the matrix cores
-    DevBuf T;
-    T.alloc((size_t)(nmax * nmax / 2 + 1) * sizeof(double));
-    recursive_inverse(s, inv.as<double>(), nmax, 0, (int)nmax, T.as<double>(), h.err_flag.as<int32_t>());
-    const int64_t elems = h.ntiles * 64 * 64;
-    hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, inv.as<double>(),
-                       h.a0_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.tile_inst.as<int32_t>(),
-                       h.tile_base_d.as<int64_t>(), h.ntiles, h.A0inv_t.as<double>());
-    DDG_HIP(hipGetLastError());
+  // recursive inverse of every coarse block, one item per system: systems sorted by
+  // order and taken in groups whose workspace (the tree of the group's largest
+  // block, for every item) stays within a budget
+  std::vector<int32_t> order(h.nb);
+  for (int32_t b = 0; b < h.nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return h.cblk_n[x] > h.cblk_n[y]; });
+  const int64_t budget = ((int64_t)1 << 30) / 8;   // workspace elements (1 GiB)
+  const int64_t need0 = binv_work_need(0, (int)nmax, 0) + 64;
+  DevBuf W, gd;
+  W.alloc((size_t)std::max(need0, std::min<int64_t>(budget, need0 * h.nb)) * sizeof(double));
+  gd.alloc((size_t)h.nb * (sizeof(int64_t) + 2 * sizeof(int32_t)));
+  std::vector<int64_t> goff;
+  std::vector<int32_t> gn, gsys;
+  for (int32_t i0 = 0; i0 < h.nb;) {
+    const int32_t nfirst = h.cblk_n[order[i0]];
+    if (nfirst == 0) break;   // the remaining systems have no coarse space
+    const int64_t need = binv_work_need(0, nfirst, 0) + 64;
+    const int32_t cnt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(h.nb - i0, (int64_t)(W.bytes / 8) / need));
+    goff.assign(cnt, 0);
+    gn.assign(cnt, 0);
+    gsys.assign(cnt, 0);
+    for (int32_t q = 0; q < cnt; ++q) {
+      goff[q] = h.a0_off[order[i0 + q]];
+      gn[q] = h.cblk_n[order[i0 + q]];
+      gsys[q] = order[i0 + q];
+    }
+    int64_t* doff = gd.as<int64_t>();
+    int32_t* dn = reinterpret_cast<int32_t*>(doff + h.nb);
+    int32_t* dsys = dn + h.nb;
+    DDG_HIP(hipMemcpyAsync(doff, goff.data(), cnt * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DDG_HIP(hipMemcpyAsync(dn, gn.data(), cnt * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    DDG_HIP(hipMemcpyAsync(dsys, gsys.data(), cnt * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    BInv bi;
+    bi.scratch = inv.as<double>();
+    bi.off = doff;
+    bi.n = dn;
+    bi.W = W.as<double>();
+    bi.wstride = need;
+    bi.woffs = nullptr;
+    bi.err_sub = nullptr;
+    bi.err_blk = dsys;
+    binv_node(s, bi, (unsigned)cnt, 0, nfirst, 0, h.err_flag.as<int32_t>());
+    // the host arrays are reused by the next group: wait for this group's copies
     DDG_HIP(hipStreamSynchronize(s));
-    return;
-  }
-  CoarseBlocks cb;
-  cb.A = inv.as<double>();
-  cb.a0_off = h.a0_off_d.as<int64_t>();
-  cb.n = h.cblk_n_d.as<int32_t>();
-  cb.pinv = work.as<double>();
-  cb.Rbuf = cb.pinv + (int64_t)kCNB * kCNB * h.nb;
-  cb.cblk_off = h.cblk_off_d.as<int64_t>();
-  cb.err_sub = nullptr;
-  cb.err_blk = nullptr;
-  const unsigned tiles = (unsigned)((nmax + 63) / 64);
-  const unsigned nb = (unsigned)h.nb;
-  for (int P0 = 0; P0 < nmax; P0 += kCNB) {
-    hipLaunchKernelGGL(k_cgj_pivot, dim3(nb), dim3(kPivThreads), 0, s, cb, P0, h.err_flag.as<int32_t>());
-    hipLaunchKernelGGL(k_cgj_row, dim3((unsigned)((nmax + kPanLines - 1) / kPanLines), nb), dim3(256), 0, s, cb, P0);
-    hipLaunchKernelGGL(k_cgj_update, dim3(tiles, tiles, nb), dim3(256), 0, s, cb, P0);
-    hipLaunchKernelGGL(k_cgj_col, dim3((unsigned)((nmax + kPanLines - 1) / kPanLines), nb), dim3(256), 0, s, cb, P0);
+    i0 += cnt;
   }
   const int64_t elems = h.ntiles * 64 * 64;
-  hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, cb.A,
+  hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, inv.as<double>(),
                      h.a0_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.tile_inst.as<int32_t>(),
                      h.tile_base_d.as<int64_t>(), h.ntiles, h.A0inv_t.as<double>());
   DDG_HIP(hipGetLastError());
