@@ -41,11 +41,18 @@ class DiffusionSolver:
         self.solver = DDGSolver(self.n, self.row_ptr, self.col_idx, val.cpu().numpy(), F, part, n_parts,
                                 overlap, precision=precision, rtol=rtol, max_iter=max_iter, **kw)
         self.val = val
+        self.theta = theta0.detach().clone()   # coefficients of the current factorisation
         self.last_info = {}
 
     def refactor(self, theta: torch.Tensor):
         stencil_assemble(self.dims, theta, self.val)
         self.solver.refactor(self.val)
+        self.theta = theta.detach().clone()
+
+    def ensure(self, theta: torch.Tensor):
+        """Refactor unless the handle already holds A(exp(theta))."""
+        if not torch.equal(self.theta, theta):
+            self.refactor(theta)
 
     def solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None):
         u, info = self.solver.solve(f, u)
@@ -64,6 +71,8 @@ class DDGSolveFunction(torch.autograd.Function):
         theta = theta.detach().contiguous()
         if refactor:
             ds.refactor(theta)
+        else:
+            ds.ensure(theta)
         u = ds.solve(f.detach().contiguous())
         ctx.ds = ds
         ctx.save_for_backward(theta, u)
@@ -73,6 +82,8 @@ class DDGSolveFunction(torch.autograd.Function):
     def backward(ctx, grad_u: torch.Tensor):
         theta, u = ctx.saved_tensors
         ds = ctx.ds
+        # another forward may have refactored the shared handle since this one ran
+        ds.ensure(theta)
         lam = ds.solve(grad_u.contiguous())
         grad_theta = ds.coeff_grad(theta, u, lam)
         return grad_theta, lam, None, None

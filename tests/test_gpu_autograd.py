@@ -219,3 +219,30 @@ def test_full_size_96_sampled():
     say(f"   FD over 32 cells: max rel err {rel.max():.2e} ({time.time() - t0:.1f} s)")
     assert not check_fd(fd, g[cells])
     ds.solver.close()
+
+
+def test_backward_after_another_forward():
+    """Two forwards on one handle, then the backwards in reverse order: each gradient
+    equals the one from its own forward/backward pair (the handle is refactored back)."""
+    from paper_1504_00907_amd import ddg_solve_fn
+    c = SMALL["3d16_b2"]()
+    ds = c.solver(rtol=1e-12)
+    ds.refactor(dev(c.theta_obs))
+    u_obs = ds.solve(dev(c.f)).clone()
+    th1 = dev(c.theta)
+    th2 = dev(c.theta + 0.3 * np.sin(np.arange(c.n)).reshape(c.theta.shape))
+    ref = []
+    for th in (th1, th2):
+        _, _, g, _ = loss_and_grad(ds, host(th).reshape(c.theta.shape), c.f, u_obs)
+        ref.append(g)
+    t1 = th1.clone().requires_grad_(True)
+    t2 = th2.clone().requires_grad_(True)
+    L1 = ((ddg_solve_fn(t1, dev(c.f), ds) - u_obs) ** 2).sum()
+    L2 = ((ddg_solve_fn(t2, dev(c.f), ds) - u_obs) ** 2).sum()
+    L2.backward()
+    L1.backward()
+    for t, g in ((t1, ref[0]), (t2, ref[1])):
+        err = np.linalg.norm(host(t.grad) - g) / np.linalg.norm(g)
+        say(f"   reordered backward: rel diff {err:.2e}")
+        assert err <= 1e-12
+    ds.solver.close()
