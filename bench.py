@@ -459,6 +459,18 @@ def main():
         }
         s64.close()
         del s64
+        if args.precision != "bf16":
+            # BF16 factors on the same system (tried and reported; FP64 Krylov vectors and coarse inverse)
+            sbf, _ = setup("bf16")
+            log("timing bf16 path")
+            ms_bf, info_bf, _, u_bf, res_bf = timed(sbf, max(1, args.steps), args.warmup, profile=False)
+            log(f"bf16: {ms_bf:.2f} ms/solve, iters {info_bf['iters']}, true res {res_bf:.2e}")
+            out64.update({
+                "bf16_ms_per_solve": ms_bf, "bf16_iters": info_bf["iters"], "bf16_true_rel_res": res_bf,
+                "bf16_vs_fp64_rel_diff": float(np.linalg.norm(u_bf - u_64) / np.linalg.norm(u_64)),
+            })
+            sbf.close()
+            del sbf
 
     ela = None
     if not args.no_elasticity:
