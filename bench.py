@@ -127,7 +127,7 @@ def cpu_baseline(P, iters: int, n_sample: int = 24, seed: int = 5):
     }
 
 
-def elasticity(nel: int, steps: int):
+def elasticity(nel: int, steps: int, tile: int = 0, block_target: int = 0):
     """3D clamped Q1 elasticity leg: FP64, FP32 and BF16 local factors on the same system.
 
     nel^3 trilinear hexahedra (default 64^3: 811,200 free dofs), E = exp(0.5 z)
@@ -154,7 +154,7 @@ def elasticity(nel: int, steps: int):
     u64 = None
     for prec in ("fp64", "fp32", "bf16"):
         t0 = time.perf_counter()
-        s = DDGSolver.from_problem(P, precision=prec, rtol=1e-8)
+        s = DDGSolver.from_problem(P, precision=prec, rtol=1e-8, tile=tile, block_target=block_target)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         u = torch.empty_like(f)
@@ -352,6 +352,8 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the forward+adjoint leg and print its record (for profiling the refactor)")
     ap.add_argument("--elasticity-nel", type=int, default=64)
+    ap.add_argument("--elasticity-tile", type=int, default=0)
+    ap.add_argument("--elasticity-block-target", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--tile", type=int, default=0, help="tile edge of the local factors (0: automatic)")
     ap.add_argument("--block-target", type=int, default=0, help="level merge target (0: merge only tiny levels)")
@@ -474,7 +476,8 @@ def main():
 
     ela = None
     if not args.no_elasticity:
-        ela = elasticity(args.elasticity_nel, max(1, args.steps // 2))
+        ela = elasticity(args.elasticity_nel, max(1, args.steps // 2), args.elasticity_tile,
+                         args.elasticity_block_target)
         torch.cuda.empty_cache()
 
     bat = None
