@@ -351,6 +351,8 @@ def main():
     ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D Q1 elasticity leg")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the forward+adjoint leg and print its record (for profiling the refactor)")
+    ap.add_argument("--elasticity-only", action="store_true",
+                    help="run only the 3D elasticity leg and print its record")
     ap.add_argument("--elasticity-nel", type=int, default=64)
     ap.add_argument("--elasticity-tile", type=int, default=0)
     ap.add_argument("--elasticity-block-target", type=int, default=0)
@@ -388,6 +390,10 @@ def main():
         ms = ev0.elapsed_time(ev1) / 10
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
                           "copy_ms": ms, "copy_GBps": 2 * a.numel() * 8 / ms / 1e6}), flush=True)
+        return
+    if args.elasticity_only:
+        print(json.dumps({"elasticity": elasticity(args.elasticity_nel, max(1, args.steps // 2), args.elasticity_tile,
+                                                   args.elasticity_block_target)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"fwd_adjoint": fwd_adjoint(args.adjoint_side, args.precision, max(1, args.steps), 1)}),

@@ -77,8 +77,9 @@ void account_bytes(Handle& h, const int64_t* rp) {
       int64_t fb = 0;
       const int32_t K = S.sub_blk_ptr[i + 1] - S.sub_blk_ptr[i];
       for (int32_t k = 0; k < K; ++k) {
+        // every level's inverse is read on the way down and back, the middle one once
         const int64_t tb = tile_bytes(S.blk_size[S.sub_blk_ptr[i] + k], S.tile, es);
-        fb += tb * (k + 1 < K ? 2 : 1);
+        fb += tb * (k == S.sub_mid[i] ? 1 : 2);
       }
       const int64_t r0 = S.set_ptr[i], r1 = S.set_ptr[i + 1];
       const int64_t ni = r1 - r0;
@@ -219,6 +220,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->blk_start.upload(S.blk_start, s);
   h->blk_size.upload(S.blk_size, s);
   h->blk_foff.upload(S.blk_foff, s);
+  h->sub_mid.upload(S.sub_mid, s);
   h->lo_col.upload(S.lo_col, s);
   h->lo_pos.upload(S.lo_pos, s);
   h->up_col.upload(S.up_col, s);
@@ -228,6 +230,18 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->in_pos.upload(S.in_pos, s);
   h->lo_val.alloc(std::max<size_t>(1, S.lo_pos.size()) * sizeof(double));
   h->up_val.alloc(std::max<size_t>(1, S.up_pos.size()) * sizeof(double));
+  if (S.sliced) {
+    h->blk_slice.upload(S.blk_slice, s);
+    h->sl_row.upload(S.sl_row, s);
+    h->sl_rows.upload(S.sl_rows, s);
+    h->sl_lo_off.upload(S.sl_lo_off, s);
+    h->sl_up_off.upload(S.sl_up_off, s);
+    h->sl_lo_col.upload(S.sl_lo_col, s);
+    h->sl_up_col.upload(S.sl_up_col, s);
+    const size_t vs = h->opt.precision == DDG_FP64 ? sizeof(double) : sizeof(float);
+    h->sl_lo_val.alloc(std::max<size_t>(1, S.sl_lo_col.size()) * vs);
+    h->sl_up_val.alloc(std::max<size_t>(1, S.sl_up_col.size()) * vs);
+  }
   // two-workgroup sweep: every pair of a colour must be resident at once
   int ncu = 0;
   DDG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -303,6 +317,16 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     DDG_HIP(hipMemsetAsync(h->cy.p, 0, (size_t)2 * h->nc_pad * sizeof(double), s));
     h->cpart.alloc((size_t)2 * h->ntiles * 64 * sizeof(double));
   }
+  // row-dot kernels: lanes per CSR row; the coarse restriction runs four passes of
+  // its workgroup per chunk of own rows
+  h->lpr = lanes_per_row(S.nnz, n);
+  if (const char* env = std::getenv("DDG_ROW_LANES")) {
+    const int v = std::atoi(env);
+    if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) h->lpr = v;
+  }
+  h->rch = 4 * 256 / h->lpr;
+  h->nch = std::max<int32_t>(1, (S.max_own + h->rch - 1) / h->rch);
+  if (h->nc > 0) h->rpart.alloc((size_t)n_parts * h->nch * 32 * sizeof(double));
   // CG workspace
   h->r.alloc((size_t)n * sizeof(double));
   h->p.alloc((size_t)n * sizeof(double));

@@ -87,6 +87,7 @@ struct Symbolic {
   std::vector<int32_t> blk_start;    // first local row of each block
   std::vector<int32_t> blk_size;     // rows of each block
   std::vector<int64_t> blk_foff;     // element offset of each block's tiles in the factor array
+  std::vector<int32_t> sub_mid;      // middle level m of each subdomain's twisted factorisation
   int64_t fac_elems = 0;
   int32_t tile = 64;
   int32_t max_set = 0, max_blk = 0, max_blocks = 0, max_own = 0;
@@ -99,12 +100,35 @@ struct Symbolic {
   std::vector<int64_t> in_ptr;                   // sum|set|+1
   std::vector<int32_t> in_col;
   std::vector<int64_t> in_pos;
+  // The same lower/upper couplings in the sweep's sliced layout, built when some row
+  // has more than kCplRegs couplings in a direction: every level is cut into slices
+  // of 64 consecutive rows; a slice stores its entries column by column (entry q of
+  // its row at lane l sits at off[slice] + 64 q + l), padded to the slice's longest
+  // row with value 0 and the row's own local index as column (lanes past the end of
+  // the block: column 0, never read).  The values are refreshed from the ELL arrays.
+  bool sliced = false;
+  std::vector<int32_t> blk_slice;                // n_blocks+1: first slice of each block
+  std::vector<int64_t> sl_row;                   // per slice: global set row of its lane 0
+  std::vector<int32_t> sl_rows;                  // per slice: rows of the block it holds (<= 64)
+  std::vector<int64_t> sl_lo_off, sl_up_off;     // n_slices+1 entry offsets
+  std::vector<int32_t> sl_lo_col, sl_up_col;     // local column of each entry
 };
+
+// Couplings per row and direction that the sweep keeps in registers; wider rows use
+// the sliced layout.
+constexpr int kCplRegs = 2;
 
 // Builds every integer structure; throws Error on malformed input.
 void build_symbolic(Symbolic& S, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                     const int32_t* part, int32_t n_parts, int32_t overlap, int32_t tile,
                     int32_t block_target);
+
+// Lanes per CSR row in the row-dot kernels for a matrix with nnz entries in n rows:
+// about ten entries per lane, one lane for stencil-sized rows.
+inline int32_t lanes_per_row(int64_t nnz, int64_t n) {
+  const double avg = n > 0 ? (double)nnz / (double)n : 0.0;
+  return avg <= 12.0 ? 1 : avg <= 24.0 ? 2 : avg <= 48.0 ? 4 : avg <= 96.0 ? 8 : 16;
+}
 
 // Tile layout helpers shared by host and device.
 __host__ __device__ inline int32_t tiles_for(int32_t b, int32_t T) {
@@ -163,6 +187,10 @@ struct Handle {
   DevBuf wg_seg, wg_lo, wg_hi, seg_wg_ptr_d;
   std::vector<int32_t> seg_wg_ptr;
   int32_t dev_lds_limit = 65536;
+  int32_t lpr = 1;                   // lanes per CSR row in the row-dot kernels (lanes_per_row)
+  int32_t rch = 1024;                // own rows per workgroup of the coarse restriction
+  int32_t nch = 1;                   // restriction workgroups per subdomain
+  DevBuf rpart;                      // restriction partials: n_parts x nch x 32
 
   // device copies
   DevBuf rowptr, col, val;           // CSR
@@ -170,10 +198,13 @@ struct Handle {
   DevBuf set_ptr, set_idx;
   DevBuf colour_subs;
   DevBuf nbr_ptr, nbr_idx;
-  DevBuf sub_blk_ptr, blk_start, blk_size, blk_foff;
+  DevBuf sub_blk_ptr, blk_start, blk_size, blk_foff, sub_mid;
   DevBuf lo_col, lo_pos, lo_val;     // ELL lower couplings
   DevBuf up_col, up_pos, up_val;     // ELL upper couplings
   DevBuf in_ptr, in_col, in_pos;
+  DevBuf blk_slice, sl_row, sl_rows;                 // sliced couplings (Symbolic::sliced)
+  DevBuf sl_lo_off, sl_up_off, sl_lo_col, sl_up_col;
+  DevBuf sl_lo_val, sl_up_val;                       // in the sweep's arithmetic type
   DevBuf xch, flags;                 // two-workgroup handoff buffers of the twisted sweep
   DevBuf bres;                       // local residuals of one colour's expanded sets
   int32_t xch_ld = 0;

@@ -1,8 +1,12 @@
-// Device helpers: fixed-order wave64/block reductions and storage-type conversions.
+// Device helpers: fixed-order wave64/block reductions, storage-type conversions and
+// CSR row dots by groups of lanes.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <type_traits>
 
 namespace ddg {
 
@@ -58,5 +62,35 @@ template <> struct Store<__hip_bfloat16> {
   __device__ static float to_acc(__hip_bfloat16 x) { return __bfloat162float(x); }
   __device__ static __hip_bfloat16 from(double x) { return __float2bfloat16((float)x); }
 };
+
+// Dot of CSR row g with x by a group of L consecutive lanes of a wave (L a power
+// of two, at most 16): lane j of the group takes the entries j, j + L, ... in
+// order, then an xor butterfly over the group adds the L partials, so every lane
+// of the group returns the same reproducible value.  L = 1 is the plain
+// sequential row sum.  All lanes of a group must be active together.
+template <int L>
+__device__ inline double row_dot_l(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                   const double* __restrict__ v, const double* __restrict__ x, int64_t g,
+                                   int j) {
+  double s = 0.0;
+  const int64_t t1 = rp[g + 1];
+#pragma unroll 4
+  for (int64_t t = rp[g] + j; t < t1; t += L) s += v[t] * x[ci[t]];
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Calls f(std::integral_constant<int, L>{}) for the run-time lanes-per-row value.
+template <class Fn>
+inline void with_lanes(int L, Fn&& f) {
+  switch (L) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
+  }
+}
 
 }  // namespace ddg

@@ -37,20 +37,19 @@ struct SegMap {
   const int32_t* ptr;   // nb+1: partials of system b are [ptr[b], ptr[b+1])
 };
 
-__device__ inline double row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                 const double* __restrict__ v, const double* __restrict__ x,
-                                 int64_t g) {
-  double s = 0.0;
-  for (int64_t t = rp[g]; t < rp[g + 1]; ++t) s += v[t] * x[ci[t]];
-  return s;
-}
-
+// Row-dot kernels take L lanes per CSR row (row_dot_l): a workgroup covers
+// kThreads / L rows per pass and lane 0 of each group stores the row's result.
+template <int L>
 __global__ void k_spmv(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                        const double* __restrict__ v, const double* __restrict__ x,
                        double* __restrict__ y, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) y[i] = row_dot(rp, ci, v, x, i);
+  const int j = threadIdx.x & (L - 1);
+  int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x / L;
+  for (; i < n; i += stride) {
+    const double s = row_dot_l<L>(rp, ci, v, x, i, j);
+    if (j == 0) y[i] = s;
+  }
 }
 
 // x = 0, r = f, partial f.f
@@ -143,6 +142,7 @@ __global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ 
 }
 
 // q = A p, partial p.q
+template <int L>
 __global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restrict__ rp,
                            const int32_t* __restrict__ ci, const double* __restrict__ v,
                            const double* __restrict__ p, double* __restrict__ q,
@@ -151,10 +151,13 @@ __global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restri
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
   const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-    double qi = row_dot(rp, ci, v, p, i);
-    q[i] = qi;
-    acc += p[i] * qi;
+  const int j = threadIdx.x & (L - 1);
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
+    const double qi = row_dot_l<L>(rp, ci, v, p, i, j);
+    if (j == 0) {
+      q[i] = qi;
+      acc += p[i] * qi;
+    }
   }
   double s = block_sum<kThreads>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -233,15 +236,17 @@ __global__ void k_xpby(const CgState* stb, SegMap m, const double* __restrict__ 
 }
 
 // partial ||f - A x||^2 (always runs)
+template <int L>
 __global__ void k_resid_dot(SegMap m, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                             const double* __restrict__ v, const double* __restrict__ f,
                             const double* __restrict__ x, double* __restrict__ part) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
   const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-    double d = f[i] - row_dot(rp, ci, v, x, i);
-    acc += d * d;
+  const int j = threadIdx.x & (L - 1);
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
+    const double d = f[i] - row_dot_l<L>(rp, ci, v, x, i, j);
+    if (j == 0) acc += d * d;
   }
   double s = block_sum<kThreads>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -266,14 +271,16 @@ SegMap segmap(const Handle& h) {
 }  // namespace
 
 // Row ranges of the reduction workgroups: each system is cut into at most 1024
-// contiguous chunks of at least 2048 rows (a multiple of 256).
+// contiguous chunks (a multiple of 256 rows) of at least 2048 rows, or 2048 / L
+// rows (but 256 at least) when the row dots take L lanes per row.
 void build_cg_map(Handle& h, hipStream_t s) {
   std::vector<int32_t> seg;
   std::vector<int64_t> lo, hi;
   h.seg_wg_ptr.assign(h.nb + 1, 0);
+  const int64_t min_chunk = std::max(256, 2048 / std::max(1, h.lpr));
   for (int32_t b = 0; b < h.nb; ++b) {
     const int64_t a0 = h.seg_off[b], a1 = h.seg_off[b + 1], nb = a1 - a0;
-    int64_t chunk = std::max<int64_t>(2048, (nb + 1023) / 1024);
+    int64_t chunk = std::max<int64_t>(min_chunk, (nb + 1023) / 1024);
     chunk = (chunk + kThreads - 1) / kThreads * kThreads;
     int64_t cnt = std::max<int64_t>(1, (nb + chunk - 1) / chunk);
     for (int64_t c = 0; c < cnt; ++c) {
@@ -300,8 +307,11 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
 }
 
 void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv, dim3(grid_for(h.S.n)), dim3(kThreads), 0, s, h.rowptr.as<int64_t>(),
-                     h.col.as<int32_t>(), h.val.as<double>(), x, y, h.S.n);
+  with_lanes(h.lpr, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    hipLaunchKernelGGL(k_spmv<L>, dim3(grid_for(h.S.n * L)), dim3(kThreads), 0, s, h.rowptr.as<int64_t>(),
+                       h.col.as<int32_t>(), h.val.as<double>(), x, y, h.S.n);
+  });
 }
 
 void launch_cg_init(Handle& h, const double* f, double* x, hipStream_t s) {
@@ -323,9 +333,12 @@ void launch_cg_start(Handle& h, hipStream_t s) {
 void launch_cg_step_a(Handle& h, double* x, hipStream_t s) {
   const SegMap m = segmap(h);
   CgState* st = h.cstate.as<CgState>();
-  hipLaunchKernelGGL(k_spmv_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.rowptr.as<int64_t>(),
-                     h.col.as<int32_t>(), h.val.as<double>(), h.p.as<double>(), h.q.as<double>(),
-                     h.part_sums.as<double>());
+  with_lanes(h.lpr, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    hipLaunchKernelGGL(k_spmv_dot<L>, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.rowptr.as<int64_t>(),
+                       h.col.as<int32_t>(), h.val.as<double>(), h.p.as<double>(), h.q.as<double>(),
+                       h.part_sums.as<double>());
+  });
   hipLaunchKernelGGL(k_alpha_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>());
   hipLaunchKernelGGL(k_axpy2_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, x, h.r.as<double>(),
                      h.p.as<double>(), h.q.as<double>(), h.part_sums.as<double>());
@@ -343,8 +356,11 @@ void launch_cg_step_b(Handle& h, hipStream_t s) {
 
 void launch_true_residual(Handle& h, const double* f, const double* x, hipStream_t s) {
   const SegMap m = segmap(h);
-  hipLaunchKernelGGL(k_resid_dot, dim3(h.n_partials), dim3(kThreads), 0, s, m, h.rowptr.as<int64_t>(),
-                     h.col.as<int32_t>(), h.val.as<double>(), f, x, h.part_sums.as<double>());
+  with_lanes(h.lpr, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    hipLaunchKernelGGL(k_resid_dot<L>, dim3(h.n_partials), dim3(kThreads), 0, s, m, h.rowptr.as<int64_t>(),
+                       h.col.as<int32_t>(), h.val.as<double>(), f, x, h.part_sums.as<double>());
+  });
   hipLaunchKernelGGL(k_true_scalar, dim3(h.nb), dim3(kThreads), 0, s, h.cstate.as<CgState>(), m,
                      h.part_sums.as<double>());
 }

@@ -21,27 +21,41 @@ namespace {
 constexpr int kRThreads = 256;
 constexpr int kMaxK = 32;
 
+// Partial restriction over one chunk of the own rows of subdomain i (workgroup
+// (c, i) takes rows [own_ptr[i] + c rch, ... + rch)), L lanes per CSR row:
+//   rpart[i, c, m] = sum_{g in chunk} Q[g, m] (r - A e)_g,   m < kcnt[i]
+// (waves in order after a butterfly per wave); empty chunks write zeros.
+template <int L>
 __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
-    const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
-    const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff, const double* __restrict__ Q,
-    int kq, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-    const double* __restrict__ val, const double* __restrict__ r, const double* __restrict__ e,
-    double* __restrict__ b0) {
-  const int i = blockIdx.x;
+    const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr,
+    const int32_t* __restrict__ own_idx, const int32_t* __restrict__ kcnt, const double* __restrict__ Q, int kq,
+    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ val,
+    const double* __restrict__ r, const double* __restrict__ e, int rch, double* __restrict__ rpart) {
+  const int i = blockIdx.y, c = blockIdx.x;
   if (st && st[sub_inst[i]].done) return;
   __shared__ double red[kRThreads / 64][kMaxK];
   const int ki = kcnt[i];
   double acc[kMaxK];
 #pragma unroll
   for (int m = 0; m < kMaxK; ++m) acc[m] = 0.0;
-  for (int64_t t = own_ptr[i] + threadIdx.x; t < own_ptr[i + 1]; t += kRThreads) {
+  const int64_t t0 = own_ptr[i] + (int64_t)c * rch;
+  const int64_t t1 = min(own_ptr[i + 1], t0 + rch);
+  const int jl = threadIdx.x & (L - 1);
+  for (int64_t t = t0 + threadIdx.x / L; t < t1; t += kRThreads / L) {
     const int g = own_idx[t];
-    double s = r[g];
-    for (int64_t u = rp[g]; u < rp[g + 1]; ++u) s -= val[u] * e[ci[u]];
-    const double* qg = Q + (int64_t)g * kq;
+    double s;
+    if constexpr (L == 1) {
+      s = r[g];
+      for (int64_t u = rp[g]; u < rp[g + 1]; ++u) s -= val[u] * e[ci[u]];
+    } else {
+      s = r[g] - row_dot_l<L>(rp, ci, val, e, g, jl);
+    }
+    if (jl == 0) {
+      const double* qg = Q + (int64_t)g * kq;
 #pragma unroll
-    for (int m = 0; m < kMaxK; ++m)
-      if (m < ki) acc[m] += qg[m] * s;
+      for (int m = 0; m < kMaxK; ++m)
+        if (m < ki) acc[m] += qg[m] * s;
+    }
   }
   const int wv = threadIdx.x >> 6;
 #pragma unroll
@@ -56,8 +70,24 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kRThreads / 64; ++w) s += red[w][threadIdx.x];
-    b0[koff[i] + threadIdx.x] = s;
+    rpart[((int64_t)i * gridDim.x + c) * kMaxK + threadIdx.x] = s;
   }
+}
+
+// b0[koff[i] + m] = sum over the nch chunks of subdomain i, in chunk order
+__global__ void k_coarse_restrict_sum(const CgState* st, const int32_t* __restrict__ sub_inst,
+                                      const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
+                                      const double* __restrict__ rpart, int nch, int n_parts,
+                                      double* __restrict__ b0) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(id / kMaxK), m = (int)(id % kMaxK);
+  if (i >= n_parts) return;
+  if (st && st[sub_inst[i]].done) return;
+  if (m >= kcnt[i]) return;
+  const double* p = rpart + (int64_t)i * nch * kMaxK + m;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += p[(int64_t)c * kMaxK];
+  b0[koff[i] + m] = s;
 }
 
 // one wave per 64x64 float64 tile: row and column partials into per-tile slots
@@ -132,10 +162,17 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
   double* b0 = h.cy.as<double>();             // padded to whole tiles, zero beyond each block
   double* y = b0 + h.nc_pad;
   const int32_t* sub_inst = h.sub_inst.as<int32_t>();
-  hipLaunchKernelGGL(k_coarse_restrict, dim3(S.n_parts), dim3(kRThreads), 0, s, st, sub_inst,
-                     h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
-                     h.koff_d.as<int64_t>(), h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(),
-                     h.col.as<int32_t>(), h.val.as<double>(), r, e, b0);
+  DDG_REQUIRE(h.rch * h.lpr == 4 * kRThreads, DDG_ERR_HIP, "internal: restriction chunking");
+  with_lanes(h.lpr, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    hipLaunchKernelGGL(k_coarse_restrict<L>, dim3((unsigned)h.nch, (unsigned)S.n_parts), dim3(kRThreads), 0, s, st,
+                       sub_inst, h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
+                       h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(), r, e,
+                       h.rch, h.rpart.as<double>());
+  });
+  hipLaunchKernelGGL(k_coarse_restrict_sum, dim3((unsigned)(((int64_t)S.n_parts * kMaxK + 255) / 256)), dim3(256), 0,
+                     s, st, sub_inst, h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(), h.rpart.as<double>(), h.nch,
+                     S.n_parts, b0);
   double* rowpart = h.cpart.as<double>();
   double* colpart = rowpart + h.ntiles * 64;
   hipLaunchKernelGGL(k_coarse_symv, dim3((unsigned)((h.ntiles + 3) / 4)), dim3(256), 0, s, st,

@@ -428,6 +428,28 @@ __global__ void k_gather_vals(const int64_t* __restrict__ pos, const double* __r
   if (i < m) out[i] = pos[i] >= 0 ? val[pos[i]] : 0.0;
 }
 
+// Sliced coupling values (one workgroup of 64 lanes per slice): entry q of the row
+// at lane l takes the row's q-th ELL value, or 0 where the row has fewer couplings
+// or the lane lies past the end of its block.  Converted to the sweep's type.
+template <class AT>
+__global__ void __launch_bounds__(64) k_gather_sliced(const int64_t* __restrict__ sl_row,
+                                                      const int32_t* __restrict__ sl_rows,
+                                                      const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ ell_col,
+                                                      const double* __restrict__ ell_val, int32_t c,
+                                                      AT* __restrict__ out) {
+  const int sl = blockIdx.x, l = threadIdx.x;
+  const int64_t o0 = off[sl];
+  const int w = (int)((off[sl + 1] - o0) / 64);
+  const bool live = l < sl_rows[sl];
+  const int64_t row = sl_row[sl] + l;
+  for (int q = 0; q < w; ++q) {
+    double v = 0.0;
+    if (live && ell_col[row * c + q] >= 0) v = ell_val[row * c + q];
+    out[o0 + 64 * q + l] = (AT)v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dense SPD inverses (coarse blocks and local levels): Gauss-Jordan on blocks
 // of at most kCNB rows, recursive Schur complements above.
@@ -727,7 +749,7 @@ void build_fac_plan(const Symbolic& S, FacPlanHost& P) {
     int32_t steps = 0;
     for (int32_t i = g0; i < g1; ++i) {
       const int32_t K = S.sub_blk_ptr[i + 1] - S.sub_blk_ptr[i];
-      const int32_t m = (K - 1) / 2;
+      const int32_t m = S.sub_mid[i];
       steps = std::max(steps, std::max(m, K - 1 - m));
     }
     // chain (i, dir) uses buffers at ((i - g0) * 2 + dir) * per_chain + {0, bmax^2}; after
@@ -739,7 +761,7 @@ void build_fac_plan(const Symbolic& S, FacPlanHost& P) {
       FacPlanHost::Stage st{(int32_t)P.items.size(), 0, 1, 0};
       for (int32_t i = g0; i < g1; ++i) {
         const int32_t kb0 = S.sub_blk_ptr[i], K = S.sub_blk_ptr[i + 1] - kb0;
-        const int32_t m = (K - 1) / 2, nB = K - 1 - m;
+        const int32_t m = S.sub_mid[i], nB = K - 1 - m;
         for (int dir = 0; dir < 2; ++dir) {
           const int32_t len = dir == 0 ? m : nB;
           if (j >= len) continue;
@@ -766,7 +788,7 @@ void build_fac_plan(const Symbolic& S, FacPlanHost& P) {
       FacPlanHost::Stage st{(int32_t)P.items.size(), 0, pass == 1, 0};
       for (int32_t i = g0; i < g1; ++i) {
         const int32_t kb0 = S.sub_blk_ptr[i], K = S.sub_blk_ptr[i + 1] - kb0;
-        const int32_t m = (K - 1) / 2, nB = K - 1 - m;
+        const int32_t m = S.sub_mid[i], nB = K - 1 - m;
         FacItem it{};
         it.cur = kb0 + m;
         it.sub = i;
@@ -974,6 +996,19 @@ void launch_local_factor(Handle& h, hipStream_t s) {
   }
 }
 
+template <class AT>
+void refresh_sliced(Handle& h, hipStream_t s) {
+  const Symbolic& S = h.S;
+  const int32_t nsl = (int32_t)S.sl_rows.size();
+  if (nsl == 0) return;
+  hipLaunchKernelGGL(k_gather_sliced<AT>, dim3((unsigned)nsl), dim3(64), 0, s, h.sl_row.as<int64_t>(),
+                     h.sl_rows.as<int32_t>(), h.sl_lo_off.as<int64_t>(), h.lo_col.as<int32_t>(),
+                     h.lo_val.as<double>(), S.cl, h.sl_lo_val.as<AT>());
+  hipLaunchKernelGGL(k_gather_sliced<AT>, dim3((unsigned)nsl), dim3(64), 0, s, h.sl_row.as<int64_t>(),
+                     h.sl_rows.as<int32_t>(), h.sl_up_off.as<int64_t>(), h.up_col.as<int32_t>(),
+                     h.up_val.as<double>(), S.cu, h.sl_up_val.as<AT>());
+}
+
 void launch_refresh_couplings(Handle& h, hipStream_t s) {
   const int64_t nlo = (int64_t)h.S.lo_pos.size(), nup = (int64_t)h.S.up_pos.size();
   if (nlo)
@@ -982,6 +1017,10 @@ void launch_refresh_couplings(Handle& h, hipStream_t s) {
   if (nup)
     hipLaunchKernelGGL(k_gather_vals, dim3((unsigned)((nup + 255) / 256)), dim3(256), 0, s,
                        h.up_pos.as<int64_t>(), h.val.as<double>(), h.up_val.as<double>(), nup);
+  if (h.S.sliced) {
+    if (h.opt.precision == DDG_FP64) refresh_sliced<double>(h, s);
+    else refresh_sliced<float>(h, s);
+  }
   DDG_HIP(hipGetLastError());
 }
 

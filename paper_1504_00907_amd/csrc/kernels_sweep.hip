@@ -6,7 +6,8 @@
 //
 // Local solve.  A_i is block tridiagonal over the K levels of its ascending
 // ordering (D_k diagonal blocks, L_k = A_{k,k-1}, U_k = A_{k,k+1}).  The
-// factorisation is "twisted": with m = (K-1)/2 it eliminates levels
+// factorisation is "twisted": with a middle level m (chosen per subdomain on
+// the host so that the two chains carry about the same work) it eliminates levels
 // 0..m-1 from the top (X+_k = S+_k^{-1}, S+_k = D_k - L_k X+_{k-1} L_k^T),
 // levels K-1..m+1 from the bottom (X-_k, S-_k = D_k - U_k X-_{k+1} U_k^T)
 // and stores X_m for the middle level S_m = D_m - L_m X+ L_m^T - U_m X- U_m^T.
@@ -38,6 +39,7 @@ struct SweepArgs {
   const int64_t* set_ptr;
   const int32_t* set_idx;
   const int32_t* sub_blk_ptr;
+  const int32_t* sub_mid;   // middle level of each subdomain's twisted factorisation
   const int32_t* blk_start;
   const int32_t* blk_size;
   const int64_t* blk_foff;
@@ -46,6 +48,14 @@ struct SweepArgs {
   const int32_t* up_col;
   const double* up_val;
   int32_t cl, cu;
+  // sliced couplings (rows with more than kCplRegs couplings in a direction)
+  const int32_t* blk_slice;
+  const int64_t* sl_lo_off;
+  const int64_t* sl_up_off;
+  const int32_t* sl_lo_col;
+  const int32_t* sl_up_col;
+  const void* sl_lo_val;   // in the sweep's arithmetic type
+  const void* sl_up_val;
   const int64_t* rp;
   const int32_t* ci;
   const double* val;
@@ -130,10 +140,37 @@ __device__ inline void handoff_signal(int32_t* flag) {
 
 }  // namespace
 
-constexpr int kMaxLevels = 96;   // levels per subdomain staged in LDS
-constexpr int kCplRegs = 2;      // coupling slots per row held in registers (per direction)
+// c + sum_q val_q * w[col_q] over the entries of one row of a slice (lane ln), in
+// the order the entries are stored.  The slice's width is the same for all lanes of
+// a wave, so the loads are coalesced and issued in unconditional groups of kCplU.
+constexpr int kCplU = 8;
 
-template <class FT, class AT, int T, int NW, int TPW>
+template <class AT>
+__device__ inline AT slice_dot(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                               const AT* __restrict__ val, int sl, int ln, const AT* w, AT c) {
+  const int64_t o1 = off[sl + 1];
+  int64_t o = off[sl] + ln;
+  for (; o + (kCplU - 1) * 64 < o1; o += kCplU * 64) {
+    int cc[kCplU];
+    AT vv[kCplU];
+#pragma unroll
+    for (int u = 0; u < kCplU; ++u) {
+      cc[u] = col[o + u * 64];
+      vv[u] = val[o + u * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < kCplU; ++u) c += vv[u] * w[cc[u]];
+  }
+  for (; o < o1; o += 64) c += val[o] * w[col[o]];
+  return c;
+}
+
+constexpr int kMaxLevels = 96;   // levels per subdomain staged in LDS
+
+// SL = false: at most kCplRegs couplings per row and direction (held in registers,
+// rows past the first NT of a level read the ELL arrays); SL = true: the sliced
+// coupling layout.
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
 __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   using G = TileGeom<FT, T>;
   constexpr int NT = NW * 64;
@@ -173,7 +210,7 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
     lv_size[k] = a.blk_size[kb0 + k];
     lv_foff[k] = a.blk_foff[kb0 + k];
   }
-  const int m = (K - 1) / 2;
+  const int m = a.sub_mid[sub];
   const int nB = K - 1 - m;
   const int split = (m + 1 < K) ? a.blk_start[kb0 + m + 1] : ni;  // first row of the bottom chain
   int r0 = 0, r1 = ni;
@@ -187,7 +224,7 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   // coupling entries of this thread's row (row tid of the level) for the next step
   int cpl_col[2 * kCplRegs];
   AT cpl_val[2 * kCplRegs];
-  const bool cpl_regs = a.cl <= kCplRegs && a.cu <= kCplRegs;
+  constexpr bool cpl_regs = !SL;
   auto load_tile = [&](int k, int j) {
     const int ntl = tiles_for(lv_size[k], T);
     const int t = j * NW + wave;
@@ -227,8 +264,13 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   }
 
   // 1. local residual b = (r - A e) on the rows this workgroup owns (computed for
-  //    the whole colour by k_local_residual)
-  for (int j = r0 + tid; j < r1; j += NT) w[j] = (AT)a.bres[s0 + j];
+  //    the whole colour by k_local_residual); with sliced couplings the other
+  //    chain's rows start at zero (the handoff writes the ones that are read)
+  if constexpr (SL) {
+    for (int j = tid; j < ni; j += NT) w[j] = (j >= r0 && j < r1) ? (AT)a.bres[s0 + j] : (AT)0;
+  } else {
+    for (int j = r0 + tid; j < r1; j += NT) w[j] = (AT)a.bres[s0 + j];
+  }
   __syncthreads();
 
   double* xch = a.xch + (int64_t)p * 2 * a.xch_ld;
@@ -267,11 +309,18 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
       AT y = 0;
       if (jj < b) {
         AT c = 0;
-        if (cpl_regs && jj == tid) {
+        if constexpr (SL) {
+          const int sl = a.blk_slice[kb0 + k] + (jj >> 6);
+          if (use_lo)
+            c = slice_dot<AT>(a.sl_lo_off, a.sl_lo_col, static_cast<const AT*>(a.sl_lo_val), sl, jj & 63, w, c);
+          if (use_up)
+            c = slice_dot<AT>(a.sl_up_off, a.sl_up_col, static_cast<const AT*>(a.sl_up_val), sl, jj & 63, w, c);
+        } else if (jj == tid) {
 #pragma unroll
           for (int q = 0; q < 2 * kCplRegs; ++q)
             if (cpl_col[q] >= 0) c += cpl_val[q] * w[cpl_col[q]];
         } else {
+          // rows past the first NT of a wide level: at most kCplRegs couplings each
           const int64_t row = s0 + bs + jj;
           if (use_lo)
             for (int q = 0; q < a.cl; ++q) {
@@ -368,7 +417,9 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   }
 }
 
-// b = (r - A e) on the expanded sets of one colour, written in set order.
+// b = (r - A e) on the expanded sets of one colour, written in set order; L lanes
+// per CSR row (one row per lane when L = 1).
+template <int L>
 __global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const int32_t* __restrict__ sub_inst,
                                                         const int32_t* __restrict__ subs,
                                                         const int64_t* __restrict__ set_ptr,
@@ -381,18 +432,23 @@ __global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const
   if (st && st[sub_inst[sub]].done) return;
   const int64_t s0 = set_ptr[sub];
   const int ni = (int)(set_ptr[sub + 1] - s0);
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= ni) return;
+  const int j = blockIdx.x * (256 / L) + threadIdx.x / L;
+  if (j >= ni) return;  // the whole lane group leaves together
   const int g = set_idx[s0 + j];
-  double acc = r[g];
-  if (!e_zero)
-    for (int64_t t = rp[g]; t < rp[g + 1]; ++t) acc -= val[t] * e[ci[t]];
-  bres[s0 + j] = acc;
+  if constexpr (L == 1) {
+    double acc = r[g];
+    if (!e_zero)
+      for (int64_t t = rp[g]; t < rp[g + 1]; ++t) acc -= val[t] * e[ci[t]];
+    bres[s0 + j] = acc;
+  } else {
+    const double ae = e_zero ? 0.0 : row_dot_l<L>(rp, ci, val, e, g, threadIdx.x & (L - 1));
+    if ((threadIdx.x & (L - 1)) == 0) bres[s0 + j] = r[g] - ae;
+  }
 }
 
 namespace {
 
-template <class FT, class AT, int T, int NW, int TPW>
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
 void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                       const CgState* st, hipStream_t s, bool residual) {
   const Symbolic& S = h.S;
@@ -405,6 +461,7 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   a.set_ptr = h.set_ptr.as<int64_t>();
   a.set_idx = h.set_idx.as<int32_t>();
   a.sub_blk_ptr = h.sub_blk_ptr.as<int32_t>();
+  a.sub_mid = h.sub_mid.as<int32_t>();
   a.blk_start = h.blk_start.as<int32_t>();
   a.blk_size = h.blk_size.as<int32_t>();
   a.blk_foff = h.blk_foff.as<int64_t>();
@@ -414,6 +471,14 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   a.up_val = h.up_val.as<double>();
   a.cl = S.cl;
   a.cu = S.cu;
+  a.blk_slice = h.blk_slice.as<int32_t>();
+  a.sl_lo_off = h.sl_lo_off.as<int64_t>();
+  a.sl_up_off = h.sl_up_off.as<int64_t>();
+  a.sl_lo_col = h.sl_lo_col.as<int32_t>();
+  a.sl_up_col = h.sl_up_col.as<int32_t>();
+  a.sl_lo_val = h.sl_lo_val.p;
+  a.sl_up_val = h.sl_up_val.p;
+  DDG_REQUIRE(S.sliced == !(S.cl <= kCplRegs && S.cu <= kCplRegs), DDG_ERR_HIP, "internal: coupling layout");
   a.rp = h.rowptr.as<int64_t>();
   a.ci = h.col.as<int32_t>();
   a.val = h.val.as<double>();
@@ -447,11 +512,15 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   DDG_REQUIRE(a.slot_tiles >= round_tiles, DDG_ERR_UNSUPPORTED,
               "local problem too large for on-chip storage (" + std::to_string(fixed) + " bytes before slots)");
   const size_t lds = (size_t)(fixed + per_tile * a.slot_tiles);
-  auto kern = k_sweep<FT, AT, T, NW, TPW>;
+  auto kern = k_sweep<FT, AT, T, NW, TPW, SL>;
   if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (residual) {
-    hipLaunchKernelGGL(k_local_residual, dim3((unsigned)((S.max_set + 255) / 256), (unsigned)nsub), dim3(256), 0,
-                       s, st, a.sub_inst, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e, a.e_zero, h.bres.as<double>());
+    with_lanes(h.lpr, [&](auto Lc) {
+      constexpr int L = decltype(Lc)::value;
+      hipLaunchKernelGGL(k_local_residual<L>, dim3((unsigned)(((int64_t)S.max_set * L + 255) / 256), (unsigned)nsub),
+                         dim3(256), 0, s, st, a.sub_inst, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e,
+                         a.e_zero, h.bres.as<double>());
+    });
     DDG_HIP(hipGetLastError());
     return;
   }
@@ -460,22 +529,29 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   DDG_HIP(hipGetLastError());
 }
 
-template <class FT, class AT>
-void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, bool e_zero,
+template <class FT, class AT, bool SL>
+void launch_sweep_l(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                     const CgState* st, hipStream_t s, bool res) {
   // (waves, tiles per wave per round) keep the register ring within 128 VGPRs at 16 waves
   // or 256 at 8 waves, without spills
   switch (h.S.tile) {
-    case 16: launch_sweep_cfg<FT, AT, 16, 4, 4>(h, colour, r, e, e_zero, st, s, res); break;
+    case 16: launch_sweep_cfg<FT, AT, 16, 4, 4, SL>(h, colour, r, e, e_zero, st, s, res); break;
     case 32:
-      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4>(h, colour, r, e, e_zero, st, s, res);
-      else launch_sweep_cfg<FT, AT, 32, 8, 9>(h, colour, r, e, e_zero, st, s, res);
+      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4, SL>(h, colour, r, e, e_zero, st, s, res);
+      else launch_sweep_cfg<FT, AT, 32, 8, 9, SL>(h, colour, r, e, e_zero, st, s, res);
       break;
     default:
-      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1>(h, colour, r, e, e_zero, st, s, res);
-      else launch_sweep_cfg<FT, AT, 64, 8, 2>(h, colour, r, e, e_zero, st, s, res);
+      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1, SL>(h, colour, r, e, e_zero, st, s, res);
+      else launch_sweep_cfg<FT, AT, 64, 8, 2, SL>(h, colour, r, e, e_zero, st, s, res);
       break;
   }
+}
+
+template <class FT, class AT>
+void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, bool e_zero,
+                    const CgState* st, hipStream_t s, bool res) {
+  if (h.S.sliced) launch_sweep_l<FT, AT, true>(h, colour, r, e, e_zero, st, s, res);
+  else launch_sweep_l<FT, AT, false>(h, colour, r, e, e_zero, st, s, res);
 }
 
 }  // namespace

@@ -4,6 +4,7 @@
 // pattern of A0, Section 4), and the block-tridiagonal level structure used by
 // the local factors.  Integer work only.
 #include <algorithm>
+#include <cstdlib>
 #include <numeric>
 #include <thread>
 
@@ -394,6 +395,32 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
   }
   S.blk_foff[nb_tot] = off;
   S.fac_elems = off;
+  // Middle level of the twisted factorisation: the top chain eliminates levels
+  // 0..m-1, the bottom chain K-1..m+1, and a solve runs both chains down, the middle
+  // level, then both back.  A level costs its tiles plus a fixed latency (in tile
+  // units); m minimises 2 max(top, bottom) + middle, nearest (K-1)/2 on ties.  Any m
+  // gives the same exact local solve.
+  S.sub_mid.assign(n_parts, 0);
+  {
+    const int64_t lat = 16;
+    for (int32_t i = 0; i < n_parts; ++i) {
+      const int32_t kb0 = S.sub_blk_ptr[i], K = S.sub_blk_ptr[i + 1] - kb0;
+      std::vector<int64_t> pre(K + 1, 0);
+      for (int32_t k = 0; k < K; ++k) pre[k + 1] = pre[k] + lat + tiles_for(S.blk_size[kb0 + k], S.tile);
+      int32_t best = (K - 1) / 2;
+      int64_t best_cost = -1;
+      for (int32_t m = 0; m < K; ++m) {
+        const int64_t top = pre[m], bot = pre[K] - pre[m + 1];
+        const int64_t cost = 2 * std::max(top, bot) + (pre[m + 1] - pre[m]);
+        const int32_t d = std::abs(m - (K - 1) / 2), db = std::abs(best - (K - 1) / 2);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && d < db)) {
+          best = m;
+          best_cost = cost;
+        }
+      }
+      S.sub_mid[i] = best;
+    }
+  }
 
   int64_t rows = S.set_ptr[n_parts];
   // ELL couplings
@@ -428,6 +455,53 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
       }
     }
   });
+  // sliced copy of the couplings for the sweep (rows with more than kCplRegs couplings)
+  S.sliced = S.cl > kCplRegs || S.cu > kCplRegs;
+  if (S.sliced) {
+    S.blk_slice.assign(nb_tot + 1, 0);
+    for (int32_t b = 0; b < nb_tot; ++b) S.blk_slice[b + 1] = S.blk_slice[b] + (S.blk_size[b] + 63) / 64;
+    const int32_t nsl = S.blk_slice[nb_tot];
+    S.sl_row.assign(nsl, 0);
+    S.sl_rows.assign(nsl, 0);
+    std::vector<int32_t> wlo(nsl, 0), wup(nsl, 0), lrow(nsl, 0);
+    parallel_for(n_parts, [&](int32_t i, int) {
+      for (int32_t b = S.sub_blk_ptr[i]; b < S.sub_blk_ptr[i + 1]; ++b)
+        for (int32_t sl = S.blk_slice[b]; sl < S.blk_slice[b + 1]; ++sl) {
+          const int32_t r0 = S.blk_start[b] + 64 * (sl - S.blk_slice[b]);
+          const int32_t nr = std::min(64, S.blk_start[b] + S.blk_size[b] - r0);
+          S.sl_row[sl] = S.set_ptr[i] + r0;
+          S.sl_rows[sl] = nr;
+          lrow[sl] = r0;
+          for (int32_t l = 0; l < nr; ++l) {
+            wlo[sl] = std::max<int32_t>(wlo[sl], (int32_t)loc[i].lo_cnt[r0 + l]);
+            wup[sl] = std::max<int32_t>(wup[sl], (int32_t)loc[i].up_cnt[r0 + l]);
+          }
+        }
+    });
+    S.sl_lo_off.assign(nsl + 1, 0);
+    S.sl_up_off.assign(nsl + 1, 0);
+    for (int32_t sl = 0; sl < nsl; ++sl) {
+      S.sl_lo_off[sl + 1] = S.sl_lo_off[sl] + 64 * (int64_t)wlo[sl];
+      S.sl_up_off[sl + 1] = S.sl_up_off[sl] + 64 * (int64_t)wup[sl];
+    }
+    S.sl_lo_col.assign(S.sl_lo_off[nsl], 0);
+    S.sl_up_col.assign(S.sl_up_off[nsl], 0);
+    // a padding entry points at its own row: the workgroup that solves a level
+    // always holds that level's rows, so the zero product never reads a stale value
+    auto fill = [&](int32_t sl, const std::vector<int32_t>& ell, int32_t c, const std::vector<int64_t>& off,
+                    std::vector<int32_t>& out) {
+      const int32_t w = (int32_t)((off[sl + 1] - off[sl]) / 64);
+      for (int32_t l = 0; l < S.sl_rows[sl]; ++l)
+        for (int32_t q = 0; q < w; ++q) {
+          const int32_t col = ell[(S.sl_row[sl] + l) * c + q];
+          out[off[sl] + 64 * q + l] = col >= 0 ? col : lrow[sl] + l;
+        }
+    };
+    parallel_for(nsl, [&](int32_t sl, int) {
+      fill(sl, S.lo_col, cl, S.sl_lo_off, S.sl_lo_col);
+      fill(sl, S.up_col, cu, S.sl_up_off, S.sl_up_col);
+    });
+  }
   // same-level entries (setup only) in CSR form
   S.in_ptr.assign(rows + 1, 0);
   for (int32_t i = 0; i < n_parts; ++i)

@@ -105,3 +105,45 @@ def test_mixed_solve(name, precision):
     else:
         assert info["iters"] <= 3 * it + 5
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_preconditioner_every_tile(tile, precision):
+    """Every tile edge of the local factors with the sliced couplings (rows here have
+    dozens of couplings per direction) under the two-workgroup schedule; three
+    applications in a row, each finite and equal to the oracle's M^{-1} r."""
+    P, o = problem("el10")
+    s = solver(P, tile=tile, precision=precision)
+    assert s.info()["tile"] == tile
+    rng = seed_rng(91, tile)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for _ in range(3):
+        r = rng.standard_normal(P.n)
+        z = host(s.apply_precond(dev(r)))
+        assert np.isfinite(z).all()
+        ref = o.apply(r)
+        err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+        say(f"   tile {tile} {precision}: precond rel err {err:.2e}")
+        assert err <= tol
+    s.close()
+
+
+def test_row_lanes_match_single_lane(monkeypatch):
+    """Row dots by groups of lanes (chosen for these ~70-entry rows) give the same
+    FP64 solve as one lane per row: equal iterations, u within 1e-12."""
+    P, o = problem("el10")
+    out = []
+    for lanes in ("1", None):
+        if lanes:
+            monkeypatch.setenv("DDG_ROW_LANES", lanes)
+        else:
+            monkeypatch.delenv("DDG_ROW_LANES", raising=False)
+        s = solver(P, rtol=1e-10)
+        u, info = s.solve(dev(P.f))
+        out.append((host(u), info))
+        s.close()
+    (u1, i1), (ul, il) = out
+    say(f"   one lane: {i1['iters']} iters; lane groups: {il['iters']} iters")
+    assert i1["iters"] == il["iters"] and i1["status"] == il["status"] == 0
+    assert np.linalg.norm(u1 - ul) <= 1e-12 * np.linalg.norm(u1)
