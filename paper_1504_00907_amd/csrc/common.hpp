@@ -108,6 +108,7 @@ struct Symbolic {
   // the block: column 0, never read).  The values are refreshed from the ELL arrays.
   bool sliced = false;
   std::vector<int32_t> blk_slice;                // n_blocks+1: first slice of each block
+  int32_t max_sub_slices = 0;                    // most slices of one subdomain
   std::vector<int64_t> sl_row;                   // per slice: global set row of its lane 0
   std::vector<int32_t> sl_rows;                  // per slice: rows of the block it holds (<= 64)
   std::vector<int64_t> sl_lo_off, sl_up_off;     // n_slices+1 entry offsets

@@ -56,6 +56,8 @@ struct SweepArgs {
   const int32_t* sl_up_col;
   const void* sl_lo_val;   // in the sweep's arithmetic type
   const void* sl_up_val;
+  int32_t tab_n;           // entries of each on-chip slice-offset table (most slices of a subdomain + 1)
+  int32_t tab_bytes;       // on-chip bytes of both tables (0 without sliced couplings)
   const int64_t* rp;
   const int32_t* ci;
   const double* val;
@@ -140,16 +142,20 @@ __device__ inline void handoff_signal(int32_t* flag) {
 
 }  // namespace
 
-// c + sum_q val_q * w[col_q] over the entries of one row of a slice (lane ln), in
-// the order the entries are stored.  The slice's width is the same for all lanes of
-// a wave, so the loads are coalesced and issued in unconditional groups of kCplU.
+// c + sum_{q >= q0} val_q * w[col_q] over the entries of one row of a slice (lane
+// ln), in the order the entries are stored; the slice's entries are
+// [base + tab[sl], base + tab[sl + 1]).  The slice's width is the same for all
+// lanes of a wave, so the loads are coalesced and issued in unconditional groups
+// of kCplU.
 constexpr int kCplU = 8;
+// entries of the first row a thread owns in a level, prefetched one level ahead
+constexpr int kCplHead = 4;
 
 template <class AT>
-__device__ inline AT slice_dot(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
-                               const AT* __restrict__ val, int sl, int ln, const AT* w, AT c) {
-  const int64_t o1 = off[sl + 1];
-  int64_t o = off[sl] + ln;
+__device__ inline AT slice_dot(const int32_t* tab, int64_t base, const int32_t* __restrict__ col,
+                               const AT* __restrict__ val, int sl, int ln, int q0, const AT* w, AT c) {
+  const int64_t o1 = base + tab[sl + 1];
+  int64_t o = base + tab[sl] + 64 * q0 + ln;
   for (; o + (kCplU - 1) * 64 < o1; o += kCplU * 64) {
     int cc[kCplU];
     AT vv[kCplU];
@@ -178,6 +184,7 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int32_t lv_start[kMaxLevels + 1], lv_size[kMaxLevels];
   __shared__ int64_t lv_foff[kMaxLevels];
+  __shared__ int32_t lv_slice[kMaxLevels];  // first slice of each level, relative to the subdomain's
   int p, role;
   if (a.twisted) {
     // pair (bottom, top) = (16g + i, 16g + i + 8): same XCD under round-robin dispatch,
@@ -197,7 +204,10 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   const int64_t s0 = a.set_ptr[sub];
   const int ni = (int)(a.set_ptr[sub + 1] - s0);
   const int ni_pad = (ni + 3) & ~3;
-  AT* w = reinterpret_cast<AT*>(smem_raw);
+  // sliced couplings: per-slice entry offsets of this subdomain, relative to its first entry
+  int32_t* tab_lo = reinterpret_cast<int32_t*>(smem_raw);
+  int32_t* tab_up = tab_lo + a.tab_n;
+  AT* w = reinterpret_cast<AT*>(smem_raw + a.tab_bytes);
   AT* tv = w + ni_pad;
   AT* acc = tv + a.ldp;     // phase accumulator (levels wider than slot_tiles only)
   AT* slots = acc + a.ldp;  // 2 * T per tile of the current phase
@@ -209,6 +219,18 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
     lv_start[k] = a.blk_start[kb0 + k];
     lv_size[k] = a.blk_size[kb0 + k];
     lv_foff[k] = a.blk_foff[kb0 + k];
+  }
+  int64_t base_lo = 0, base_up = 0;
+  if constexpr (SL) {
+    const int sl0 = a.blk_slice[kb0];
+    const int nsl = a.blk_slice[kb0 + K] - sl0;  // < tab_n (checked on the host)
+    base_lo = a.sl_lo_off[sl0];
+    base_up = a.sl_up_off[sl0];
+    for (int k = tid; k < K; k += NT) lv_slice[k] = a.blk_slice[kb0 + k] - sl0;
+    for (int t = tid; t <= nsl; t += NT) {
+      tab_lo[t] = (int32_t)(a.sl_lo_off[sl0 + t] - base_lo);
+      tab_up[t] = (int32_t)(a.sl_up_off[sl0 + t] - base_up);
+    }
   }
   const int m = a.sub_mid[sub];
   const int nB = K - 1 - m;
@@ -254,13 +276,46 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
       }
     }
   };
-  // the first level's tiles are requested before the residual is read
+  // sliced couplings: the first kCplHead entries of row tid of the next step's level,
+  // per direction (hw = the slice's width, 0 when the direction is unused)
+  int hcol[2][kCplHead];
+  AT hval[2][kCplHead];
+  int hw[2] = {0, 0};
+  auto load_head = [&](int kind, int k) {
+    if constexpr (SL) {
+      const int b = lv_size[k];
+      const bool use[2] = {kind == FWD_LO || kind == MID || kind == BWD_LO,
+                           kind == FWD_UP || kind == MID || kind == BWD_UP};
+      const int slr = lv_slice[k] + wave;  // slice of row tid (valid when tid < b)
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        hw[d] = 0;
+        if (use[d] && tid < b) {
+          const int32_t* tab = d ? tab_up : tab_lo;
+          const int64_t o = (d ? base_up : base_lo) + tab[slr] + lane;
+          hw[d] = (tab[slr + 1] - tab[slr]) >> 6;
+          const int32_t* col = d ? a.sl_up_col : a.sl_lo_col;
+          const AT* val = static_cast<const AT*>(d ? a.sl_up_val : a.sl_lo_val);
+#pragma unroll
+          for (int u = 0; u < kCplHead; ++u)
+            if (u < hw[d]) {
+              hcol[d][u] = col[o + 64 * u];
+              hval[d][u] = val[o + 64 * u];
+            }
+        }
+      }
+    }
+  };
+  // the first level's couplings, then its tiles, are requested before the residual
+  // is read (vector loads complete in issue order, so a wait for the couplings does
+  // not wait for the tiles)
   if (ns > 0) {
     int kind, k;
     decode_step(role, 0, K, m, kind, k);
+    load_cpl(kind, k);
+    load_head(kind, k);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) load_tile(k, j);
-    load_cpl(kind, k);
   }
 
   // 1. local residual b = (r - A e) on the rows this workgroup owns (computed for
@@ -310,11 +365,22 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
       if (jj < b) {
         AT c = 0;
         if constexpr (SL) {
-          const int sl = a.blk_slice[kb0 + k] + (jj >> 6);
-          if (use_lo)
-            c = slice_dot<AT>(a.sl_lo_off, a.sl_lo_col, static_cast<const AT*>(a.sl_lo_val), sl, jj & 63, w, c);
-          if (use_up)
-            c = slice_dot<AT>(a.sl_up_off, a.sl_up_col, static_cast<const AT*>(a.sl_up_val), sl, jj & 63, w, c);
+          const int slr = lv_slice[k] + (jj >> 6);
+          const bool use[2] = {use_lo, use_up};
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            if (!use[d]) continue;
+            int q0 = 0;
+            if (jj == tid) {
+              // prefetched head
+#pragma unroll
+              for (int u = 0; u < kCplHead; ++u)
+                if (u < hw[d]) c += hval[d][u] * w[hcol[d][u]];
+              q0 = kCplHead;
+            }
+            c = slice_dot<AT>(d ? tab_up : tab_lo, d ? base_up : base_lo, d ? a.sl_up_col : a.sl_lo_col,
+                              static_cast<const AT*>(d ? a.sl_up_val : a.sl_lo_val), slr, jj & 63, q0, w, c);
+          }
         } else if (jj == tid) {
 #pragma unroll
           for (int q = 0; q < 2 * kCplRegs; ++q)
@@ -359,6 +425,11 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
         }
       }
       const bool last = round + 1 == rounds;
+      if (last && has_next) {
+        // the next step's couplings go out before its tiles
+        load_cpl(kind2, k2);
+        load_head(kind2, k2);
+      }
 #pragma unroll
       for (int j = 0; j < TPW; ++j) {
         const int t = (round * TPW + j) * NW + wave;
@@ -381,7 +452,6 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
         __syncthreads();
       }
     }
-    if (has_next) load_cpl(kind2, k2);
     __syncthreads();
     for (int jj = tid; jj < b; jj += NT) {
       const AT sum = phased ? acc[jj] : sum_slots<AT, T>(slots, nt, jj);
@@ -501,9 +571,11 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   // on-chip plan: w (set), tv and the phase accumulator (one level each), then the
   // per-tile slots of up to slot_tiles tiles (whole rounds of NW * TPW tiles)
   const int round_tiles = NW * TPW;
-  const int64_t fixed = sizeof(AT) * ((int64_t)ni_pad + 2 * (int64_t)maxpad);
+  a.tab_n = SL ? S.max_sub_slices + 1 : 0;
+  a.tab_bytes = (int32_t)(((int64_t)2 * a.tab_n * 4 + 15) / 16 * 16);
+  const int64_t fixed = a.tab_bytes + sizeof(AT) * ((int64_t)ni_pad + 2 * (int64_t)maxpad);
   const int64_t per_tile = sizeof(AT) * 2 * (int64_t)T;
-  // (the kernel's static level metadata takes about 1.5 KiB of the same LDS)
+  // (the kernel's static level metadata takes about 1.9 KiB of the same LDS)
   int64_t cap = (h.dev_lds_limit - 2048 - fixed) / per_tile;
   cap = cap / round_tiles * round_tiles;
   if (const char* env = std::getenv("DDG_SWEEP_SLOT_TILES")) cap = std::min<int64_t>(cap, std::max(1, std::atoi(env)) * (int64_t)round_tiles);
@@ -533,11 +605,13 @@ template <class FT, class AT, bool SL>
 void launch_sweep_l(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                     const CgState* st, hipStream_t s, bool res) {
   // (waves, tiles per wave per round) keep the register ring within 128 VGPRs at 16 waves
-  // or 256 at 8 waves, without spills
+  // or 256 at 8 waves, without spills (the sliced path's prefetched couplings take a
+  // few registers of their own)
   switch (h.S.tile) {
     case 16: launch_sweep_cfg<FT, AT, 16, 4, 4, SL>(h, colour, r, e, e_zero, st, s, res); break;
     case 32:
       if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4, SL>(h, colour, r, e, e_zero, st, s, res);
+      else if constexpr (SL) launch_sweep_cfg<FT, AT, 32, 8, 8, SL>(h, colour, r, e, e_zero, st, s, res);
       else launch_sweep_cfg<FT, AT, 32, 8, 9, SL>(h, colour, r, e, e_zero, st, s, res);
       break;
     default:

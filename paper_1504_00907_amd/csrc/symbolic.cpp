@@ -461,6 +461,8 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
     S.blk_slice.assign(nb_tot + 1, 0);
     for (int32_t b = 0; b < nb_tot; ++b) S.blk_slice[b + 1] = S.blk_slice[b] + (S.blk_size[b] + 63) / 64;
     const int32_t nsl = S.blk_slice[nb_tot];
+    for (int32_t i = 0; i < n_parts; ++i)
+      S.max_sub_slices = std::max(S.max_sub_slices, S.blk_slice[S.sub_blk_ptr[i + 1]] - S.blk_slice[S.sub_blk_ptr[i]]);
     S.sl_row.assign(nsl, 0);
     S.sl_rows.assign(nsl, 0);
     std::vector<int32_t> wlo(nsl, 0), wup(nsl, 0), lrow(nsl, 0);
