@@ -57,13 +57,13 @@ void check_values(int64_t n, const int64_t* rp, const int32_t* ci, const double*
   }
 }
 
-// Algorithmic HBM bytes of one local-solve kernel launch per colour (see the
-// design notes): factor tiles read once per substitution (the levels of the
-// two chains and the middle level), per local row the residual read, the set
-// index and the read-modify-write of e in the scatter, and the coupling slots.
-// The local-residual kernel that precedes it is counted separately
-// (residual_bytes): set index, r, residual write, and for colours that start
-// from a non-zero e the CSR rows and one read of e.
+// Algorithmic HBM bytes of one local-solve kernel launch per colour: factor
+// tiles read once per substitution (every level twice, the middle level once),
+// the couplings (ELL slots or sliced entries), and per local row the residual
+// read, the set index and the read-modify-write of e in the scatter.  The
+// local-residual kernel that precedes it is counted separately (residual_bytes):
+// set index, r, residual write, and for colours that start from a non-zero e the
+// row pointers, the CSR rows and one read of e per entry.
 void account_bytes(Handle& h, const int64_t* rp) {
   const Symbolic& S = h.S;
   const int es = storage_size(h.opt.precision);
@@ -83,10 +83,17 @@ void account_bytes(Handle& h, const int64_t* rp) {
       }
       const int64_t r0 = S.set_ptr[i], r1 = S.set_ptr[i + 1];
       const int64_t ni = r1 - r0;
-      const int64_t ncpl = ni * (S.cl + S.cu);  // ELL slots read by the sweep
+      // couplings read by the local solves: ELL slots (8-byte values) or sliced entries
+      // (values in the solve's arithmetic type)
+      int64_t cpl = ni * (S.cl + S.cu) * 12;
+      if (S.sliced) {
+        const int32_t a0 = S.blk_slice[S.sub_blk_ptr[i]], a1 = S.blk_slice[S.sub_blk_ptr[i + 1]];
+        const int64_t ent = (S.sl_lo_off[a1] - S.sl_lo_off[a0]) + (S.sl_up_off[a1] - S.sl_up_off[a0]);
+        cpl = ent * (4 + (h.opt.precision == DDG_FP64 ? 8 : 4));
+      }
       int64_t nnz_rows = 0;
       for (int64_t t = r0; t < r1; ++t) nnz_rows += rp[S.set_idx[t] + 1] - rp[S.set_idx[t]];
-      bytes += fb + ni * (8 + 4 + 16) + ncpl * 12;
+      bytes += fb + cpl + ni * (8 + 4 + 16);
       resid0 += ni * (4 + 8 + 8);
       resid += ni * (4 + 8 + 8 + 16 + 8) + nnz_rows * 12;
     }

@@ -68,14 +68,65 @@ template <> struct Store<__hip_bfloat16> {
 // order, then an xor butterfly over the group adds the L partials, so every lane
 // of the group returns the same reproducible value.  L = 1 is the plain
 // sequential row sum.  All lanes of a group must be active together.
+// Rows of at most kShortRow entries (stencils) issue all their loads at once,
+// predicated, and then combine them in the stored order.
+constexpr int kShortRow = 8;
+
+// acc - sum_t v_t x_{c_t} over CSR row g, the entries subtracted in order.
+__device__ inline double row_sub(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const double* __restrict__ v, const double* __restrict__ x, int64_t g,
+                                 double acc) {
+  const int64_t t0 = rp[g], t1 = rp[g + 1];
+  if (t1 - t0 <= kShortRow) {
+    int c[kShortRow];
+    double a[kShortRow], xv[kShortRow];
+#pragma unroll
+    for (int q = 0; q < kShortRow; ++q) {
+      c[q] = 0;
+      a[q] = 0.0;
+      if (t0 + q < t1) {
+        c[q] = ci[t0 + q];
+        a[q] = v[t0 + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kShortRow; ++q) xv[q] = (t0 + q < t1) ? x[c[q]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kShortRow; ++q)
+      if (t0 + q < t1) acc -= a[q] * xv[q];
+    return acc;
+  }
+  for (int64_t t = t0; t < t1; ++t) acc -= v[t] * x[ci[t]];
+  return acc;
+}
+
 template <int L>
 __device__ inline double row_dot_l(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                    const double* __restrict__ v, const double* __restrict__ x, int64_t g,
                                    int j) {
   double s = 0.0;
-  const int64_t t1 = rp[g + 1];
+  const int64_t t0 = rp[g], t1 = rp[g + 1];
+  if (L == 1 && t1 - t0 <= kShortRow) {
+    int c[kShortRow];
+    double a[kShortRow], xv[kShortRow];
+#pragma unroll
+    for (int q = 0; q < kShortRow; ++q) {
+      c[q] = 0;
+      a[q] = 0.0;
+      if (t0 + q < t1) {
+        c[q] = ci[t0 + q];
+        a[q] = v[t0 + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kShortRow; ++q) xv[q] = (t0 + q < t1) ? x[c[q]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kShortRow; ++q)
+      if (t0 + q < t1) s += a[q] * xv[q];
+    return s;
+  }
 #pragma unroll 4
-  for (int64_t t = rp[g] + j; t < t1; t += L) s += v[t] * x[ci[t]];
+  for (int64_t t = t0 + j; t < t1; t += L) s += v[t] * x[ci[t]];
 #pragma unroll
   for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   return s;

@@ -45,8 +45,7 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     const int g = own_idx[t];
     double s;
     if constexpr (L == 1) {
-      s = r[g];
-      for (int64_t u = rp[g]; u < rp[g + 1]; ++u) s -= val[u] * e[ci[u]];
+      s = row_sub(rp, ci, val, e, g, r[g]);
     } else {
       s = r[g] - row_dot_l<L>(rp, ci, val, e, g, jl);
     }

@@ -506,10 +506,8 @@ __global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const
   if (j >= ni) return;  // the whole lane group leaves together
   const int g = set_idx[s0 + j];
   if constexpr (L == 1) {
-    double acc = r[g];
-    if (!e_zero)
-      for (int64_t t = rp[g]; t < rp[g + 1]; ++t) acc -= val[t] * e[ci[t]];
-    bres[s0 + j] = acc;
+    const double rg = r[g];
+    bres[s0 + j] = e_zero ? rg : row_sub(rp, ci, val, e, g, rg);
   } else {
     const double ae = e_zero ? 0.0 : row_dot_l<L>(rp, ci, val, e, g, threadIdx.x & (L - 1));
     if ((threadIdx.x & (L - 1)) == 0) bres[s0 + j] = r[g] - ae;
