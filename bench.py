@@ -416,9 +416,10 @@ def main():
                  "candidates": [{"tile": c[0], "block_target": c[1], "precond_ms": c[2]} for c in cands]}
         log(f"autotuner: tile {tt}, block_target {bt} ({tuned['tune_s']:.1f} s): {cands}")
 
-    def setup(precision):
+    def setup(precision, schedule="colours"):
         t0 = time.perf_counter()
-        s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol, tile=tile_bt[0], block_target=tile_bt[1])
+        s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol, tile=tile_bt[0], block_target=tile_bt[1],
+                                   schedule=schedule)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         log(f"setup {precision}: wall {wall:.2f} s, device numeric {s.info()['setup_ms']:.1f} ms")
@@ -453,6 +454,15 @@ def main():
     smx.close()
     del smx
     torch.cuda.empty_cache()
+
+    # the same solve with the task-queue schedule (one launch per sweep direction)
+    sq, _ = setup(args.precision, "queue")
+    ms_q, info_q, _, u_q, _ = timed(sq, max(1, args.steps // 2), 1, profile=False)
+    sq.close()
+    del sq
+    torch.cuda.empty_cache()
+    queue = {"ms_per_solve": ms_q, "iters": info_q["iters"], "same_u_as_colour_launches": bool(np.array_equal(u_q, u_mx))}
+    log(f"task-queue schedule: {ms_q:.2f} ms/solve, iters {info_q['iters']}, same u: {queue['same_u_as_colour_launches']}")
 
     out64 = {}
     if not args.no_fp64:
@@ -545,6 +555,7 @@ def main():
         "batched": bat,
         "elasticity": ela,
         "tuned": tuned,
+        "queue_schedule": queue,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

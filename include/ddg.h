@@ -56,6 +56,14 @@ typedef enum {
   DDG_MIXED_BF16 = 2   /* local factors stored in bfloat16, float32 accumulation */
 } ddg_precision;
 
+/* How a preconditioner application schedules its local solves. */
+typedef enum {
+  DDG_SCHEDULE_COLOURS = 0,  /* one launch per colour phase, each preceded by a local-residual launch */
+  DDG_SCHEDULE_QUEUE = 1     /* one launch per sweep direction: (subdomain, chain) tasks taken from a
+                                device queue in sweep order, each waiting only for the earlier
+                                subdomains whose sets meet its neighbourhood; same results bit for bit */
+} ddg_schedule;
+
 typedef struct {
   int32_t precision;   /* ddg_precision */
   int32_t max_iter;    /* CG iteration cap (default 1000, Section 7) */
@@ -64,7 +72,7 @@ typedef struct {
   int32_t tile;        /* factor tile edge 16/32/64; 0 = chosen by the autotuner */
   int32_t block_target;/* merge local levels up to this many rows; 0 = automatic */
   int32_t check_every; /* CG iterations enqueued between host convergence checks (0 = 4) */
-  int32_t reserved;
+  int32_t schedule;    /* ddg_schedule (default DDG_SCHEDULE_COLOURS) */
   void* stream;        /* hipStream_t for all work; NULL = the null stream */
 } ddg_options;
 

@@ -22,11 +22,14 @@ PRECISION = {"fp64": 0, "fp32": 1, "mixed": 1, "bf16": 2}
 EXPORT_COLOURS, EXPORT_SET_PTR, EXPORT_SET_IDX, EXPORT_KCOUNTS, EXPORT_A0, EXPORT_Q, EXPORT_BLOCKS = range(7)
 
 
+SCHEDULE = {"colours": 0, "queue": 1}
+
+
 class Options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
         ("rank_tol", C.c_double), ("tile", C.c_int32), ("block_target", C.c_int32),
-        ("check_every", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p),
+        ("check_every", C.c_int32), ("schedule", C.c_int32), ("stream", C.c_void_p),
     ]
 
 

@@ -69,7 +69,7 @@ void account_bytes(Handle& h, const int64_t* rp) {
   const int es = storage_size(h.opt.precision);
   const int32_t C = S.n_colours;
   h.colour_bytes.assign(2 * C, 0);
-  int64_t resid = 0, resid0 = 0;
+  int64_t resid = 0, resid0 = 0, flow0 = 0, flow1 = 0;
   for (int32_t c = 0; c < C; ++c) {
     int64_t bytes = 0;
     for (int32_t q = S.colour_ptr[c]; q < S.colour_ptr[c + 1]; ++q) {
@@ -96,14 +96,25 @@ void account_bytes(Handle& h, const int64_t* rp) {
       bytes += fb + cpl + ni * (8 + 4 + 16);
       resid0 += ni * (4 + 8 + 8);
       resid += ni * (4 + 8 + 8 + 16 + 8) + nnz_rows * 12;
+      // persistent sweep: the same local solves, each forming its residual rows itself
+      // (set index, r, row pointers, CSR rows and e; set index and r when e = 0)
+      const int64_t own = fb + cpl + ni * (4 + 16);
+      flow1 += own + ni * (4 + 8 + 16 + 8) + nnz_rows * 12;
+      flow0 += own + (c == 0 ? ni * (4 + 8) : ni * (4 + 8 + 16 + 8) + nnz_rows * 12);
     }
     h.colour_bytes[c] = bytes;
     h.colour_bytes[C + c] = bytes;
   }
   h.residual_bytes = resid;
+  h.flow_bytes[0] = flow0;
+  h.flow_bytes[1] = flow1;
   int64_t sweep = 0;
-  for (int32_t c = 0; c < C; ++c) sweep += 2 * h.colour_bytes[c];
-  sweep += (2 * C - 1) * (resid / C) + resid0 / C;  // residual kernels (per-colour average)
+  if (h.flow_ok) {
+    sweep = flow0 + flow1;
+  } else {
+    for (int32_t c = 0; c < C; ++c) sweep += 2 * h.colour_bytes[c];
+    sweep += (2 * C - 1) * (resid / C) + resid0 / C;  // residual kernels (per-colour average)
+  }
   h.info.sweep_bytes = sweep;
   const int64_t n = S.n, nnzb = S.nnz * 12 + (n + 1) * 8;
   const int64_t ntiles = h.ntiles;
@@ -124,11 +135,20 @@ void check_err_flag(Handle& h, const char* what) {
   if (e[0] != 0) {
     std::string m = std::string(what) + ": ";
     if (e[0] == DDG_ERR_RANK) m += "every generating vector vanishes on subdomain " + std::to_string(e[1]);
+    else if (e[0] == DDG_ERR_HIP && e[2] == -8) m += "sweep task of subdomain " + std::to_string(e[1]) + " timed out waiting for a dependency";
+    else if (e[0] == DDG_ERR_HIP && e[2] == -9) m += "sweep task queue out of step";
     else if (e[0] == DDG_ERR_HIP) m += "workgroup handoff timed out in subdomain " + std::to_string(e[1]);
     else if (e[1] < 0) m += "coarse pivot " + std::to_string(e[3]) + " not positive (A0 not SPD)";
     else m += "local pivot not positive in subdomain " + std::to_string(e[1]) + " block " + std::to_string(e[2]) +
               " row " + std::to_string(e[3]);
     DDG_HIP(hipMemsetAsync(h.err_flag.p, 0, sizeof(e), h.stream));
+    if (h.flow_ok) {
+      // the task queue may be out of step after a failed sweep: start it afresh
+      DDG_HIP(hipMemsetAsync(h.flow_done.p, 0, (size_t)h.S.n_parts * sizeof(int32_t), h.stream));
+      DDG_HIP(hipMemsetAsync(h.flow_counter.p, 0, sizeof(unsigned long long), h.stream));
+      h.flow_base = 0;
+      h.flow_seq = 0;
+    }
     throw Error{e[0], m};
   }
 }
@@ -330,6 +350,39 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   if (const char* env = std::getenv("DDG_ROW_LANES")) {
     const int v = std::atoi(env);
     if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) h->lpr = v;
+  }
+  // sweep over a device task queue (each task forms its own residual rows)
+  DDG_REQUIRE(h->opt.schedule == DDG_SCHEDULE_COLOURS || h->opt.schedule == DDG_SCHEDULE_QUEUE,
+              DDG_ERR_INVALID_ARG, "schedule must be DDG_SCHEDULE_COLOURS or DDG_SCHEDULE_QUEUE");
+  h->flow_ok = h->opt.schedule == DDG_SCHEDULE_QUEUE;
+  if (h->flow_ok) {
+    const int32_t C = S.n_colours;
+    for (int dir = 0; dir < 2; ++dir) {
+      std::vector<int32_t> order;
+      order.reserve(n_parts);
+      for (int32_t q = 0; q < C; ++q) {
+        const int32_t c = dir == 0 ? q : C - 1 - q;
+        for (int32_t t = S.colour_ptr[c]; t < S.colour_ptr[c + 1]; ++t) order.push_back(S.colour_subs[t]);
+      }
+      std::vector<int32_t> dptr(n_parts + 1, 0), didx;
+      for (int32_t i = 0; i < n_parts; ++i) {
+        for (int32_t t = S.conf_ptr[i]; t < S.conf_ptr[i + 1]; ++t) {
+          const int32_t j = S.conf_idx[t];
+          if (dir == 0 ? S.colour[j] < S.colour[i] : S.colour[j] > S.colour[i]) didx.push_back(j);
+        }
+        dptr[i + 1] = (int32_t)didx.size();
+      }
+      if (didx.empty()) didx.push_back(0);
+      h->flow_order[dir].upload(order, s);
+      h->flow_dep_ptr[dir].upload(dptr, s);
+      h->flow_dep_idx[dir].upload(didx, s);
+    }
+    h->flow_done.alloc((size_t)n_parts * sizeof(int32_t));
+    DDG_HIP(hipMemsetAsync(h->flow_done.p, 0, (size_t)n_parts * sizeof(int32_t), s));
+    h->flow_counter.alloc(sizeof(unsigned long long));
+    DDG_HIP(hipMemsetAsync(h->flow_counter.p, 0, sizeof(unsigned long long), s));
+    h->flow_base = 0;
+    h->flow_seq = 0;
   }
   h->rch = 4 * 256 / h->lpr;
   h->nch = std::max<int32_t>(1, (S.max_own + h->rch - 1) / h->rch);

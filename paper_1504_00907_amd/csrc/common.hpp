@@ -82,6 +82,8 @@ struct Symbolic {
   std::vector<int32_t> colour_subs;  // subdomains grouped by colour, ascending id
   std::vector<int32_t> nbr_ptr;      // n_parts+1, coupled subdomains (incl. self), ascending
   std::vector<int32_t> nbr_idx;
+  std::vector<int32_t> conf_ptr;     // n_parts+1, conflicting subdomains (set meets the other's
+  std::vector<int32_t> conf_idx;     //   neighbourhood), ascending, self excluded
   // blocks of the local factors
   std::vector<int32_t> sub_blk_ptr;  // n_parts+1 into block arrays
   std::vector<int32_t> blk_start;    // first local row of each block
@@ -207,6 +209,15 @@ struct Handle {
   DevBuf sl_lo_off, sl_up_off, sl_lo_col, sl_up_col;
   DevBuf sl_lo_val, sl_up_val;                       // in the sweep's arithmetic type
   DevBuf xch, flags;                 // two-workgroup handoff buffers of the twisted sweep
+  // persistent sweep over a task queue (one launch per sweep direction): per
+  // direction the subdomains in sweep order and each subdomain's earlier
+  // conflicting subdomains; per subdomain a completion count; the queue counter
+  bool flow_ok = false;
+  DevBuf flow_order[2], flow_dep_ptr[2], flow_dep_idx[2];
+  DevBuf flow_done, flow_counter;
+  mutable int64_t flow_base = 0;     // queue counter value before the next flow launch
+  mutable int32_t flow_seq = 0;      // flow launches so far
+  int64_t flow_bytes[2] = {0, 0};    // algorithmic bytes of one flow launch per direction
   DevBuf bres;                       // local residuals of one colour's expanded sets
   int32_t xch_ld = 0;
   bool twisted_ok = false;
@@ -273,6 +284,8 @@ void build_cg_map(Handle& h, hipStream_t s);
 // preconditioner
 void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded,
                     hipStream_t s);
+// one sweep direction (0: colours ascending, 1: descending) as a persistent launch
+void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s);
 
 // setup numerics
 void launch_coarse_basis(Handle& h, hipStream_t s);

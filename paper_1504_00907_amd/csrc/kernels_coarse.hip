@@ -210,12 +210,40 @@ static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez
   h.pending.push_back({idx, ez ? h.colour_bytes[h.S.n_colours + c] : h.colour_bytes[c]});
 }
 
+// One persistent sweep direction; when profiling, an event pair brackets it.
+static void flow_profiled(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s) {
+  if (!h.profiling) {
+    launch_sweep_flow(h, dir, r, e, st, s);
+    return;
+  }
+  if (h.ev_used + 2 > (int)h.ev_pool.size()) {
+    for (int t = 0; t < 64; ++t) {
+      hipEvent_t ev;
+      DDG_HIP(hipEventCreate(&ev));
+      h.ev_pool.push_back(ev);
+    }
+  }
+  int idx = h.ev_used;
+  h.ev_used += 2;
+  DDG_HIP(hipEventRecord(h.ev_pool[idx], s));
+  launch_sweep_flow(h, dir, r, e, st, s);
+  DDG_HIP(hipEventRecord(h.ev_pool[idx + 1], s));
+  h.pending.push_back({idx, h.flow_bytes[dir]});
+}
+
 void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded, hipStream_t s) {
   const CgState* st = guarded ? h.cstate.as<CgState>() : nullptr;
   const int C = h.S.n_colours;
   const int total = 2 * C + 1;
   if (stages < 0 || stages > total) stages = total;
   launch_fill(e, 0.0, h.S.n, s);
+  if (h.flow_ok && stages == total) {
+    // whole application: each sweep direction as one persistent launch
+    flow_profiled(h, 0, r, e, st, s);
+    launch_coarse(h, r, e, st, s);
+    flow_profiled(h, 1, r, e, st, s);
+    return;
+  }
   int done = 0;
   for (int c = 0; c < C && done < stages; ++c, ++done) sweep_profiled(h, c, r, e, c == 0, st, s);
   if (done < stages) {

@@ -173,11 +173,15 @@ __device__ inline AT slice_dot(const int32_t* tab, int64_t base, const int32_t* 
 
 constexpr int kMaxLevels = 96;   // levels per subdomain staged in LDS
 
-// SL = false: at most kCplRegs couplings per row and direction (held in registers,
-// rows past the first NT of a level read the ELL arrays); SL = true: the sliced
-// coupling layout.
-template <class FT, class AT, int T, int NW, int TPW, bool SL>
-__global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
+// One local solve: subdomain `sub`, chain `role` (0: whole subdomain; 1: top chain
+// and middle level; 2: bottom chain), exchange slot `xs` of the two-workgroup
+// handoff.  SL = false: at most kCplRegs couplings per row and direction (held in
+// registers, rows past the first NT of a level read the ELL arrays); SL = true:
+// the sliced coupling layout.  OWN_RES: the workgroup forms b = (r - A e) on its
+// own rows from the CSR rows of A (res_e_zero: e is zero there) instead of reading
+// the local-residual kernel's output.
+template <class FT, class AT, int T, int NW, int TPW, bool SL, bool OWN_RES>
+__device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs, bool res_e_zero) {
   using G = TileGeom<FT, T>;
   constexpr int NT = NW * 64;
   constexpr int TT = T * T;
@@ -185,22 +189,7 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   __shared__ int32_t lv_start[kMaxLevels + 1], lv_size[kMaxLevels];
   __shared__ int64_t lv_foff[kMaxLevels];
   __shared__ int32_t lv_slice[kMaxLevels];  // first slice of each level, relative to the subdomain's
-  int p, role;
-  if (a.twisted) {
-    // pair (bottom, top) = (16g + i, 16g + i + 8): same XCD under round-robin dispatch,
-    // bottom chain dispatched first
-    const int g = blockIdx.x >> 4, w16 = blockIdx.x & 15;
-    p = g * 8 + (w16 & 7);
-    role = (w16 < 8) ? 2 : 1;
-  } else {
-    p = blockIdx.x;
-    role = 0;
-  }
-  if (p >= a.nsub) return;
-  const int sub = a.subs[p];
-  // both workgroups of a pair read the same flag (stable during the launch), so
-  // they skip together and no handoff is left waiting
-  if (a.st && a.st[a.sub_inst[sub]].done) return;
+  const int p = xs;
   const int64_t s0 = a.set_ptr[sub];
   const int ni = (int)(a.set_ptr[sub + 1] - s0);
   const int ni_pad = (ni + 3) & ~3;
@@ -306,24 +295,36 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
       }
     }
   };
-  // the first level's couplings, then its tiles, are requested before the residual
-  // is read (vector loads complete in issue order, so a wait for the couplings does
-  // not wait for the tiles)
-  if (ns > 0) {
-    int kind, k;
-    decode_step(role, 0, K, m, kind, k);
-    load_cpl(kind, k);
-    load_head(kind, k);
+  // 1. local residual b = (r - A e) on the rows this workgroup owns; with sliced
+  //    couplings the other chain's rows start at zero (the handoff writes the ones
+  //    that are read).  OWN_RES: formed here from the CSR rows of A before the first
+  //    level's tiles are requested (its loads then hold no tile registers); otherwise
+  //    the first level's couplings and tiles are requested first and the residual
+  //    that k_local_residual wrote is read after them (vector loads complete in
+  //    issue order, so a wait for the couplings does not wait for the tiles).
+  auto prefetch_first = [&]() {
+    if (ns > 0) {
+      int kind, k;
+      decode_step(role, 0, K, m, kind, k);
+      load_cpl(kind, k);
+      load_head(kind, k);
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) load_tile(k, j);
-  }
-
-  // 1. local residual b = (r - A e) on the rows this workgroup owns (computed for
-  //    the whole colour by k_local_residual); with sliced couplings the other
-  //    chain's rows start at zero (the handoff writes the ones that are read)
+      for (int j = 0; j < TPW; ++j) load_tile(k, j);
+    }
+  };
   if constexpr (SL) {
-    for (int j = tid; j < ni; j += NT) w[j] = (j >= r0 && j < r1) ? (AT)a.bres[s0 + j] : (AT)0;
+    for (int j = tid; j < ni; j += NT)
+      if (j < r0 || j >= r1) w[j] = (AT)0;
+  }
+  if constexpr (OWN_RES) {
+    for (int j = r0 + tid; j < r1; j += NT) {
+      const int g = a.set_idx[s0 + j];
+      const double rg = a.r[g];
+      w[j] = (AT)(res_e_zero ? rg : row_sub(a.rp, a.ci, a.val, a.e, g, rg));
+    }
+    prefetch_first();
   } else {
+    prefetch_first();
     for (int j = r0 + tid; j < r1; j += NT) w[j] = (AT)a.bres[s0 + j];
   }
   __syncthreads();
@@ -487,6 +488,111 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   }
 }
 
+// One colour phase: workgroup per (subdomain, chain) of the colour.
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
+__global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
+  int p, role;
+  if (a.twisted) {
+    // pair (bottom, top) = (16g + i, 16g + i + 8): same XCD under round-robin dispatch,
+    // bottom chain dispatched first
+    const int g = blockIdx.x >> 4, w16 = blockIdx.x & 15;
+    p = g * 8 + (w16 & 7);
+    role = (w16 < 8) ? 2 : 1;
+  } else {
+    p = blockIdx.x;
+    role = 0;
+  }
+  if (p >= a.nsub) return;
+  const int sub = a.subs[p];
+  // both workgroups of a pair read the same flag (stable during the launch), so
+  // they skip together and no handoff is left waiting
+  if (a.st && a.st[a.sub_inst[sub]].done) return;
+  sweep_task<FT, AT, T, NW, TPW, SL, false>(a, sub, role, p, false);
+}
+
+// A whole sweep direction (every colour) as one launch over a task queue.  Tasks
+// are (subdomain, chain) in sweep order, colour by colour (bottom chain first).
+// Each workgroup, when it starts, takes the next task from a 64-bit counter, waits
+// until every earlier subdomain of the sweep that conflicts with its subdomain
+// (whose set meets its set's neighbourhood) has finished, forms its residual rows
+// and solves.  Subdomains of one colour never conflict, so the corrections and
+// every value computed are those of the colour-by-colour launches.  Tasks are
+// taken in the order workgroups start, and a task waits only for earlier tasks,
+// held by workgroups that are running; a chain's partner is the next task, and
+// the workgroups holding earlier tasks never wait for it, so they finish and
+// free a slot for it.  Each finished task adds 1 to its subdomain's completion
+// count; a dependency is met when the count reaches `target` (chains per
+// subdomain times the sweeps launched so far).
+struct FlowArgs {
+  const int32_t* order;     // subdomains in sweep order
+  const int32_t* dep_ptr;   // per subdomain: earlier conflicting subdomains of this sweep
+  const int32_t* dep_idx;
+  int32_t* done;            // per subdomain completion count
+  unsigned long long* counter;
+  int64_t base;             // counter value at the start of this launch
+  int64_t ntasks;
+  int64_t zero_tasks;       // the first zero_tasks tasks start from e = 0
+  int32_t roles;            // chains per subdomain (2 with the two-workgroup schedule)
+  int32_t target;
+};
+
+// Bounded wait for a completion count; gives up at once when an error is already
+// flagged, so a failed sweep drains instead of running every wait to its limit.
+__device__ inline void flow_wait(const int32_t* cnt, int32_t target, int32_t* err, int sub) {
+  int spins = 0;
+  while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(2);
+    ++spins;
+    if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+    if (spins > kSpinLimit) {
+      if (atomicCAS(err, 0, DDG_ERR_HIP) == 0) {
+        err[1] = sub;
+        err[2] = -8;
+      }
+      break;
+    }
+  }
+}
+
+// Wait for every dependency of subdomain `sub`, then acquire.  Kept out of line:
+// inlined, its polling loop raises the register allocation of the whole kernel.
+__device__ __attribute__((noinline)) void flow_wait_deps(const int32_t* dep_ptr, const int32_t* dep_idx,
+                                                         const int32_t* done, int32_t target, int32_t* err,
+                                                         int sub) {
+  for (int d = dep_ptr[sub]; d < dep_ptr[sub + 1]; ++d) flow_wait(done + dep_idx[d], target, err, sub);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
+__global__ void __launch_bounds__(NW * 64) k_sweep_flow(SweepArgs a, FlowArgs f) {
+  __shared__ int64_t task_s;
+  if (threadIdx.x == 0) task_s = (int64_t)atomicAdd(f.counter, 1ull) - f.base;
+  __syncthreads();
+  const int64_t t = task_s;  // in [0, ntasks): one workgroup per task, counter base kept by the host
+  if (t < 0 || t >= f.ntasks) {
+    if (threadIdx.x == 0 && atomicCAS(a.err, 0, DDG_ERR_HIP) == 0) {
+      a.err[1] = -1;
+      a.err[2] = -9;
+    }
+    return;
+  }
+  const int sub = f.order[t / f.roles];
+  const int role = f.roles == 2 ? ((t & 1) ? 1 : 2) : 0;
+  if (threadIdx.x == 0) {
+    flow_wait_deps(f.dep_ptr, f.dep_idx, f.done, f.target, a.err, sub);
+  }
+  __syncthreads();
+  if (!(a.st && a.st[a.sub_inst[sub]].done))
+    sweep_task<FT, AT, T, NW, TPW, SL, true>(a, sub, role, sub, t < f.zero_tasks);
+  // publish this chain's corrections of e, then count the task as finished
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(f.done + sub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // b = (r - A e) on the expanded sets of one colour, written in set order; L lanes
 // per CSR row (one row per lane when L = 1).
 template <int L>
@@ -516,14 +622,17 @@ __global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const
 
 namespace {
 
+// flow_dir < 0: one colour phase (its local-residual kernel when `residual`, else its
+// local solves); flow_dir = 0 / 1: the whole ascending / descending sweep as one
+// persistent launch.
 template <class FT, class AT, int T, int NW, int TPW, bool SL>
 void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                      const CgState* st, hipStream_t s, bool residual) {
+                      const CgState* st, hipStream_t s, bool residual, int flow_dir) {
   const Symbolic& S = h.S;
-  const int nsub = S.colour_ptr[colour + 1] - S.colour_ptr[colour];
+  const int nsub = flow_dir >= 0 ? S.n_parts : S.colour_ptr[colour + 1] - S.colour_ptr[colour];
   if (nsub == 0) return;
   SweepArgs a;
-  a.subs = h.colour_subs.as<int32_t>() + S.colour_ptr[colour];
+  a.subs = h.colour_subs.as<int32_t>() + (flow_dir >= 0 ? 0 : S.colour_ptr[colour]);
   a.nsub = nsub;
   a.twisted = h.twisted_ok ? 1 : 0;
   a.set_ptr = h.set_ptr.as<int64_t>();
@@ -582,6 +691,27 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   DDG_REQUIRE(a.slot_tiles >= round_tiles, DDG_ERR_UNSUPPORTED,
               "local problem too large for on-chip storage (" + std::to_string(fixed) + " bytes before slots)");
   const size_t lds = (size_t)(fixed + per_tile * a.slot_tiles);
+  if (flow_dir >= 0) {
+    auto fk = k_sweep_flow<FT, AT, T, NW, TPW, SL>;
+    if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    FlowArgs f;
+    f.roles = h.twisted_ok ? 2 : 1;
+    f.ntasks = (int64_t)f.roles * S.n_parts;
+    f.zero_tasks = flow_dir == 0 && e_zero ? (int64_t)f.roles * (S.colour_ptr[1] - S.colour_ptr[0]) : 0;
+    f.order = h.flow_order[flow_dir].as<int32_t>();
+    f.dep_ptr = h.flow_dep_ptr[flow_dir].as<int32_t>();
+    f.dep_idx = h.flow_dep_idx[flow_dir].as<int32_t>();
+    f.done = h.flow_done.as<int32_t>();
+    f.counter = h.flow_counter.as<unsigned long long>();
+    f.base = h.flow_base;
+    f.target = f.roles * (h.flow_seq + 1);
+    // one workgroup per task; each takes one counter value
+    hipLaunchKernelGGL(fk, dim3((unsigned)f.ntasks), dim3(NW * 64), lds, s, a, f);
+    DDG_HIP(hipGetLastError());
+    h.flow_base += f.ntasks;
+    h.flow_seq += 1;
+    return;
+  }
   auto kern = k_sweep<FT, AT, T, NW, TPW, SL>;
   if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (residual) {
@@ -601,29 +731,29 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
 
 template <class FT, class AT, bool SL>
 void launch_sweep_l(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                    const CgState* st, hipStream_t s, bool res) {
+                    const CgState* st, hipStream_t s, bool res, int fd) {
   // (waves, tiles per wave per round) keep the register ring within 128 VGPRs at 16 waves
   // or 256 at 8 waves, without spills (the sliced path's prefetched couplings take a
   // few registers of their own)
   switch (h.S.tile) {
-    case 16: launch_sweep_cfg<FT, AT, 16, 4, 4, SL>(h, colour, r, e, e_zero, st, s, res); break;
+    case 16: launch_sweep_cfg<FT, AT, 16, 4, 4, SL>(h, colour, r, e, e_zero, st, s, res, fd); break;
     case 32:
-      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4, SL>(h, colour, r, e, e_zero, st, s, res);
-      else if constexpr (SL) launch_sweep_cfg<FT, AT, 32, 8, 8, SL>(h, colour, r, e, e_zero, st, s, res);
-      else launch_sweep_cfg<FT, AT, 32, 8, 9, SL>(h, colour, r, e, e_zero, st, s, res);
+      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      else if constexpr (SL) launch_sweep_cfg<FT, AT, 32, 8, 8, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      else launch_sweep_cfg<FT, AT, 32, 8, 9, SL>(h, colour, r, e, e_zero, st, s, res, fd);
       break;
     default:
-      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1, SL>(h, colour, r, e, e_zero, st, s, res);
-      else launch_sweep_cfg<FT, AT, 64, 8, 2, SL>(h, colour, r, e, e_zero, st, s, res);
+      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      else launch_sweep_cfg<FT, AT, 64, 8, 2, SL>(h, colour, r, e, e_zero, st, s, res, fd);
       break;
   }
 }
 
 template <class FT, class AT>
 void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                    const CgState* st, hipStream_t s, bool res) {
-  if (h.S.sliced) launch_sweep_l<FT, AT, true>(h, colour, r, e, e_zero, st, s, res);
-  else launch_sweep_l<FT, AT, false>(h, colour, r, e, e_zero, st, s, res);
+                    const CgState* st, hipStream_t s, bool res, int fd) {
+  if (h.S.sliced) launch_sweep_l<FT, AT, true>(h, colour, r, e, e_zero, st, s, res, fd);
+  else launch_sweep_l<FT, AT, false>(h, colour, r, e, e_zero, st, s, res, fd);
 }
 
 }  // namespace
@@ -632,9 +762,19 @@ void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, boo
 void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                   const CgState* st, hipStream_t s, bool res) {
   switch (h.opt.precision) {
-    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, colour, r, e, e_zero, st, s, res); break;
-    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, colour, r, e, e_zero, st, s, res); break;
-    default: launch_sweep_p<double, double>(h, colour, r, e, e_zero, st, s, res); break;
+    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, colour, r, e, e_zero, st, s, res, -1); break;
+    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, colour, r, e, e_zero, st, s, res, -1); break;
+    default: launch_sweep_p<double, double>(h, colour, r, e, e_zero, st, s, res, -1); break;
+  }
+}
+
+// dir 0: the ascending sweep (e is zero on entry); 1: the descending sweep.
+void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s) {
+  DDG_REQUIRE(h.flow_ok, DDG_ERR_HIP, "internal: persistent sweep not prepared");
+  switch (h.opt.precision) {
+    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, 0, r, e, dir == 0, st, s, false, dir); break;
+    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, 0, r, e, dir == 0, st, s, false, dir); break;
+    default: launch_sweep_p<double, double>(h, 0, r, e, dir == 0, st, s, false, dir); break;
   }
 }
 

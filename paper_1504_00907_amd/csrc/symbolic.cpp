@@ -174,6 +174,10 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
       S.n_colours = std::max(S.n_colours, c + 1);
     }
   }
+  S.conf_ptr.assign(n_parts + 1, 0);
+  for (int32_t i = 0; i < n_parts; ++i) S.conf_ptr[i + 1] = S.conf_ptr[i] + (int32_t)conf[i].size();
+  S.conf_idx.resize(S.conf_ptr[n_parts]);
+  for (int32_t i = 0; i < n_parts; ++i) std::copy(conf[i].begin(), conf[i].end(), S.conf_idx.begin() + S.conf_ptr[i]);
   S.colour_ptr.assign(S.n_colours + 1, 0);
   for (int32_t i = 0; i < n_parts; ++i) S.colour_ptr[S.colour[i] + 1]++;
   for (int32_t c = 0; c < S.n_colours; ++c) S.colour_ptr[c + 1] += S.colour_ptr[c];

@@ -27,7 +27,8 @@ def _dev(t: torch.Tensor, n: int, name: str) -> int:
     return t.data_ptr()
 
 
-def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream):
+def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream,
+             schedule="colours"):
     opt = Options()
     lib.ddg_default_options(C.byref(opt))
     opt.precision = _lib.PRECISION[precision]
@@ -37,6 +38,7 @@ def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check
     opt.tile = tile
     opt.block_target = block_target
     opt.check_every = check_every
+    opt.schedule = _lib.SCHEDULE[schedule]
     opt.stream = C.c_void_p(stream.cuda_stream)
     return opt
 
@@ -47,7 +49,7 @@ class DDGSolver:
     def __init__(self, n: int, row_ptr, col_idx, val, F: Optional[np.ndarray], part, n_parts: int,
                  overlap: int, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000,
                  rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0, check_every: int = 4,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "colours"):
         lib = _lib.load()
         self._lib = lib
         self.n = int(n)
@@ -68,7 +70,8 @@ class DDGSolver:
         if Fh is not None and Fh.shape[0] != self.n:
             raise ValueError("F must have n rows")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream)
+        opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
+                       schedule)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
@@ -230,12 +233,13 @@ class DDGBatchSolver(DDGSolver):
 
     def __init__(self, problems, overlap: int, precision: str = "fp64", rtol: float = 1e-8,
                  max_iter: int = 1000, rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0,
-                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None):
+                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "colours"):
         lib = _lib.load()
         self._lib = lib
         arr, keep = _problem_array(problems)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream)
+        opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
+                       schedule)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup_batched(C.byref(h), len(problems), arr, int(overlap), C.byref(opt)))

@@ -38,6 +38,7 @@ def test_default_options():
     o = _lib.Options()
     lib.ddg_default_options(C.byref(o))
     assert (o.precision, o.max_iter, o.rtol, o.rank_tol) == (0, 1000, 1e-8, 1e-10)
+    assert (o.tile, o.block_target, o.check_every, o.schedule) == (0, 0, 4, 0)
 
 
 class Analysis:

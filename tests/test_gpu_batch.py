@@ -146,6 +146,22 @@ def test_mixed_solve_per_system():
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_task_queue_schedule_matches_colour_launches(precision):
+    """The task-queue schedule over the whole batch (tasks of all systems in one
+    queue, converged systems skipped) gives the colour-by-colour results bit for bit."""
+    Ps, Os = systems()
+    f = dev(np.concatenate([P.f for P in Ps]))
+    out = []
+    for schedule in ("queue", "colours"):
+        b = make_batch(Ps, precision=precision, rtol=1e-8, schedule=schedule)
+        u, infos = b.solve(f)
+        out.append((host(u), [i["iters"] for i in infos]))
+        b.close()
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 def test_systems_stop_independently():
     from paper_1504_00907_amd import DDGError
     Ps, Os = systems()

@@ -262,6 +262,38 @@ def test_sweep_paths_match_oracle(name, single, monkeypatch):
     s.close()
 
 
+@pytest.mark.parametrize("single", [False, True], ids=["two_wg", "one_wg"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cfg1", "3d20", "3d18_b3", "slab"])
+def test_task_queue_sweep_matches_colour_launches(name, precision, single, monkeypatch):
+    """A whole sweep direction as one launch over the task queue (each task waits for
+    its earlier conflicting subdomains and forms its own residual rows) computes
+    exactly what the colour-by-colour launches compute: preconditioner applications
+    in a row and a solve agree bit for bit, and with the oracle."""
+    if single:
+        monkeypatch.setenv("DDG_NO_TWIST", "1")
+    P, o = problem(name)
+    rng = seed_rng(68, 0)
+    rs = [rng.standard_normal(P.n) for _ in range(3)]
+    out = []
+    for colour_launches in (False, True):
+        s = make_solver(P, precision=precision, rtol=1e-8, schedule="colours" if colour_launches else "queue")
+        s.profile_enable(True)
+        zs = [host(s.apply_precond(dev(r))) for r in rs]
+        launches = s.profile_read()["launches"]
+        C = s.info()["n_colours"]
+        assert launches == (2 * C if colour_launches else 2) * len(rs)
+        u, info = s.solve(dev(P.f))
+        out.append((zs, host(u), info["iters"]))
+        s.close()
+    (z_q, u_q, it_q), (z_c, u_c, it_c) = out
+    for zq, zc, r in zip(z_q, z_c, rs):
+        assert np.array_equal(zq, zc)
+        ref = o.apply(r)
+        assert np.linalg.norm(zq - ref) <= (1e-12 if precision == "fp64" else 1e-5) * np.linalg.norm(ref)
+    assert it_q == it_c and np.array_equal(u_q, u_c)
+
+
 @pytest.mark.parametrize("block_target,tile", [(100000, 32), (40, 16), (0, 64)],
                          ids=["one_level", "merged", "tile64"])
 def test_level_structures_match_oracle(block_target, tile):
