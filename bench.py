@@ -10,9 +10,10 @@ A step is one complete DDG-PCG solve (f resident in HBM -> u in HBM) with the
 mixed-precision path (FP32 local factors, FP64 Krylov vectors, dots and
 coarse inverse).  The FP64 path is timed on the same problem beside it.
 Setup (coarse basis, Galerkin product, coarse inverse, local factors) is
-reported separately.  The dominant kernel (colour-phase local solve) is timed
-with HIP events on the handle's stream during the timed region, and its
-algorithmic bytes give the roofline fraction.  The oracle's CPU time is
+reported separately.  The dominant kernel (the local solves, one launch per
+colour phase with the library's default schedule) is timed with HIP events on
+the handle's stream during the timed region, and its algorithmic bytes give
+the roofline fraction.  The oracle's CPU time is
 measured on a bounded sample (see `cpu_baseline`).
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -39,14 +40,14 @@ SWEEP_SOURCES = ["paper_1504_00907_amd/csrc/kernels_sweep.hip", "paper_1504_0090
                  "paper_1504_00907_amd/csrc/device_util.hpp"]
 
 
-def profiled_traffic(precision: str, tile: int):
-    """HBM bytes per k_sweep dispatch from the committed rocprofv3 counter summary.
+def profiled_traffic(kernel: str, precision: str, tile: int):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary.
 
     Returns None when no summary exists for this precision or when the kernel
     sources changed since the counters were taken (hash mismatch).
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_sweep_diffusion3d_128_{precision}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_diffusion3d_128_{precision}.md")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -339,7 +340,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=128)
     ap.add_argument("--box", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -416,7 +417,7 @@ def main():
                  "candidates": [{"tile": c[0], "block_target": c[1], "precond_ms": c[2]} for c in cands]}
         log(f"autotuner: tile {tt}, block_target {bt} ({tuned['tune_s']:.1f} s): {cands}")
 
-    def setup(precision, schedule="colours"):
+    def setup(precision, schedule="auto"):
         t0 = time.perf_counter()
         s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol, tile=tile_bt[0], block_target=tile_bt[1],
                                    schedule=schedule)
@@ -455,14 +456,16 @@ def main():
     del smx
     torch.cuda.empty_cache()
 
-    # the same solve with the task-queue schedule (one launch per sweep direction)
+    # the same solve with the other sweep schedule (the library's automatic choice is
+    # one launch per colour phase): one launch per sweep direction over the task queue
     sq, _ = setup(args.precision, "queue")
     ms_q, info_q, _, u_q, _ = timed(sq, max(1, args.steps // 2), 1, profile=False)
     sq.close()
     del sq
     torch.cuda.empty_cache()
-    queue = {"ms_per_solve": ms_q, "iters": info_q["iters"], "same_u_as_colour_launches": bool(np.array_equal(u_q, u_mx))}
-    log(f"task-queue schedule: {ms_q:.2f} ms/solve, iters {info_q['iters']}, same u: {queue['same_u_as_colour_launches']}")
+    alt = {"schedule": "task queue", "ms_per_solve": ms_q, "iters": info_q["iters"],
+           "same_u": bool(np.array_equal(u_q, u_mx))}
+    log(f"task-queue schedule: {ms_q:.2f} ms/solve, iters {info_q['iters']}, same u: {alt['same_u']}")
 
     out64 = {}
     if not args.no_fp64:
@@ -507,11 +510,15 @@ def main():
         torch.cuda.empty_cache()
 
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else 0.0
+    sweep_kernel = "k_sweep_flow" if hinfo["schedule"] == 2 else "k_sweep"
     roofline = {
-        "bound": "hbm", "kernel": "k_sweep (colour-phase local solve)",
+        "bound": "hbm",
+        "kernel": sweep_kernel + (" (one sweep direction over the task queue)" if sweep_kernel == "k_sweep_flow"
+                                  else " (one colour phase)"),
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": profiled_traffic(args.precision, hinfo["tile"]) if args.side == 128 and args.box == 16 else None,
+        "traffic": (profiled_traffic(sweep_kernel, args.precision, hinfo["tile"])
+                    if args.side == 128 and args.box == 16 else None),
         "launches": prof["launches"] if prof else 0,
         "avg_launch_us": (prof["ms"] * 1e3 / prof["launches"]) if prof and prof["launches"] else None,
         "bytes_per_launch": (prof["bytes"] / prof["launches"]) if prof and prof["launches"] else None,
@@ -540,7 +547,8 @@ def main():
             "workload": f"diffusion3d_{args.side}^3_variable_kappa",
             "n": P.n, "subdomains": P.n_parts, "box": args.box, "overlap": P.overlap, "p": 2,
             "n_coarse": hinfo["n_coarse"], "colours": hinfo["n_colours"], "rtol": P.rtol,
-            "precision": args.precision, "parallelism": "single GPU",
+            "precision": args.precision, "schedule": "task queue" if hinfo["schedule"] == 2 else "colour launches",
+            "parallelism": "single GPU",
         },
         "iters": info_mx["iters"],
         "true_rel_res": res_mx,
@@ -555,7 +563,7 @@ def main():
         "batched": bat,
         "elasticity": ela,
         "tuned": tuned,
-        "queue_schedule": queue,
+        "other_schedule": alt,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

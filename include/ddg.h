@@ -56,12 +56,15 @@ typedef enum {
   DDG_MIXED_BF16 = 2   /* local factors stored in bfloat16, float32 accumulation */
 } ddg_precision;
 
-/* How a preconditioner application schedules its local solves. */
+/* How a preconditioner application schedules its local solves (the results are
+ * the same bit for bit). */
 typedef enum {
-  DDG_SCHEDULE_COLOURS = 0,  /* one launch per colour phase, each preceded by a local-residual launch */
-  DDG_SCHEDULE_QUEUE = 1     /* one launch per sweep direction: (subdomain, chain) tasks taken from a
+  DDG_SCHEDULE_AUTO = 0,     /* the library's choice: currently COLOURS, measured as fast or faster
+                                on every workload tried */
+  DDG_SCHEDULE_COLOURS = 1,  /* one launch per colour phase, each preceded by a local-residual launch */
+  DDG_SCHEDULE_QUEUE = 2     /* one launch per sweep direction: (subdomain, chain) tasks taken from a
                                 device queue in sweep order, each waiting only for the earlier
-                                subdomains whose sets meet its neighbourhood; same results bit for bit */
+                                subdomains whose sets meet its neighbourhood */
 } ddg_schedule;
 
 typedef struct {
@@ -72,7 +75,7 @@ typedef struct {
   int32_t tile;        /* factor tile edge 16/32/64; 0 = chosen by the autotuner */
   int32_t block_target;/* merge local levels up to this many rows; 0 = automatic */
   int32_t check_every; /* CG iterations enqueued between host convergence checks (0 = 4) */
-  int32_t schedule;    /* ddg_schedule (default DDG_SCHEDULE_COLOURS) */
+  int32_t schedule;    /* ddg_schedule (default DDG_SCHEDULE_AUTO) */
   void* stream;        /* hipStream_t for all work; NULL = the null stream */
 } ddg_options;
 
@@ -92,7 +95,7 @@ typedef struct {
   int64_t sweep_bytes;     /* algorithmic HBM bytes of one full preconditioner sweep (both passes) */
   int64_t iter_bytes;      /* algorithmic HBM bytes of one CG iteration */
   int32_t tile;            /* tile edge of the local factors (16, 32 or 64) */
-  int32_t reserved2;
+  int32_t schedule;        /* ddg_schedule in effect: DDG_SCHEDULE_COLOURS or DDG_SCHEDULE_QUEUE */
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */

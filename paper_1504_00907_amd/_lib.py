@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "mixed": 1, "bf16": 2}
 EXPORT_COLOURS, EXPORT_SET_PTR, EXPORT_SET_IDX, EXPORT_KCOUNTS, EXPORT_A0, EXPORT_Q, EXPORT_BLOCKS = range(7)
 
 
-SCHEDULE = {"colours": 0, "queue": 1}
+SCHEDULE = {"auto": 0, "colours": 1, "queue": 2}
 
 
 class Options(C.Structure):
@@ -39,7 +39,7 @@ class Info(C.Structure):
         ("true_rel_res", C.c_double), ("n_coarse", C.c_int32), ("n_colours", C.c_int32),
         ("n_parts", C.c_int32), ("n_blocks", C.c_int32), ("setup_ms", C.c_double),
         ("solve_ms", C.c_double), ("factor_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
-        ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("reserved2", C.c_int32),
+        ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("schedule", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

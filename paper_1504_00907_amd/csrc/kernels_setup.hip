@@ -400,25 +400,36 @@ __global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
   }
 }
 
-// lower T x T tiles of the symmetric n x n matrix S (layout of symv_tile.hpp), converted to FT
+// lower T x T tiles of the symmetric n x n matrix S (layout of symv_tile.hpp, diagonal
+// tiles compact for compact_diag(T)), converted to FT
 template <class FT, int T>
 __global__ void __launch_bounds__(256) k_fac_pack(FacArgs a) {
+  using G = TileGeom<FT, T>;
   const FacItem it = a.items[blockIdx.x];
   const int b = a.blk_size[it.cur];
   const int nt = (b + T - 1) / T;
-  const int64_t total = (int64_t)nt * (nt + 1) / 2 * T * T;
+  const int64_t total = (int64_t)nt * (nt + 1) / 2 * T * T;  // full-tile index space
   const double* S = a.scratch + it.s_off;
   FT* out = static_cast<FT*>(a.fac) + a.blk_foff[it.cur];
   for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
     const int t = (int)(idx / (T * T));
-    int rr, cc;
-    tile_rc<FT, T>((int)(idx % (T * T)), rr, cc);
+    const int within = (int)(idx % (T * T));
     int I, J;
     tile_ij(t, I, J);
+    int64_t dst = tile_off<FT, T>(t, I);
+    if (compact_diag(T) && I == J) {
+      const int lane = (within / G::E) % 64;
+      if (!diag_kept(lane)) continue;  // transpose of a stored sub-tile
+      dst += ((within / (64 * G::E)) * kDiagLanes + diag_slot(lane)) * G::E + within % G::E;
+    } else {
+      dst += within;
+    }
+    int rr, cc;
+    tile_rc<FT, T>(within, rr, cc);
     const int row = I * T + rr, col = J * T + cc;
     double v = 0.0;
     if (row < b && col < b) v = (row >= col) ? S[(int64_t)row * b + col] : S[(int64_t)col * b + row];
-    out[idx] = Store<FT>::from(v);
+    out[dst] = Store<FT>::from(v);
   }
 }
 

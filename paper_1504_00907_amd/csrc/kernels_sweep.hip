@@ -184,7 +184,6 @@ template <class FT, class AT, int T, int NW, int TPW, bool SL, bool OWN_RES>
 __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs, bool res_e_zero) {
   using G = TileGeom<FT, T>;
   constexpr int NT = NW * 64;
-  constexpr int TT = T * T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int32_t lv_start[kMaxLevels + 1], lv_size[kMaxLevels];
   __shared__ int64_t lv_foff[kMaxLevels];
@@ -232,6 +231,17 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   __syncthreads();  // level metadata visible
 
   FT R[TPW][G::SS];
+  // the wave's first-round tiles are the same at every level
+  int tI[TPW], tJ[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) tile_ij(j * NW + wave, tI[j], tJ[j]);
+  // tile t = (I, J) of level k into register set j
+  constexpr bool CD = compact_diag(T);
+  auto load_tile_at = [&](int k, int t, int I, int J, int j) {
+    const FT* src = fac + lv_foff[k] + tile_off<FT, T>(t, I);
+    if (CD && I == J) load_subtile_diag<FT, T>(src, lane, R[j]);
+    else load_subtile<FT, T>(src, lane, R[j]);
+  };
   // coupling entries of this thread's row (row tid of the level) for the next step
   int cpl_col[2 * kCplRegs];
   AT cpl_val[2 * kCplRegs];
@@ -239,7 +249,7 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   auto load_tile = [&](int k, int j) {
     const int ntl = tiles_for(lv_size[k], T);
     const int t = j * NW + wave;
-    if (t < ntl) load_subtile<FT, T>(fac + lv_foff[k] + (int64_t)t * TT, lane, R[j]);
+    if (t < ntl) load_tile_at(k, t, tI[j], tJ[j], j);
   };
   auto load_cpl = [&](int kind, int k) {
     if (!cpl_regs) return;
@@ -331,10 +341,6 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
 
   double* xch = a.xch + (int64_t)p * 2 * a.xch_ld;
   int32_t* flags = a.flags + 2 * p;
-  // the wave's first-round tiles are the same at every level
-  int tI[TPW], tJ[TPW];
-#pragma unroll
-  for (int j = 0; j < TPW; ++j) tile_ij(j * NW + wave, tI[j], tJ[j]);
 
   for (int s = 0; s < ns; ++s) {
     int kind, k;
@@ -417,12 +423,18 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
     if (has_next) decode_step(role, s + 1, K, m, kind2, k2);
     for (int round = 0; round < rounds; ++round) {
       const int t_phase = (round / phase_rounds) * phase_rounds * NW * TPW;  // first tile of the phase
+      int rI[TPW], rJ[TPW];
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) {
+        rI[j] = tI[j];
+        rJ[j] = tJ[j];
+        if (round > 0) tile_ij((round * TPW + j) * NW + wave, rI[j], rJ[j]);
+      }
       if (round > 0) {
-        const FT* base = fac + lv_foff[k];
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
           const int t = (round * TPW + j) * NW + wave;
-          if (t < ntl) load_subtile<FT, T>(base + (int64_t)t * TT, lane, R[j]);
+          if (t < ntl) load_tile_at(k, t, rI[j], rJ[j], j);
         }
       }
       const bool last = round + 1 == rounds;
@@ -435,10 +447,8 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
       for (int j = 0; j < TPW; ++j) {
         const int t = (round * TPW + j) * NW + wave;
         const bool valid = t < ntl;
-        int I = tI[j], J = tJ[j];
-        if (round > 0) tile_ij(t, I, J);
-        if (!valid) I = J = 0;
-        symv_tile_slots<FT, AT, T>(R[j], I, J, tv, slots + (int64_t)(2 * (t - t_phase)) * T,
+        const int I = valid ? rI[j] : 0, J = valid ? rJ[j] : 0;
+        symv_tile_slots<FT, AT, T, CD>(R[j], I, J, tv, slots + (int64_t)(2 * (t - t_phase)) * T,
                                    slots + (int64_t)(2 * (t - t_phase) + 1) * T, lane, valid);
         if (last && has_next) load_tile(k2, j);
       }
@@ -447,7 +457,7 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
         __syncthreads();
         const int t_end = min(ntl, t_phase + phase_rounds * NW * TPW);
         for (int jj = tid; jj < b; jj += NT) {
-          const AT part = sum_slots_range<AT, T>(slots, nt, jj, t_phase, t_end);
+          const AT part = sum_slots_range<AT, T, CD>(slots, nt, jj, t_phase, t_end);
           acc[jj] = t_phase == 0 ? part : acc[jj] + part;
         }
         __syncthreads();
@@ -455,7 +465,7 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
     }
     __syncthreads();
     for (int jj = tid; jj < b; jj += NT) {
-      const AT sum = phased ? acc[jj] : sum_slots<AT, T>(slots, nt, jj);
+      const AT sum = phased ? acc[jj] : sum_slots<AT, T, CD>(slots, nt, jj);
       if (fwd) w[bs + jj] = sum;
       else w[bs + jj] -= sum;
     }
@@ -739,8 +749,8 @@ void launch_sweep_l(const Handle& h, int colour, const double* r, double* e, boo
     case 16: launch_sweep_cfg<FT, AT, 16, 4, 4, SL>(h, colour, r, e, e_zero, st, s, res, fd); break;
     case 32:
       if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4, SL>(h, colour, r, e, e_zero, st, s, res, fd);
-      else if constexpr (SL) launch_sweep_cfg<FT, AT, 32, 8, 8, SL>(h, colour, r, e, e_zero, st, s, res, fd);
-      else launch_sweep_cfg<FT, AT, 32, 8, 9, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      else if constexpr (SL) launch_sweep_cfg<FT, AT, 32, 8, 7, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      else launch_sweep_cfg<FT, AT, 32, 8, 8, SL>(h, colour, r, e, e_zero, st, s, res, fd);
       break;
     default:
       if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1, SL>(h, colour, r, e, e_zero, st, s, res, fd);

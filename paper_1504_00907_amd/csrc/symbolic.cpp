@@ -9,6 +9,7 @@
 #include <thread>
 
 #include "common.hpp"
+#include "symv_tile.hpp"
 
 namespace ddg {
 
@@ -395,7 +396,7 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
   int64_t off = 0;
   for (int32_t b = 0; b < nb_tot; ++b) {
     S.blk_foff[b] = off;
-    off += (int64_t)tiles_for(S.blk_size[b], S.tile) * S.tile * S.tile;
+    off += level_elems(S.blk_size[b], S.tile);  // lower tiles, diagonal tiles compact
   }
   S.blk_foff[nb_tot] = off;
   S.fac_elems = off;

@@ -15,7 +15,12 @@
 // load instruction of a wave reads one contiguous 1 KiB line.
 //
 // An off-diagonal tile contributes M x_J to rows I and M^T x_I to rows J, so
-// each stored value is read once and used twice.  Row partials are reduced
+// each stored value is read once and used twice.  A diagonal tile may be stored
+// compact: only the sub-tiles of the lanes with p >= q (36 of 64), the others
+// being transposes of stored ones; kept lane L's chunk m then sits at element
+// (m*36 + c(L))*E, c(L) = the number of kept lanes below L.  Such a tile's kept
+// off-diagonal sub-tiles then contribute to the rows through both M x (row
+// butterfly) and M^T x (column butterfly), like an off-diagonal tile.  Row partials are reduced
 // across the 8 lanes that share p, column partials across the 8 lanes that
 // share q, by butterfly halving.  With the bit assignment above the row
 // butterfly only needs lane exchanges xor 8, 2, 1 (DPP moves inside a 16-lane
@@ -26,18 +31,54 @@
 
 namespace ddg {
 
+constexpr int kDiagLanes = 36;   // lanes that keep a sub-tile of a compact diagonal tile
+
 template <class FT, int T>
 struct TileGeom {
   static constexpr int S = T / 8;                                    // sub-tile edge
   static constexpr int SS = S * S;                                   // values per lane
+  static constexpr int TD = kDiagLanes * SS;                         // values of a compact diagonal tile
   static constexpr int E = (16 / (int)sizeof(FT)) < SS ? (16 / (int)sizeof(FT)) : SS;  // values per chunk
   static constexpr int NCH = SS / E;                                 // chunks per lane
   static constexpr int LOGS = (S == 8) ? 3 : (S == 4 ? 2 : 1);
 };
 
 // Sub-tile coordinates of a lane.
-__host__ __device__ inline int lane_q(int lane) { return (lane & 3) | ((lane >> 1) & 4); }
-__host__ __device__ inline int lane_p(int lane) { return ((lane >> 2) & 1) | ((lane >> 3) & 6); }
+__host__ __device__ constexpr int lane_q(int lane) { return (lane & 3) | ((lane >> 1) & 4); }
+__host__ __device__ constexpr int lane_p(int lane) { return ((lane >> 2) & 1) | ((lane >> 3) & 6); }
+
+// Lanes that keep their sub-tile of a compact diagonal tile (p >= q), and the
+// position of a kept lane among them.
+__host__ __device__ constexpr unsigned long long diag_lane_mask() {
+  unsigned long long m = 0;
+  for (int L = 0; L < 64; ++L)
+    if (lane_p(L) >= lane_q(L)) m |= 1ull << L;
+  return m;
+}
+__host__ __device__ inline bool diag_kept(int lane) { return lane_p(lane) >= lane_q(lane); }
+__host__ __device__ inline int diag_slot(int lane) {
+  return __builtin_popcountll(diag_lane_mask() & ((1ull << lane) - 1ull));
+}
+
+// The local factors store their diagonal tiles compact for tile edges 32 and 64.
+// (At edge 16, half of a typical level's tiles are diagonal and the solve is
+// bound by latency, not bytes: the idle lanes cost more than the bytes saved.)
+__host__ __device__ constexpr bool compact_diag(int T) { return T >= 32; }
+
+// Elements of the packed lower tiles of a b-row level of the local factors.
+__host__ __device__ inline int64_t level_elems(int32_t b, int32_t T) {
+  const int64_t nt = (b + T - 1) / T, S = T / 8;
+  const int64_t full = nt * (nt + 1) / 2 * T * T;
+  return compact_diag(T) ? full - nt * (T * T - kDiagLanes * S * S) : full;
+}
+
+// Element offset of tile t = (I, J) of a level of the local factors (I diagonal
+// tiles precede it in the row-major lower order).
+template <class FT, int T>
+__host__ __device__ inline int64_t tile_off(int t, int I) {
+  if constexpr (compact_diag(T)) return (int64_t)t * T * T - (int64_t)I * (T * T - TileGeom<FT, T>::TD);
+  else return (int64_t)t * T * T;
+}
 
 // Element offset (within a tile) of sub-tile value (a, b) of lane L.
 template <class FT, int T>
@@ -81,6 +122,38 @@ __device__ inline void load_subtile(const FT* __restrict__ tile, int lane, FT (&
 #pragma unroll
       for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
     }
+  }
+}
+
+// Load the lane's values of a compact diagonal tile (zeros for the lanes whose
+// sub-tile is not stored).
+template <class FT, int T>
+__device__ inline void load_subtile_diag(const FT* __restrict__ tile, int lane, FT (&v)[TileGeom<FT, T>::SS]) {
+  using G = TileGeom<FT, T>;
+  if (diag_kept(lane)) {
+    const int c = diag_slot(lane);
+    constexpr int BYTES = G::E * (int)sizeof(FT);
+#pragma unroll
+    for (int m = 0; m < G::NCH; ++m) {
+      const FT* src = tile + (m * kDiagLanes + c) * G::E;
+      if constexpr (BYTES == 16) {
+        uint4 raw = *reinterpret_cast<const uint4*>(src);
+        const FT* w = reinterpret_cast<const FT*>(&raw);
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
+      } else if constexpr (BYTES == 8) {
+        uint2 raw = *reinterpret_cast<const uint2*>(src);
+        const FT* w = reinterpret_cast<const FT*>(&raw);
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < G::SS; ++i) v[i] = Store<FT>::from(0.0);
   }
 }
 
@@ -137,10 +210,13 @@ __device__ inline AT group_reduce_scatter(AT (&v)[S], int c, bool& writer) {
 
 // Contributions of tile (I, J), whose values this lane holds in `m`:
 //   rowslot[0..T) = (M x_J) over the tile's rows,
-//   colslot[0..T) = (M^T x_I) over the tile's columns (off-diagonal tiles only).
+//   colslot[0..T) = (M^T x_I) over the tile's columns (off-diagonal tiles; with
+//                   CD, also compact diagonal tiles, where it holds the
+//                   contribution of the sub-tiles below the diagonal to the rows
+//                   of their columns).
 // x is indexed from the block's first row.  The slots are written, not
 // accumulated, so the final sum over tiles has a fixed order.
-template <class FT, class AT, int T>
+template <class FT, class AT, int T, bool CD = false>
 __device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I, int J,
                                        const AT* __restrict__ x, AT* __restrict__ rowslot,
                                        AT* __restrict__ colslot, int lane, bool valid) {
@@ -169,11 +245,18 @@ __device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I
       colp[j] += mv * xc[i];
     }
   }
+  if constexpr (CD) {
+    // a diagonal sub-tile already gave its rows through M x
+    if (I == J && p == q) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) colp[j] = 0;
+    }
+  }
   bool w;
   AT rs = group_reduce_scatter<AT, S, G::LOGS, 8, 2, 1>(rowp, q, w);
   if (valid && w) rowslot[p * S + (q >> (3 - G::LOGS))] = rs;
   AT cs = group_reduce_scatter<AT, S, G::LOGS, 32, 16, 4>(colp, p, w);
-  if (valid && I != J && w) colslot[q * S + (p >> (3 - G::LOGS))] = cs;
+  if (valid && (CD || I != J) && w) colslot[q * S + (p >> (3 - G::LOGS))] = cs;
 }
 
 // Tile (I, J) of linear index t in row-major lower order.
@@ -187,19 +270,21 @@ __host__ __device__ inline void tile_ij(int t, int& I, int& J) {
 
 // Fixed-order sum of the slots of output row r (0 <= r < nt*T) of a block with
 // nt tile rows; slots of tile t sit at [2t][T] (rows) and [2t+1][T] (columns):
-// sum_{J<=I} rowslot(I,J) + sum_{J>I} colslot(J,I), I = r/T.
-template <class AT, int T>
+// sum_{J<=I} rowslot(I,J) (+ colslot(I,I) with compact diagonal tiles)
+// + sum_{J>I} colslot(J,I), I = r/T.
+template <class AT, int T, bool CD = false>
 __device__ inline AT sum_slots(const AT* __restrict__ slots, int nt, int r) {
   const int I = r / T, rr = r % T;
   AT s = 0;
   for (int J = 0; J <= I; ++J) s += slots[(2 * (I * (I + 1) / 2 + J)) * T + rr];
+  if constexpr (CD) s += slots[(2 * (I * (I + 1) / 2 + I) + 1) * T + rr];
   for (int J = I + 1; J < nt; ++J) s += slots[(2 * (J * (J + 1) / 2 + I) + 1) * T + rr];
   return s;
 }
 
 // As sum_slots, restricted to the tiles t0 <= t < t1 whose slots sit at
 // [2(t - t0)][T] (rows) and [2(t - t0) + 1][T] (columns); same tile order.
-template <class AT, int T>
+template <class AT, int T, bool CD = false>
 __device__ inline AT sum_slots_range(const AT* __restrict__ slots, int nt, int r, int t0, int t1) {
   const int I = r / T, rr = r % T;
   AT s = 0;
@@ -207,6 +292,10 @@ __device__ inline AT sum_slots_range(const AT* __restrict__ slots, int nt, int r
   for (int J = 0; J <= I; ++J) {
     const int t = a0 + J;
     if (t >= t0 && t < t1) s += slots[(2 * (t - t0)) * T + rr];
+  }
+  if constexpr (CD) {
+    const int t = a0 + I;
+    if (t >= t0 && t < t1) s += slots[(2 * (t - t0) + 1) * T + rr];
   }
   for (int J = I + 1; J < nt; ++J) {
     const int t = J * (J + 1) / 2 + I;

@@ -28,7 +28,7 @@ def _dev(t: torch.Tensor, n: int, name: str) -> int:
 
 
 def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream,
-             schedule="colours"):
+             schedule="auto"):
     opt = Options()
     lib.ddg_default_options(C.byref(opt))
     opt.precision = _lib.PRECISION[precision]
@@ -49,7 +49,7 @@ class DDGSolver:
     def __init__(self, n: int, row_ptr, col_idx, val, F: Optional[np.ndarray], part, n_parts: int,
                  overlap: int, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000,
                  rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0, check_every: int = 4,
-                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "colours"):
+                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto"):
         lib = _lib.load()
         self._lib = lib
         self.n = int(n)
@@ -233,7 +233,7 @@ class DDGBatchSolver(DDGSolver):
 
     def __init__(self, problems, overlap: int, precision: str = "fp64", rtol: float = 1e-8,
                  max_iter: int = 1000, rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0,
-                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "colours"):
+                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto"):
         lib = _lib.load()
         self._lib = lib
         arr, keep = _problem_array(problems)
