@@ -36,8 +36,10 @@ METRIC = "DDG-PCG time-to-1e-8 residual & iters: mixed vs FP64 GPU; fwd+adjoint 
 HBM_PEAK_GBS = 8000.0
 
 
+# the local-solve kernel, its tile helpers, and the code that lays out what it reads
 SWEEP_SOURCES = ["paper_1504_00907_amd/csrc/kernels_sweep.hip", "paper_1504_00907_amd/csrc/symv_tile.hpp",
-                 "paper_1504_00907_amd/csrc/device_util.hpp"]
+                 "paper_1504_00907_amd/csrc/device_util.hpp", "paper_1504_00907_amd/csrc/kernels_setup.hip",
+                 "paper_1504_00907_amd/csrc/symbolic.cpp"]
 
 
 def profiled_traffic(kernel: str, precision: str, tile: int):
