@@ -26,6 +26,7 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
 Handle::~Handle() {
   for (auto ev : ev_pool) (void)hipEventDestroy(ev);
   if (h_state) (void)hipHostFree(h_state);
+  if (side) (void)hipStreamDestroy(side);
 }
 
 namespace {
@@ -161,12 +162,26 @@ void numeric_setup(Handle& h) {
   DDG_HIP(hipEventCreate(&e1));
   DDG_HIP(hipEventRecord(e0, h.stream));
   launch_refresh_couplings(h, h.stream);
+  if (h.nc > 0) launch_galerkin(h, h.stream);
+  // The local factorisation (wide batched launches) and the coarse inverse (a tree of
+  // small, latency-bound launches) are independent: the coarse inverse runs on a
+  // second stream once A0 is formed, the local levels on the handle's stream.
+  hipEvent_t eg = nullptr, ec = nullptr;
   if (h.nc > 0) {
-    launch_galerkin(h, h.stream);
-    launch_coarse_invert(h, h.stream);
-    check_err_flag(h, "coarse factorisation");
+    if (!h.side) DDG_HIP(hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking));
+    DDG_HIP(hipEventCreateWithFlags(&eg, hipEventDisableTiming));
+    DDG_HIP(hipEventCreateWithFlags(&ec, hipEventDisableTiming));
+    DDG_HIP(hipEventRecord(eg, h.stream));
   }
   launch_local_factor(h, h.stream);
+  if (h.nc > 0) {
+    DDG_HIP(hipStreamWaitEvent(h.side, eg, 0));
+    launch_coarse_invert(h, h.side);
+    DDG_HIP(hipEventRecord(ec, h.side));
+    DDG_HIP(hipStreamWaitEvent(h.stream, ec, 0));
+    (void)hipEventDestroy(eg);
+    (void)hipEventDestroy(ec);
+  }
   DDG_HIP(hipEventRecord(e1, h.stream));
   DDG_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -174,7 +189,7 @@ void numeric_setup(Handle& h) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h.info.setup_ms = ms;
-  check_err_flag(h, "local factorisation");
+  check_err_flag(h, "numeric factorisation");
 }
 
 void flush_profile(Handle& h) {

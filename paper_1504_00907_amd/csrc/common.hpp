@@ -227,6 +227,8 @@ struct Handle {
   DevBuf kcnt_d, koff_d;
   DevBuf A0;              // dense coarse blocks, one per system (kept for export)
   DevBuf A0inv_t;         // tiled lower inverses, float64, tile 64
+  DevBuf cinv, cwork, cgd;   // coarse inverse: copy of A0 being inverted, recursion workspace, group tables
+  hipStream_t side = nullptr;  // second stream: the coarse inverse runs beside the local factorisation
   DevBuf fac;             // local factor tiles (storage precision)
   // batched local factorisation: item schedule (built once per handle) and scratch
   struct FacStage {

@@ -941,9 +941,10 @@ void launch_coarse_invert(Handle& h, hipStream_t s) {
   const int64_t total = h.a0_off[h.nb];
   int64_t nmax = 0;
   for (int32_t b = 0; b < h.nb; ++b) nmax = std::max<int64_t>(nmax, h.cblk_n[b]);
-  // the inverse is formed in a copy so that A0 stays available for export
-  DevBuf inv;
-  inv.alloc((size_t)total * sizeof(double));
+  // the inverse is formed in a copy so that A0 stays available for export; the
+  // buffers stay with the handle (freeing device memory would synchronise the device)
+  DevBuf& inv = h.cinv;
+  if (inv.bytes < (size_t)total * sizeof(double)) inv.alloc((size_t)total * sizeof(double));
   DDG_HIP(hipMemcpyAsync(inv.p, h.A0.p, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
   // recursive inverse of every coarse block, one item per system: systems sorted by
   // order and taken in groups whose workspace (the tree of the group's largest
@@ -953,9 +954,12 @@ void launch_coarse_invert(Handle& h, hipStream_t s) {
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return h.cblk_n[x] > h.cblk_n[y]; });
   const int64_t budget = ((int64_t)1 << 30) / 8;   // workspace elements (1 GiB)
   const int64_t need0 = binv_work_need(0, (int)nmax, 0) + 64;
-  DevBuf W, gd;
-  W.alloc((size_t)std::max(need0, std::min<int64_t>(budget, need0 * h.nb)) * sizeof(double));
-  gd.alloc((size_t)h.nb * (sizeof(int64_t) + 2 * sizeof(int32_t)));
+  DevBuf& W = h.cwork;
+  DevBuf& gd = h.cgd;
+  const size_t wbytes = (size_t)std::max(need0, std::min<int64_t>(budget, need0 * h.nb)) * sizeof(double);
+  if (W.bytes < wbytes) W.alloc(wbytes);
+  const size_t gbytes = (size_t)h.nb * (sizeof(int64_t) + 2 * sizeof(int32_t));
+  if (gd.bytes < gbytes) gd.alloc(gbytes);
   std::vector<int64_t> goff;
   std::vector<int32_t> gn, gsys;
   for (int32_t i0 = 0; i0 < h.nb;) {
