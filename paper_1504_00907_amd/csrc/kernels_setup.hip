@@ -472,40 +472,56 @@ constexpr int kPivThreads = 256;
 // Gauss-Jordan inverse of a w x w (w <= 64) block held in registers: thread x
 // owns the 4 x 4 sub-block at rows 4 (x / 16).., columns 4 (x % 16)..; each
 // step publishes only the pivot row and column through LDS (double-buffered,
-// one barrier per step).  On return m holds the inverse (zeros outside w x w).
+// one barrier per step).  On return m holds the inverse (identity outside w x w).
 __device__ inline void gj_regs(double (&m)[4][4], int w, int32_t* err, int sub, int blk, int row0) {
   __shared__ double prow[2][kCNB], pcol[2][kCNB];
-  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
-  for (int t = 0; t < w; ++t) {
-    const int buf = t & 1;
-    if (t >= r0 && t < r0 + 4)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) prow[buf][c0 + j] = m[t - r0][j];
-    if (t >= c0 && t < c0 + 4)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) pcol[buf][r0 + i] = m[i][t - c0];
-    __syncthreads();
-    double d = prow[buf][t];
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, sub, blk, row0 + t);
-      d = 1.0;
-    }
-    const double rd = 1.0 / d;
-    // branch-free step: with P_i = rd on the pivot row (else -a_it rd) and Q_j = 1 on the
-    // pivot column (else a_tj), every entry becomes (row t or column t ? 0 : a_ij) + P_i Q_j
-    double P[4], Q[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) P[i] = (r0 + i == t) ? rd : -pcol[buf][r0 + i] * rd;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Q[j] = (c0 + j == t) ? 1.0 : prow[buf][c0 + j];
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;  // this thread's 4 x 4 block
+  const int r0 = tr * 4, c0 = tc * 4;
+  // rows and columns past w become identity (zero outside the diagonal on entry), so
+  // the pivots run in groups of four whose position inside a block is known at
+  // compile time; identity rows keep pivot 1 and leave the others untouched
+  if (tr == tc) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
+      if (r0 + i >= w) m[i][i] = 1.0;
+  }
+  const int nq = (w + 3) >> 2;
+  for (int tau = 0; tau < nq; ++tau) {
+    const bool prow_mine = tr == tau, pcol_mine = tc == tau;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double base = (r0 + i == t || c0 + j == t) ? 0.0 : m[i][j];
-        m[i][j] = __builtin_fma(P[i], Q[j], base);
+    for (int u = 0; u < 4; ++u) {
+      const int t = 4 * tau + u;
+      const int buf = u & 1;
+      if (prow_mine)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) prow[buf][c0 + j] = m[u][j];
+      if (pcol_mine)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pcol[buf][r0 + i] = m[i][u];
+      __syncthreads();
+      double d = prow[buf][t];
+      if (t < w && (!(d > 0.0) || !isfinite(d))) {
+        if (threadIdx.x == 0) record_error(err, DDG_ERR_NOT_SPD, sub, blk, row0 + t);
+        d = 1.0;
       }
-    // a buffer is rewritten two steps later, after the next step's barrier
+      const double rd = 1.0 / d;
+      // branch-free step: with P_i = rd on the pivot row (else -a_it rd) and Q_j = 1 on
+      // the pivot column (else a_tj), every entry becomes (row t or column t ? 0 : a_ij)
+      // + P_i Q_j
+      double P[4], Q[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) P[i] = (prow_mine && i == u) ? rd : -pcol[buf][r0 + i] * rd;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Q[j] = (pcol_mine && j == u) ? 1.0 : prow[buf][c0 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool zero = (prow_mine && i == u) || (pcol_mine && j == u);
+          m[i][j] = __builtin_fma(P[i], Q[j], zero ? 0.0 : m[i][j]);
+        }
+      // a buffer is rewritten two steps later, after the next step's barrier
+    }
   }
 }
 
