@@ -553,9 +553,12 @@ struct GemmArgs {
 // the 4 waves computes a 32 x 32 quadrant as 2 x 2 products of 16 x 16 tiles
 // (v_mfma_f64_16x16x4: lane l feeds A[l%16][l/16] and B[l/16][l%16] and receives
 // D[4r + l/16][l%16] in result register r), the operands staged through LDS in
-// 32-wide chunks of the reduction dimension.
+// 32-wide chunks of the reduction dimension.  The next chunk's global loads are
+// issued into registers before the current chunk's products, so their latency
+// overlaps the matrix-core work.
 __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
   constexpr int UC = 32;
+  constexpr int PER = 64 * UC / 256;  // elements of each operand chunk per thread
   __shared__ double As[64][UC + 1];
   __shared__ double Bs[UC][64 + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -566,19 +569,37 @@ __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < g.K; k0 += UC) {
-    for (int idx = threadIdx.x; idx < 64 * UC; idx += 256) {
+  double ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + q * 256;
       const int r = idx / UC, u = idx % UC;
-      As[r][u] = (i0 + r < g.M && k0 + u < g.K) ? g.A[(i0 + r) * g.lda + k0 + u] : 0.0;
+      ra[q] = (i0 + r < g.M && k0 + u < g.K) ? g.A[(i0 + r) * g.lda + k0 + u] : 0.0;
       if (g.tb) {
-        const int c = idx / UC, uu = idx % UC;
-        Bs[uu][c] = (j0 + c < g.N && k0 + uu < g.K) ? g.B[(j0 + c) * g.ldb + k0 + uu] : 0.0;
+        rb[q] = (j0 + r < g.N && k0 + u < g.K) ? g.B[(j0 + r) * g.ldb + k0 + u] : 0.0;
       } else {
         const int uu = idx / 64, c = idx % 64;
-        Bs[uu][c] = (j0 + c < g.N && k0 + uu < g.K) ? g.B[(int64_t)(k0 + uu) * g.ldb + j0 + c] : 0.0;
+        rb[q] = (j0 + c < g.N && k0 + uu < g.K) ? g.B[(int64_t)(k0 + uu) * g.ldb + j0 + c] : 0.0;
       }
     }
-    __syncthreads();
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + q * 256;
+      const int r = idx / UC, u = idx % UC;
+      As[r][u] = ra[q];
+      if (g.tb) Bs[u][r] = rb[q];
+      else Bs[idx / 64][idx % 64] = rb[q];
+    }
+  };
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int k0 = 0; k0 < g.K; k0 += UC) {
+    const bool more = k0 + UC < g.K;
+    if (more) fetch(k0 + UC);
 #pragma unroll
     for (int kk = 0; kk < UC; kk += 4) {
       double af[2], bf[2];
@@ -592,6 +613,10 @@ __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
         for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
