@@ -386,11 +386,13 @@ void build_symbolic(Symbolic& S, int64_t n, const int64_t* rp, const int32_t* ci
     for (int32_t b : loc[i].bsize) S.max_blk = std::max(S.max_blk, b);
   }
   if (S.tile <= 0) {
-    // automatic: the typical level width decides the tile edge
+    // automatic: the typical level width decides the tile edge.  Edge 64 streams about
+    // a quarter faster per byte than 32 (measured, compact diagonal tiles), so it wins
+    // once its padding costs less than that: from about 168 rows
     std::vector<int32_t> w(S.blk_size);
     std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
     int32_t med = w[w.size() / 2];
-    S.tile = med >= 192 ? 64 : (med >= 48 ? 32 : 16);
+    S.tile = med >= 168 ? 64 : (med >= 48 ? 32 : 16);
   }
   DDG_REQUIRE(S.tile == 16 || S.tile == 32 || S.tile == 64, DDG_ERR_INVALID_ARG, "tile must be 16, 32 or 64");
   int64_t off = 0;
