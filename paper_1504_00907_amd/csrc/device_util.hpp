@@ -132,6 +132,18 @@ __device__ inline double row_dot_l(const int64_t* __restrict__ rp, const int32_t
   return s;
 }
 
+// row_dot_l<L> for a run-time group width L > 1 (a power of two, at most 16): the
+// same products, added in the same order, so both return the same bits.
+__device__ inline double row_dot_rt(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                    const double* __restrict__ v, const double* __restrict__ x, int64_t g,
+                                    int j, int L) {
+  double s = 0.0;
+  const int64_t t0 = rp[g], t1 = rp[g + 1];
+  for (int64_t t = t0 + j; t < t1; t += L) s += v[t] * x[ci[t]];
+  for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
 // Calls f(std::integral_constant<int, L>{}) for the run-time lanes-per-row value.
 template <class Fn>
 inline void with_lanes(int L, Fn&& f) {

@@ -61,6 +61,7 @@ struct SweepArgs {
   const int64_t* rp;
   const int32_t* ci;
   const double* val;
+  int lpr;          // lanes per CSR row of the residual rows (as k_local_residual<L>)
   const void* fac;
   const double* r;
   double* e;
@@ -327,10 +328,21 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
       if (j < r0 || j >= r1) w[j] = (AT)0;
   }
   if constexpr (OWN_RES) {
-    for (int j = r0 + tid; j < r1; j += NT) {
-      const int g = a.set_idx[s0 + j];
-      const double rg = a.r[g];
-      w[j] = (AT)(res_e_zero ? rg : row_sub(a.rp, a.ci, a.val, a.e, g, rg));
+    // the same arithmetic as k_local_residual<lpr>, so both schedules agree bit for bit
+    const int L = a.lpr;
+    if (L == 1) {
+      for (int j = r0 + tid; j < r1; j += NT) {
+        const int g = a.set_idx[s0 + j];
+        const double rg = a.r[g];
+        w[j] = (AT)(res_e_zero ? rg : row_sub(a.rp, a.ci, a.val, a.e, g, rg));
+      }
+    } else {
+      const int lg = tid & (L - 1);
+      for (int j = r0 + tid / L; j < r1; j += NT / L) {  // a lane group shares j
+        const int g = a.set_idx[s0 + j];
+        const double ae = res_e_zero ? 0.0 : row_dot_rt(a.rp, a.ci, a.val, a.e, g, lg, L);
+        if (lg == 0) w[j] = (AT)(a.r[g] - ae);
+      }
     }
     prefetch_first();
   } else {
@@ -666,6 +678,7 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   a.sl_lo_val = h.sl_lo_val.p;
   a.sl_up_val = h.sl_up_val.p;
   DDG_REQUIRE(S.sliced == !(S.cl <= kCplRegs && S.cu <= kCplRegs), DDG_ERR_HIP, "internal: coupling layout");
+  a.lpr = h.lpr;
   a.rp = h.rowptr.as<int64_t>();
   a.ci = h.col.as<int32_t>();
   a.val = h.val.as<double>();

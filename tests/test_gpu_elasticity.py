@@ -147,3 +147,30 @@ def test_row_lanes_match_single_lane(monkeypatch):
     say(f"   one lane: {i1['iters']} iters; lane groups: {il['iters']} iters")
     assert i1["iters"] == il["iters"] and i1["status"] == il["status"] == 0
     assert np.linalg.norm(u1 - ul) <= 1e-12 * np.linalg.norm(u1)
+
+
+@pytest.mark.parametrize("lanes", ["4", None], ids=["lanes4", "lanes_auto"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_task_queue_matches_colour_launches(precision, lanes, monkeypatch):
+    """With several lanes per residual row, the task-queue sweep forms each task's
+    residual rows with the same lane groups as the colour launches' residual kernel:
+    preconditioner applications and the solve agree bit for bit."""
+    if lanes:
+        monkeypatch.setenv("DDG_ROW_LANES", lanes)
+    else:
+        monkeypatch.delenv("DDG_ROW_LANES", raising=False)
+    P, o = problem("el10")
+    rs = [seed_rng(75, 0).standard_normal(P.n) for _ in range(2)]
+    out = []
+    for sched in ("queue", "colours"):
+        s = solver(P, precision=precision, rtol=1e-8, schedule=sched)
+        assert s.info()["schedule"] == {"queue": 2, "colours": 1}[sched]
+        zs = [host(s.apply_precond(dev(r))) for r in rs]
+        u, info = s.solve(dev(P.f))
+        out.append((zs, host(u), info["iters"]))
+        s.close()
+    (z_q, u_q, it_q), (z_c, u_c, it_c) = out
+    for zq, zc in zip(z_q, z_c):
+        assert np.array_equal(zq, zc)
+    say(f"   {precision}: {it_q} iters both schedules")
+    assert it_q == it_c and np.array_equal(u_q, u_c)
