@@ -262,6 +262,9 @@ struct Handle {
   int64_t prof_launches = 0, prof_bytes = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int64_t>> pending;  // (event pair index, bytes)
+  // when set, the next local-solve launch carries this event pair on its own dispatch
+  // (start and end of the kernel itself, not markers queued around it)
+  mutable hipEvent_t kev0 = nullptr, kev1 = nullptr;
   int ev_used = 0;
 
   ~Handle();

@@ -186,8 +186,18 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
   DDG_HIP(hipGetLastError());
 }
 
-// Local residual of one colour, then its local solves; when profiling, an event
-// pair brackets the local-solve kernel alone.
+// Attaches an event pair to the next local-solve dispatch for the scope's lifetime.
+struct KernelEvents {
+  const Handle& h;
+  KernelEvents(const Handle& hh, hipEvent_t a, hipEvent_t b) : h(hh) {
+    h.kev0 = a;
+    h.kev1 = b;
+  }
+  ~KernelEvents() { h.kev0 = h.kev1 = nullptr; }
+};
+
+// Local residual of one colour, then its local solves; when profiling, the local-solve
+// dispatch carries an event pair that records its own start and end.
 static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez, const CgState* st,
                            hipStream_t s) {
   launch_sweep(h, c, r, e, ez, st, s, true);
@@ -204,13 +214,14 @@ static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez
   }
   int idx = h.ev_used;
   h.ev_used += 2;
-  DDG_HIP(hipEventRecord(h.ev_pool[idx], s));
-  launch_sweep(h, c, r, e, ez, st, s, false);
-  DDG_HIP(hipEventRecord(h.ev_pool[idx + 1], s));
+  {
+    KernelEvents ke(h, h.ev_pool[idx], h.ev_pool[idx + 1]);
+    launch_sweep(h, c, r, e, ez, st, s, false);
+  }
   h.pending.push_back({idx, ez ? h.colour_bytes[h.S.n_colours + c] : h.colour_bytes[c]});
 }
 
-// One persistent sweep direction; when profiling, an event pair brackets it.
+// One persistent sweep direction; when profiling, its dispatch carries an event pair.
 static void flow_profiled(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s) {
   if (!h.profiling) {
     launch_sweep_flow(h, dir, r, e, st, s);
@@ -225,9 +236,10 @@ static void flow_profiled(Handle& h, int dir, const double* r, double* e, const 
   }
   int idx = h.ev_used;
   h.ev_used += 2;
-  DDG_HIP(hipEventRecord(h.ev_pool[idx], s));
-  launch_sweep_flow(h, dir, r, e, st, s);
-  DDG_HIP(hipEventRecord(h.ev_pool[idx + 1], s));
+  {
+    KernelEvents ke(h, h.ev_pool[idx], h.ev_pool[idx + 1]);
+    launch_sweep_flow(h, dir, r, e, st, s);
+  }
   h.pending.push_back({idx, h.flow_bytes[dir]});
 }
 

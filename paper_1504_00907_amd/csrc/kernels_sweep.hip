@@ -27,6 +27,8 @@
 // the reductions and barriers between levels.
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "symv_tile.hpp"
 
@@ -106,10 +108,19 @@ __device__ inline void decode_step(int role, int s, int K, int m, int& kind, int
 
 constexpr int kSpinLimit = 1 << 22;
 
+// Explicit vmcnt(0) (expcnt and lgkmcnt left alone).  After an agent-scope release
+// it makes the L2 write-back finish before the flag or count that follows: once
+// every wave has waited for its own stores before the barrier, the compiler's wait
+// pass counts no outstanding vector-memory operation and drops the wait that the
+// release fence carries, and the write-back is not counted.  After an agent-scope
+// acquire it makes the cache invalidation finish before the barrier lets the other
+// waves load.
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Bounded wait for the partner workgroup's flag.  Only thread 0 polls and
-// performs the agent-scope acquire (which also invalidates this CU's vector
-// cache); the barrier then orders every wave's reads of the exchange buffer
-// after it.  The reader clears the flag for the next launch.
+// performs the agent-scope acquire (which invalidates this CU's vector cache and
+// the die's L2 lines); the barrier then orders every wave's reads of the exchange
+// buffer after it.  The reader clears the flag for the next launch.
 __device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub) {
   if (threadIdx.x == 0) {
     int spins = 0;
@@ -124,6 +135,7 @@ __device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub) {
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    wait_vm();
     __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
@@ -133,10 +145,11 @@ __device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub) {
 // complete (vmcnt 0), the barrier collects the waves, and thread 0 issues one
 // agent-scope release before raising the flag.
 __device__ inline void handoff_signal(int32_t* flag) {
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), leave expcnt/lgkmcnt untouched
+  wait_vm();
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    wait_vm();
     __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -583,6 +596,7 @@ __device__ __attribute__((noinline)) void flow_wait_deps(const int32_t* dep_ptr,
                                                          int sub) {
   for (int d = dep_ptr[sub]; d < dep_ptr[sub + 1]; ++d) flow_wait(done + dep_idx[d], target, err, sub);
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  wait_vm();
 }
 
 template <class FT, class AT, int T, int NW, int TPW, bool SL>
@@ -607,10 +621,11 @@ __global__ void __launch_bounds__(NW * 64) k_sweep_flow(SweepArgs a, FlowArgs f)
   if (!(a.st && a.st[a.sub_inst[sub]].done))
     sweep_task<FT, AT, T, NW, TPW, SL, true>(a, sub, role, sub, t < f.zero_tasks);
   // publish this chain's corrections of e, then count the task as finished
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  wait_vm();
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    wait_vm();
     __hip_atomic_fetch_add(f.done + sub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -729,7 +744,10 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
     f.base = h.flow_base;
     f.target = f.roles * (h.flow_seq + 1);
     // one workgroup per task; each takes one counter value
-    hipLaunchKernelGGL(fk, dim3((unsigned)f.ntasks), dim3(NW * 64), lds, s, a, f);
+    if (h.kev0)
+      hipExtLaunchKernelGGL(fk, dim3((unsigned)f.ntasks), dim3(NW * 64), (uint32_t)lds, s, h.kev0, h.kev1, 0u, a, f);
+    else
+      hipLaunchKernelGGL(fk, dim3((unsigned)f.ntasks), dim3(NW * 64), lds, s, a, f);
     DDG_HIP(hipGetLastError());
     h.flow_base += f.ntasks;
     h.flow_seq += 1;
@@ -748,7 +766,10 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
     return;
   }
   const unsigned grid = a.twisted ? (unsigned)(16 * ((nsub + 7) / 8)) : (unsigned)nsub;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, s, a);
+  if (h.kev0)
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), (uint32_t)lds, s, h.kev0, h.kev1, 0u, a);
+  else
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, s, a);
   DDG_HIP(hipGetLastError());
 }
 

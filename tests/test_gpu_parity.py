@@ -294,6 +294,40 @@ def test_task_queue_sweep_matches_colour_launches(name, precision, single, monke
     assert it_q == it_c and np.array_equal(u_q, u_c)
 
 
+def test_task_queue_repeatable_at_full_size():
+    """The task-queue sweep at the timed workload's size (128^3 cells, 512
+    subdomains, 64-wide tiles), where the two chain workgroups of a subdomain and
+    tasks that depend on each other mostly run on different compute dies (each
+    with its own L2): 400 preconditioner applications and 10 solves in a row equal
+    the colour launches' results bit for bit.  Each release waits for its L2
+    write-back before raising the flag or count; a release that did not (an
+    earlier form) changed about 1 application in 300 here."""
+    from workloads import cfg2
+    P = cfg2()
+    r = dev(seed_rng(90, 0).standard_normal(P.n))
+    f = dev(P.f)
+    s = make_solver(P, rtol=P.rtol, precision="fp32", schedule="colours")
+    z_ref = s.apply_precond(r).clone()
+    u_ref, info_ref = s.solve(f)
+    u_ref = u_ref.clone()
+    s.close()
+    s = make_solver(P, rtol=P.rtol, precision="fp32", schedule="queue")
+    assert s.info()["schedule"] == 2
+    z = torch.empty_like(r)
+    bad_z = 0
+    for _ in range(400):
+        s.apply_precond(r, z)
+        bad_z += int(not torch.equal(z, z_ref))
+    u = torch.empty_like(f)
+    bad_u = 0
+    for _ in range(10):
+        _, info = s.solve(f, u)
+        bad_u += int(info["iters"] != info_ref["iters"] or not torch.equal(u, u_ref))
+    s.close()
+    say(f"   differing applications {bad_z}/400, solves {bad_u}/10")
+    assert bad_z == 0 and bad_u == 0
+
+
 @pytest.mark.parametrize("block_target,tile", [(100000, 32), (40, 16), (0, 64)],
                          ids=["one_level", "merged", "tile64"])
 def test_level_structures_match_oracle(block_target, tile):
