@@ -408,6 +408,7 @@ __global__ void __launch_bounds__(256) k_fac_pack(FacArgs a) {
   const FacItem it = a.items[blockIdx.x];
   const int b = a.blk_size[it.cur];
   const int nt = (b + T - 1) / T;
+  const int ph = last_row_subtiles(b, T);
   const int64_t total = (int64_t)nt * (nt + 1) / 2 * T * T;  // full-tile index space
   const double* S = a.scratch + it.s_off;
   FT* out = static_cast<FT*>(a.fac) + a.blk_foff[it.cur];
@@ -416,11 +417,15 @@ __global__ void __launch_bounds__(256) k_fac_pack(FacArgs a) {
     const int within = (int)(idx % (T * T));
     int I, J;
     tile_ij(t, I, J);
-    int64_t dst = tile_off<FT, T>(t, I);
-    if (compact_diag(T) && I == J) {
+    int64_t dst = tile_off<FT, T>(t, I, J, nt, ph);
+    const unsigned long long mask = tile_lanes<T>(I, J, nt, ph);
+    if (mask != ~0ull) {
+      // a compact diagonal tile or a tile of the short last row: only the kept lanes
+      // are stored (the others are transposes of stored sub-tiles, or rows past b)
       const int lane = (within / G::E) % 64;
-      if (!diag_kept(lane)) continue;  // transpose of a stored sub-tile
-      dst += ((within / (64 * G::E)) * kDiagLanes + diag_slot(lane)) * G::E + within % G::E;
+      if (!((mask >> lane) & 1ull)) continue;
+      const int c = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+      dst += ((within / (64 * G::E)) * __builtin_popcountll(mask) + c) * G::E + within % G::E;
     } else {
       dst += within;
     }

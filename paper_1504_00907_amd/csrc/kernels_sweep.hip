@@ -252,9 +252,12 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   // tile t = (I, J) of level k into register set j
   constexpr bool CD = compact_diag(T);
   auto load_tile_at = [&](int k, int t, int I, int J, int j) {
-    const FT* src = fac + lv_foff[k] + tile_off<FT, T>(t, I);
-    if (CD && I == J) load_subtile_diag<FT, T>(src, lane, R[j]);
-    else load_subtile<FT, T>(src, lane, R[j]);
+    const int bk = lv_size[k];
+    const int ntk = (bk + T - 1) / T;
+    const int ph = last_row_subtiles(bk, T);
+    const FT* src = fac + lv_foff[k] + tile_off<FT, T>(t, I, J, ntk, ph);
+    if (I < ntk - 1 && !(CD && I == J)) load_subtile<FT, T>(src, lane, R[j]);
+    else load_subtile_kept<FT, T>(src, lane, tile_lanes<T>(I, J, ntk, ph), R[j]);
   };
   // coupling entries of this thread's row (row tid of the level) for the next step
   int cpl_col[2 * kCplRegs];

@@ -18,7 +18,9 @@
 // each stored value is read once and used twice.  A diagonal tile may be stored
 // compact: only the sub-tiles of the lanes with p >= q (36 of 64), the others
 // being transposes of stored ones; kept lane L's chunk m then sits at element
-// (m*36 + c(L))*E, c(L) = the number of kept lanes below L.  Such a tile's kept
+// (m*36 + c(L))*E, c(L) = the number of kept lanes below L.  The tiles of a
+// level's last tile-row likewise keep only the lanes whose sub-tile rows lie
+// inside the level (see last_row_subtiles).  A compact diagonal tile's kept
 // off-diagonal sub-tiles then contribute to the rows through both M x (row
 // butterfly) and M^T x (column butterfly), like an off-diagonal tile.  Row partials are reduced
 // across the 8 lanes that share p, column partials across the 8 lanes that
@@ -47,37 +49,112 @@ struct TileGeom {
 __host__ __device__ constexpr int lane_q(int lane) { return (lane & 3) | ((lane >> 1) & 4); }
 __host__ __device__ constexpr int lane_p(int lane) { return ((lane >> 2) & 1) | ((lane >> 3) & 6); }
 
-// Lanes that keep their sub-tile of a compact diagonal tile (p >= q), and the
-// position of a kept lane among them.
-__host__ __device__ constexpr unsigned long long diag_lane_mask() {
-  unsigned long long m = 0;
-  for (int L = 0; L < 64; ++L)
-    if (lane_p(L) >= lane_q(L)) m |= 1ull << L;
-  return m;
-}
-__host__ __device__ inline bool diag_kept(int lane) { return lane_p(lane) >= lane_q(lane); }
-__host__ __device__ inline int diag_slot(int lane) {
-  return __builtin_popcountll(diag_lane_mask() & ((1ull << lane) - 1ull));
-}
-
 // The local factors store their diagonal tiles compact for tile edges 32 and 64.
 // (At edge 16, half of a typical level's tiles are diagonal and the solve is
 // bound by latency, not bytes: the idle lanes cost more than the bytes saved.)
 __host__ __device__ constexpr bool compact_diag(int T) { return T >= 32; }
 
-// Elements of the packed lower tiles of a b-row level of the local factors.
-__host__ __device__ inline int64_t level_elems(int32_t b, int32_t T) {
-  const int64_t nt = (b + T - 1) / T, S = T / 8;
-  const int64_t full = nt * (nt + 1) / 2 * T * T;
-  return compact_diag(T) ? full - nt * (T * T - kDiagLanes * S * S) : full;
+// Short last tile-row.  The last tile-row of a b-row level holds h = b - (nt-1) T
+// rows, i.e. data in its first ph = ceil(h / S) sub-tile rows; its tiles keep only
+// the lanes with p < ph (the other lanes' sub-tiles are rows past b, all zero).
+// Its off-diagonal tiles keep 8 ph lanes; its diagonal tile keeps the lanes with
+// q <= p < ph when diagonal tiles are compact, else those with p, q < ph.  With
+// ph = 8 these are the full and compact tiles of the other rows.
+__host__ __device__ inline int last_row_subtiles(int32_t b, int32_t T) {
+  const int nt = (b + T - 1) / T, S = T / 8;
+  return (b - (nt - 1) * T + S - 1) / S;
 }
 
-// Element offset of tile t = (I, J) of a level of the local factors (I diagonal
-// tiles precede it in the row-major lower order).
+// Lanes kept by a tile with pmax sub-tile rows of data (diag: a diagonal tile,
+// compact or full per cd).
+__host__ __device__ constexpr unsigned long long kept_lanes(int pmax, bool diag, bool cd) {
+  unsigned long long m = 0;
+  for (int p = 0; p < pmax; ++p)
+    for (int q = 0; q < 8; ++q) {
+      if (diag && (cd ? q > p : q >= pmax)) continue;
+      m |= 1ull << (((p & 1) << 2) | ((p >> 1) << 4) | (q & 3) | ((q >> 2) << 3));
+    }
+  return m;
+}
+
+// kept_lanes for a run-time pmax in 1..8 (each case folds to a constant).
+template <bool CD>
+__host__ __device__ inline unsigned long long kept_lanes_rt(int pmax, bool diag) {
+  switch (pmax) {
+    case 1: return diag ? kept_lanes(1, true, CD) : kept_lanes(1, false, CD);
+    case 2: return diag ? kept_lanes(2, true, CD) : kept_lanes(2, false, CD);
+    case 3: return diag ? kept_lanes(3, true, CD) : kept_lanes(3, false, CD);
+    case 4: return diag ? kept_lanes(4, true, CD) : kept_lanes(4, false, CD);
+    case 5: return diag ? kept_lanes(5, true, CD) : kept_lanes(5, false, CD);
+    case 6: return diag ? kept_lanes(6, true, CD) : kept_lanes(6, false, CD);
+    case 7: return diag ? kept_lanes(7, true, CD) : kept_lanes(7, false, CD);
+    default: return diag ? kept_lanes(8, true, CD) : kept_lanes(8, false, CD);
+  }
+}
+
+// Lanes kept by tile (I, J) of a level with nt tile-rows and ph data sub-tile rows
+// in its last tile-row (all 64 for a full tile).
+template <int T>
+__host__ __device__ inline unsigned long long tile_lanes(int I, int J, int nt, int ph) {
+  constexpr bool CD = compact_diag(T);
+  if (I < nt - 1) return I == J ? kept_lanes(8, true, CD) : ~0ull;
+  return kept_lanes_rt<CD>(ph, I == J);
+}
+
+// Elements of the packed lower tiles of a b-row level of the local factors.
+__host__ __device__ inline int64_t level_elems(int32_t b, int32_t T) {
+  const int64_t nt = (b + T - 1) / T, S = T / 8, ph = last_row_subtiles(b, T);
+  const int64_t dl = compact_diag(T) ? kDiagLanes : 64;
+  const int64_t last_diag = compact_diag(T) ? ph * (ph + 1) / 2 : ph * ph;
+  const int64_t lanes = (nt - 1) * (nt - 2) / 2 * 64 + (nt - 1) * dl + (nt - 1) * 8 * ph + last_diag;
+  return lanes * S * S;
+}
+
+// Element offset of tile t = (I, J) of a level of the local factors with nt
+// tile-rows and ph data sub-tile rows in the last one (row-major lower order).
 template <class FT, int T>
-__host__ __device__ inline int64_t tile_off(int t, int I) {
-  if constexpr (compact_diag(T)) return (int64_t)t * T * T - (int64_t)I * (T * T - TileGeom<FT, T>::TD);
-  else return (int64_t)t * T * T;
+__host__ __device__ inline int64_t tile_off(int t, int I, int J, int nt, int ph) {
+  using G = TileGeom<FT, T>;
+  const int tr = I < nt - 1 ? t : (nt - 1) * nt / 2;  // first tile of the last row
+  int64_t off = (int64_t)tr * T * T;
+  if constexpr (compact_diag(T)) off -= (int64_t)(I < nt - 1 ? I : nt - 1) * (T * T - G::TD);
+  if (I == nt - 1) off += (int64_t)J * 8 * ph * G::SS;
+  return off;
+}
+
+// Load the lane's values of a tile that keeps only the lanes in `mask` (zeros for
+// the others); kept lane L's chunk m sits at element (m * popc(mask) + c(L)) * E,
+// c(L) = the number of kept lanes below L.
+template <class FT, int T>
+__device__ inline void load_subtile_kept(const FT* __restrict__ tile, int lane, unsigned long long mask,
+                                         FT (&v)[TileGeom<FT, T>::SS]) {
+  using G = TileGeom<FT, T>;
+  if ((mask >> lane) & 1ull) {
+    const int nk = __builtin_popcountll(mask);
+    const int c = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+    constexpr int BYTES = G::E * (int)sizeof(FT);
+#pragma unroll
+    for (int m = 0; m < G::NCH; ++m) {
+      const FT* src = tile + (m * nk + c) * G::E;
+      if constexpr (BYTES == 16) {
+        uint4 raw = *reinterpret_cast<const uint4*>(src);
+        const FT* w = reinterpret_cast<const FT*>(&raw);
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
+      } else if constexpr (BYTES == 8) {
+        uint2 raw = *reinterpret_cast<const uint2*>(src);
+        const FT* w = reinterpret_cast<const FT*>(&raw);
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < G::SS; ++u) v[u] = Store<FT>::from(0.0);
+  }
 }
 
 // Element offset (within a tile) of sub-tile value (a, b) of lane L.
@@ -122,38 +199,6 @@ __device__ inline void load_subtile(const FT* __restrict__ tile, int lane, FT (&
 #pragma unroll
       for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
     }
-  }
-}
-
-// Load the lane's values of a compact diagonal tile (zeros for the lanes whose
-// sub-tile is not stored).
-template <class FT, int T>
-__device__ inline void load_subtile_diag(const FT* __restrict__ tile, int lane, FT (&v)[TileGeom<FT, T>::SS]) {
-  using G = TileGeom<FT, T>;
-  if (diag_kept(lane)) {
-    const int c = diag_slot(lane);
-    constexpr int BYTES = G::E * (int)sizeof(FT);
-#pragma unroll
-    for (int m = 0; m < G::NCH; ++m) {
-      const FT* src = tile + (m * kDiagLanes + c) * G::E;
-      if constexpr (BYTES == 16) {
-        uint4 raw = *reinterpret_cast<const uint4*>(src);
-        const FT* w = reinterpret_cast<const FT*>(&raw);
-#pragma unroll
-        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
-      } else if constexpr (BYTES == 8) {
-        uint2 raw = *reinterpret_cast<const uint2*>(src);
-        const FT* w = reinterpret_cast<const FT*>(&raw);
-#pragma unroll
-        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
-      } else {
-#pragma unroll
-        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < G::SS; ++i) v[i] = Store<FT>::from(0.0);
   }
 }
 

@@ -164,12 +164,29 @@ def test_factor_bytes_follow_tiles(tile):
     blocks = an.export(_lib.EXPORT_BLOCKS, np.int32).reshape(-1, 3)
     info = an.info()
     an.close()
-    nt = (blocks[:, 2] + tile - 1) // tile
-    # lower tiles of every level; at tile edges 32 and 64 a diagonal tile keeps 36 of
-    # its 64 lane sub-tiles
-    sub = (tile // 8) ** 2
-    elems = nt * (nt + 1) // 2 * tile * tile - (nt * (64 - 36) * sub if tile >= 32 else 0)
-    assert info.factor_bytes == int(np.sum(elems) * 8)
+    # lower tiles of every level, 64 lane sub-tiles of edge S = tile/8 each (sub-tile
+    # row p, column q); a sub-tile is stored when it holds rows and columns inside the
+    # level, and on a diagonal tile at edges 32 and 64 only when p >= q
+    S = tile // 8
+    lanes = np.arange(64)
+    p = ((lanes >> 2) & 1) | ((lanes >> 3) & 6)
+    q = (lanes & 3) | ((lanes >> 1) & 4)
+
+    def level_elems(b):
+        nt = (b + tile - 1) // tile
+        kept = 0
+        for I in range(nt):
+            for J in range(I + 1):
+                data = (I * tile + p * S < b) & (J * tile + q * S < b)
+                if I == J and tile >= 32:
+                    data &= p >= q
+                kept += int(data.sum())
+        return kept * S * S
+
+    sizes, counts = np.unique(blocks[:, 2], return_counts=True)
+    elems = sum(level_elems(int(b)) * int(c) for b, c in zip(sizes, counts))
+    assert (sizes % tile != 0).any()  # some levels end in a short tile-row
+    assert info.factor_bytes == elems * 8
 
 
 def test_block_target_merges_levels():
