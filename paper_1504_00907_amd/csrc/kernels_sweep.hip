@@ -213,7 +213,7 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   AT* tv = w + ni_pad;
   AT* acc = tv + a.ldp;     // phase accumulator (levels wider than slot_tiles only)
   AT* slots = acc + a.ldp;  // 2 * T per tile of the current phase
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const FT* fac = static_cast<const FT*>(a.fac);
   const int kb0 = a.sub_blk_ptr[sub];
   const int K = a.sub_blk_ptr[sub + 1] - kb0;  // <= kMaxLevels (checked on the host)
@@ -251,19 +251,36 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   for (int j = 0; j < TPW; ++j) tile_ij(j * NW + wave, tI[j], tJ[j]);
   // tile t = (I, J) of level k into register set j
   constexpr bool CD = compact_diag(T);
-  auto load_tile_at = [&](int k, int t, int I, int J, int j) {
-    const int bk = lv_size[k];
+  // this lane's place in a compact diagonal tile (p >= q lanes kept)
+  const bool dkept = lane_p(lane) >= lane_q(lane);
+  const int dslot = __builtin_popcountll(kept_lanes(8, true, true) & ((1ull << lane) - 1ull));
+  const unsigned long long below = (1ull << lane) - 1ull;
+  auto load_tile_at = [&](int k, int t, int I, int J, int j) __attribute__((always_inline)) {
+    const int bk = __builtin_amdgcn_readfirstlane(lv_size[k]);
     const int ntk = (bk + T - 1) / T;
-    const int ph = last_row_subtiles(bk, T);
+    bool kept = true;
+    int c = lane, nk = 64, ph = 8;
+    if (I == ntk - 1) {
+      // short last tile-row: the kept lanes of its tiles (wave-uniform mask)
+      ph = last_row_subtiles(bk, T);
+      const unsigned long long mask = kept_lanes_rt<CD>(ph, I == J);
+      kept = (mask >> lane) & 1ull;
+      c = __builtin_popcountll(mask & below);
+      nk = __builtin_popcountll(mask);
+    } else if (CD && I == J) {
+      kept = dkept;
+      c = dslot;
+      nk = kDiagLanes;
+    }
     const FT* src = fac + lv_foff[k] + tile_off<FT, T>(t, I, J, ntk, ph);
-    if (I < ntk - 1 && !(CD && I == J)) load_subtile<FT, T>(src, lane, R[j]);
-    else load_subtile_kept<FT, T>(src, lane, tile_lanes<T>(I, J, ntk, ph), R[j]);
+    if (nk == 64) load_subtile<FT, T>(src, lane, R[j]);  // full tile: constant chunk offsets
+    else load_subtile_at<FT, T>(src, kept, c, nk, R[j]);
   };
   // coupling entries of this thread's row (row tid of the level) for the next step
   int cpl_col[2 * kCplRegs];
   AT cpl_val[2 * kCplRegs];
   constexpr bool cpl_regs = !SL;
-  auto load_tile = [&](int k, int j) {
+  auto load_tile = [&](int k, int j) __attribute__((always_inline)) {
     const int ntl = tiles_for(lv_size[k], T);
     const int t = j * NW + wave;
     if (t < ntl) load_tile_at(k, t, tI[j], tJ[j], j);
@@ -477,7 +494,7 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
         const bool valid = t < ntl;
         const int I = valid ? rI[j] : 0, J = valid ? rJ[j] : 0;
         symv_tile_slots<FT, AT, T, CD>(R[j], I, J, tv, slots + (int64_t)(2 * (t - t_phase)) * T,
-                                   slots + (int64_t)(2 * (t - t_phase) + 1) * T, lane, valid);
+                                       slots + (int64_t)(2 * (t - t_phase) + 1) * T, lane, valid);
         if (last && has_next) load_tile(k2, j);
       }
       if (phased && ((round + 1) % phase_rounds == 0 || last)) {

@@ -122,41 +122,6 @@ __host__ __device__ inline int64_t tile_off(int t, int I, int J, int nt, int ph)
   return off;
 }
 
-// Load the lane's values of a tile that keeps only the lanes in `mask` (zeros for
-// the others); kept lane L's chunk m sits at element (m * popc(mask) + c(L)) * E,
-// c(L) = the number of kept lanes below L.
-template <class FT, int T>
-__device__ inline void load_subtile_kept(const FT* __restrict__ tile, int lane, unsigned long long mask,
-                                         FT (&v)[TileGeom<FT, T>::SS]) {
-  using G = TileGeom<FT, T>;
-  if ((mask >> lane) & 1ull) {
-    const int nk = __builtin_popcountll(mask);
-    const int c = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-    constexpr int BYTES = G::E * (int)sizeof(FT);
-#pragma unroll
-    for (int m = 0; m < G::NCH; ++m) {
-      const FT* src = tile + (m * nk + c) * G::E;
-      if constexpr (BYTES == 16) {
-        uint4 raw = *reinterpret_cast<const uint4*>(src);
-        const FT* w = reinterpret_cast<const FT*>(&raw);
-#pragma unroll
-        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
-      } else if constexpr (BYTES == 8) {
-        uint2 raw = *reinterpret_cast<const uint2*>(src);
-        const FT* w = reinterpret_cast<const FT*>(&raw);
-#pragma unroll
-        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
-      } else {
-#pragma unroll
-        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < G::SS; ++u) v[u] = Store<FT>::from(0.0);
-  }
-}
-
 // Element offset (within a tile) of sub-tile value (a, b) of lane L.
 template <class FT, int T>
 __host__ __device__ inline int tile_elem(int lane, int a, int b) {
@@ -199,6 +164,39 @@ __device__ inline void load_subtile(const FT* __restrict__ tile, int lane, FT (&
 #pragma unroll
       for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
     }
+  }
+}
+
+// Load the lane's values of a tile that stores nk lanes' sub-tiles, this lane's
+// (if kept) as the c-th of them: chunk m at element (m * nk + c) * E; zeros when
+// not kept.  A full tile is (kept, c, nk) = (true, lane, 64).
+template <class FT, int T>
+__device__ inline void load_subtile_at(const FT* __restrict__ tile, bool kept, int c, int nk,
+                                       FT (&v)[TileGeom<FT, T>::SS]) {
+  using G = TileGeom<FT, T>;
+  constexpr int BYTES = G::E * (int)sizeof(FT);
+  if (kept) {
+#pragma unroll
+    for (int m = 0; m < G::NCH; ++m) {
+      const FT* src = tile + (m * nk + c) * G::E;
+      if constexpr (BYTES == 16) {
+        uint4 raw = *reinterpret_cast<const uint4*>(src);
+        const FT* w = reinterpret_cast<const FT*>(&raw);
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
+      } else if constexpr (BYTES == 8) {
+        uint2 raw = *reinterpret_cast<const uint2*>(src);
+        const FT* w = reinterpret_cast<const FT*>(&raw);
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = w[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < G::E; ++u) v[m * G::E + u] = src[u];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < G::SS; ++u) v[u] = Store<FT>::from(0.0);
   }
 }
 
