@@ -213,7 +213,11 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   AT* tv = w + ni_pad;
   AT* acc = tv + a.ldp;     // phase accumulator (levels wider than slot_tiles only)
   AT* slots = acc + a.ldp;  // 2 * T per tile of the current phase
-  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // the wave index is read as wave-uniform where the tile loads find kept lanes
+  // (edges 32 and 64: it keeps their index arithmetic scalar); at edge 16 the plain
+  // index compiles to the faster kernel
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = short_last_row(T) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6);
   const FT* fac = static_cast<const FT*>(a.fac);
   const int kb0 = a.sub_blk_ptr[sub];
   const int K = a.sub_blk_ptr[sub + 1] - kb0;  // <= kMaxLevels (checked on the host)
@@ -256,6 +260,11 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   const int dslot = __builtin_popcountll(kept_lanes(8, true, true) & ((1ull << lane) - 1ull));
   const unsigned long long below = (1ull << lane) - 1ull;
   auto load_tile_at = [&](int k, int t, int I, int J, int j) __attribute__((always_inline)) {
+    if constexpr (!short_last_row(T) && !CD) {
+      // full tiles only
+      load_subtile<FT, T>(fac + lv_foff[k] + (int64_t)t * T * T, lane, R[j]);
+      return;
+    }
     const int bk = __builtin_amdgcn_readfirstlane(lv_size[k]);
     const int ntk = (bk + T - 1) / T;
     bool kept = true;

@@ -60,7 +60,12 @@ __host__ __device__ constexpr bool compact_diag(int T) { return T >= 32; }
 // Its off-diagonal tiles keep 8 ph lanes; its diagonal tile keeps the lanes with
 // q <= p < ph when diagonal tiles are compact, else those with p, q < ph.  With
 // ph = 8 these are the full and compact tiles of the other rows.
+// Like compact diagonal tiles, short last rows are used at tile edges 32 and 64 only
+// (at edge 16 a level has many small tiles and the per-tile work of finding the kept
+// lanes costs more than the bytes save); at edge 16 ph is 8.
+__host__ __device__ constexpr bool short_last_row(int T) { return T >= 32; }
 __host__ __device__ inline int last_row_subtiles(int32_t b, int32_t T) {
+  if (!short_last_row(T)) return 8;
   const int nt = (b + T - 1) / T, S = T / 8;
   return (b - (nt - 1) * T + S - 1) / S;
 }
