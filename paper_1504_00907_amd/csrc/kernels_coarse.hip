@@ -41,19 +41,37 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
   const int64_t t0 = own_ptr[i] + (int64_t)c * rch;
   const int64_t t1 = min(own_ptr[i + 1], t0 + rch);
   const int jl = threadIdx.x & (L - 1);
-  for (int64_t t = t0 + threadIdx.x / L; t < t1; t += kRThreads / L) {
-    const int g = own_idx[t];
-    double s;
-    if constexpr (L == 1) {
-      s = row_sub(rp, ci, val, e, g, r[g]);
-    } else {
-      s = r[g] - row_dot_l<L>(rp, ci, val, e, g, jl);
-    }
-    if (jl == 0) {
-      const double* qg = Q + (int64_t)g * kq;
+  if constexpr (L == 1) {
+    // a thread's rows t, t + 256, ... four at a time: each stage's loads (row index,
+    // row pointers, entries, e) go out for all four rows together; the rows are
+    // still added in the same order
+    constexpr int U = 4;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += (int64_t)U * kRThreads) {
+      int g[U];
+      double sv[U];
 #pragma unroll
-      for (int m = 0; m < kMaxK; ++m)
-        if (m < ki) acc[m] += qg[m] * s;
+      for (int u = 0; u < U; ++u) g[u] = t + u * kRThreads < t1 ? own_idx[t + u * kRThreads] : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) sv[u] = g[u] >= 0 ? row_sub(rp, ci, val, e, g[u], r[g[u]]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (g[u] < 0) continue;
+        const double* qg = Q + (int64_t)g[u] * kq;
+#pragma unroll
+        for (int m = 0; m < kMaxK; ++m)
+          if (m < ki) acc[m] += qg[m] * sv[u];
+      }
+    }
+  } else {
+    for (int64_t t = t0 + threadIdx.x / L; t < t1; t += kRThreads / L) {
+      const int g = own_idx[t];
+      const double s = r[g] - row_dot_l<L>(rp, ci, val, e, g, jl);
+      if (jl == 0) {
+        const double* qg = Q + (int64_t)g * kq;
+#pragma unroll
+        for (int m = 0; m < kMaxK; ++m)
+          if (m < ki) acc[m] += qg[m] * s;
+      }
     }
   }
   const int wv = threadIdx.x >> 6;
@@ -139,13 +157,20 @@ __global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ 
                                  double* __restrict__ e, int64_t n) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
+  // the row of Q (stride kq) is requested before the subdomain's count and offset
+  // are known, so its loads do not wait behind that chain of lookups
+  const double* qg = Q + g * kq;
+  double q[kMaxK];
+#pragma unroll
+  for (int m = 0; m < kMaxK; ++m) q[m] = m < kq ? qg[m] : 0.0;
   const int i = part[g];
   if (st && st[sub_inst[i]].done) return;
   const int ki = kcnt[i];
   const double* yi = y + koff[i];
-  const double* qg = Q + g * kq;
   double s = 0.0;
-  for (int m = 0; m < ki; ++m) s += qg[m] * yi[m];
+#pragma unroll
+  for (int m = 0; m < kMaxK; ++m)
+    if (m < ki) s += q[m] * yi[m];
   e[g] += s;
 }
 
