@@ -75,7 +75,7 @@ def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, iters: int, n_sample: int = 24, seed: int = 5):
+def cpu_baseline(P, iters: int, n_sample: int = 256, seed: int = 5):
     """Oracle time per solve on this host, extrapolated from a bounded sample.
 
     The sample factors `n_sample` of the subdomains with the oracle's banded
