@@ -328,6 +328,36 @@ def test_task_queue_repeatable_at_full_size():
     assert bad_z == 0 and bad_u == 0
 
 
+_short_cache = {}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile", [32, 64])
+@pytest.mark.parametrize("width", [63, 64, 70, 118, 119, 125])
+def test_short_last_tile_rows(width, tile, precision):
+    """Levels whose last tile-row is short.  A 40 x 3W grid (second index
+    fastest) in 2 x 3 boxes with overlap 1 has grid-line levels of W - 1 to W + 3
+    rows, so these widths give last tile-rows of 1-3, 5-9, 53-58 and 60-64 rows
+    at edge 64 (tiles keeping 1, 2, 7 or all 8 of their sub-tile rows), and a
+    similar spread at edge 32.  Preconditioner applications match the oracle."""
+    if width not in _short_cache:
+        P = diffusion_problem((40, 3 * width), (2, 3), 1, 2, cfg_id=7, rtol=1e-8, name=f"short_rows_{width}")
+        _short_cache[width] = (P, DDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap))
+    P, o = _short_cache[width]
+    s = make_solver(P, precision=precision, tile=tile)
+    sizes = set(int(b) for b in s.blocks()[:, 2])
+    assert {width + 1, width + 2} <= sizes
+    assert s.info()["tile"] == tile
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    rng = seed_rng(69, width)
+    for _ in range(2):
+        r = rng.standard_normal(P.n)
+        z = host(s.apply_precond(dev(r)))
+        ref = o.apply(r)
+        assert np.linalg.norm(z - ref) <= tol * np.linalg.norm(ref)
+    s.close()
+
+
 @pytest.mark.parametrize("block_target,tile", [(100000, 32), (40, 16), (0, 64)],
                          ids=["one_level", "merged", "tile64"])
 def test_level_structures_match_oracle(block_target, tile):
