@@ -306,18 +306,26 @@ class DDGOracle:
         I = np.eye(self.n)
         return np.stack([self.apply(I[:, j]) for j in range(self.n)], axis=1)
 
-    def pcg(self, f, rtol: float, max_iter: int = 1000):
-        return pcg(self.A, self.apply, f, rtol, max_iter)
+    def pcg(self, f, rtol: float, max_iter: int = 1000, variant: str = "fr", trace: bool = False):
+        return pcg(self.A, self.apply, f, rtol, max_iter, variant=variant, trace=trace)
 
 
-def pcg(A, apply_minv, f, rtol: float, max_iter: int = 1000):
+def pcg(A, apply_minv, f, rtol: float, max_iter: int = 1000, variant: str = "fr", trace: bool = False):
     """Preconditioned CG from x0 = 0 (Section 7 protocol).
 
     Stops at the first k with ||r_k|| <= rtol ||f|| (recurrence residual);
     the iteration count is the number of products A p.  Returns
     (x, iterations, info) with info holding status, residual history, the
     CG coefficients (alpha, beta) and the true relative residual.
+
+    ``variant`` picks the direction update: "fr" (Fletcher-Reeves,
+    beta = r_new^T z_new / r^T z) or "pr" (Polak-Ribiere,
+    beta = z_new^T (r_new - r) / r^T z), which stays usable when the
+    preconditioner is not exactly a fixed linear operator.  With
+    ``trace`` the search directions are kept in info["p"].
     """
+    if variant not in ("fr", "pr"):
+        raise OracleError("INVALID_ARG", "variant must be 'fr' or 'pr'")
     A = _as_csr(A)
     f = np.asarray(f, dtype=np.float64)
     nf = float(np.linalg.norm(f))
@@ -332,6 +340,8 @@ def pcg(A, apply_minv, f, rtol: float, max_iter: int = 1000):
     z = apply_minv(r)
     p = z.copy()
     rho = float(r @ z)
+    if trace:
+        info["p"] = [p.copy()]
     it = 0
     while True:
         if it >= max_iter:
@@ -344,6 +354,7 @@ def pcg(A, apply_minv, f, rtol: float, max_iter: int = 1000):
             break
         alpha = rho / pq
         x += alpha * p
+        r_prev = r.copy() if variant == "pr" else None
         r -= alpha * q
         it += 1
         rn = float(np.linalg.norm(r))
@@ -353,10 +364,15 @@ def pcg(A, apply_minv, f, rtol: float, max_iter: int = 1000):
             break
         z = apply_minv(r)
         rho_new = float(r @ z)
-        beta = rho_new / rho
+        if variant == "pr":
+            beta = float(z @ (r - r_prev)) / rho
+        else:
+            beta = rho_new / rho
         info["beta"].append(beta)
         p = z + beta * p
         rho = rho_new
+        if trace:
+            info["p"].append(p.copy())
     info["rel_res"] = info["res"][-1]
     info["true_rel_res"] = float(np.linalg.norm(f - A @ x)) / nf
     return x, it, info
@@ -376,3 +392,43 @@ def lanczos_ritz(alphas, betas) -> np.ndarray:
         if j + 1 < m:
             T[j, j + 1] = T[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
     return np.linalg.eigvalsh(T)
+
+
+def fractional_iterations(res, tol: float) -> float:
+    """Fractional iteration count (Section 7 protocol).
+
+    ``res[k]`` is the relative residual after k iterations (res[0] = 1).
+    The log-residual is interpolated linearly between the last iterate
+    above the tolerance and the first one at or below it; the fractional
+    count is where that line meets log(tol).  Returns nan if no iterate
+    reaches tol, and 0 if res[0] already does.
+    """
+    res = np.asarray(res, dtype=np.float64)
+    hit = np.flatnonzero(res <= tol)
+    if hit.size == 0:
+        return float("nan")
+    k = int(hit[0])
+    if k == 0:
+        return 0.0
+    a, b = np.log(res[k - 1]), np.log(res[k])
+    return (k - 1) + (np.log(tol) - a) / (b - a)
+
+
+def condition_estimate(alphas, betas):
+    """(lambda_min, lambda_max, kappa) of M^{-1} A from the extreme Ritz values (Section 7)."""
+    ritz = lanczos_ritz(alphas, betas)
+    lo, hi = float(ritz.min()), float(ritz.max())
+    return lo, hi, hi / lo
+
+
+def cg_iteration_bound(kappa: float, tol: float) -> int:
+    """Smallest k with 2 ((sqrt(kappa) - 1) / (sqrt(kappa) + 1))^k <= tol.
+
+    The classical CG bound on the A-norm error reduction, used with the
+    Lanczos condition estimate as the iteration bound the paper reports
+    for solves stopped at the iteration cap (Section 7).
+    """
+    if kappa <= 1.0:
+        return 0 if tol >= 2.0 else 1
+    q = (np.sqrt(kappa) - 1.0) / (np.sqrt(kappa) + 1.0)
+    return max(0, int(np.ceil(np.log(tol / 2.0) / np.log(q))))

@@ -4,7 +4,11 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The operator is the cell-centred finite-volume diffusion matrix with
 harmonic-mean face coefficients a_f = 2 kL kR / (kL + kR) and zero-Dirichlet
-ghost faces of coefficient 2 kc, kappa = exp(theta).  Its assembly is written
+ghost faces of coefficient 2 kc, kappa = exp(theta).  Boundary conditions:
+``bc="dirichlet"`` puts such a ghost face on every boundary face;
+``bc="x0"`` (problem A of Section 7: one Dirichlet face, the rest Neumann)
+keeps only the ghost faces on the x = 0 face (x is the last, fastest
+array axis) and leaves every other boundary face without flux.  Its assembly is written
 here independently of the input generators so that the derivative below is
 checked against this module's own operator.
 
@@ -24,7 +28,19 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def assemble_cc(kappa: np.ndarray) -> sp.csr_matrix:
+BCS = ("dirichlet", "x0")
+
+
+def _ghost_ends(ndim: int, ax: int, bc: str):
+    """Which ends (low, high) of axis ``ax`` carry a Dirichlet ghost face."""
+    if bc not in BCS:
+        raise ValueError(f"bc must be one of {BCS}")
+    if bc == "dirichlet":
+        return True, True
+    return ax == ndim - 1, False
+
+
+def assemble_cc(kappa: np.ndarray, bc: str = "dirichlet") -> sp.csr_matrix:
     """Harmonic-mean cell-centred operator (oracle's own assembly)."""
     kappa = np.asarray(kappa, dtype=np.float64)
     shape = kappa.shape
@@ -43,8 +59,11 @@ def assemble_cc(kappa: np.ndarray) -> sp.csr_matrix:
         rows += [il, ir]
         cols += [ir, il]
         vals += [-a, -a]
-        np.add.at(diag, I[0].ravel(), 2.0 * L[0].ravel())
-        np.add.at(diag, I[-1].ravel(), 2.0 * L[-1].ravel())
+        lo, hi = _ghost_ends(kappa.ndim, ax, bc)
+        if lo:
+            np.add.at(diag, I[0].ravel(), 2.0 * L[0].ravel())
+        if hi:
+            np.add.at(diag, I[-1].ravel(), 2.0 * L[-1].ravel())
     rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(diag)
     M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
@@ -52,7 +71,7 @@ def assemble_cc(kappa: np.ndarray) -> sp.csr_matrix:
     return M
 
 
-def coeff_grad_cc(kappa: np.ndarray, u: np.ndarray, lam: np.ndarray) -> np.ndarray:
+def coeff_grad_cc(kappa: np.ndarray, u: np.ndarray, lam: np.ndarray, bc: str = "dirichlet") -> np.ndarray:
     """Per-cell -kappa_c * lam^T (dA/dkappa_c) u, returned in grid shape."""
     kappa = np.asarray(kappa, dtype=np.float64)
     U = np.asarray(u, dtype=np.float64).reshape(kappa.shape)
@@ -68,6 +87,9 @@ def coeff_grad_cc(kappa: np.ndarray, u: np.ndarray, lam: np.ndarray) -> np.ndarr
         jump = (Ll[:-1] - Ll[1:]) * (Uu[:-1] - Uu[1:])
         G[:-1] += 2.0 * kr ** 2 / s2 * jump
         G[1:] += 2.0 * kl ** 2 / s2 * jump
-        G[0] += 2.0 * Ll[0] * Uu[0]
-        G[-1] += 2.0 * Ll[-1] * Uu[-1]
+        lo, hi = _ghost_ends(kappa.ndim, ax, bc)
+        if lo:
+            G[0] += 2.0 * Ll[0] * Uu[0]
+        if hi:
+            G[-1] += 2.0 * Ll[-1] * Uu[-1]
     return -kappa * acc

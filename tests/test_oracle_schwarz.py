@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import DDGOracle, OracleError, pcg
-from oracle.ddg import lanczos_ritz
+from oracle import (DDGOracle, OracleError, cg_iteration_bound, condition_estimate, fractional_iterations,
+                    lanczos_ritz, pcg)
 from workloads import (CSR, box_partition, cell_coords, diffusion_cc, laplace5_nodes, monomials,
                        node_coords_2d, poisson2d_nodes, seed_rng)
 
@@ -180,6 +180,91 @@ def test_lanczos_ritz_values_in_unit_interval():
     x, it, info = o.pcg(f, 1e-10)
     ritz = lanczos_ritz(info["alpha"], info["beta"])
     assert ritz.min() > 0 and ritz.max() <= 1 + 1e-8
+
+
+def test_lanczos_extremes_equal_preconditioned_spectrum():
+    """The extreme Ritz values from the CG coefficients converge to the extreme
+    eigenvalues of M^{-1} A (Section 7: condition estimates from the Lanczos
+    coefficients).  Reference: eigenvalues of L^T M^{-1} L with A = L L^T, from the
+    dense preconditioner."""
+    A, F, part, nparts = tiny3d(side=8)
+    o = DDGOracle(A, F, part, nparts, 0)
+    f = seed_rng(28, 0).standard_normal(A.n)
+    x, it, info = o.pcg(f, 1e-13)
+    assert info["status"] == "ok" and it >= 10
+    Minv = o.dense_operator()
+    L = np.linalg.cholesky(A.to_scipy().toarray())
+    ev = np.linalg.eigvalsh(0.5 * ((L.T @ Minv @ L) + (L.T @ Minv @ L).T))
+    lo, hi, kappa = condition_estimate(info["alpha"], info["beta"])
+    # the smallest eigenvalue is isolated and converges first
+    assert abs(lo - ev.min()) <= 1e-8 * ev.min()
+    # the top of the spectrum is a cluster at 1: Ritz values interlace, so the largest
+    # lies just below the largest eigenvalue
+    assert ev.max() - 1e-4 <= hi <= ev.max() + 1e-12
+    ritz = lanczos_ritz(info["alpha"], info["beta"])
+    assert ritz.size == it and ritz.min() >= ev.min() - 1e-12
+
+
+def test_fractional_iterations_closed_forms():
+    """Log-linear interpolation of the residual history (Section 7 protocol): on an
+    exactly geometric history res_k = q^k it meets tol at log(tol)/log(q)."""
+    for q in (0.5, 0.1, 0.37):
+        res = q ** np.arange(30)
+        for tol in (1e-3, 1e-8, 2.5e-6):
+            assert abs(fractional_iterations(res, tol) - np.log(tol) / np.log(q)) <= 1e-9
+    res = np.array([1.0, 1e-2, 1e-4, 1e-9])
+    assert fractional_iterations(res, 1e-4) == 2.0
+    assert abs(fractional_iterations(res, 1e-6) - (2 + 2.0 / 5.0)) <= 1e-12
+    assert fractional_iterations(res, 1e-12) != fractional_iterations(res, 1e-12)  # nan: never reached
+    assert fractional_iterations(res, 1.0) == 0.0
+
+
+def test_cg_iteration_bound_closed_forms():
+    """k = ceil(log(tol/2) / log((sqrt(kappa)-1)/(sqrt(kappa)+1))): kappa = 9 gives q = 1/2."""
+    assert cg_iteration_bound(9.0, 2.0 ** -10) == 11
+    assert cg_iteration_bound(9.0, 2.0 ** -10 * 1.0001) == 11
+    assert cg_iteration_bound(9.0, 2.0 ** -9 * 0.9999) == 11
+    assert cg_iteration_bound(1.0, 1e-8) == 1
+    # monotone in kappa and tol
+    ks = [cg_iteration_bound(k, 1e-8) for k in (2.0, 10.0, 100.0, 1e4)]
+    assert ks == sorted(ks) and ks[-1] > ks[0]
+    # for large kappa about sqrt(kappa)/2 ln(2/tol)
+    k = cg_iteration_bound(1e6, 1e-9)
+    assert abs(k - 0.5 * 1e3 * np.log(2e9)) <= 2
+
+
+def test_polak_ribiere_keeps_directions_conjugate():
+    """With Polak-Ribiere beta = z+^T (r+ - r) / r^T z, consecutive directions stay
+    A-conjugate (p+^T A p = 0) even when the preconditioner changes from one
+    iteration to the next; Fletcher-Reeves loses this.  With the fixed two-level
+    preconditioner both give the same iterates (exact arithmetic)."""
+    A, F, part, nparts = tiny3d(side=6)
+    As = A.to_scipy()
+    rng = seed_rng(29, 0)
+    n = A.n
+    diags = [np.exp(rng.standard_normal(n)) for _ in range(40)]
+    calls = {"k": 0}
+
+    def varying(r):
+        d = diags[calls["k"] % len(diags)]
+        calls["k"] += 1
+        return d * r
+
+    f = rng.standard_normal(n)
+    worst = {}
+    for variant in ("pr", "fr"):
+        calls["k"] = 0
+        _, it, info = pcg(As, varying, f, 1e-10, max_iter=30, variant=variant, trace=True)
+        ps = info["p"]
+        worst[variant] = max(abs(ps[j + 1] @ (As @ ps[j])) / (np.linalg.norm(ps[j + 1]) * np.linalg.norm(As @ ps[j]))
+                             for j in range(len(ps) - 1))
+    assert worst["pr"] <= 1e-12
+    assert worst["fr"] >= 1e-4
+    o = DDGOracle(A, F, part, nparts, 1)
+    x_fr, it_fr, _ = o.pcg(f, 1e-10)
+    x_pr, it_pr, _ = o.pcg(f, 1e-10, variant="pr")
+    assert it_fr == it_pr
+    assert np.linalg.norm(x_fr - x_pr) <= 1e-9 * np.linalg.norm(x_fr)
 
 
 def test_pcg_conventions():
