@@ -75,20 +75,35 @@ def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, iters: int, n_sample: int = 256, seed: int = 5):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(P, iters: int, n_sample: int = 256, seed: int = 5, workers: int = 16):
     """Oracle time per solve on this host, extrapolated from a bounded sample.
 
     The sample factors `n_sample` of the subdomains with the oracle's banded
-    Cholesky and times their pre- and post-sweep local updates; the full coarse
-    setup (per-subdomain QR, Galerkin product, dense Cholesky) and its
-    application plus one SpMV are timed whole.  Per-iteration time =
-    (sampled local time) * n_parts / n_sample + coarse apply + 2 SpMV; the
-    solve time is that times the iteration count.
+    Cholesky and times their pre- and post-sweep local updates twice: on one
+    thread (BLAS limited to one thread), and with a thread pool of `workers`
+    threads over the subdomains of each colour (independent by the colouring;
+    BLAS one thread per worker).  The full coarse setup (per-subdomain QR,
+    Galerkin product, dense Cholesky) and its application plus one SpMV are
+    timed whole.  Per-iteration time = (sampled local time) * n_parts /
+    n_sample + coarse apply + SpMV; the solve time is that times the
+    iteration count.  `value` is the thread-pool figure.
     """
-    import scipy.linalg as sla
-    from threadpoolctl import threadpool_info
+    from concurrent.futures import ThreadPoolExecutor
 
-    from oracle.ddg import _LocalSolver, coarse_basis, galerkin, overlap_sets
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ddg import _LocalSolver, coarse_basis, conflict_lists, galerkin, greedy_colouring, overlap_sets
 
     A = P.A.to_scipy()
     rng = np.random.default_rng(seed)
@@ -99,37 +114,91 @@ def cpu_baseline(P, iters: int, n_sample: int = 256, seed: int = 5):
     t_coarse_setup = time.perf_counter() - t0
     sample = np.sort(rng.choice(P.n_parts, size=min(n_sample, P.n_parts), replace=False))
     sets = overlap_sets(A, P.part, P.n_parts, P.overlap)
+    colours = greedy_colouring(conflict_lists(A, sets, P.n))
     t0 = time.perf_counter()
-    solvers = [(_LocalSolver(A[sets[i]][:, sets[i]], int(i)), sets[i], A[sets[i]]) for i in sample]
+    solvers = {int(i): (_LocalSolver(A[sets[i]][:, sets[i]], int(i)), sets[i], A[sets[i]]) for i in sample}
     t_local_setup = (time.perf_counter() - t0) * P.n_parts / len(sample)
+    order = [[int(i) for i in sample if colours[i] == c] for c in range(int(colours.max()) + 1)]
     r = np.random.default_rng(seed + 1).standard_normal(P.n)
-    e = np.zeros(P.n)
-    t0 = time.perf_counter()
-    for _ in range(2):  # pre- and post-sweep visit every subdomain once each
-        for ls, s, rows in solvers:
-            b = r[s] - rows @ e
-            e[s] += ls.solve(b)
-    t_local = (time.perf_counter() - t0) * P.n_parts / len(sample)
+
+    def update(i, e):
+        ls, st, rows = solvers[i]
+        e[st] += ls.solve(r[st] - rows @ e)
+
+    with threadpool_limits(1):
+        e = np.zeros(P.n)
+        t0 = time.perf_counter()
+        for seq in (order, order[::-1]):  # pre- and post-sweep
+            for ids in seq:
+                for i in ids:
+                    update(i, e)
+        t_local_1 = (time.perf_counter() - t0) * P.n_parts / len(sample)
+        e = np.zeros(P.n)
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            t0 = time.perf_counter()
+            for seq in (order, order[::-1]):
+                for ids in seq:
+                    # same-colour subdomains: no set meets another's neighbourhood
+                    list(ex.map(lambda i: update(i, e), ids))
+            t_local_w = (time.perf_counter() - t0) * P.n_parts / len(sample)
     t0 = time.perf_counter()
     q = A @ r
     y = R0.T @ sla.cho_solve(fac, R0 @ (r - A @ e))
     t_rest = time.perf_counter() - t0
     del q, y
-    per_iter = t_local + t_rest
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    per_iter_1 = t_local_1 + t_rest
+    per_iter_w = t_local_w + t_rest
     return {
-        "value": per_iter * iters * 1e3,
+        "value": per_iter_w * iters * 1e3,
         "unit": "ms",
-        "cores": int(threads),
+        "cores": int(workers),
         "kind": "oracle",
         "sample": (f"oracle FP64 local solves on {len(sample)} of {P.n_parts} subdomains (banded "
-                   f"LAPACK Cholesky) scaled by {P.n_parts}/{len(sample)}, plus full coarse apply and "
-                   f"SpMV, times {iters} iterations; solve only (setup extrapolated separately: "
+                   f"LAPACK Cholesky), colour by colour with a pool of {workers} threads (BLAS 1 thread each), "
+                   f"scaled by {P.n_parts}/{len(sample)}, plus full coarse apply and SpMV, times {iters} "
+                   f"iterations; solve only (setup extrapolated separately: "
                    f"{(t_coarse_setup + t_local_setup):.1f} s)"),
+        "single_thread_ms": per_iter_1 * iters * 1e3,
+        "pool_threads": int(workers),
         "setup_s_extrapolated": t_coarse_setup + t_local_setup,
-        "per_iter_ms": per_iter * 1e3,
+        "per_iter_ms": per_iter_w * 1e3,
+        "per_iter_ms_single_thread": per_iter_1 * 1e3,
         "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }
+
+
+def cpu_fwd_adjoint(side: int, g_gpu: np.ndarray, tol: float = 1e-11):
+    """The oracle's forward + adjoint + gradient on the differentiation workload.
+
+    Two oracle setups (theta_obs, theta) and three PCG solves (u_obs, u,
+    lambda) at rtol `tol`, then the oracle gradient formula; timed, and the
+    GPU gradient's relative error against it (2-norm).
+    """
+    from oracle import DDGOracle
+    from oracle.gradient import assemble_cc, coeff_grad_cc
+    from workloads import box_partition, cell_coords, grf, monomials, seed_rng
+
+    shape = (side,) * 3
+    boxes = (side // 12,) * 3
+    theta = grf(shape, 8.0, 1.0, seed_rng(4, 1))
+    theta_obs = grf(shape, 8.0, 1.0, seed_rng(4, 2))
+    fh = seed_rng(4, 0).uniform(-1.0, 1.0, side ** 3)
+    part = box_partition(shape, boxes)
+    F = monomials(cell_coords(shape), 2)
+    nparts = int(np.prod(boxes))
+    t0 = time.perf_counter()
+    o = DDGOracle(assemble_cc(np.exp(theta_obs)), F, part, nparts, 1)
+    uobs, _, _ = o.pcg(fh, tol)
+    del o
+    o = DDGOracle(assemble_cc(np.exp(theta)), F, part, nparts, 1)
+    u, it_u, _ = o.pcg(fh, tol)
+    lam, it_l, _ = o.pcg(2.0 * (u - uobs), tol)
+    g = coeff_grad_cc(np.exp(theta), u, lam).ravel()
+    t = time.perf_counter() - t0
+    err = float(np.linalg.norm(g_gpu - g) / np.linalg.norm(g))
+    return {"oracle_s": t, "oracle_rtol": tol, "oracle_iters_fwd": it_u, "oracle_iters_adj": it_l,
+            "grad_rel_err_vs_oracle": err}
 
 
 def elasticity(nel: int, steps: int, tile: int = 0, block_target: int = 0):
@@ -215,8 +284,13 @@ def batched(count: int, precision: str, steps: int, warmup: int):
 
     sides = cfg4_sides(count)
     t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+    pool = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1))
+    try:
         res = pool.map(_batch_instance, list(enumerate(sides)), chunksize=4)
+    finally:
+        # let the workers exit on their own (no terminate signal on the way out)
+        pool.close()
+        pool.join()
     probs = [r[0] for r in res]
     f = torch.from_numpy(np.concatenate([r[1] for r in res])).cuda()
     del res
@@ -253,6 +327,8 @@ def batched(count: int, precision: str, steps: int, warmup: int):
     ms_ev = (time.perf_counter() - t0) * 1e3 / steps
     prof = b.profile_read(reset=True)
     b.profile_enable(False)
+    # bytes are credited per system only for launches enqueued while it still iterated;
+    # launches that ran for no system are counted apart (idle)
     sweep_gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
     per = np.array([i["solve_ms"] for i in infos])
     its = np.array([i["iters"] for i in infos])
@@ -278,7 +354,11 @@ def batched(count: int, precision: str, steps: int, warmup: int):
         "sweep_kernel": {"achieved_GBps": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
                          "launches": prof["launches"],
                          "avg_launch_us": prof["ms"] * 1e3 / prof["launches"] if prof["launches"] else None,
-                         "share_of_solve": prof["ms"] / (ms_ev * steps), "ms_per_batch_with_events": ms_ev},
+                         "idle_launches": prof["idle_launches"],
+                         "idle_avg_us": (prof["idle_ms"] * 1e3 / prof["idle_launches"]
+                                         if prof["idle_launches"] else None),
+                         "share_of_solve": (prof["ms"] + prof["idle_ms"]) / (ms_ev * steps),
+                         "ms_per_batch_with_events": ms_ev},
     }
 
 
@@ -328,6 +408,22 @@ def fwd_adjoint(side: int, precision: str, steps: int, warmup: int):
         fwd, adj, g = pair()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+
+    # the same pairs on a handle that already holds A(exp(theta)) (no refactor)
+    def pair_kept():
+        t = th.clone().requires_grad_(True)
+        u = ddg_solve_fn(t, f, ds, refactor=False)
+        L = ((u - u_obs) ** 2).sum()
+        L.backward()
+        return t.grad
+
+    pair_kept()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pair_kept()
+    torch.cuda.synchronize()
+    ms_kept = (time.perf_counter() - t0) * 1e3 / steps
     # refactor alone
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -335,15 +431,45 @@ def fwd_adjoint(side: int, precision: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     ref_ms = (time.perf_counter() - t1) * 1e3
     info = ds.solver.info()
+    g_host = g.detach().cpu().numpy().copy()
+    # central differences of L at the exact perturbed solves (residual correction
+    # u+- = u0 + A+-^{-1} (f - A+- u0), each correction solved by the same DDG-PCG)
+    t_fd = time.perf_counter()
+    u0 = ddg_solve_fn(th, f, ds).detach().clone()
+    cells = seed_rng(4, 5).choice(side ** 3, size=32, replace=False)
+    h = 1e-6
+    fd = []
+    for c in cells:
+        deltas = []
+        for sgn in (1.0, -1.0):
+            tp = th.clone()
+            tp[int(c)] += sgn * h
+            ds.refactor(tp)
+            deltas.append(ds.solve(f - ds.solver.spmv(u0)))
+        dp, dm = deltas
+        fd.append(float(torch.dot(dp - dm, 2.0 * u0 + dp + dm - 2.0 * u_obs)) / (2.0 * h))
+    fd = np.array(fd)
+    gc = g_host[cells]
+    big = np.abs(gc) >= 1e-3 * np.abs(g_host).max()
+    fd_rel = np.abs(fd - gc) / np.abs(gc)
+    t_fd = time.perf_counter() - t_fd
     ds.solver.close()
-    log(f"fwd+adjoint: {ms:.1f} ms/pair (refactor {ref_ms:.1f} ms), iters {fwd['iters']} + {adj['iters']}")
+    log(f"fwd+adjoint: {ms:.1f} ms/pair (refactor {ref_ms:.1f} ms; {ms_kept:.1f} ms without), "
+        f"iters {fwd['iters']} + {adj['iters']}, FD max rel err {fd_rel[big].max():.2e} ({t_fd:.1f} s)")
     return {
         "workload": f"diffusion3d_{side}^3_exp_theta_L2_loss", "n": side ** 3, "subdomains": int(np.prod(boxes)),
         "precision": precision, "rtol": 1e-10, "steps": steps,
         "pairs_per_s": 1e3 / ms, "ms_per_pair": ms, "refactor_ms": ref_ms,
+        "pairs_per_s_without_refactor": 1e3 / ms_kept, "ms_per_pair_without_refactor": ms_kept,
         "solve_ms_fwd": fwd["solve_ms"], "solve_ms_adj": adj["solve_ms"],
         "iters_fwd": fwd["iters"], "iters_adj": adj["iters"], "setup_ms_device": info["setup_ms"],
-        "grad_norm": float(torch.linalg.norm(g)),
+        "grad_norm": float(np.linalg.norm(g_host)),
+        "fd_check": {"cells": 32, "step": h, "protocol": "central difference of the exact perturbed solves "
+                     "(residual correction)", "max_rel_err": float(fd_rel[big].max()),
+                     "cells_relative": int(big.sum()),
+                     "max_abs_err_small_cells_over_gmax": (float(np.abs(fd - gc)[~big].max() / np.abs(g_host).max())
+                                                           if (~big).any() else None)},
+        "_grad": g_host,
     }
 
 
@@ -528,27 +654,59 @@ def main():
 
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else 0.0
     sweep_kernel = "k_sweep_flow" if hinfo["schedule"] == 2 else "k_sweep"
+    avg_s = prof["ms"] * 1e-3 / prof["launches"] if prof and prof["launches"] else None
+    # the survey's count of the same launches: factors at the envelope size E (every
+    # local matrix's envelope, where a banded Cholesky factor's fill stays), two
+    # substitutions per launch, plus the gathers (r and e on each set and its one-ring,
+    # a symmetric 7-point row of 32 bytes, e read and written): per launch the average
+    # over the 2C launches of one application
+    s_f = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
+    E, Nhat, Srows, C2 = hinfo["envelope_elems"], hinfo["nbhd_rows"], hinfo["set_rows"], 2 * hinfo["n_colours"]
+    survey_app = 4 * E * s_f + 2 * (Nhat * 16 + Srows * (32 + 16))
+    survey_launch = survey_app / C2
+    traffic = (profiled_traffic(sweep_kernel, args.precision, hinfo["tile"])
+               if args.side == 128 and args.box == 16 else None)
     roofline = {
         "bound": "hbm",
         "kernel": sweep_kernel + (" (one sweep direction over the task queue)" if sweep_kernel == "k_sweep_flow"
                                   else " (one colour phase)"),
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": (profiled_traffic(sweep_kernel, args.precision, hinfo["tile"])
-                    if args.side == 128 and args.box == 16 else None),
+        "traffic": traffic,
+        "frac_counters": (round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic and avg_s else None),
+        "frac_survey": round(survey_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4) if avg_s else None,
+        "survey_bytes_per_launch": survey_launch,
         "launches": prof["launches"] if prof else 0,
-        "avg_launch_us": (prof["ms"] * 1e3 / prof["launches"]) if prof and prof["launches"] else None,
+        "idle_launches": prof["idle_launches"] if prof else 0,
+        "idle_avg_us": (prof["idle_ms"] * 1e3 / prof["idle_launches"]) if prof and prof["idle_launches"] else None,
+        "avg_launch_us": avg_s * 1e6 if avg_s else None,
         "bytes_per_launch": (prof["bytes"] / prof["launches"]) if prof and prof["launches"] else None,
-        "kernel_share_of_solve": (prof["ms"] / (ms_ev * args.steps)) if prof else None,
-        "timed_pass": "a second pass of the same K solves with a HIP event pair attached to each launch's dispatch",
+        "kernel_share_of_solve": ((prof["ms"] + prof["idle_ms"]) / (ms_ev * args.steps)) if prof else None,
+        "timed_pass": "a second pass of the same K solves with a HIP event pair attached to each launch's dispatch; "
+                      "launches enqueued after convergence ran for no system and are counted apart (idle)",
         "ms_per_step_with_events": round(ms_ev, 3),
     }
     whole = hinfo["iter_bytes"] * info_mx["iters"] / (ms_mx * 1e-3) / 1e9
+    # the survey's bytes of one whole CG iteration: the sweeps above, the coarse step
+    # (residual SpMV, Q^T s, the dense inverse read twice as two triangular solves would,
+    # e += Q y) and the CG SpMV and vector updates
+    n, k, Nc = P.n, 10, hinfo["n_coarse"]
+    survey_iter = (survey_app + P.n * (16 + 32) + 2 * n * k * 8 + 2 * (Nc * (Nc + 1) // 2) * 8 + 16 * n
+                   + n * (16 + 32) + 10 * n * 8)
+    whole_survey = survey_iter * info_mx["iters"] / (ms_mx * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline (bounded sample)")
         cpu = cpu_baseline(P, info_mx["iters"])
-        log(f"oracle estimate {cpu['value']:.0f} ms/solve")
+        log(f"oracle estimate {cpu['value']:.0f} ms/solve ({cpu['single_thread_ms']:.0f} ms single-threaded)")
+        if adj is not None:
+            log("oracle forward + adjoint + gradient on the differentiation workload")
+            cf = cpu_fwd_adjoint(args.adjoint_side, adj["_grad"])
+            adj["grad_rel_err_vs_oracle"] = cf["grad_rel_err_vs_oracle"]
+            cpu["fwd_adjoint"] = cf
+            log(f"oracle gradient {cf['oracle_s']:.1f} s; GPU gradient rel err {cf['grad_rel_err_vs_oracle']:.2e}")
+    if adj is not None:
+        adj.pop("_grad", None)
     rec = {
         "metric": METRIC,
         "value": round(ms_mx, 3),
@@ -577,6 +735,10 @@ def main():
         "factor_bytes": hinfo["factor_bytes"],
         "iter_bytes": hinfo["iter_bytes"],
         "whole_solve_GBps": round(whole, 1),
+        "whole_solve_frac": round(whole / HBM_PEAK_GBS, 4),
+        "whole_solve_frac_survey": round(whole_survey / HBM_PEAK_GBS, 4),
+        "survey_iter_bytes": survey_iter,
+        "envelope_elems": E,
         **out64,
         "fwd_adjoint": adj,
         "batched": bat,

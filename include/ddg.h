@@ -67,6 +67,15 @@ typedef enum {
                                 subdomains whose sets meet its neighbourhood */
 } ddg_schedule;
 
+/* Direction update of CG (Sections 1 and 7 use CG; the paper does not fix the
+ * formula).  Both give the same iterates when the preconditioner is a fixed
+ * symmetric linear operator; Polak-Ribiere keeps consecutive directions
+ * A-conjugate when it is not (an inexact inner solve, reduced precision). */
+typedef enum {
+  DDG_CG_FLETCHER_REEVES = 0,  /* beta = r_{k+1}^T z_{k+1} / r_k^T z_k */
+  DDG_CG_POLAK_RIBIERE = 1     /* beta = z_{k+1}^T (r_{k+1} - r_k) / r_k^T z_k */
+} ddg_cg_variant;
+
 typedef struct {
   int32_t precision;   /* ddg_precision */
   int32_t max_iter;    /* CG iteration cap (default 1000, Section 7) */
@@ -76,6 +85,7 @@ typedef struct {
   int32_t block_target;/* merge local levels up to this many rows; 0 = automatic */
   int32_t check_every; /* CG iterations enqueued between host convergence checks (0 = 4) */
   int32_t schedule;    /* ddg_schedule (default DDG_SCHEDULE_AUTO) */
+  int32_t cg_variant;  /* ddg_cg_variant (default DDG_CG_FLETCHER_REEVES) */
   void* stream;        /* hipStream_t for all work; NULL = the null stream */
 } ddg_options;
 
@@ -96,6 +106,10 @@ typedef struct {
   int64_t iter_bytes;      /* algorithmic HBM bytes of one CG iteration */
   int32_t tile;            /* tile edge of the local factors (16, 32 or 64) */
   int32_t schedule;        /* ddg_schedule in effect: DDG_SCHEDULE_COLOURS or DDG_SCHEDULE_QUEUE */
+  int64_t envelope_elems;  /* sum over subdomains of the envelope of the lower triangle of A_i in its
+                              local order: the entries a banded (envelope) Cholesky factor would store */
+  int64_t set_rows;        /* sum over subdomains of |expanded set| */
+  int64_t nbhd_rows;       /* sum over subdomains of |expanded set plus the rows coupled to it by A| */
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */
@@ -224,6 +238,41 @@ int ddg_spmv(ddg_handle h, const double* x_dev, double* y_dev);
 /* Fill *info with the handle's sizes and the statistics of the last setup/solve. */
 int ddg_get_info(ddg_handle h, ddg_info* info);
 
+/*
+ * CG history of system `system` (0 for a single system) in the last solve:
+ * alpha[j] = r_j^T z_j / p_j^T A p_j (j < iters), beta[j] of the direction
+ * update after iteration j+1 (j < iters - 1), rel_res[j] = ||r_j|| / ||f||
+ * (j <= iters; rel_res[0] = 1).  Host buffers of cap entries each (any may be
+ * NULL); *count receives iters.  Errors: INVALID_ARG (bad system, no solve yet).
+ */
+int ddg_cg_history(ddg_handle h, int32_t system, double* alpha, double* beta, double* rel_res, int32_t cap,
+                   int32_t* count);
+
+/*
+ * Reporting of Section 7 for system `system` of the last solve:
+ *   frac_iters  where the linear interpolation of log ||r_j|| / ||f|| between
+ *               the last iterate above rtol and the first at or below it meets
+ *               log rtol (NaN when rtol was not reached);
+ *   lambda_min, lambda_max  extreme eigenvalues of the Lanczos tridiagonal
+ *               built from the CG coefficients (T_jj = 1/alpha_j +
+ *               beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j), by
+ *               Sturm-sequence bisection; kappa = lambda_max / lambda_min, the
+ *               condition estimate of M^{-1} A;
+ *   iter_bound  smallest k with 2 ((sqrt(kappa)-1)/(sqrt(kappa)+1))^k <= rtol,
+ *               the CG bound the paper reports for solves stopped at the cap.
+ * Computed on the host from ddg_cg_history.  Errors as ddg_cg_history.
+ */
+typedef struct {
+  int32_t iters;
+  int32_t iter_bound;
+  double frac_iters;
+  double lambda_min;
+  double lambda_max;
+  double kappa;
+} ddg_cg_report;
+
+int ddg_cg_report_get(ddg_handle h, int32_t system, ddg_cg_report* out);
+
 /* Items for ddg_export (host buffers; `bytes` must equal the exact size). */
 typedef enum {
   DDG_EXPORT_COLOURS = 0,   /* int32[n_parts]: colour of each subdomain */
@@ -248,6 +297,12 @@ int ddg_export(ddg_handle h, int32_t what, void* host_buf, int64_t bytes, int64_
 int ddg_profile_enable(ddg_handle h, int32_t on);
 int ddg_profile_read(ddg_handle h, double* sweep_ms, int64_t* sweep_launches, int64_t* sweep_bytes,
                      int32_t reset);
+/* Launches that ran for no system (enqueued ahead of the convergence check
+ * after every system had stopped; their kernels return at once): their total
+ * milliseconds and count since the last reset of ddg_profile_read.  They are
+ * not part of ddg_profile_read's figures.  A launch enqueued by CG iteration t
+ * is credited with the bytes of the systems still iterating after t. */
+int ddg_profile_read_idle(ddg_handle h, double* idle_ms, int64_t* idle_launches);
 
 /*
  * Host-only symbolic analysis (no device memory, no GPU calls): validates the
@@ -269,31 +324,40 @@ const char* ddg_last_error(void);
 /* ---------------------------------------------------------------------------
  * Cell-centred variable-coefficient diffusion (the operator family of the
  * differentiation workload).  dims[3] = (nx, ny, nz), cells x-fastest;
- * the grid is 3D when nz > 1, 2D when nz = 1 < ny, else 1D, and ghost faces
+ * the grid is 3D when nz > 1, 2D when nz = 1 < ny, else 1D, and boundary faces
  * exist only along its own axes.  Face coefficient between cells L, R is the harmonic
- * mean 2 kL kR / (kL + kR); each boundary face is a zero-Dirichlet ghost face
- * of coefficient 2 kc.  kappa = exp(theta).
+ * mean 2 kL kR / (kL + kR); a boundary face with a zero-Dirichlet ghost adds
+ * 2 kc to the diagonal, a boundary face without one carries no flux (Neumann).
+ * kappa = exp(theta).
  * ------------------------------------------------------------------------- */
+
+/* Which boundary faces carry the zero-Dirichlet ghost. */
+typedef enum {
+  DDG_BC_DIRICHLET = 0,  /* every boundary face */
+  DDG_BC_X0 = 1          /* only the faces on x = 0; Neumann elsewhere (Section 7, 3D Poisson problem:
+                            one Dirichlet face, the rest Neumann) */
+} ddg_bc;
 
 /*
  * Write the CSR values of A(exp(theta)) into val_dev, in the sorted-column
  * CSR order of the same operator: row g holds its existing neighbours
  * g - nx*ny, g - nx, g - 1, the diagonal, g + 1, g + nx, g + nx*ny, in that
  * order (the pattern is the caller's; it is fixed by dims).  theta_dev[ncell],
- * val_dev[nnz] device, caller-owned; stream may be NULL (default stream).
- * Errors: DDG_ERR_INVALID_ARG for non-positive dims or NULL pointers; the
- * launch is asynchronous and reads no other memory.
+ * val_dev[nnz] device, caller-owned; bc a ddg_bc value; stream may be NULL
+ * (default stream).  Errors: DDG_ERR_INVALID_ARG for non-positive dims, NULL
+ * pointers or an unknown bc; the launch is asynchronous and reads no other memory.
  */
-int ddg_stencil_assemble(const int32_t dims[3], const double* theta_dev, double* val_dev,
+int ddg_stencil_assemble(const int32_t dims[3], const double* theta_dev, int32_t bc, double* val_dev,
                          void* stream);
 
 /*
  * Per-cell gradient dL/dtheta_c = -kappa_c * lam^T (dA/dkappa_c) u
- * (adjoint identity for L(u(theta)) with A lam = dL/du).
- * theta_dev, u_dev, lam_dev, grad_dev: device [ncell].
+ * (adjoint identity for L(u(theta)) with A lam = dL/du), for the operator
+ * ddg_stencil_assemble builds with the same bc.
+ * theta_dev, u_dev, lam_dev, grad_dev: device [ncell].  Errors as ddg_stencil_assemble.
  */
 int ddg_stencil_coeff_grad(const int32_t dims[3], const double* theta_dev, const double* u_dev,
-                           const double* lam_dev, double* grad_dev, void* stream);
+                           const double* lam_dev, int32_t bc, double* grad_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -23,13 +23,16 @@ EXPORT_COLOURS, EXPORT_SET_PTR, EXPORT_SET_IDX, EXPORT_KCOUNTS, EXPORT_A0, EXPOR
 
 
 SCHEDULE = {"auto": 0, "colours": 1, "queue": 2}
+BC = {"dirichlet": 0, "x0": 1}
+CG_VARIANT = {"fr": 0, "pr": 1}
 
 
 class Options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
         ("rank_tol", C.c_double), ("tile", C.c_int32), ("block_target", C.c_int32),
-        ("check_every", C.c_int32), ("schedule", C.c_int32), ("stream", C.c_void_p),
+        ("check_every", C.c_int32), ("schedule", C.c_int32), ("cg_variant", C.c_int32),
+        ("stream", C.c_void_p),
     ]
 
 
@@ -40,12 +43,21 @@ class Info(C.Structure):
         ("n_parts", C.c_int32), ("n_blocks", C.c_int32), ("setup_ms", C.c_double),
         ("solve_ms", C.c_double), ("factor_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
         ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("schedule", C.c_int32),
+        ("envelope_elems", C.c_int64), ("set_rows", C.c_int64), ("nbhd_rows", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
         d["status_name"] = STATUS.get(self.status, str(self.status))
         return d
+
+
+class CgReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("iter_bound", C.c_int32), ("frac_iters", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("kappa", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Problem(C.Structure):
@@ -87,17 +99,21 @@ _SIGS = [
     ("ddg_apply_precond_stages", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("ddg_spmv", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ddg_get_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    ("ddg_cg_history", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.POINTER(C.c_int32)]),
+    ("ddg_cg_report_get", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(CgReport)]),
     ("ddg_export", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     ("ddg_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
     ("ddg_profile_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), C.c_int32]),
+    ("ddg_profile_read_idle", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("ddg_analyze", C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_int32, C.c_int32, C.POINTER(Options)]),
     ("ddg_destroy", None, [C.c_void_p]),
     ("ddg_last_error", C.c_char_p, []),
-    ("ddg_stencil_assemble", C.c_int, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ddg_stencil_assemble", C.c_int, [C.POINTER(C.c_int32), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("ddg_stencil_coeff_grad", C.c_int, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p,
-                                         C.c_void_p, C.c_void_p]),
+                                         C.c_int32, C.c_void_p, C.c_void_p]),
 ]
 
 SYMBOLS = [s[0] for s in _SIGS]

@@ -30,13 +30,14 @@ class DiffusionSolver:
 
     def __init__(self, dims, F: np.ndarray, part: np.ndarray, n_parts: int, overlap: int,
                  theta0: torch.Tensor, precision: str = "fp64", rtol: float = 1e-10,
-                 max_iter: int = 1000, **kw):
+                 max_iter: int = 1000, bc: str = "dirichlet", **kw):
         self.dims = tuple(int(d) for d in dims)
+        self.bc = bc
         self.n = int(np.prod(self.dims))
         self.row_ptr, self.col_idx = cc_pattern(self.dims)
         self.nnz = int(self.row_ptr[-1])
         val = torch.empty(self.nnz, dtype=torch.float64, device=theta0.device)
-        stencil_assemble(self.dims, theta0.contiguous(), val)
+        stencil_assemble(self.dims, theta0.contiguous(), val, bc=bc)
         torch.cuda.current_stream().synchronize()
         self.solver = DDGSolver(self.n, self.row_ptr, self.col_idx, val.cpu().numpy(), F, part, n_parts,
                                 overlap, precision=precision, rtol=rtol, max_iter=max_iter, **kw)
@@ -45,7 +46,7 @@ class DiffusionSolver:
         self.last_info = {}
 
     def refactor(self, theta: torch.Tensor):
-        stencil_assemble(self.dims, theta, self.val)
+        stencil_assemble(self.dims, theta, self.val, bc=self.bc)
         self.solver.refactor(self.val)
         self.theta = theta.detach().clone()
 
@@ -60,7 +61,7 @@ class DiffusionSolver:
         return u
 
     def coeff_grad(self, theta, u, lam):
-        return stencil_coeff_grad(self.dims, theta, u, lam)
+        return stencil_coeff_grad(self.dims, theta, u, lam, bc=self.bc)
 
 
 class DDGSolveFunction(torch.autograd.Function):

@@ -59,6 +59,37 @@ void check_values(int64_t n, const int64_t* rp, const int32_t* ci, const double*
   }
 }
 
+// Envelope of each local matrix in its local order: per local row j, the
+// columns from its first stored lower entry to j (the storage of a banded or
+// envelope Cholesky factor, where the fill stays).  Also the rows of every
+// expanded set with its one-ring of neighbours in the graph of A.
+void count_envelope(Handle& h, const int64_t* rp, const int32_t* ci) {
+  const Symbolic& S = h.S;
+  std::vector<int32_t> loc((size_t)S.n, -1), stamp((size_t)S.n, -1);
+  int64_t env = 0, nbhd = 0;
+  for (int32_t i = 0; i < S.n_parts; ++i) {
+    const int64_t r0 = S.set_ptr[i], r1 = S.set_ptr[i + 1];
+    for (int64_t t = r0; t < r1; ++t) loc[S.set_idx[t]] = (int32_t)(t - r0);
+    for (int64_t t = r0; t < r1; ++t) {
+      const int32_t g = S.set_idx[t], j = (int32_t)(t - r0);
+      int32_t first = j;
+      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+        const int32_t l = loc[ci[e]];
+        if (l >= 0 && l < first) first = l;
+        if (stamp[ci[e]] != i) {
+          stamp[ci[e]] = i;
+          ++nbhd;
+        }
+      }
+      env += j - first + 1;
+    }
+    for (int64_t t = r0; t < r1; ++t) loc[S.set_idx[t]] = -1;
+  }
+  h.info.envelope_elems = env;
+  h.info.set_rows = S.set_ptr[S.n_parts];
+  h.info.nbhd_rows = nbhd;
+}
+
 // Algorithmic HBM bytes of one local-solve kernel launch per colour: factor
 // tiles read once per substitution (every level twice, the middle level once),
 // the couplings (ELL slots or sliced entries), and per local row the residual
@@ -66,16 +97,22 @@ void check_values(int64_t n, const int64_t* rp, const int32_t* ci, const double*
 // local-residual kernel that precedes it is counted separately (residual_bytes):
 // set index, r, residual write, and for colours that start from a non-zero e the
 // row pointers, the CSR rows and one read of e per entry.
-void account_bytes(Handle& h, const int64_t* rp) {
+void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
   const Symbolic& S = h.S;
   const int es = storage_size(h.opt.precision);
   const int32_t C = S.n_colours;
   h.colour_bytes.assign(2 * C, 0);
+  h.colour_bytes_sys.assign((size_t)h.nb * 2 * C, 0);
+  h.flow_bytes_sys.assign((size_t)h.nb * 2, 0);
+  std::vector<int32_t> sys_of(S.n_parts, 0);
+  for (int32_t b = 0; b < h.nb; ++b)
+    for (int32_t i = h.sub_off[b]; i < h.sub_off[b + 1]; ++i) sys_of[i] = b;
   int64_t resid = 0, resid0 = 0, flow0 = 0, flow1 = 0;
   for (int32_t c = 0; c < C; ++c) {
     int64_t bytes = 0;
     for (int32_t q = S.colour_ptr[c]; q < S.colour_ptr[c + 1]; ++q) {
       const int32_t i = S.colour_subs[q];
+      const int64_t before = bytes, f0 = flow0, f1 = flow1;
       int64_t fb = 0;
       const int32_t K = S.sub_blk_ptr[i + 1] - S.sub_blk_ptr[i];
       for (int32_t k = 0; k < K; ++k) {
@@ -103,10 +140,16 @@ void account_bytes(Handle& h, const int64_t* rp) {
       const int64_t own = fb + cpl + ni * (4 + 16);
       flow1 += own + ni * (4 + 8 + 16 + 8) + nnz_rows * 12;
       flow0 += own + (c == 0 ? ni * (4 + 8) : ni * (4 + 8 + 16 + 8) + nnz_rows * 12);
+      const size_t b = (size_t)sys_of[i];
+      h.colour_bytes_sys[b * 2 * C + c] += bytes - before;
+      h.colour_bytes_sys[b * 2 * C + C + c] += bytes - before;
+      h.flow_bytes_sys[b * 2] += flow0 - f0;
+      h.flow_bytes_sys[b * 2 + 1] += flow1 - f1;
     }
     h.colour_bytes[c] = bytes;
     h.colour_bytes[C + c] = bytes;
   }
+  count_envelope(h, rp, ci);
   h.residual_bytes = resid;
   h.flow_bytes[0] = flow0;
   h.flow_bytes[1] = flow1;
@@ -145,6 +188,11 @@ void check_err_flag(Handle& h, const char* what) {
     else m += "local pivot not positive in subdomain " + std::to_string(e[1]) + " block " + std::to_string(e[2]) +
               " row " + std::to_string(e[3]);
     DDG_HIP(hipMemsetAsync(h.err_flag.p, 0, sizeof(e), h.stream));
+    if (h.twisted_ok) {
+      // a partner that arrived after its handoff wait gave up has raised its flag:
+      // clear every flag so that the next launch's readers wait for fresh data
+      DDG_HIP(hipMemsetAsync(h.flags.p, 0, (size_t)h.S.n_parts * 2 * sizeof(int32_t), h.stream));
+    }
     if (h.flow_ok) {
       // the task queue may be out of step after a failed sweep: start it afresh
       DDG_HIP(hipMemsetAsync(h.flow_done.p, 0, (size_t)h.S.n_parts * sizeof(int32_t), h.stream));
@@ -192,18 +240,72 @@ void numeric_setup(Handle& h) {
   check_err_flag(h, "numeric factorisation");
 }
 
+// Durations of the profiled local-solve launches.  A launch enqueued by CG
+// iteration t ran for system b unless b had already stopped after at most t
+// iterations (its kernels then return at once); launches outside a solve (tag
+// -1) ran for every system.  Only the bytes of the systems a launch ran for are
+// credited, and launches that ran for none are kept apart as idle.  The host
+// mirror of the CG states must be current (it is after every convergence check).
 void flush_profile(Handle& h) {
   if (h.pending.empty()) return;
   DDG_HIP(hipStreamSynchronize(h.stream));
-  for (auto& pb : h.pending) {
+  const int32_t C = h.S.n_colours;
+  for (auto& pl : h.pending) {
     float ms = 0.f;
-    DDG_HIP(hipEventElapsedTime(&ms, h.ev_pool[pb.first], h.ev_pool[pb.first + 1]));
-    h.prof_ms += ms;
-    h.prof_launches += 1;
-    h.prof_bytes += pb.second;
+    DDG_HIP(hipEventElapsedTime(&ms, h.ev_pool[pl.ev], h.ev_pool[pl.ev + 1]));
+    int64_t bytes = 0;
+    for (int32_t b = 0; b < h.nb; ++b) {
+      const CgState& st = h.h_state[b];
+      const bool ran = pl.tag < 0 || !st.done || st.iters > pl.tag;
+      if (!ran) continue;
+      bytes += pl.what < 2 * C ? h.colour_bytes_sys[(size_t)b * 2 * C + pl.what]
+                               : h.flow_bytes_sys[(size_t)b * 2 + (pl.what - 2 * C)];
+    }
+    if (bytes > 0) {
+      h.prof_ms += ms;
+      h.prof_launches += 1;
+      h.prof_bytes += bytes;
+    } else {
+      h.prof_idle_ms += ms;
+      h.prof_idle_launches += 1;
+    }
   }
   h.pending.clear();
   h.ev_used = 0;
+}
+
+// Smallest and largest eigenvalue of the symmetric tridiagonal matrix (d, e)
+// (e[j] couples rows j and j+1) by bisection on the Sturm count.
+void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double& lo, double& hi) {
+  const size_t m = d.size();
+  double gl = d[0], gu = d[0];
+  for (size_t j = 0; j < m; ++j) {
+    const double r = (j > 0 ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < m ? std::fabs(e[j]) : 0.0);
+    gl = std::min(gl, d[j] - r);
+    gu = std::max(gu, d[j] + r);
+  }
+  auto below = [&](double x) {  // eigenvalues < x
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0) ++cnt;
+    for (size_t j = 1; j < m; ++j) {
+      if (q == 0.0) q = 1e-300;
+      q = d[j] - x - e[j - 1] * e[j - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  auto kth = [&](int k) {  // smallest x with below(x) >= k
+    double a = gl, b = gu;
+    for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+      const double mid = 0.5 * (a + b);
+      if (below(mid) >= k) b = mid;
+      else a = mid;
+    }
+    return 0.5 * (a + b);
+  };
+  lo = kth(1);
+  hi = kth((int)m);
 }
 
 // Setup of one handle holding nb independent systems: system b owns rows
@@ -218,6 +320,8 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   DDG_REQUIRE(h->opt.precision >= DDG_FP64 && h->opt.precision <= DDG_MIXED_BF16, DDG_ERR_INVALID_ARG,
               "unknown precision");
   DDG_REQUIRE(h->opt.rtol >= 0.0 && h->opt.rank_tol >= 0.0, DDG_ERR_INVALID_ARG, "negative tolerance");
+  DDG_REQUIRE(h->opt.cg_variant == DDG_CG_FLETCHER_REEVES || h->opt.cg_variant == DDG_CG_POLAK_RIBIERE,
+              DDG_ERR_INVALID_ARG, "cg_variant must be a ddg_cg_variant value");
   h->stream = static_cast<hipStream_t>(h->opt.stream);
   h->k = k;
   h->nb = (int32_t)seg_off.size() - 1;
@@ -416,7 +520,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   DDG_HIP(hipHostMalloc((void**)&h->h_state, (size_t)h->nb * sizeof(CgState), hipHostMallocDefault));
   h->sys_info.assign(h->nb, ddg_info{});
   numeric_setup(*h);
-  account_bytes(*h, row_ptr);
+  account_bytes(*h, row_ptr, col_idx);
   h->info.n_coarse = (int32_t)h->nc;
   h->info.n_colours = S.n_colours;
   h->info.n_parts = n_parts;
@@ -640,6 +744,8 @@ void ddg_default_options(ddg_options* opt) {
   opt->tile = 0;
   opt->block_target = 0;
   opt->check_every = 4;
+  opt->schedule = DDG_SCHEDULE_AUTO;
+  opt->cg_variant = DDG_CG_FLETCHER_REEVES;
   opt->stream = nullptr;
 }
 
@@ -709,6 +815,7 @@ int ddg_analyze(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_
     h->info.n_blocks = (int32_t)h->S.blk_size.size();
     h->info.factor_bytes = h->S.fac_elems * storage_size(h->opt.precision);
     h->info.tile = h->S.tile;
+    count_envelope(*h, row_ptr, col_idx);
     hp = h.release();
   });
   if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
@@ -738,6 +845,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     double* z = h->z.as<double>();
     const size_t sb = (size_t)h->nb * sizeof(CgState);
     launch_cg_init(*h, f_dev, x, s);
+    h->cur_tag = 0;
     launch_precond(*h, h->r.as<double>(), z, -1, true, s);
     launch_cg_start(*h, s);
     const int chunk = h->opt.check_every;
@@ -745,9 +853,11 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     while (true) {
       for (int t = 0; t < chunk; ++t) {
         launch_cg_step_a(*h, x, s);
+        h->cur_tag = enqueued + t + 1;  // the preconditioner of iteration enqueued + t + 1
         launch_precond(*h, h->r.as<double>(), z, -1, true, s);
         launch_cg_step_b(*h, s);
       }
+      h->cur_tag = -1;
       enqueued += chunk;
       DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sb, hipMemcpyDeviceToHost, s));
       DDG_HIP(hipStreamSynchronize(s));
@@ -759,6 +869,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     }
     launch_true_residual(*h, f_dev, x, s);
     DDG_HIP(hipEventRecord(e1, s));
+    h->solved = true;
     check_err_flag(*h, "solve");
     DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sb, hipMemcpyDeviceToHost, s));
     DDG_HIP(hipStreamSynchronize(s));
@@ -850,6 +961,76 @@ int ddg_spmv(ddg_handle hd, const double* x_dev, double* y_dev) {
   });
 }
 
+int ddg_cg_history(ddg_handle hd, int32_t system, double* alpha, double* beta, double* rel_res, int32_t cap,
+                   int32_t* count) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && !h->host_only, DDG_ERR_INVALID_ARG, "null or analysis-only handle");
+    DDG_REQUIRE(system >= 0 && system < h->nb, DDG_ERR_INVALID_ARG, "system out of range");
+    DDG_REQUIRE(h->solved, DDG_ERR_INVALID_ARG, "no solve has run on this handle");
+    DDG_REQUIRE(cap >= 0, DDG_ERR_INVALID_ARG, "negative capacity");
+    const int64_t M = (int64_t)h->opt.max_iter + 1;
+    std::vector<double> hv((size_t)(3 * M));
+    DDG_HIP(hipMemcpyAsync(hv.data(), h->hist.as<double>() + (int64_t)system * 3 * M, hv.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    DDG_HIP(hipStreamSynchronize(h->stream));
+    const CgState& st = h->h_state[system];
+    const int32_t it = st.iters;
+    if (count) *count = it;
+    const double f2 = hv[2 * M];
+    for (int32_t j = 0; j < cap; ++j) {
+      if (alpha && j < it) alpha[j] = hv[j];
+      if (beta && j + 1 < it) beta[j] = hv[M + j];
+      if (rel_res && j <= it) rel_res[j] = f2 > 0 ? std::sqrt(hv[2 * M + j] / f2) : 0.0;
+    }
+  });
+}
+
+int ddg_cg_report_get(ddg_handle hd, int32_t system, ddg_cg_report* out) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(out, DDG_ERR_INVALID_ARG, "null argument");
+    int32_t it = 0;
+    const int32_t cap = h ? h->opt.max_iter + 1 : 0;
+    std::vector<double> a((size_t)std::max(cap, 1)), b((size_t)std::max(cap, 1)), r((size_t)std::max(cap, 1));
+    const int rc = ddg_cg_history(hd, system, a.data(), b.data(), r.data(), cap, &it);
+    if (rc != DDG_OK) throw Error{rc, ddg_last_error()};
+    const double tol = h->opt.rtol;
+    ddg_cg_report rep{};
+    rep.iters = it;
+    rep.frac_iters = std::nan("");
+    for (int32_t j = 0; j <= it; ++j) {
+      if (r[j] <= tol) {
+        if (j == 0) {
+          rep.frac_iters = 0.0;
+        } else {
+          const double la = std::log(r[j - 1]), lb = std::log(r[j]);
+          rep.frac_iters = (j - 1) + (std::log(tol) - la) / (lb - la);
+        }
+        break;
+      }
+    }
+    rep.lambda_min = rep.lambda_max = rep.kappa = std::nan("");
+    rep.iter_bound = -1;
+    if (it > 0) {
+      std::vector<double> d((size_t)it), e((size_t)std::max(it - 1, 1));
+      for (int32_t j = 0; j < it; ++j) {
+        d[j] = 1.0 / a[j] + (j > 0 ? b[j - 1] / a[j - 1] : 0.0);
+        if (j + 1 < it) e[j] = std::sqrt(b[j]) / a[j];
+      }
+      tridiag_extremes(d, e, rep.lambda_min, rep.lambda_max);
+      rep.kappa = rep.lambda_max / rep.lambda_min;
+      if (rep.kappa <= 1.0) {
+        rep.iter_bound = tol >= 2.0 ? 0 : 1;
+      } else {
+        const double q = (std::sqrt(rep.kappa) - 1.0) / (std::sqrt(rep.kappa) + 1.0);
+        rep.iter_bound = std::max(0, (int32_t)std::ceil(std::log(tol / 2.0) / std::log(q)));
+      }
+    }
+    *out = rep;
+  });
+}
+
 int ddg_get_info(ddg_handle hd, ddg_info* info) {
   return guarded([&]() {
     Handle* h = H(hd);
@@ -926,7 +1107,19 @@ int ddg_profile_read(ddg_handle hd, double* ms, int64_t* launches, int64_t* byte
       h->prof_ms = 0.0;
       h->prof_launches = 0;
       h->prof_bytes = 0;
+      h->prof_idle_ms = 0.0;
+      h->prof_idle_launches = 0;
     }
+  });
+}
+
+int ddg_profile_read_idle(ddg_handle hd, double* ms, int64_t* launches) {
+  return guarded([&]() {
+    Handle* h = H(hd);
+    DDG_REQUIRE(h && !h->host_only, DDG_ERR_INVALID_ARG, "null or analysis-only handle");
+    flush_profile(*h);
+    if (ms) *ms = h->prof_idle_ms;
+    if (launches) *launches = h->prof_idle_launches;
   });
 }
 

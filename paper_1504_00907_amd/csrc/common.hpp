@@ -244,6 +244,8 @@ struct Handle {
 
   // CG workspace
   DevBuf r, p, q, z, part_sums, cstate;
+  DevBuf hist;            // per system: alpha, beta, ||r||^2 histories (max_iter + 1 each)
+  bool solved = false;    // a solve has run (the history is valid)
   DevBuf cy, cpart;       // coarse rhs/solution (nc_pad each) and GEMV partials
   DevBuf pinned_state;    // unused placeholder
   CgState* h_state = nullptr;   // pinned host mirror (nb entries)
@@ -254,14 +256,28 @@ struct Handle {
   std::vector<ddg_info> sys_info;      // per system, last solve
   int32_t clock_khz = 100000;          // device real-time counter rate
   std::vector<int64_t> colour_bytes;   // algorithmic bytes of one local-solve launch per colour
+  std::vector<int64_t> colour_bytes_sys;  // the same per system: [b * 2C + c]
+  std::vector<int64_t> flow_bytes_sys;    // per system and sweep direction: [b * 2 + dir]
   int64_t residual_bytes = 0;          // all colours' local-residual kernels (non-zero e)
 
   // profiling
   bool profiling = false;
   double prof_ms = 0.0;
   int64_t prof_launches = 0, prof_bytes = 0;
+  double prof_idle_ms = 0.0;       // launches that ran for no system (every one had stopped)
+  int64_t prof_idle_launches = 0;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, int64_t>> pending;  // (event pair index, bytes)
+  // profiled local-solve launches awaiting their durations: the event pair, the
+  // launch (colour c, or 2C + dir for a task-queue sweep direction) and the CG
+  // iteration that enqueued it (-1 outside a solve).  Bytes are credited only for
+  // the systems that were still iterating when it ran.
+  struct PendingLaunch {
+    int ev;
+    int32_t what;
+    int32_t tag;
+  };
+  std::vector<PendingLaunch> pending;
+  int32_t cur_tag = -1;   // CG iteration of the launches being enqueued
   // when set, the next local-solve launch carries this event pair on its own dispatch
   // (start and end of the kernel itself, not markers queued around it)
   mutable hipEvent_t kev0 = nullptr, kev1 = nullptr;

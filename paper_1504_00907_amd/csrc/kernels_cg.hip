@@ -70,13 +70,26 @@ __global__ void k_cg_init(SegMap m, const double* __restrict__ f, double* __rest
 
 __device__ inline uint64_t device_clock() { return wall_clock64(); }
 
+// Per-system history of the CG coefficients and residuals (for the Lanczos
+// estimates and the fractional iteration count of Section 7): system b owns
+// hist[b * 3 * (max_iter + 1) ...], as alpha[j] (j = 0..iters-1), then
+// beta[j] (j = 0..iters-2), then ||r_j||^2 (j = 0..iters).
+struct Hist {
+  double* base;
+  int64_t stride;  // max_iter + 1
+  __device__ double* alpha(int b) const { return base + (int64_t)b * 3 * stride; }
+  __device__ double* beta(int b) const { return base + ((int64_t)b * 3 + 1) * stride; }
+  __device__ double* rr(int b) const { return base + ((int64_t)b * 3 + 2) * stride; }
+};
+
 __global__ void k_cg_init_scalar(CgState* stb, SegMap m, const double* __restrict__ part, double rtol,
-                                 int max_iter) {
+                                 int max_iter, Hist hist) {
   __shared__ double red[kThreads / 64];
   const int b = blockIdx.x;
   CgState* st = stb + b;
   double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
   if (threadIdx.x == 0) {
+    hist.rr(b)[0] = s;
     st->iters = 0;
     st->max_iter = max_iter;
     st->status = DDG_OK;
@@ -121,12 +134,18 @@ __device__ inline void stop(CgState* st, int32_t status) {
   st->t_done = device_clock();
 }
 
-__global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ part, int first) {
+// rho' = r^T z from the partials; beta = rho' / rho (Fletcher-Reeves), or with
+// the z^T q partials (part2 non-null) the Polak-Ribiere value
+// z^T (r - r_prev) / rho = -alpha z^T q / rho, since r - r_prev = -alpha q.
+__global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ part,
+                             const double* __restrict__ part2, int first, Hist hist) {
   const int b = blockIdx.x;
   CgState* st = stb + b;
   if (st->done) return;
   __shared__ double red[kThreads / 64];
   double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
+  double zq = 0.0;
+  if (part2) zq = sum_partials<kThreads>(part2 + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
   if (threadIdx.x == 0) {
     if (!(s > 0.0) || !isfinite(s)) {
       stop(st, DDG_ERR_BREAKDOWN);
@@ -135,8 +154,14 @@ __global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ 
     if (first) {
       st->rho = s;
     } else {
-      st->beta = s / st->rho;
+      const double beta = part2 ? -st->alpha * zq / st->rho : s / st->rho;
+      if (!isfinite(beta)) {
+        stop(st, DDG_ERR_BREAKDOWN);
+        return;
+      }
+      st->beta = beta;
       st->rho = s;
+      hist.beta(b)[st->iters - 1] = beta;
     }
   }
 }
@@ -163,7 +188,7 @@ __global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_alpha_scalar(CgState* stb, SegMap m, const double* __restrict__ part) {
+__global__ void k_alpha_scalar(CgState* stb, SegMap m, const double* __restrict__ part, Hist hist) {
   const int b = blockIdx.x;
   CgState* st = stb + b;
   if (st->done) return;
@@ -176,6 +201,7 @@ __global__ void k_alpha_scalar(CgState* stb, SegMap m, const double* __restrict_
       return;
     }
     st->alpha = st->rho / s;
+    hist.alpha(b)[st->iters] = st->alpha;
   }
 }
 
@@ -199,7 +225,7 @@ __global__ void k_axpy2_dot(const CgState* stb, SegMap m, double* __restrict__ x
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void k_conv_scalar(CgState* stb, SegMap m, const double* __restrict__ part) {
+__global__ void k_conv_scalar(CgState* stb, SegMap m, const double* __restrict__ part, Hist hist) {
   const int b = blockIdx.x;
   CgState* st = stb + b;
   if (st->done) return;
@@ -208,6 +234,7 @@ __global__ void k_conv_scalar(CgState* stb, SegMap m, const double* __restrict__
   if (threadIdx.x == 0) {
     st->rr = s;
     st->iters += 1;
+    hist.rr(b)[st->iters] = s;
     if (!isfinite(s)) stop(st, DDG_ERR_BREAKDOWN);
     else if (s <= st->tol2) stop(st, DDG_OK);
     else if (st->iters >= st->max_iter) stop(st, DDG_ERR_NO_CONVERGENCE);
@@ -224,6 +251,26 @@ __global__ void k_dot(const CgState* stb, SegMap m, const double* __restrict__ a
   for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) acc += a[i] * b[i];
   double s = block_sum<kThreads>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// partials r.z and z.q in one pass (Polak-Ribiere direction update)
+__global__ void k_dot2(const CgState* stb, SegMap m, const double* __restrict__ r, const double* __restrict__ z,
+                       const double* __restrict__ q, double* __restrict__ part, double* __restrict__ part2) {
+  if (stb[m.seg[blockIdx.x]].done) return;
+  __shared__ double red[kThreads / 64];
+  double a1 = 0.0, a2 = 0.0;
+  const int64_t hi = m.hi[blockIdx.x];
+  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
+    const double zi = z[i];
+    a1 += r[i] * zi;
+    a2 += zi * q[i];
+  }
+  double s1 = block_sum<kThreads>(a1, red);
+  double s2 = block_sum<kThreads>(a2, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part2[blockIdx.x] = s2;
+  }
 }
 
 // p = z + beta p
@@ -268,6 +315,8 @@ SegMap segmap(const Handle& h) {
   return SegMap{h.wg_seg.as<int32_t>(), h.wg_lo.as<int64_t>(), h.wg_hi.as<int64_t>(), h.seg_wg_ptr_d.as<int32_t>()};
 }
 
+Hist history(const Handle& h) { return Hist{h.hist.as<double>(), (int64_t)h.opt.max_iter + 1}; }
+
 }  // namespace
 
 // Row ranges of the reduction workgroups: each system is cut into at most 1024
@@ -295,7 +344,9 @@ void build_cg_map(Handle& h, hipStream_t s) {
   h.wg_lo.upload(lo, s);
   h.wg_hi.upload(hi, s);
   h.seg_wg_ptr_d.upload(h.seg_wg_ptr, s);
-  h.part_sums.alloc((size_t)h.n_partials * sizeof(double));
+  // two partial arrays: the Polak-Ribiere update reduces r.z and z.q together
+  h.part_sums.alloc((size_t)2 * h.n_partials * sizeof(double));
+  h.hist.alloc((size_t)h.nb * 3 * ((size_t)h.opt.max_iter + 1) * sizeof(double));
 }
 
 void launch_fill(double* x, double v, int64_t n, hipStream_t s) {
@@ -319,7 +370,7 @@ void launch_cg_init(Handle& h, const double* f, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, dim3(h.n_partials), dim3(kThreads), 0, s, m, f, x, h.r.as<double>(),
                      h.part_sums.as<double>());
   hipLaunchKernelGGL(k_cg_init_scalar, dim3(h.nb), dim3(kThreads), 0, s, h.cstate.as<CgState>(), m,
-                     h.part_sums.as<double>(), h.opt.rtol, h.opt.max_iter);
+                     h.part_sums.as<double>(), h.opt.rtol, h.opt.max_iter, history(h));
 }
 
 void launch_cg_start(Handle& h, hipStream_t s) {
@@ -327,7 +378,8 @@ void launch_cg_start(Handle& h, hipStream_t s) {
   CgState* st = h.cstate.as<CgState>();
   hipLaunchKernelGGL(k_copy_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.r.as<double>(),
                      h.z.as<double>(), h.p.as<double>(), h.part_sums.as<double>());
-  hipLaunchKernelGGL(k_rho_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), 1);
+  hipLaunchKernelGGL(k_rho_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(),
+                     (const double*)nullptr, 1, history(h));
 }
 
 void launch_cg_step_a(Handle& h, double* x, hipStream_t s) {
@@ -339,18 +391,27 @@ void launch_cg_step_a(Handle& h, double* x, hipStream_t s) {
                        h.col.as<int32_t>(), h.val.as<double>(), h.p.as<double>(), h.q.as<double>(),
                        h.part_sums.as<double>());
   });
-  hipLaunchKernelGGL(k_alpha_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_alpha_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), history(h));
   hipLaunchKernelGGL(k_axpy2_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, x, h.r.as<double>(),
                      h.p.as<double>(), h.q.as<double>(), h.part_sums.as<double>());
-  hipLaunchKernelGGL(k_conv_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>());
+  hipLaunchKernelGGL(k_conv_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), history(h));
 }
 
 void launch_cg_step_b(Handle& h, hipStream_t s) {
   const SegMap m = segmap(h);
   CgState* st = h.cstate.as<CgState>();
-  hipLaunchKernelGGL(k_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.r.as<double>(), h.z.as<double>(),
-                     h.part_sums.as<double>());
-  hipLaunchKernelGGL(k_rho_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), 0);
+  double* part = h.part_sums.as<double>();
+  double* part2 = nullptr;
+  if (h.opt.cg_variant == DDG_CG_POLAK_RIBIERE) {
+    part2 = part + h.n_partials;
+    hipLaunchKernelGGL(k_dot2, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.r.as<double>(), h.z.as<double>(),
+                       h.q.as<double>(), part, part2);
+  } else {
+    hipLaunchKernelGGL(k_dot, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.r.as<double>(), h.z.as<double>(),
+                       part);
+  }
+  hipLaunchKernelGGL(k_rho_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, part, (const double*)part2, 0,
+                     history(h));
   hipLaunchKernelGGL(k_xpby, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.z.as<double>(), h.p.as<double>());
 }
 

@@ -243,7 +243,7 @@ static void sweep_profiled(Handle& h, int c, const double* r, double* e, bool ez
     KernelEvents ke(h, h.ev_pool[idx], h.ev_pool[idx + 1]);
     launch_sweep(h, c, r, e, ez, st, s, false);
   }
-  h.pending.push_back({idx, ez ? h.colour_bytes[h.S.n_colours + c] : h.colour_bytes[c]});
+  h.pending.push_back({idx, ez ? h.S.n_colours + c : c, h.cur_tag});
 }
 
 // One persistent sweep direction; when profiling, its dispatch carries an event pair.
@@ -265,7 +265,7 @@ static void flow_profiled(Handle& h, int dir, const double* r, double* e, const 
     KernelEvents ke(h, h.ev_pool[idx], h.ev_pool[idx + 1]);
     launch_sweep_flow(h, dir, r, e, st, s);
   }
-  h.pending.push_back({idx, h.flow_bytes[dir]});
+  h.pending.push_back({idx, 2 * h.S.n_colours + dir, h.cur_tag});
 }
 
 void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded, hipStream_t s) {

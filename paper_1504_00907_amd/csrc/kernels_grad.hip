@@ -5,8 +5,10 @@
 // grid's own axes.
 //
 // Face between cells L and R: a = 2 kL kR / (kL + kR), entries -a off the
-// diagonal, +a on both diagonals; each boundary face adds 2 kc (zero-Dirichlet
-// ghost).  For L(u), A u = f, the adjoint lam (A lam = dL/du) gives
+// diagonal, +a on both diagonals; a boundary face with a zero-Dirichlet ghost
+// adds 2 kc.  Which boundary faces have one is the ddg_bc choice: all of them
+// (DDG_BC_DIRICHLET) or only those on x = 0 (DDG_BC_X0, the other faces
+// carrying no flux, as in the 3D Poisson problem of Section 7).  For L(u), A u = f, the adjoint lam (A lam = dL/du) gives
 //   dL/dtheta_c = -kappa_c * lam^T (dA/dkappa_c) u
 //              = -kappa_c [ sum_faces 2 k_o^2/(k_c+k_o)^2 (lam_c-lam_o)(u_c-u_o)
 //                           + sum_boundary_faces 2 lam_c u_c ].
@@ -18,7 +20,21 @@ namespace {
 
 struct Grid {
   int nx, ny, nz;
+  int bc;  // ddg_bc
 };
+
+// Boundary faces of a cell that carry a zero-Dirichlet ghost, in the order
+// z-1, y-1, x-1, x+1, y+1, z+1; only the grid's own axes have faces.
+__device__ inline void ghost_faces(const Grid& G, bool active[6]) {
+  const bool ay = G.ny > 1 || G.nz > 1, az = G.nz > 1;  // grid dimension: 3 if nz > 1, 2 if ny > 1
+  const bool all = G.bc == DDG_BC_DIRICHLET;
+  active[0] = az && all;
+  active[1] = ay && all;
+  active[2] = true;
+  active[3] = all;
+  active[4] = ay && all;
+  active[5] = az && all;
+}
 
 // Stored entries of all rows before cell (x, y, z) in sorted-column CSR order.
 __device__ inline int64_t entries_before(const Grid& G, int x, int y, int z) {
@@ -52,8 +68,8 @@ __global__ void k_assemble(Grid G, const double* __restrict__ theta, double* __r
   // order: z-1, y-1, x-1, x+1, y+1, z+1
   const int64_t nb[6] = {g - sz, g - sy, g - sx, g + sx, g + sy, g + sz};
   const bool in[6] = {z > 0, y > 0, x > 0, x < G.nx - 1, y < G.ny - 1, z < G.nz - 1};
-  const bool ay = G.ny > 1 || G.nz > 1, az = G.nz > 1;  // grid dimension: 3 if nz > 1, 2 if ny > 1
-  const bool active[6] = {az, ay, true, true, ay, az};
+  bool active[6];
+  ghost_faces(G, active);
   for (int d = 0; d < 6; ++d) {
     has[d] = in[d];
     off[d] = 0.0;
@@ -85,8 +101,8 @@ __global__ void k_coeff_grad(Grid G, const double* __restrict__ theta, const dou
   const int64_t sx = 1, sy = G.nx, sz = (int64_t)G.nx * G.ny;
   const int64_t nb[6] = {g - sz, g - sy, g - sx, g + sx, g + sy, g + sz};
   const bool in[6] = {z > 0, y > 0, x > 0, x < G.nx - 1, y < G.ny - 1, z < G.nz - 1};
-  const bool ay = G.ny > 1 || G.nz > 1, az = G.nz > 1;  // grid dimension: 3 if nz > 1, 2 if ny > 1
-  const bool active[6] = {az, ay, true, true, ay, az};
+  bool active[6];
+  ghost_faces(G, active);
   double acc = 0.0;
   for (int d = 0; d < 6; ++d) {
     if (in[d]) {
@@ -106,13 +122,14 @@ __global__ void k_coeff_grad(Grid G, const double* __restrict__ theta, const dou
 
 using namespace ddg;
 
-extern "C" int ddg_stencil_assemble(const int32_t dims[3], const double* theta_dev, double* val_dev,
+extern "C" int ddg_stencil_assemble(const int32_t dims[3], const double* theta_dev, int32_t bc, double* val_dev,
                                     void* stream) {
   try {
     clear_error();
     DDG_REQUIRE(dims && dims[0] > 0 && dims[1] > 0 && dims[2] > 0, DDG_ERR_INVALID_ARG, "bad grid dims");
     DDG_REQUIRE(theta_dev && val_dev, DDG_ERR_INVALID_ARG, "null pointer");
-    Grid G{dims[0], dims[1], dims[2]};
+    DDG_REQUIRE(bc == DDG_BC_DIRICHLET || bc == DDG_BC_X0, DDG_ERR_INVALID_ARG, "bc must be a ddg_bc value");
+    Grid G{dims[0], dims[1], dims[2], bc};
     const int64_t n = (int64_t)G.nx * G.ny * G.nz;
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, G,
                        theta_dev, val_dev);
@@ -125,12 +142,13 @@ extern "C" int ddg_stencil_assemble(const int32_t dims[3], const double* theta_d
 }
 
 extern "C" int ddg_stencil_coeff_grad(const int32_t dims[3], const double* theta_dev, const double* u_dev,
-                                      const double* lam_dev, double* grad_dev, void* stream) {
+                                      const double* lam_dev, int32_t bc, double* grad_dev, void* stream) {
   try {
     clear_error();
     DDG_REQUIRE(dims && dims[0] > 0 && dims[1] > 0 && dims[2] > 0, DDG_ERR_INVALID_ARG, "bad grid dims");
     DDG_REQUIRE(theta_dev && u_dev && lam_dev && grad_dev, DDG_ERR_INVALID_ARG, "null pointer");
-    Grid G{dims[0], dims[1], dims[2]};
+    DDG_REQUIRE(bc == DDG_BC_DIRICHLET || bc == DDG_BC_X0, DDG_ERR_INVALID_ARG, "bc must be a ddg_bc value");
+    Grid G{dims[0], dims[1], dims[2], bc};
     const int64_t n = (int64_t)G.nx * G.ny * G.nz;
     hipLaunchKernelGGL(k_coeff_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, G,
                        theta_dev, u_dev, lam_dev, grad_dev);

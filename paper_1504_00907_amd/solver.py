@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DDGError, Info, Options, Problem, TuneEntry, check
+from ._lib import CgReport, DDGError, Info, Options, Problem, TuneEntry, check
 
 
 def _ptr(a: np.ndarray):
@@ -28,7 +28,7 @@ def _dev(t: torch.Tensor, n: int, name: str) -> int:
 
 
 def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream,
-             schedule="auto"):
+             schedule="auto", cg_variant="fr"):
     opt = Options()
     lib.ddg_default_options(C.byref(opt))
     opt.precision = _lib.PRECISION[precision]
@@ -39,6 +39,7 @@ def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check
     opt.block_target = block_target
     opt.check_every = check_every
     opt.schedule = _lib.SCHEDULE[schedule]
+    opt.cg_variant = _lib.CG_VARIANT[cg_variant]
     opt.stream = C.c_void_p(stream.cuda_stream)
     return opt
 
@@ -49,10 +50,11 @@ class DDGSolver:
     def __init__(self, n: int, row_ptr, col_idx, val, F: Optional[np.ndarray], part, n_parts: int,
                  overlap: int, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000,
                  rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0, check_every: int = 4,
-                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto"):
+                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto", cg_variant: str = "fr"):
         lib = _lib.load()
         self._lib = lib
         self.n = int(n)
+        self.max_iter = int(max_iter)
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         vv = np.ascontiguousarray(val, dtype=np.float64)
@@ -71,7 +73,7 @@ class DDGSolver:
             raise ValueError("F must have n rows")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
-                       schedule)
+                       schedule, cg_variant)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
@@ -121,6 +123,21 @@ class DDGSolver:
         check(self._lib.ddg_get_info(self._h, C.byref(info)))
         return info.as_dict()
 
+    def cg_history(self, system: int = 0):
+        """(alpha, beta, rel_res) of the last solve (numpy float64 arrays)."""
+        cap = self.max_iter + 1
+        a, b, r = (np.zeros(cap) for _ in range(3))
+        cnt = C.c_int32()
+        check(self._lib.ddg_cg_history(self._h, int(system), _ptr(a), _ptr(b), _ptr(r), cap, C.byref(cnt)))
+        it = cnt.value
+        return a[:it], b[:max(it - 1, 0)], r[:it + 1]
+
+    def cg_report(self, system: int = 0) -> dict:
+        """Fractional iteration count, Lanczos extremes, condition estimate and CG bound of the last solve."""
+        rep = CgReport()
+        check(self._lib.ddg_cg_report_get(self._h, int(system), C.byref(rep)))
+        return rep.as_dict()
+
     def export(self, what: int) -> np.ndarray:
         need = C.c_int64()
         check(self._lib.ddg_export(self._h, what, None, 0, C.byref(need)))
@@ -157,9 +174,12 @@ class DDGSolver:
         check(self._lib.ddg_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self, reset: bool = True):
+        ims, ila = C.c_double(), C.c_int64()
+        check(self._lib.ddg_profile_read_idle(self._h, C.byref(ims), C.byref(ila)))
         ms, la, by = C.c_double(), C.c_int64(), C.c_int64()
         check(self._lib.ddg_profile_read(self._h, C.byref(ms), C.byref(la), C.byref(by), 1 if reset else 0))
-        return {"ms": ms.value, "launches": la.value, "bytes": by.value}
+        return {"ms": ms.value, "launches": la.value, "bytes": by.value, "idle_ms": ims.value,
+                "idle_launches": ila.value}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -233,13 +253,15 @@ class DDGBatchSolver(DDGSolver):
 
     def __init__(self, problems, overlap: int, precision: str = "fp64", rtol: float = 1e-8,
                  max_iter: int = 1000, rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0,
-                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto"):
+                 check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto",
+                 cg_variant: str = "fr"):
         lib = _lib.load()
         self._lib = lib
+        self.max_iter = int(max_iter)
         arr, keep = _problem_array(problems)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
-                       schedule)
+                       schedule, cg_variant)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup_batched(C.byref(h), len(problems), arr, int(overlap), C.byref(opt)))
@@ -269,17 +291,17 @@ class DDGBatchSolver(DDGSolver):
         return [x[self.row_off[b]:self.row_off[b + 1]] for b in range(self.nb)]
 
 
-def stencil_assemble(dims, theta: torch.Tensor, val: torch.Tensor, stream=None):
+def stencil_assemble(dims, theta: torch.Tensor, val: torch.Tensor, stream=None, bc: str = "dirichlet"):
     """CSR values of the cell-centred harmonic-mean operator for kappa = exp(theta)."""
     lib = _lib.load()
     d = (C.c_int32 * 3)(*[int(x) for x in dims])
     s = (stream or torch.cuda.current_stream()).cuda_stream
     n = int(np.prod(dims))
-    check(lib.ddg_stencil_assemble(d, _dev(theta, n, "theta"), val.data_ptr(), C.c_void_p(s)))
+    check(lib.ddg_stencil_assemble(d, _dev(theta, n, "theta"), _lib.BC[bc], val.data_ptr(), C.c_void_p(s)))
     return val
 
 
-def stencil_coeff_grad(dims, theta, u, lam, grad=None, stream=None):
+def stencil_coeff_grad(dims, theta, u, lam, grad=None, stream=None, bc: str = "dirichlet"):
     """Per-cell dL/dtheta = -kappa lam^T (dA/dkappa) u."""
     lib = _lib.load()
     n = int(np.prod(dims))
@@ -287,5 +309,5 @@ def stencil_coeff_grad(dims, theta, u, lam, grad=None, stream=None):
     d = (C.c_int32 * 3)(*[int(x) for x in dims])
     s = (stream or torch.cuda.current_stream()).cuda_stream
     check(lib.ddg_stencil_coeff_grad(d, _dev(theta, n, "theta"), _dev(u, n, "u"), _dev(lam, n, "lam"),
-                                     _dev(grad, n, "grad"), C.c_void_p(s)))
+                                     _lib.BC[bc], _dev(grad, n, "grad"), C.c_void_p(s)))
     return grad

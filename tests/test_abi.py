@@ -38,7 +38,7 @@ def test_default_options():
     o = _lib.Options()
     lib.ddg_default_options(C.byref(o))
     assert (o.precision, o.max_iter, o.rtol, o.rank_tol) == (0, 1000, 1e-8, 1e-10)
-    assert (o.tile, o.block_target, o.check_every, o.schedule) == (0, 0, 4, 0)
+    assert (o.tile, o.block_target, o.check_every, o.schedule, o.cg_variant) == (0, 0, 4, 0, 0)
 
 
 class Analysis:
@@ -122,6 +122,18 @@ def test_symbolic_matches_oracle(case):
             loc = idx[ptr[i]:ptr[i + 1]]          # local order of the factors
             Ai = As[loc][:, loc].tocoo()
             assert np.abs(lab[Ai.row] - lab[Ai.col]).max() <= 1
+        # envelope of every local matrix in the factors' local order, and the
+        # expanded sets with their one-ring, counted directly
+        env = nb = 0
+        for i in range(n_parts):
+            loc = idx[ptr[i]:ptr[i + 1]]
+            Ai = As[loc][:, loc].tocsr()
+            for j in range(len(loc)):
+                cols = Ai.indices[Ai.indptr[j]:Ai.indptr[j + 1]]
+                env += j - min(cols.min(), j) + 1
+            nb += np.union1d(loc, As[loc].indices).size
+        assert info.envelope_elems == env and info.nbhd_rows == nb
+        assert info.set_rows == sum(len(st) for st in o.sets)
     finally:
         an.close()
 

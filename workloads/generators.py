@@ -156,13 +156,17 @@ def laplace5_nodes(m: int) -> CSR:
     return CSR.from_scipy(A)
 
 
-def diffusion_cc(kappa: np.ndarray) -> CSR:
+def diffusion_cc(kappa: np.ndarray, bc: str = "dirichlet") -> CSR:
     """Cell-centred finite-volume diffusion operator with harmonic-mean faces.
 
     ``kappa`` has shape (ny, nx) or (nz, ny, nx).  Interior face between cells
-    L and R carries a_f = 2 kL kR / (kL + kR); each boundary face of cell c is
-    a zero-Dirichlet ghost face with coefficient 2 kc.  Unit grid spacing.
+    L and R carries a_f = 2 kL kR / (kL + kR).  With ``bc="dirichlet"`` each
+    boundary face of cell c is a zero-Dirichlet ghost face with coefficient
+    2 kc; with ``bc="x0"`` only the faces on x = 0 are (the paper's problem A:
+    one Dirichlet face, Neumann elsewhere).  Unit grid spacing.
     """
+    if bc not in ("dirichlet", "x0"):
+        raise ValueError("bc must be 'dirichlet' or 'x0'")
     kappa = np.asarray(kappa, dtype=np.float64)
     shape = kappa.shape
     n = kappa.size
@@ -183,8 +187,10 @@ def diffusion_cc(kappa: np.ndarray) -> CSR:
         hi = [slice(None)] * kappa.ndim
         lo[ax] = 0
         hi[ax] = m - 1
-        diag[tuple(lo)] += 2.0 * kappa[tuple(lo)]
-        diag[tuple(hi)] += 2.0 * kappa[tuple(hi)]
+        if bc == "dirichlet" or ax == kappa.ndim - 1:
+            diag[tuple(lo)] += 2.0 * kappa[tuple(lo)]
+        if bc == "dirichlet":
+            diag[tuple(hi)] += 2.0 * kappa[tuple(hi)]
     # CSR rows directly, columns ascending: minus-neighbours along axes 0..d-1
     # (largest stride first), the diagonal, then plus-neighbours along d-1..0
     d = kappa.ndim
@@ -328,7 +334,7 @@ def cfg1() -> Problem:
 
 def diffusion_problem(shape, boxes, overlap: int, p: int, cfg_id: int, rtol: float,
                       ell: float = 8.0, sigma: float = 1.0, kappa: Optional[np.ndarray] = None,
-                      stream: int = STREAM_KAPPA, name: str = "") -> Problem:
+                      stream: int = STREAM_KAPPA, name: str = "", bc: str = "dirichlet") -> Problem:
     """Cell-centred variable-coefficient diffusion on a box grid.
 
     kappa = exp(g) with g a GRF (``ell``, ``sigma``) unless ``kappa`` is given;
@@ -340,7 +346,7 @@ def diffusion_problem(shape, boxes, overlap: int, p: int, cfg_id: int, rtol: flo
             kappa = np.ones(shape)
         else:
             kappa = np.exp(grf(shape, ell, sigma, seed_rng(cfg_id, stream)))
-    A = diffusion_cc(kappa)
+    A = diffusion_cc(kappa, bc=bc)
     part = box_partition(shape, boxes)
     F = monomials(cell_coords(shape), p)
     n = int(np.prod(shape))
@@ -348,7 +354,7 @@ def diffusion_problem(shape, boxes, overlap: int, p: int, cfg_id: int, rtol: flo
     nparts = int(np.prod(boxes))
     return Problem(A=A, F=F, part=part, n_parts=nparts, overlap=overlap, f=f, rtol=rtol,
                    name=name or f"diffusion_{'x'.join(map(str, shape))}",
-                   meta={"grid": shape, "p": p, "kappa": kappa, "boxes": tuple(boxes)})
+                   meta={"grid": shape, "p": p, "kappa": kappa, "boxes": tuple(boxes), "bc": bc})
 
 
 def cfg2(side: int = 128, box: int = 16) -> Problem:
