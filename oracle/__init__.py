@@ -6,6 +6,6 @@ its Python binding) never imports, links or calls it, and it shares no code
 with that path: only the seeded input generators in ``workloads`` feed both.
 """
 
-from .ddg import (DDGOracle, OracleError, cg_iteration_bound, condition_estimate,  # noqa: F401
-                  fractional_iterations, lanczos_ritz, pcg)
+from .ddg import (DDGOracle, OracleError, ThreeLevelOracle, cg_iteration_bound,  # noqa: F401
+                  condition_estimate, fractional_iterations, lanczos_ritz, pcg)
 from .gradient import coeff_grad_cc, assemble_cc  # noqa: F401

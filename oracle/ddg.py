@@ -432,3 +432,82 @@ def cg_iteration_bound(kappa: float, tol: float) -> int:
         return 0 if tol >= 2.0 else 1
     q = (np.sqrt(kappa) - 1.0) / (np.sqrt(kappa) + 1.0)
     return max(0, int(np.ceil(np.log(tol / 2.0) / np.log(q))))
+
+
+# ---------------------------------------------------------------------------
+# Three-level V-cycle (Section 6, three-level paragraph)
+
+
+def subdomain_adjacency(A: sp.csr_matrix, part: np.ndarray, n_parts: int) -> sp.csr_matrix:
+    """Boolean n_parts x n_parts matrix: subdomains i, j coupled by a stored entry of A."""
+    n = A.shape[0]
+    P = sp.csr_matrix((np.ones(n), (np.asarray(part), np.arange(n))), shape=(n_parts, n))
+    pat = A.copy()
+    pat.data = np.ones_like(pat.data)
+    adj = (P @ pat @ P.T).tocsr()
+    adj.data = np.ones_like(adj.data)
+    return adj
+
+
+class ThreeLevelOracle:
+    """Three-level DDG preconditioner, FP64 (Section 6, three-level paragraph).
+
+    The two-level method is applied again to the coarse matrix A0: the coarse
+    unknowns (the kept columns of subdomain i) are grouped into coarse
+    subdomains by ``part0`` (coarse subdomain of each fine subdomain), the
+    coarsened generating vectors are F0 = R0 F, and the same overlap Delta is
+    used in the graph of A0.  The graph of A0 is its block pattern: unknowns of
+    subdomains i and j are coupled when A couples Omega_i and Omega_j.  One
+    preconditioner application is a V-cycle: the fine pre-sweep, then
+    R0^T M0^{-1} R0 (r - A e) with M0^{-1} one application of the two-level
+    preconditioner of A0 (its own pre-sweep, the coarsest correction
+    R1^T A1^{-1} R1, its post-sweep), then the fine post-sweep.
+    """
+
+    def __init__(self, A, F, part, n_parts: int, overlap: int, part0, n_parts0: int,
+                 rank_tol: float = 1e-10):
+        self.fine = DDGOracle(A, F, part, n_parts, overlap, rank_tol=rank_tol)
+        fine = self.fine
+        if not fine.coarse:
+            raise OracleError("INVALID_ARG", "the three-level method needs generating vectors")
+        F = np.asarray(F, dtype=np.float64)
+        part0 = np.asarray(part0, dtype=np.int64)
+        if part0.shape != (n_parts,) or part0.min() < 0 or part0.max() >= n_parts0:
+            raise OracleError("INVALID_ARG", "coarse partition out of range")
+        # graph of A0: blocks of coupled subdomain pairs
+        adj = subdomain_adjacency(fine.A, fine.part, n_parts).tocoo()
+        owner = np.repeat(np.arange(n_parts), fine.k_counts)          # subdomain of each coarse unknown
+        first = fine.k_offsets[:-1]
+        rows, cols = [], []
+        for i, j in zip(adj.row, adj.col):
+            ri = first[i] + np.arange(fine.k_counts[i])
+            cj = first[j] + np.arange(fine.k_counts[j])
+            rows.append(np.repeat(ri, cj.size))
+            cols.append(np.tile(cj, ri.size))
+        rows = np.concatenate(rows)
+        cols = np.concatenate(cols)
+        A0s = sp.csr_matrix((fine.A0[rows, cols], (rows, cols)), shape=fine.A0.shape)
+        A0s.sort_indices()
+        self.A0 = A0s
+        self.F0 = np.asarray(fine.R0 @ F)
+        self.part_c = part0[owner]
+        self.coarse = DDGOracle(A0s, self.F0, self.part_c, n_parts0, overlap, rank_tol=rank_tol)
+        self.A = fine.A
+        self.n = fine.n
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """M^{-1} r: fine pre-sweep, R0^T M0^{-1} R0 (r - A e), fine post-sweep."""
+        f = self.fine
+        r = np.asarray(r, dtype=np.float64)
+        e = np.zeros(self.n)
+        seq = [list(f.order[c]) for c in range(f.n_colours)]
+        for ids in seq:
+            f._colour(ids, r, e, False, None)
+        b0 = f.R0 @ (r - self.A @ e)
+        e += f.R0.T @ self.coarse.apply(b0)
+        for ids in reversed(seq):
+            f._colour(list(reversed(ids)), r, e, False, None)
+        return e
+
+    def pcg(self, f, rtol: float, max_iter: int = 1000, variant: str = "fr", trace: bool = False):
+        return pcg(self.A, self.apply, f, rtol, max_iter, variant=variant, trace=trace)

@@ -35,7 +35,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "CSR", "Problem", "seed_rng", "grf", "laplace5_nodes", "diffusion_cc",
-    "box_partition", "monomials", "monomial_count", "node_coords_2d",
+    "box_partition", "box_groups", "monomials", "monomial_count", "node_coords_2d",
     "cell_coords", "cfg1", "poisson2d_nodes", "diffusion_problem", "cfg2",
     "cfg5", "cfg5_pair", "cfg4_sides", "cfg4_instance", "STREAM_F",
     "STREAM_KAPPA", "STREAM_KAPPA_OBS", "STREAM_SIDES", "STREAM_CELLS",
@@ -261,6 +261,25 @@ def box_partition(shape, boxes) -> np.ndarray:
         ids = ids + mult * c.reshape(sh)
         mult *= boxes[ax]
     return ids.ravel().astype(np.int32)
+
+
+def box_groups(boxes, group):
+    """Coarse partition of the boxes of ``box_partition`` (numpy axis order).
+
+    Box (b_z, b_y, b_x) goes to coarse box (b_z // g_z, ...), numbered x-fastest
+    like the boxes themselves; ``group`` gives g per numpy axis.  Returns the
+    coarse id of every box and the number of coarse boxes.
+    """
+    boxes = tuple(boxes)
+    group = tuple(group)
+    cnt = tuple((m + g - 1) // g for m, g in zip(boxes, group))
+    grids = np.meshgrid(*[np.arange(m) for m in boxes], indexing="ij")
+    ids = np.zeros(boxes, dtype=np.int64)
+    mult = 1
+    for ax in reversed(range(len(boxes))):
+        ids = ids + mult * (grids[ax] // group[ax])
+        mult *= cnt[ax]
+    return ids.ravel().astype(np.int32), int(np.prod(cnt))
 
 
 def monomial_count(dim: int, p: int) -> int:
