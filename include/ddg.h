@@ -225,6 +225,25 @@ int ddg_batch_layout(ddg_handle h, int32_t* nb, int64_t* row_off, int32_t* sub_o
 int ddg_apply_precond(ddg_handle h, const double* r_dev, double* z_dev);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): z = M^{-1} r
+ * exactly as ddg_apply_precond computes it (same kernels, same order, same
+ * bits), with the buffers those kernels fill and read back within the call
+ * (local residuals, coarse restriction partials, coarse right-hand side and
+ * solution, coarse GEMV partials) taken from a static device array of 32 MiB
+ * that the library holds on every GPU it runs on until the process ends.  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating library call
+ * (profiling, if enabled on the handle, is skipped for the call).
+ *   r_dev[n], z_dev[n] device, caller-owned; the handle's device must be current.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind; calls that overlap on one GPU (several streams or threads) race.
+ * Errors: INVALID_ARG (null pointers, analysis-only handle, another device
+ * current), UNSUPPORTED (the handle needs more than 32 MiB of such buffers:
+ * 8 bytes per row of every expanded set plus the coarse buffers), HIP.
+ */
+int ddg_apply_precond_noalloc(ddg_handle h, const double* r_dev, double* z_dev);
+
+/*
  * The first `stages` steps of M^{-1} r: stages 0..C-1 are the pre-sweep
  * colour phases, stage C the coarse correction, C+1..2C the post-sweep phases
  * (so stages = 2C+1 equals ddg_apply_precond).  Writes the partial

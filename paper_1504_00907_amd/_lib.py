@@ -96,6 +96,7 @@ _SIGS = [
                                    C.POINTER(C.c_int32)]),
     ("ddg_batch_layout", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]),
     ("ddg_apply_precond", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ddg_apply_precond_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ddg_apply_precond_stages", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("ddg_spmv", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ddg_get_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),

@@ -336,6 +336,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   Symbolic& S = h->S;
   int dev = 0;
   DDG_HIP(hipGetDevice(&dev));
+  h->device = dev;
   int lds = 0;
   DDG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   h->dev_lds_limit = lds;
@@ -519,6 +520,10 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->cstate.alloc((size_t)h->nb * sizeof(CgState));
   DDG_HIP(hipHostMalloc((void**)&h->h_state, (size_t)h->nb * sizeof(CgState), hipHostMallocDefault));
   h->sys_info.assign(h->nb, ddg_info{});
+  h->ws.bres = h->bres.as<double>();
+  h->ws.rpart = h->nc > 0 ? h->rpart.as<double>() : nullptr;
+  h->ws.cy = h->nc > 0 ? h->cy.as<double>() : nullptr;
+  h->ws.cpart = h->nc > 0 ? h->cpart.as<double>() : nullptr;
   numeric_setup(*h);
   account_bytes(*h, row_ptr, col_idx);
   h->info.n_coarse = (int32_t)h->nc;
@@ -703,26 +708,6 @@ void tune_batch(int32_t nb, const ddg_problem* probs, int32_t overlap, const ddg
   if (cache_path) {
     std::ofstream outf(cache_path, std::ios::app);
     outf << key << ' ' << best.tile << ' ' << best.block_target << ' ' << best_ms << '\n';
-  }
-}
-
-Handle* H(ddg_handle p) { return reinterpret_cast<Handle*>(p); }
-
-template <class Fn>
-int guarded(Fn&& fn) {
-  try {
-    clear_error();
-    fn();
-    return DDG_OK;
-  } catch (const Error& e) {
-    set_error(e.msg);
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return DDG_ERR_OOM;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return DDG_ERR_HIP;
   }
 }
 

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -159,6 +161,18 @@ struct CgState {
 };
 
 // ---------------------------------------------------------------------------
+// Buffers that the preconditioner's kernels write and read back within one
+// application (nothing in them outlives it): the handle's own, allocated at
+// setup, or the library's static scratch (ddg_apply_precond_noalloc).
+
+struct PrecondWs {
+  double* bres = nullptr;   // local residuals of one colour's expanded sets (sum |set| values)
+  double* rpart = nullptr;  // coarse restriction partials (n_parts x nch x 32)
+  double* cy = nullptr;     // coarse right-hand side then solution (2 x nc_pad); zero padding
+  double* cpart = nullptr;  // coarse GEMV row and column partials (2 x ntiles x 64)
+};
+
+// ---------------------------------------------------------------------------
 // Handle
 
 struct Handle {
@@ -219,6 +233,8 @@ struct Handle {
   mutable int32_t flow_seq = 0;      // flow launches so far
   int64_t flow_bytes[2] = {0, 0};    // algorithmic bytes of one flow launch per direction
   DevBuf bres;                       // local residuals of one colour's expanded sets
+  PrecondWs ws;                      // the buffers the preconditioner's kernels use (see PrecondWs)
+  int32_t device = 0;                // HIP device current at setup
   int32_t xch_ld = 0;
   bool twisted_ok = false;
   int32_t n_cu = 256;
@@ -285,6 +301,27 @@ struct Handle {
 
   ~Handle();
 };
+
+inline Handle* H(ddg_handle p) { return reinterpret_cast<Handle*>(p); }
+
+// Runs fn and turns every exception into a status code and the thread-local message.
+template <class Fn>
+int guarded(Fn&& fn) {
+  try {
+    clear_error();
+    fn();
+    return DDG_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DDG_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return DDG_ERR_HIP;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip translation units)

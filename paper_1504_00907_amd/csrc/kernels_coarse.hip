@@ -183,7 +183,7 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
   if (h.nc == 0) return;
   const Symbolic& S = h.S;
   DDG_REQUIRE(h.k <= kMaxK, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
-  double* b0 = h.cy.as<double>();             // padded to whole tiles, zero beyond each block
+  double* b0 = h.ws.cy;             // padded to whole tiles, zero beyond each block
   double* y = b0 + h.nc_pad;
   const int32_t* sub_inst = h.sub_inst.as<int32_t>();
   DDG_REQUIRE(h.rch * h.lpr == 4 * kRThreads, DDG_ERR_HIP, "internal: restriction chunking");
@@ -192,12 +192,12 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
     hipLaunchKernelGGL(k_coarse_restrict<L>, dim3((unsigned)h.nch, (unsigned)S.n_parts), dim3(kRThreads), 0, s, st,
                        sub_inst, h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
                        h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(), r, e,
-                       h.rch, h.rpart.as<double>());
+                       h.rch, h.ws.rpart);
   });
   hipLaunchKernelGGL(k_coarse_restrict_sum, dim3((unsigned)(((int64_t)S.n_parts * kMaxK + 255) / 256)), dim3(256), 0,
-                     s, st, sub_inst, h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(), h.rpart.as<double>(), h.nch,
+                     s, st, sub_inst, h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(), h.ws.rpart, h.nch,
                      S.n_parts, b0);
-  double* rowpart = h.cpart.as<double>();
+  double* rowpart = h.ws.cpart;
   double* colpart = rowpart + h.ntiles * 64;
   hipLaunchKernelGGL(k_coarse_symv, dim3((unsigned)((h.ntiles + 3) / 4)), dim3(256), 0, s, st,
                      h.tile_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),

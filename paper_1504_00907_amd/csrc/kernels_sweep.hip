@@ -729,7 +729,7 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   a.fac = h.fac.p;
   a.r = r;
   a.e = e;
-  a.bres = h.bres.as<double>();
+  a.bres = h.ws.bres;
   a.st = st;
   a.sub_inst = h.sub_inst.as<int32_t>();
   a.e_zero = e_zero ? 1 : 0;
@@ -789,7 +789,7 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
       constexpr int L = decltype(Lc)::value;
       hipLaunchKernelGGL(k_local_residual<L>, dim3((unsigned)(((int64_t)S.max_set * L + 255) / 256), (unsigned)nsub),
                          dim3(256), 0, s, st, a.sub_inst, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e,
-                         a.e_zero, h.bres.as<double>());
+                         a.e_zero, h.ws.bres);
     });
     DDG_HIP(hipGetLastError());
     return;
