@@ -76,6 +76,16 @@ typedef enum {
   DDG_CG_POLAK_RIBIERE = 1     /* beta = z_{k+1}^T (r_{k+1} - r_k) / r_k^T z_k */
 } ddg_cg_variant;
 
+/* Storage of A for the row dots of the solve (SpMV, local residuals, coarse
+ * restriction, true residual).  The results are the same bit for bit. */
+typedef enum {
+  DDG_MATRIX_AUTO = 0,  /* diagonals when every system's entries lie on at most 6 offset pairs +-o
+                           (5-, 7- and 13-point stencils), its rows are short and its values are
+                           symmetric bit for bit; else the CSR rows */
+  DDG_MATRIX_CSR = 1,   /* always the CSR rows */
+  DDG_MATRIX_DIA = 2    /* (reported in ddg_info only) the diagonals are in use */
+} ddg_matrix_format;
+
 typedef struct {
   int32_t precision;   /* ddg_precision */
   int32_t max_iter;    /* CG iteration cap (default 1000, Section 7) */
@@ -87,6 +97,7 @@ typedef struct {
   int32_t schedule;    /* ddg_schedule (default DDG_SCHEDULE_AUTO) */
   int32_t cg_variant;  /* ddg_cg_variant (default DDG_CG_FLETCHER_REEVES) */
   void* stream;        /* hipStream_t for all work; NULL = the null stream */
+  int32_t matrix_format; /* DDG_MATRIX_AUTO (default) or DDG_MATRIX_CSR */
 } ddg_options;
 
 typedef struct {
@@ -110,6 +121,9 @@ typedef struct {
                               local order: the entries a banded (envelope) Cholesky factor would store */
   int64_t set_rows;        /* sum over subdomains of |expanded set| */
   int64_t nbhd_rows;       /* sum over subdomains of |expanded set plus the rows coupled to it by A| */
+  int32_t matrix_format;   /* storage the row dots read: DDG_MATRIX_CSR or DDG_MATRIX_DIA */
+  int32_t levels;          /* 1 (no coarse space), 2, or 3 (ddg_setup_three_level) */
+  int32_t n_coarsest;      /* unknowns of the coarsest level (N_c with two levels) */
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */
@@ -131,6 +145,29 @@ void ddg_default_options(ddg_options* opt);
 int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
               const double* val, int32_t k, const double* F, const int32_t* part,
               int32_t n_parts, int32_t overlap, const ddg_options* opt);
+
+/*
+ * Three-level V-cycle (Section 6, three-level paragraph): the two-level method
+ * is applied again to the coarse matrix A0 = R0 A R0^T, and one application of
+ * that coarse two-level preconditioner M0^{-1} replaces the coarse solve
+ * A0^{-1} inside every application on the fine level:
+ *   e = fine pre-sweep;  e += R0^T M0^{-1} R0 (r - A e);  fine post-sweep.
+ * The coarse level's unknowns are the kept coarse columns (subdomain-major);
+ * its partition puts the columns of subdomain i into coarse subdomain part0[i],
+ * its generating vectors are F0 = R0 F, its graph is the block pattern of A0
+ * (subdomains coupled by A), and it uses the same overlap.  The coarse level is
+ * FP64 throughout and ends with the exact coarsest solve of A1 = R1 A0 R1^T.
+ *   arguments as ddg_setup, plus
+ *   part0[n_parts]  host; coarse subdomain of every subdomain, in [0, n_parts0),
+ *                   every coarse subdomain non-empty.
+ * ddg_solve, ddg_refactor (both levels refactored), ddg_apply_precond and the
+ * other single-system calls accept the handle; ddg_info.levels = 3.
+ * Errors: as ddg_setup (a coarse-level failure's message starts with
+ * "coarse level:"); INVALID_ARG also for k = 0 or a bad part0.
+ */
+int ddg_setup_three_level(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                          const double* val, int32_t k, const double* F, const int32_t* part, int32_t n_parts,
+                          int32_t overlap, const int32_t* part0, int32_t n_parts0, const ddg_options* opt);
 
 /*
  * New matrix values with the same pattern (device pointer, nnz float64 in the

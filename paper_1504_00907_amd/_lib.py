@@ -25,6 +25,8 @@ EXPORT_COLOURS, EXPORT_SET_PTR, EXPORT_SET_IDX, EXPORT_KCOUNTS, EXPORT_A0, EXPOR
 SCHEDULE = {"auto": 0, "colours": 1, "queue": 2}
 BC = {"dirichlet": 0, "x0": 1}
 CG_VARIANT = {"fr": 0, "pr": 1}
+MATRIX_FORMAT = {"auto": 0, "csr": 1}
+MATRIX_FORMAT_NAME = {1: "csr", 2: "dia"}
 
 
 class Options(C.Structure):
@@ -32,7 +34,7 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
         ("rank_tol", C.c_double), ("tile", C.c_int32), ("block_target", C.c_int32),
         ("check_every", C.c_int32), ("schedule", C.c_int32), ("cg_variant", C.c_int32),
-        ("stream", C.c_void_p),
+        ("stream", C.c_void_p), ("matrix_format", C.c_int32),
     ]
 
 
@@ -44,6 +46,7 @@ class Info(C.Structure):
         ("solve_ms", C.c_double), ("factor_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
         ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("schedule", C.c_int32),
         ("envelope_elems", C.c_int64), ("set_rows", C.c_int64), ("nbhd_rows", C.c_int64),
+        ("matrix_format", C.c_int32), ("levels", C.c_int32), ("n_coarsest", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -86,6 +89,9 @@ _SIGS = [
     ("ddg_default_options", None, [C.POINTER(Options)]),
     ("ddg_setup", C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Options)]),
+    ("ddg_setup_three_level", C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                        C.c_int32, C.POINTER(Options)]),
     ("ddg_refactor", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ddg_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Info)]),
     ("ddg_setup_batched", C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Problem), C.c_int32,

@@ -24,6 +24,7 @@ void clear_error() { g_last_error.clear(); }
 void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s);
 
 Handle::~Handle() {
+  delete inner;
   for (auto ev : ev_pool) (void)hipEventDestroy(ev);
   if (h_state) (void)hipHostFree(h_state);
   if (side) (void)hipStreamDestroy(side);
@@ -134,7 +135,8 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
       for (int64_t t = r0; t < r1; ++t) nnz_rows += rp[S.set_idx[t] + 1] - rp[S.set_idx[t]];
       bytes += fb + cpl + ni * (8 + 4 + 16);
       resid0 += ni * (4 + 8 + 8);
-      resid += ni * (4 + 8 + 8 + 16 + 8) + nnz_rows * 12;
+      // a gathered row from the diagonals reads its diagonal and both sides' entries
+      resid += ni * (4 + 8 + 8 + 8) + (h.dia_ok ? ni * 8 * (1 + 2 * (int64_t)h.dia_nd) : nnz_rows * 12 + ni * 16);
       // persistent sweep: the same local solves, each forming its residual rows itself
       // (set index, r, row pointers, CSR rows and e; set index and r when e = 0)
       const int64_t own = fb + cpl + ni * (4 + 16);
@@ -161,10 +163,14 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
     sweep += (2 * C - 1) * (resid / C) + resid0 / C;  // residual kernels (per-colour average)
   }
   h.info.sweep_bytes = sweep;
-  const int64_t n = S.n, nnzb = S.nnz * 12 + (n + 1) * 8;
+  // one full pass over A: CSR (row pointers, columns, values) or the stored diagonals
+  const int64_t n = S.n, nnzb = h.dia_ok ? n * 8 * (1 + (int64_t)h.dia_nd) : S.nnz * 12 + (n + 1) * 8;
   const int64_t ntiles = h.ntiles;
   // coarse: restrict (residual SpMV + Q), tiled inverse GEMV, prolong (Q, e rmw)
-  const int64_t coarse = h.nc ? (nnzb + 3 * n * 8 + n * h.k * 8 + ntiles * 64 * 64 * 8 + n * h.k * 8 + 16 * n) : 0;
+  // (the dense inverse's tiles, or one application of the coarse level's preconditioner)
+  const int64_t core = h.inner ? h.inner->apply_bytes : ntiles * 64 * 64 * 8;
+  const int64_t coarse = h.nc ? (nnzb + 3 * n * 8 + n * h.k * 8 + core + n * h.k * 8 + 16 * n) : 0;
+  h.apply_bytes = sweep + coarse;
   // CG: SpMV (p, q), x/r/p/q update, two dots, p update
   const int64_t cg = nnzb + 2 * n * 8 + 6 * n * 8 + 4 * n * 8 + 3 * n * 8;
   h.info.iter_bytes = sweep + coarse + cg + n * 8;
@@ -210,6 +216,7 @@ void numeric_setup(Handle& h) {
   DDG_HIP(hipEventCreate(&e1));
   DDG_HIP(hipEventRecord(e0, h.stream));
   launch_refresh_couplings(h, h.stream);
+  launch_dia_refresh(h, h.stream);
   if (h.nc > 0) launch_galerkin(h, h.stream);
   // The local factorisation (wide batched launches) and the coarse inverse (a tree of
   // small, latency-bound launches) are independent: the coarse inverse runs on a
@@ -222,13 +229,18 @@ void numeric_setup(Handle& h) {
     DDG_HIP(hipEventRecord(eg, h.stream));
   }
   launch_local_factor(h, h.stream);
-  if (h.nc > 0) {
+  if (h.nc > 0 && !h.three_level) {
     DDG_HIP(hipStreamWaitEvent(h.side, eg, 0));
     launch_coarse_invert(h, h.side);
     DDG_HIP(hipEventRecord(ec, h.side));
     DDG_HIP(hipStreamWaitEvent(h.stream, ec, 0));
-    (void)hipEventDestroy(eg);
-    (void)hipEventDestroy(ec);
+  }
+  if (eg) (void)hipEventDestroy(eg);
+  if (ec) (void)hipEventDestroy(ec);
+  if (h.inner) {
+    // the coarse level's values from the new A0, then its own factorisation
+    launch_gather(h.a0_pos.as<int64_t>(), h.A0.as<double>(), h.inner->val.as<double>(), h.inner->S.nnz, h.stream);
+    numeric_setup(*h.inner);
   }
   DDG_HIP(hipEventRecord(e1, h.stream));
   DDG_HIP(hipEventSynchronize(e1));
@@ -238,6 +250,53 @@ void numeric_setup(Handle& h) {
   (void)hipEventDestroy(e1);
   h.info.setup_ms = ms;
   check_err_flag(h, "numeric factorisation");
+  if (h.dia_possible) {
+    // the diagonals represent A only when its values are symmetric bit for bit;
+    // otherwise the row dots read the CSR rows (until a refactor makes them so)
+    int32_t bad = 0;
+    DDG_HIP(hipMemcpyAsync(&bad, h.err_flag.as<int32_t>() + 4, sizeof(bad), hipMemcpyDeviceToHost, h.stream));
+    DDG_HIP(hipStreamSynchronize(h.stream));
+    if (bad) DDG_HIP(hipMemsetAsync(h.err_flag.as<int32_t>() + 4, 0, sizeof(int32_t), h.stream));
+    h.dia_ok = bad == 0;
+  }
+  h.info.matrix_format = h.dia_ok ? DDG_MATRIX_DIA : DDG_MATRIX_CSR;
+}
+
+// Diagonal storage is possible when no system's rows have more than kDiaMax
+// distinct positive column offsets and the rows are short (one lane per row).
+void plan_dia(Handle& h, const int64_t* rp, const int32_t* ci) {
+  h.dia_possible = false;
+  h.dia_ok = false;
+  if (h.opt.matrix_format == DDG_MATRIX_CSR || h.lpr != 1) return;
+  std::vector<DiaSys> sys((size_t)h.nb);
+  for (int32_t b = 0; b < h.nb; ++b) {
+    DiaSys& d = sys[b];
+    std::memset(&d, 0, sizeof(d));
+    d.lo = h.seg_off[b];
+    d.hi = h.seg_off[b + 1];
+    std::vector<int32_t> offs;
+    for (int64_t g = d.lo; g < d.hi; ++g) {
+      for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+        const int64_t o = (int64_t)ci[t] - g;
+        if (o <= 0) continue;
+        if (std::find(offs.begin(), offs.end(), (int32_t)o) == offs.end()) {
+          if ((int)offs.size() == kDiaMax) return;
+          offs.push_back((int32_t)o);
+        }
+      }
+    }
+    std::sort(offs.begin(), offs.end());
+    d.nd = (int32_t)offs.size();
+    for (int32_t q = 0; q < d.nd; ++q) d.off[q] = offs[q];
+  }
+  int32_t nd = 0;
+  for (const auto& d : sys) nd = std::max(nd, d.nd);
+  h.dia_sys_h = sys;
+  h.dia_nd = std::max(nd, 1);
+  h.dia_sys.upload(sys, h.stream);
+  h.dia_diag.alloc((size_t)h.S.n * sizeof(double));
+  h.dia_up.alloc((size_t)h.dia_nd * h.S.n * sizeof(double));
+  h.dia_possible = true;
 }
 
 // Durations of the profiled local-solve launches.  A launch enqueued by CG
@@ -405,8 +464,10 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     DDG_HIP(hipMemsetAsync(h->flags.p, 0, (size_t)n_parts * 2 * sizeof(int32_t), s));
   }
   h->bres.alloc((size_t)S.set_ptr[n_parts] * sizeof(double));
-  h->err_flag.alloc(4 * sizeof(int32_t));
-  DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 4 * sizeof(int32_t), s));
+  // [0..3] setup/solve error (code, subdomain, block, pivot); [4] entries whose transpose
+  // differs in its bits (diagonal storage check)
+  h->err_flag.alloc(8 * sizeof(int32_t));
+  DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 8 * sizeof(int32_t), s));
   h->fac.alloc((size_t)S.fac_elems * storage_size(h->opt.precision));
   // coarse basis (depends only on F and the partition)
   h->kcnt.assign(n_parts, 0);
@@ -438,7 +499,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     h->koff[n_parts] = run;
     h->cblk_off[h->nb] = run;
     h->koff_d.upload(h->koff, s);
-    h->F.release();
+    if (!h->three_level) h->F.release();   // a three-level handle still forms F0 = R0 F
   }
   h->nc_pad = h->cblk_off[h->nb];
   if (h->nc > 0) {
@@ -461,10 +522,10 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     h->tile_inst.upload(tinst, s);
     h->trow_inst.upload(rinst, s);
     h->A0.alloc((size_t)h->a0_off[h->nb] * sizeof(double));
-    h->A0inv_t.alloc((size_t)h->ntiles * 64 * 64 * sizeof(double));
+    if (!h->three_level) h->A0inv_t.alloc((size_t)h->ntiles * 64 * 64 * sizeof(double));
     h->cy.alloc((size_t)2 * h->nc_pad * sizeof(double));
     DDG_HIP(hipMemsetAsync(h->cy.p, 0, (size_t)2 * h->nc_pad * sizeof(double), s));
-    h->cpart.alloc((size_t)2 * h->ntiles * 64 * sizeof(double));
+    if (!h->three_level) h->cpart.alloc((size_t)2 * h->ntiles * 64 * sizeof(double));
   }
   // row-dot kernels: lanes per CSR row; the coarse restriction runs four passes of
   // its workgroup per chunk of own rows
@@ -473,6 +534,9 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     const int v = std::atoi(env);
     if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) h->lpr = v;
   }
+  DDG_REQUIRE(h->opt.matrix_format == DDG_MATRIX_AUTO || h->opt.matrix_format == DDG_MATRIX_CSR,
+              DDG_ERR_INVALID_ARG, "matrix_format must be DDG_MATRIX_AUTO or DDG_MATRIX_CSR");
+  plan_dia(*h, row_ptr, col_idx);
   // sweep over a device task queue (each task forms its own residual rows) on request;
   // the automatic choice is the colour launches (measured: 21.7 vs 21.9 ms at 128^3
   // FP32, 123 vs 139 ms for the batch of 256)
@@ -523,10 +587,12 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->ws.bres = h->bres.as<double>();
   h->ws.rpart = h->nc > 0 ? h->rpart.as<double>() : nullptr;
   h->ws.cy = h->nc > 0 ? h->cy.as<double>() : nullptr;
-  h->ws.cpart = h->nc > 0 ? h->cpart.as<double>() : nullptr;
+  h->ws.cpart = h->nc > 0 && !h->three_level ? h->cpart.as<double>() : nullptr;
   numeric_setup(*h);
   account_bytes(*h, row_ptr, col_idx);
   h->info.n_coarse = (int32_t)h->nc;
+  h->info.levels = h->nc > 0 ? 2 : 1;
+  h->info.n_coarsest = (int32_t)h->nc;
   h->info.n_colours = S.n_colours;
   h->info.n_parts = n_parts;
   h->info.n_blocks = (int32_t)S.blk_size.size();
@@ -731,6 +797,7 @@ void ddg_default_options(ddg_options* opt) {
   opt->check_every = 4;
   opt->schedule = DDG_SCHEDULE_AUTO;
   opt->cg_variant = DDG_CG_FLETCHER_REEVES;
+  opt->matrix_format = DDG_MATRIX_AUTO;
   opt->stream = nullptr;
 }
 
@@ -748,6 +815,90 @@ int ddg_setup(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t*
     if (opt) h->opt = *opt;
     else ddg_default_options(&h->opt);
     setup_impl(*h, n, row_ptr, col_idx, val, k, F, part, n_parts, overlap, {0, n}, {0, n_parts});
+    hp = h.release();
+  });
+  if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
+  return rc;
+}
+
+int ddg_setup_three_level(ddg_handle* out, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                          const double* val, int32_t k, const double* F, const int32_t* part, int32_t n_parts,
+                          int32_t overlap, const int32_t* part0, int32_t n_parts0, const ddg_options* opt) {
+  if (out) *out = nullptr;
+  Handle* hp = nullptr;
+  int rc = guarded([&]() {
+    DDG_REQUIRE(out && row_ptr && col_idx && val && part && part0, DDG_ERR_INVALID_ARG, "null argument");
+    DDG_REQUIRE(k > 0 && F, DDG_ERR_INVALID_ARG, "the three-level method needs generating vectors (k > 0)");
+    DDG_REQUIRE(n_parts > 0 && n_parts0 > 0, DDG_ERR_INVALID_ARG, "empty partition");
+    std::vector<int32_t> used(n_parts0, 0);
+    for (int32_t i = 0; i < n_parts; ++i) {
+      DDG_REQUIRE(part0[i] >= 0 && part0[i] < n_parts0, DDG_ERR_INVALID_ARG,
+                  "coarse partition id out of range at subdomain " + std::to_string(i));
+      used[part0[i]] = 1;
+    }
+    for (int32_t c = 0; c < n_parts0; ++c)
+      DDG_REQUIRE(used[c], DDG_ERR_INVALID_ARG, "empty coarse subdomain " + std::to_string(c));
+    auto h = std::make_unique<Handle>();
+    if (opt) h->opt = *opt;
+    else ddg_default_options(&h->opt);
+    h->three_level = true;
+    setup_impl(*h, n, row_ptr, col_idx, val, k, F, part, n_parts, overlap, {0, n}, {0, n_parts});
+    hipStream_t s = h->stream;
+    const Symbolic& S = h->S;
+    const int64_t nc = h->nc;
+    DDG_REQUIRE(nc > 0, DDG_ERR_RANK, "no coarse columns");
+    // the coarse level's matrix: A0 with the block pattern of the subdomain couplings
+    // (the unknowns of subdomains i and j are coupled when A couples their sets)
+    std::vector<double> A0((size_t)(nc * nc));
+    DDG_HIP(hipMemcpyAsync(A0.data(), h->A0.p, A0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> rp0((size_t)nc + 1, 0), pos;
+    std::vector<int32_t> ci0, part_c((size_t)nc);
+    for (int32_t i = 0; i < n_parts; ++i) {
+      for (int32_t jj = 0; jj < h->kcnt[i]; ++jj) {
+        const int64_t a = h->koff[i] + jj;
+        part_c[(size_t)a] = part0[i];
+        for (int32_t t = S.nbr_ptr[i]; t < S.nbr_ptr[i + 1]; ++t) {
+          const int32_t j = S.nbr_idx[t];
+          for (int32_t m = 0; m < h->kcnt[j]; ++m) {
+            ci0.push_back((int32_t)(h->koff[j] + m));
+            pos.push_back(a * nc + h->koff[j] + m);
+          }
+        }
+        rp0[(size_t)a + 1] = (int64_t)ci0.size();
+      }
+    }
+    // F0 = R0 F on the device
+    DevBuf F0d;
+    F0d.alloc((size_t)h->nc_pad * k * sizeof(double));
+    launch_restrict_columns(*h, F0d.as<double>(), s);
+    std::vector<double> F0((size_t)(h->nc_pad * k));
+    DDG_HIP(hipMemcpyAsync(F0.data(), F0d.p, F0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DDG_HIP(hipStreamSynchronize(s));
+    h->F.release();
+    std::vector<double> F0c((size_t)(nc * k)), v0(pos.size());
+    for (int32_t c = 0; c < k; ++c)
+      for (int64_t a = 0; a < nc; ++a) F0c[(size_t)(c * nc + a)] = F0[(size_t)(c * h->nc_pad + a)];
+    for (size_t t = 0; t < pos.size(); ++t) v0[t] = A0[(size_t)pos[t]];
+    // the coarse level: FP64 throughout, colour launches, the library's tile choice
+    auto in = std::make_unique<Handle>();
+    in->opt = h->opt;
+    in->opt.precision = DDG_FP64;
+    in->opt.tile = 0;
+    in->opt.block_target = 0;
+    in->opt.schedule = DDG_SCHEDULE_COLOURS;
+    try {
+      setup_impl(*in, nc, rp0.data(), ci0.data(), v0.data(), k, F0c.data(), part_c.data(), n_parts0, overlap,
+                 {0, nc}, {0, n_parts0});
+    } catch (Error& e) {
+      e.msg = "coarse level: " + e.msg;
+      throw;
+    }
+    h->a0_pos.upload(pos, s);
+    h->inner = in.release();
+    account_bytes(*h, row_ptr, col_idx);
+    h->info.levels = 3;
+    h->info.n_coarsest = (int32_t)h->inner->nc;
+    DDG_HIP(hipStreamSynchronize(s));
     hp = h.release();
   });
   if (rc == DDG_OK) *out = reinterpret_cast<ddg_handle>(hp);
@@ -856,6 +1007,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     DDG_HIP(hipEventRecord(e1, s));
     h->solved = true;
     check_err_flag(*h, "solve");
+    if (h->inner) check_err_flag(*h->inner, "solve (coarse level)");
     DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sb, hipMemcpyDeviceToHost, s));
     DDG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/ddg.h"
+#include "device_util.hpp"
 
 namespace ddg {
 
@@ -233,11 +234,24 @@ struct Handle {
   mutable int32_t flow_seq = 0;      // flow launches so far
   int64_t flow_bytes[2] = {0, 0};    // algorithmic bytes of one flow launch per direction
   DevBuf bres;                       // local residuals of one colour's expanded sets
+  // diagonal storage of A (DiaView): possible when every system's entries lie on at
+  // most kDiaMax offset pairs; in use while the values are also symmetric bit for bit
+  bool dia_possible = false, dia_ok = false;
+  int32_t dia_nd = 1;                // upper diagonals stored (most of any system)
+  std::vector<DiaSys> dia_sys_h;
+  DevBuf dia_sys, dia_diag, dia_up;
   PrecondWs ws;                      // the buffers the preconditioner's kernels use (see PrecondWs)
   int32_t device = 0;                // HIP device current at setup
   int32_t xch_ld = 0;
   bool twisted_ok = false;
   int32_t n_cu = 256;
+  // three-level V-cycle: one application of the two-level method of A0 (coarse
+  // partition of the subdomains, generating vectors F0 = R0 F, the same overlap)
+  // replaces the coarse inverse
+  bool three_level = false;
+  Handle* inner = nullptr;           // owned: the coarse level's handle
+  DevBuf a0_pos;                     // per stored entry of the coarse level's CSR: position in the dense A0
+  int64_t apply_bytes = 0;           // algorithmic bytes of one preconditioner application
   DevBuf F;               // n x k column-major (setup input)
   DevBuf Q;               // n x k node-major orthonormal basis (zero-padded)
   DevBuf kcnt_d, koff_d;
@@ -326,6 +340,22 @@ int guarded(Fn&& fn) {
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip translation units)
 
+// The handle's diagonal storage of A for the row-dot kernels (diag null: CSR rows).
+inline DiaView dia_view(const Handle& h) {
+  DiaView d{};
+  if (h.dia_ok) {
+    d.diag = h.dia_diag.as<double>();
+    d.up = h.dia_up.as<double>();
+    d.sys = h.dia_sys.as<DiaSys>();
+  }
+  d.n = h.S.n;
+  d.nb = h.nb;
+  return d;
+}
+// Refill the diagonals from the CSR values and count entries whose transpose
+// differs in its bits (into err_flag[4]).
+void launch_dia_refresh(Handle& h, hipStream_t s);
+
 // cg kernels
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
@@ -340,8 +370,10 @@ void launch_true_residual(Handle& h, const double* f, const double* x, hipStream
 void build_cg_map(Handle& h, hipStream_t s);
 
 // preconditioner
+// guard: CG states whose done flags the kernels obey (default: the handle's own when
+// guarded, none otherwise); the coarse level of a three-level handle obeys the fine one's
 void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded,
-                    hipStream_t s);
+                    hipStream_t s, const CgState* guard = nullptr);
 // one sweep direction (0: colours ascending, 1: descending) as a persistent launch
 void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s);
 
@@ -349,7 +381,11 @@ void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgS
 void launch_coarse_basis(Handle& h, hipStream_t s);
 void launch_galerkin(Handle& h, hipStream_t s);
 void launch_coarse_invert(Handle& h, hipStream_t s);
+// F0 = R0 F (nc_pad x k column-major, zero padding) from the device copy of F
+void launch_restrict_columns(Handle& h, double* F0, hipStream_t s);
 void launch_local_factor(Handle& h, hipStream_t s);
 void launch_refresh_couplings(Handle& h, hipStream_t s);
+// dst[t] = src[pos[t]] (0 where pos[t] < 0), t < m
+void launch_gather(const int64_t* pos, const double* src, double* dst, int64_t m, hipStream_t s);
 
 }  // namespace ddg

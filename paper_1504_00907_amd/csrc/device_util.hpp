@@ -144,6 +144,102 @@ __device__ inline double row_dot_rt(const int64_t* __restrict__ rp, const int32_
   return s;
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal (DIA) storage of a stencil operator, used for every row dot when each
+// system's stored entries lie on at most kDiaMax offset pairs +-o (5-, 7- and
+// 13-point stencils).  The values are symmetric bit for bit (checked when they
+// are filled), so only the diagonal and the upper diagonals are stored:
+// A[g, g] = diag[g], A[g, g + o_d] = A[g + o_d, g] = up[d n + g], zero where the
+// CSR row has no such entry.  A row is read back in its sorted-column order
+// (lower diagonals by descending offset, the diagonal, upper ones by ascending
+// offset), so every sum equals the CSR one bit for bit (a missing entry adds
+// 0 * x).  Each system of a batch has its own offsets and row range.
+constexpr int kDiaMax = 6;
+
+struct DiaSys {
+  int64_t lo, hi;        // rows of the system
+  int32_t nd;            // upper diagonals (<= kDiaMax)
+  int32_t off[kDiaMax];  // ascending positive offsets
+  int32_t pad;
+};
+
+struct DiaView {
+  const double* diag;    // n; null when the handle uses CSR rows
+  const double* up;      // kDiaMax x n (diagonal d at up + d n)
+  const DiaSys* sys;     // per system
+  int64_t n;
+  int32_t nb;
+};
+
+// System holding row g (binary search over the row ranges).
+__device__ inline int dia_system_of(const DiaView& D, int64_t g) {
+  int lo = 0, hi = D.nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (D.sys[mid].lo <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Loads the entries of row g in sorted-column order into a[], x values into xv[]:
+// slots 0..nd-1 the lower diagonals (largest offset first), slot kDiaMax the
+// diagonal, slots kDiaMax+1.. the upper ones; a slot whose neighbour lies
+// outside the system holds 0.
+__device__ inline void dia_row_load(const DiaView& D, const DiaSys& s, const double* __restrict__ x, int64_t g,
+                                    double (&a)[2 * kDiaMax + 1], double (&xv)[2 * kDiaMax + 1]) {
+  const int nd = s.nd;
+#pragma unroll
+  for (int q = 0; q < kDiaMax; ++q) {
+    a[q] = 0.0;
+    xv[q] = 0.0;
+    const int d = nd - 1 - q;
+    if (d >= 0) {
+      const int64_t c = g - s.off[d];
+      if (c >= s.lo) {
+        a[q] = D.up[(int64_t)d * D.n + c];
+        xv[q] = x[c];
+      }
+    }
+  }
+  a[kDiaMax] = D.diag[g];
+  xv[kDiaMax] = x[g];
+#pragma unroll
+  for (int q = 0; q < kDiaMax; ++q) {
+    a[kDiaMax + 1 + q] = 0.0;
+    xv[kDiaMax + 1 + q] = 0.0;
+    if (q < nd) {
+      const int64_t c = g + s.off[q];
+      if (c < s.hi) {
+        a[kDiaMax + 1 + q] = D.up[(int64_t)q * D.n + g];
+        xv[kDiaMax + 1 + q] = x[c];
+      }
+    }
+  }
+}
+
+// acc - (A x)_g, the entries subtracted in sorted-column order (as row_sub).
+__device__ inline double dia_row_sub(const DiaView& D, const DiaSys& s, const double* __restrict__ x, int64_t g,
+                                     double acc) {
+  double a[2 * kDiaMax + 1], xv[2 * kDiaMax + 1];
+  dia_row_load(D, s, x, g, a, xv);
+#pragma unroll
+  for (int q = 0; q < 2 * kDiaMax + 1; ++q)
+    if (q < kDiaMax ? q < s.nd : q == kDiaMax || q - kDiaMax - 1 < s.nd) acc -= a[q] * xv[q];
+  return acc;
+}
+
+// (A x)_g, the products added in sorted-column order (as row_dot_l<1>).
+__device__ inline double dia_row_dot(const DiaView& D, const DiaSys& s, const double* __restrict__ x, int64_t g) {
+  double a[2 * kDiaMax + 1], xv[2 * kDiaMax + 1];
+  dia_row_load(D, s, x, g, a, xv);
+  double r = 0.0;
+#pragma unroll
+  for (int q = 0; q < 2 * kDiaMax + 1; ++q)
+    if (q < kDiaMax ? q < s.nd : q == kDiaMax || q - kDiaMax - 1 < s.nd) r += a[q] * xv[q];
+  return r;
+}
+
 // Calls f(std::integral_constant<int, L>{}) for the run-time lanes-per-row value.
 template <class Fn>
 inline void with_lanes(int L, Fn&& f) {

@@ -39,16 +39,56 @@ struct SegMap {
 
 // Row-dot kernels take L lanes per CSR row (row_dot_l): a workgroup covers
 // kThreads / L rows per pass and lane 0 of each group stores the row's result.
+// With diagonal storage (D.diag non-null, L = 1) the rows come from the diagonals.
 template <int L>
 __global__ void k_spmv(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                       const double* __restrict__ v, const double* __restrict__ x,
+                       const double* __restrict__ v, DiaView D, const double* __restrict__ x,
                        double* __restrict__ y, int64_t n) {
   const int j = threadIdx.x & (L - 1);
   int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x / L;
+  if (L == 1 && D.diag) {
+    for (; i < n; i += stride) y[i] = dia_row_dot(D, D.sys[dia_system_of(D, i)], x, i);
+    return;
+  }
   for (; i < n; i += stride) {
     const double s = row_dot_l<L>(rp, ci, v, x, i, j);
     if (j == 0) y[i] = s;
+  }
+}
+
+// Diagonal storage from the CSR values: row g's diagonal entry and its entries at
+// g + o_d (up was cleared first, so absent entries stay zero).
+__global__ void k_dia_fill(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, DiaView D, double* __restrict__ diag,
+                           double* __restrict__ up) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < D.n; g += stride) {
+    const DiaSys& s = D.sys[dia_system_of(D, g)];
+    for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+      const int64_t c = ci[t];
+      if (c == g) diag[g] = v[t];
+      if (c <= g) continue;
+      for (int d = 0; d < s.nd; ++d)
+        if (c - g == s.off[d]) up[(int64_t)d * D.n + g] = v[t];
+    }
+  }
+}
+
+// Counts lower entries A[g, g - o] whose bits differ from the stored upper entry
+// A[g - o, g] (the diagonal storage then does not represent A exactly).
+__global__ void k_dia_check(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const double* __restrict__ v, DiaView D, int32_t* __restrict__ bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < D.n; g += stride) {
+    const DiaSys& s = D.sys[dia_system_of(D, g)];
+    for (int64_t t = rp[g]; t < rp[g + 1]; ++t) {
+      const int64_t c = ci[t];
+      if (c >= g) break;
+      for (int d = 0; d < s.nd; ++d)
+        if (g - c == s.off[d] && __double_as_longlong(D.up[(int64_t)d * D.n + c]) != __double_as_longlong(v[t]))
+          atomicAdd(bad, 1);
+    }
   }
 }
 
@@ -169,7 +209,7 @@ __global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ 
 // q = A p, partial p.q
 template <int L>
 __global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restrict__ rp,
-                           const int32_t* __restrict__ ci, const double* __restrict__ v,
+                           const int32_t* __restrict__ ci, const double* __restrict__ v, DiaView D,
                            const double* __restrict__ p, double* __restrict__ q,
                            double* __restrict__ part) {
   if (stb[m.seg[blockIdx.x]].done) return;
@@ -177,11 +217,20 @@ __global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restri
   double acc = 0.0;
   const int64_t hi = m.hi[blockIdx.x];
   const int j = threadIdx.x & (L - 1);
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
-    const double qi = row_dot_l<L>(rp, ci, v, p, i, j);
-    if (j == 0) {
+  if (L == 1 && D.diag) {
+    const DiaSys& sy = D.sys[m.seg[blockIdx.x]];
+    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
+      const double qi = dia_row_dot(D, sy, p, i);
       q[i] = qi;
       acc += p[i] * qi;
+    }
+  } else {
+    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
+      const double qi = row_dot_l<L>(rp, ci, v, p, i, j);
+      if (j == 0) {
+        q[i] = qi;
+        acc += p[i] * qi;
+      }
     }
   }
   double s = block_sum<kThreads>(acc, red);
@@ -285,15 +334,23 @@ __global__ void k_xpby(const CgState* stb, SegMap m, const double* __restrict__ 
 // partial ||f - A x||^2 (always runs)
 template <int L>
 __global__ void k_resid_dot(SegMap m, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                            const double* __restrict__ v, const double* __restrict__ f,
+                            const double* __restrict__ v, DiaView D, const double* __restrict__ f,
                             const double* __restrict__ x, double* __restrict__ part) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
   const int64_t hi = m.hi[blockIdx.x];
   const int j = threadIdx.x & (L - 1);
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
-    const double d = f[i] - row_dot_l<L>(rp, ci, v, x, i, j);
-    if (j == 0) acc += d * d;
+  if (L == 1 && D.diag) {
+    const DiaSys& sy = D.sys[m.seg[blockIdx.x]];
+    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
+      const double d = f[i] - dia_row_dot(D, sy, x, i);
+      acc += d * d;
+    }
+  } else {
+    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
+      const double d = f[i] - row_dot_l<L>(rp, ci, v, x, i, j);
+      if (j == 0) acc += d * d;
+    }
   }
   double s = block_sum<kThreads>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -361,8 +418,24 @@ void launch_spmv(const Handle& h, const double* x, double* y, hipStream_t s) {
   with_lanes(h.lpr, [&](auto Lc) {
     constexpr int L = decltype(Lc)::value;
     hipLaunchKernelGGL(k_spmv<L>, dim3(grid_for(h.S.n * L)), dim3(kThreads), 0, s, h.rowptr.as<int64_t>(),
-                       h.col.as<int32_t>(), h.val.as<double>(), x, y, h.S.n);
+                       h.col.as<int32_t>(), h.val.as<double>(), dia_view(h), x, y, h.S.n);
   });
+}
+
+void launch_dia_refresh(Handle& h, hipStream_t s) {
+  if (!h.dia_possible) return;
+  DiaView D{};
+  D.diag = h.dia_diag.as<double>();
+  D.up = h.dia_up.as<double>();
+  D.sys = h.dia_sys.as<DiaSys>();
+  D.n = h.S.n;
+  D.nb = h.nb;
+  launch_fill(h.dia_up.as<double>(), 0.0, (int64_t)h.dia_nd * h.S.n, s);
+  hipLaunchKernelGGL(k_dia_fill, dim3(grid_for(h.S.n)), dim3(kThreads), 0, s, h.rowptr.as<int64_t>(),
+                     h.col.as<int32_t>(), h.val.as<double>(), D, h.dia_diag.as<double>(), h.dia_up.as<double>());
+  hipLaunchKernelGGL(k_dia_check, dim3(grid_for(h.S.n)), dim3(kThreads), 0, s, h.rowptr.as<int64_t>(),
+                     h.col.as<int32_t>(), h.val.as<double>(), D, h.err_flag.as<int32_t>() + 4);
+  DDG_HIP(hipGetLastError());
 }
 
 void launch_cg_init(Handle& h, const double* f, double* x, hipStream_t s) {
@@ -388,7 +461,7 @@ void launch_cg_step_a(Handle& h, double* x, hipStream_t s) {
   with_lanes(h.lpr, [&](auto Lc) {
     constexpr int L = decltype(Lc)::value;
     hipLaunchKernelGGL(k_spmv_dot<L>, dim3(h.n_partials), dim3(kThreads), 0, s, st, m, h.rowptr.as<int64_t>(),
-                       h.col.as<int32_t>(), h.val.as<double>(), h.p.as<double>(), h.q.as<double>(),
+                       h.col.as<int32_t>(), h.val.as<double>(), dia_view(h), h.p.as<double>(), h.q.as<double>(),
                        h.part_sums.as<double>());
   });
   hipLaunchKernelGGL(k_alpha_scalar, dim3(h.nb), dim3(kThreads), 0, s, st, m, h.part_sums.as<double>(), history(h));
@@ -420,7 +493,7 @@ void launch_true_residual(Handle& h, const double* f, const double* x, hipStream
   with_lanes(h.lpr, [&](auto Lc) {
     constexpr int L = decltype(Lc)::value;
     hipLaunchKernelGGL(k_resid_dot<L>, dim3(h.n_partials), dim3(kThreads), 0, s, m, h.rowptr.as<int64_t>(),
-                       h.col.as<int32_t>(), h.val.as<double>(), f, x, h.part_sums.as<double>());
+                       h.col.as<int32_t>(), h.val.as<double>(), dia_view(h), f, x, h.part_sums.as<double>());
   });
   hipLaunchKernelGGL(k_true_scalar, dim3(h.nb), dim3(kThreads), 0, s, h.cstate.as<CgState>(), m,
                      h.part_sums.as<double>());

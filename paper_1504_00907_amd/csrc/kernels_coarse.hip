@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr,
     const int32_t* __restrict__ own_idx, const int32_t* __restrict__ kcnt, const double* __restrict__ Q, int kq,
     const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ val,
-    const double* __restrict__ r, const double* __restrict__ e, int rch, double* __restrict__ rpart) {
+    DiaView D, const double* __restrict__ r, const double* __restrict__ e, int rch, double* __restrict__ rpart) {
   const int i = blockIdx.y, c = blockIdx.x;
   if (st && st[sub_inst[i]].done) return;
   __shared__ double red[kRThreads / 64][kMaxK];
@@ -51,8 +51,14 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
       double sv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) g[u] = t + u * kRThreads < t1 ? own_idx[t + u * kRThreads] : -1;
+      if (D.diag) {
+        const DiaSys& sy = D.sys[sub_inst[i]];
 #pragma unroll
-      for (int u = 0; u < U; ++u) sv[u] = g[u] >= 0 ? row_sub(rp, ci, val, e, g[u], r[g[u]]) : 0.0;
+        for (int u = 0; u < U; ++u) sv[u] = g[u] >= 0 ? dia_row_sub(D, sy, e, g[u], r[g[u]]) : 0.0;
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) sv[u] = g[u] >= 0 ? row_sub(rp, ci, val, e, g[u], r[g[u]]) : 0.0;
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (g[u] < 0) continue;
@@ -174,7 +180,34 @@ __global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ 
   e[g] += s;
 }
 
+// F0[koff[i] + j, c] = sum over the own rows g of subdomain i of Q[g, j] F[g, c]
+// (F0 = R0 F); one workgroup per subdomain, one thread per (j, c), rows in order.
+__global__ void k_restrict_columns(const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
+                                   const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
+                                   const double* __restrict__ Q, int kq, const double* __restrict__ F, int64_t n,
+                                   int64_t ld0, double* __restrict__ F0) {
+  const int i = blockIdx.x;
+  const int ki = kcnt[i];
+  for (int t = threadIdx.x; t < ki * kq; t += blockDim.x) {
+    const int j = t % ki, c = t / ki;
+    double s = 0.0;
+    for (int64_t u = own_ptr[i]; u < own_ptr[i + 1]; ++u) {
+      const int g = own_idx[u];
+      s += Q[(int64_t)g * kq + j] * F[(int64_t)c * n + g];
+    }
+    F0[(int64_t)c * ld0 + koff[i] + j] = s;
+  }
+}
+
 }  // namespace
+
+void launch_restrict_columns(Handle& h, double* F0, hipStream_t s) {
+  launch_fill(F0, 0.0, h.nc_pad * h.k, s);
+  hipLaunchKernelGGL(k_restrict_columns, dim3((unsigned)h.S.n_parts), dim3(256), 0, s, h.own_ptr.as<int64_t>(),
+                     h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(), h.Q.as<double>(), h.k,
+                     h.F.as<double>(), h.S.n, h.nc_pad, F0);
+  DDG_HIP(hipGetLastError());
+}
 
 void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                   const CgState* st, hipStream_t s, bool residual);
@@ -191,12 +224,17 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
     constexpr int L = decltype(Lc)::value;
     hipLaunchKernelGGL(k_coarse_restrict<L>, dim3((unsigned)h.nch, (unsigned)S.n_parts), dim3(kRThreads), 0, s, st,
                        sub_inst, h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
-                       h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(), r, e,
-                       h.rch, h.ws.rpart);
+                       h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(),
+                       dia_view(h), r, e, h.rch, h.ws.rpart);
   });
   hipLaunchKernelGGL(k_coarse_restrict_sum, dim3((unsigned)(((int64_t)S.n_parts * kMaxK + 255) / 256)), dim3(256), 0,
                      s, st, sub_inst, h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(), h.ws.rpart, h.nch,
                      S.n_parts, b0);
+  if (h.inner) {
+    // three levels: y = M0^{-1} b0, one application of the coarse level's two-level
+    // preconditioner (its kernels skip work once this handle's system has stopped)
+    launch_precond(*h.inner, b0, y, -1, false, s, st);
+  } else {
   double* rowpart = h.ws.cpart;
   double* colpart = rowpart + h.ntiles * 64;
   hipLaunchKernelGGL(k_coarse_symv, dim3((unsigned)((h.ntiles + 3) / 4)), dim3(256), 0, s, st,
@@ -205,6 +243,7 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
   hipLaunchKernelGGL(k_coarse_sum, dim3((unsigned)((h.nc_pad + 255) / 256)), dim3(256), 0, s, st,
                      h.trow_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
                      rowpart, colpart, h.nc_pad, y);
+  }
   hipLaunchKernelGGL(k_coarse_prolong, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st, sub_inst,
                      h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
                      h.Q.as<double>(), h.k, y, e, S.n);
@@ -268,8 +307,9 @@ static void flow_profiled(Handle& h, int dir, const double* r, double* e, const 
   h.pending.push_back({idx, 2 * h.S.n_colours + dir, h.cur_tag});
 }
 
-void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded, hipStream_t s) {
-  const CgState* st = guarded ? h.cstate.as<CgState>() : nullptr;
+void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool guarded, hipStream_t s,
+                    const CgState* guard) {
+  const CgState* st = guard ? guard : (guarded ? h.cstate.as<CgState>() : nullptr);
   const int C = h.S.n_colours;
   const int total = 2 * C + 1;
   if (stages < 0 || stages > total) stages = total;

@@ -1070,6 +1070,12 @@ void refresh_sliced(Handle& h, hipStream_t s) {
                      h.up_val.as<double>(), S.cu, h.sl_up_val.as<AT>());
 }
 
+void launch_gather(const int64_t* pos, const double* src, double* dst, int64_t m, hipStream_t s) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_gather_vals, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, pos, src, dst, m);
+  DDG_HIP(hipGetLastError());
+}
+
 void launch_refresh_couplings(Handle& h, hipStream_t s) {
   const int64_t nlo = (int64_t)h.S.lo_pos.size(), nup = (int64_t)h.S.up_pos.size();
   if (nlo)

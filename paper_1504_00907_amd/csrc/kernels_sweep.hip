@@ -660,14 +660,16 @@ __global__ void __launch_bounds__(NW * 64) k_sweep_flow(SweepArgs a, FlowArgs f)
 }
 
 // b = (r - A e) on the expanded sets of one colour, written in set order; L lanes
-// per CSR row (one row per lane when L = 1).
+// per CSR row (one row per lane when L = 1, from the diagonals when the handle
+// stores them).
 template <int L>
 __global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const int32_t* __restrict__ sub_inst,
                                                         const int32_t* __restrict__ subs,
                                                         const int64_t* __restrict__ set_ptr,
                                                         const int32_t* __restrict__ set_idx,
                                                         const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                        const double* __restrict__ val, const double* __restrict__ r,
+                                                        const double* __restrict__ val, DiaView D,
+                                                        const double* __restrict__ r,
                                                         const double* __restrict__ e, int e_zero,
                                                         double* __restrict__ bres) {
   const int sub = subs[blockIdx.y];
@@ -679,7 +681,9 @@ __global__ void __launch_bounds__(256) k_local_residual(const CgState* st, const
   const int g = set_idx[s0 + j];
   if constexpr (L == 1) {
     const double rg = r[g];
-    bres[s0 + j] = e_zero ? rg : row_sub(rp, ci, val, e, g, rg);
+    if (e_zero) bres[s0 + j] = rg;
+    else if (D.diag) bres[s0 + j] = dia_row_sub(D, D.sys[sub_inst[sub]], e, g, rg);
+    else bres[s0 + j] = row_sub(rp, ci, val, e, g, rg);
   } else {
     const double ae = e_zero ? 0.0 : row_dot_l<L>(rp, ci, val, e, g, threadIdx.x & (L - 1));
     if ((threadIdx.x & (L - 1)) == 0) bres[s0 + j] = r[g] - ae;
@@ -788,8 +792,8 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
     with_lanes(h.lpr, [&](auto Lc) {
       constexpr int L = decltype(Lc)::value;
       hipLaunchKernelGGL(k_local_residual<L>, dim3((unsigned)(((int64_t)S.max_set * L + 255) / 256), (unsigned)nsub),
-                         dim3(256), 0, s, st, a.sub_inst, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val, r, e,
-                         a.e_zero, h.ws.bres);
+                         dim3(256), 0, s, st, a.sub_inst, a.subs, a.set_ptr, a.set_idx, a.rp, a.ci, a.val,
+                         dia_view(h), r, e, a.e_zero, h.ws.bres);
     });
     DDG_HIP(hipGetLastError());
     return;

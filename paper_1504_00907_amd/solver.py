@@ -28,7 +28,7 @@ def _dev(t: torch.Tensor, n: int, name: str) -> int:
 
 
 def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream,
-             schedule="auto", cg_variant="fr"):
+             schedule="auto", cg_variant="fr", matrix_format="auto"):
     opt = Options()
     lib.ddg_default_options(C.byref(opt))
     opt.precision = _lib.PRECISION[precision]
@@ -40,6 +40,7 @@ def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check
     opt.check_every = check_every
     opt.schedule = _lib.SCHEDULE[schedule]
     opt.cg_variant = _lib.CG_VARIANT[cg_variant]
+    opt.matrix_format = _lib.MATRIX_FORMAT[matrix_format]
     opt.stream = C.c_void_p(stream.cuda_stream)
     return opt
 
@@ -50,7 +51,10 @@ class DDGSolver:
     def __init__(self, n: int, row_ptr, col_idx, val, F: Optional[np.ndarray], part, n_parts: int,
                  overlap: int, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000,
                  rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0, check_every: int = 4,
-                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto", cg_variant: str = "fr"):
+                 stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto", cg_variant: str = "fr",
+                 matrix_format: str = "auto", part0=None, n_parts0: int = 0):
+        """``part0`` (coarse subdomain of every subdomain, ``n_parts0`` of them) selects
+        the three-level V-cycle (``ddg_setup_three_level``)."""
         lib = _lib.load()
         self._lib = lib
         self.n = int(n)
@@ -73,11 +77,18 @@ class DDGSolver:
             raise ValueError("F must have n rows")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
-                       schedule, cg_variant)
+                       schedule, cg_variant, matrix_format)
         self.precision = precision
         h = C.c_void_p()
-        check(lib.ddg_setup(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
-                            int(n_parts), int(overlap), C.byref(opt)))
+        if part0 is None:
+            check(lib.ddg_setup(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
+                                int(n_parts), int(overlap), C.byref(opt)))
+        else:
+            p0 = np.ascontiguousarray(part0, dtype=np.int32)
+            if p0.shape != (int(n_parts),):
+                raise ValueError("part0 must have n_parts entries")
+            check(lib.ddg_setup_three_level(C.byref(h), self.n, _ptr(rp), _ptr(ci), _ptr(vv), k, Fp, _ptr(pp),
+                                            int(n_parts), int(overlap), _ptr(p0), int(n_parts0), C.byref(opt)))
         self._h = h
         self.nnz = int(rp[-1])
         self.k = k
@@ -254,14 +265,14 @@ class DDGBatchSolver(DDGSolver):
     def __init__(self, problems, overlap: int, precision: str = "fp64", rtol: float = 1e-8,
                  max_iter: int = 1000, rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0,
                  check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto",
-                 cg_variant: str = "fr"):
+                 cg_variant: str = "fr", matrix_format: str = "auto"):
         lib = _lib.load()
         self._lib = lib
         self.max_iter = int(max_iter)
         arr, keep = _problem_array(problems)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
-                       schedule, cg_variant)
+                       schedule, cg_variant, matrix_format)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup_batched(C.byref(h), len(problems), arr, int(overlap), C.byref(opt)))

@@ -39,6 +39,7 @@ def test_default_options():
     lib.ddg_default_options(C.byref(o))
     assert (o.precision, o.max_iter, o.rtol, o.rank_tol) == (0, 1000, 1e-8, 1e-10)
     assert (o.tile, o.block_target, o.check_every, o.schedule, o.cg_variant) == (0, 0, 4, 0, 0)
+    assert o.matrix_format == 0
 
 
 class Analysis:
