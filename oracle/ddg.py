@@ -248,7 +248,11 @@ class DDGOracle:
         self.n_colours = int(self.colours.max()) + 1
         self.order = [np.flatnonzero(self.colours == c) for c in range(self.n_colours)]
         self.rows = [A[s] for s in self.sets]
-        self.local = [_LocalSolver(A[s][:, s], i) for i, s in enumerate(self.sets)]
+        self.local = [self._make_local(A[s][:, s], i) for i, s in enumerate(self.sets)]
+
+    def _make_local(self, Ai, i):
+        """Exact solver of the local problem A_i (Section 6: solved exactly)."""
+        return _LocalSolver(Ai, i)
 
     # -- pieces ------------------------------------------------------------
 
