@@ -257,6 +257,159 @@ def elasticity(nel: int, steps: int, tile: int = 0, block_target: int = 0):
     return out
 
 
+def three_level(P, precision: str, steps: int, group: int = 2):
+    """Three-level V-cycle on the headline workload (Section 6, three-level paragraph).
+
+    The 8^3 boxes are grouped 2^3 per coarse subdomain (64 coarse subdomains); the
+    coarse level applies the two-level method to A0 with F0 = R0 F and overlap 1,
+    in FP64.  Iterations and time per solve beside the two-level method's (Table 1
+    compares the two: context, parity unpinned).
+    """
+    import torch
+
+    from paper_1504_00907_amd import DDGSolver
+    from workloads import box_groups
+
+    m = round(P.n_parts ** (1 / 3))
+    part0, n0 = box_groups((m, m, m), (group, group, group))
+    f = torch.from_numpy(P.f).cuda()
+    t0 = time.perf_counter()
+    s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol, part0=part0, n_parts0=n0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    u = torch.empty_like(f)
+    s.solve(f, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = s.solve(f, u)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    uh = u.cpu().numpy()
+    true_res = float(np.linalg.norm(P.f - P.A.to_scipy() @ uh) / np.linalg.norm(P.f))
+    hi = s.info()
+    s.close()
+    rec = {"coarse_subdomains": n0, "group": group, "precision": precision, "ms_per_solve": ms,
+           "iters": info["iters"], "true_rel_res": true_res, "n_coarse": hi["n_coarse"],
+           "n_coarsest": hi["n_coarsest"], "setup_s": setup_s, "setup_ms_device": hi["setup_ms"]}
+    log(f"three-level: {ms:.2f} ms/solve, iters {info['iters']}, true res {true_res:.2e}, "
+        f"N_c {hi['n_coarse']} -> {hi['n_coarsest']}")
+    return rec
+
+
+def inexact(P, steps: int, omega: float = 1.0, sweeps: int = 1):
+    """Section 7's inexact variant on the headline workload: the subdomains smoothed by
+    symmetric SOR (no local factors) instead of solved exactly, coarse inverse exact,
+    FP64.  Iterations, time per solve and setup beside the exact solves (context for
+    Table 2: cheaper setup and memory, more iterations)."""
+    import torch
+
+    from paper_1504_00907_amd import DDGSolver
+
+    f = torch.from_numpy(P.f).cuda()
+    t0 = time.perf_counter()
+    s = DDGSolver.from_problem(P, precision="fp64", rtol=P.rtol, local_solver="ssor", ssor_omega=omega,
+                               ssor_sweeps=sweeps)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    u = torch.empty_like(f)
+    s.solve(f, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = s.solve(f, u)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    uh = u.cpu().numpy()
+    true_res = float(np.linalg.norm(P.f - P.A.to_scipy() @ uh) / np.linalg.norm(P.f))
+    hi = s.info()
+    s.close()
+    log(f"ssor local smoothing: {ms:.2f} ms/solve, iters {info['iters']}, true res {true_res:.2e}, "
+        f"setup {setup_s:.2f} s")
+    return {"local_solver": "ssor", "omega": omega, "sweeps": sweeps, "precision": "fp64", "ms_per_solve": ms,
+            "iters": info["iters"], "true_rel_res": true_res, "setup_s": setup_s,
+            "setup_ms_device": hi["setup_ms"], "factor_bytes": hi["factor_bytes"]}
+
+
+def biharmonic(m: int, boxes: int, overlap: int, ps, steps: int):
+    """Biharmonic high-p study (Section 7 problem F; Fig. 5's setting: m = 1000,
+    H/h = 125, overlap 2, tolerance 1e-6), FP64 local factors: iterations, time
+    and coarse size per degree p.  The iteration counts are context (Fig. 5's
+    plotted values are not available)."""
+    import torch
+
+    from paper_1504_00907_amd import DDGSolver
+    from workloads.biharmonic import biharmonic_problem
+
+    out = {"workload": f"biharmonic13_{m}^2", "n": m * m, "subdomains": boxes * boxes, "overlap": overlap,
+           "rtol": 1e-6, "precision": "fp64", "per_p": []}
+    for p in ps:
+        P = biharmonic_problem(m, boxes, overlap, p, rtol=1e-6)
+        f = torch.from_numpy(P.f).cuda()
+        t0 = time.perf_counter()
+        s = DDGSolver.from_problem(P, precision="fp64", rtol=1e-6)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        u = torch.empty_like(f)
+        _, info = s.solve(f, u, raise_on_error=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, info = s.solve(f, u, raise_on_error=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        uh = u.cpu().numpy()
+        true_res = float(np.linalg.norm(P.f - P.A.to_scipy() @ uh) / np.linalg.norm(P.f))
+        hi = s.info()
+        rep = s.cg_report()
+        s.close()
+        fin = lambda x: float(x) if np.isfinite(x) else None  # noqa: E731
+        rec = {"p": p, "k": int(P.F.shape[1]), "n_coarse": hi["n_coarse"], "iters": info["iters"],
+               "frac_iters": fin(rep["frac_iters"]), "kappa_estimate": fin(rep["kappa"]),
+               "iter_bound": rep["iter_bound"], "status": info["status_name"],
+               "ms_per_solve": ms, "true_rel_res": true_res, "setup_s": setup_s,
+               "matrix_format": _lib_format(hi)}
+        out["per_p"].append(rec)
+        log(f"biharmonic p={p}: k {rec['k']}, N_c {hi['n_coarse']}, iters {info['iters']}, {ms:.1f} ms/solve, "
+            f"true res {true_res:.2e}")
+        torch.cuda.empty_cache()
+    return out
+
+
+def materials(L: int, boxes: int, p: int, steps: int):
+    """Two-material diffusion (Section 7 problem C) with plain and material-aware
+    generating vectors (degree p, tolerance 1e-9, FP32 local factors): the paper
+    reports close to half the iterations with the aware cubic basis (context)."""
+    import torch
+
+    from paper_1504_00907_amd import DDGSolver
+    from workloads.materials import material_problem
+
+    out = {"workload": f"two_material_{L}^2", "n": L * L, "subdomains": boxes * boxes, "p": p, "rtol": 1e-9}
+    for aware in (False, True):
+        P = material_problem(L, boxes, 1, p, aware)
+        f = torch.from_numpy(P.f).cuda()
+        s = DDGSolver.from_problem(P, precision="fp32", rtol=1e-9)
+        u = torch.empty_like(f)
+        s.solve(f, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, info = s.solve(f, u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        hi = s.info()
+        s.close()
+        out["aware" if aware else "plain"] = {"k": int(P.F.shape[1]), "n_coarse": hi["n_coarse"],
+                                             "iters": info["iters"], "ms_per_solve": ms}
+        log(f"materials {'aware' if aware else 'plain'}: N_c {hi['n_coarse']}, iters {info['iters']}, {ms:.2f} ms")
+    return out
+
+
+def _lib_format(info: dict) -> str:
+    return {1: "csr", 2: "dia"}.get(info.get("matrix_format"), "?")
+
+
 def _batch_instance(arg):
     """Host arrays of one system of the batched workload (runs in a worker process)."""
     from workloads import cfg4_instance
@@ -487,6 +640,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg (256 uneven 2D systems)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D Q1 elasticity leg")
+    ap.add_argument("--no-three-level", action="store_true", help="skip the three-level V-cycle leg")
+    ap.add_argument("--no-biharmonic", action="store_true", help="skip the biharmonic high-p leg")
+    ap.add_argument("--biharmonic-m", type=int, default=1000)
+    ap.add_argument("--biharmonic-boxes", type=int, default=8)
+    ap.add_argument("--biharmonic-p", default="1,2,3,4,6")
+    ap.add_argument("--no-materials", action="store_true", help="skip the two-material leg")
+    ap.add_argument("--no-inexact", action="store_true", help="skip the SSOR local smoothing leg")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the forward+adjoint leg and print its record (for profiling the refactor)")
     ap.add_argument("--elasticity-only", action="store_true",
@@ -636,6 +796,31 @@ def main():
             sbf.close()
             del sbf
 
+    lvl3 = None
+    if not args.no_three_level:
+        lvl3 = three_level(P, args.precision, max(1, args.steps // 2))
+        lvl3["two_level_ms_per_solve"] = ms_mx
+        lvl3["two_level_iters"] = info_mx["iters"]
+        torch.cuda.empty_cache()
+
+    inx = None
+    if not args.no_inexact:
+        inx = inexact(P, max(1, args.steps // 2))
+        inx["exact_fp64_ms_per_solve"] = out64.get("fp64_ms_per_solve")
+        inx["exact_iters"] = info_mx["iters"]
+        torch.cuda.empty_cache()
+
+    bih = None
+    if not args.no_biharmonic:
+        bih = biharmonic(args.biharmonic_m, args.biharmonic_boxes, 2,
+                         [int(x) for x in args.biharmonic_p.split(",") if x], 1)
+        torch.cuda.empty_cache()
+
+    mat = None
+    if not args.no_materials:
+        mat = materials(512, 16, 3, max(1, args.steps // 2))
+        torch.cuda.empty_cache()
+
     ela = None
     if not args.no_elasticity:
         ela = elasticity(args.elasticity_nel, max(1, args.steps // 2), args.elasticity_tile,
@@ -740,7 +925,12 @@ def main():
         "survey_iter_bytes": survey_iter,
         "envelope_elems": E,
         **out64,
+        "matrix_format": _lib_format(hinfo),
         "fwd_adjoint": adj,
+        "three_level": lvl3,
+        "inexact": inx,
+        "biharmonic": bih,
+        "materials": mat,
         "batched": bat,
         "elasticity": ela,
         "tuned": tuned,

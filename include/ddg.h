@@ -86,6 +86,15 @@ typedef enum {
   DDG_MATRIX_DIA = 2    /* (reported in ddg_info only) the diagonals are in use */
 } ddg_matrix_format;
 
+/* How each subdomain problem is treated inside the Schwarz sweeps. */
+typedef enum {
+  DDG_LOCAL_EXACT = 0,  /* solved exactly (Section 6): stored factorisation of every A_i */
+  DDG_LOCAL_SSOR = 1    /* smoothed by symmetric SOR (Section 7, the timed 3D runs): ssor_sweeps
+                           forward-then-backward sweeps from zero with relaxation ssor_omega, rows
+                           taken colour by colour in a greedy colouring of the graph of A_i
+                           (ascending local index); FP64; no local factors are stored */
+} ddg_local_solver;
+
 typedef struct {
   int32_t precision;   /* ddg_precision */
   int32_t max_iter;    /* CG iteration cap (default 1000, Section 7) */
@@ -98,6 +107,9 @@ typedef struct {
   int32_t cg_variant;  /* ddg_cg_variant (default DDG_CG_FLETCHER_REEVES) */
   void* stream;        /* hipStream_t for all work; NULL = the null stream */
   int32_t matrix_format; /* DDG_MATRIX_AUTO (default) or DDG_MATRIX_CSR */
+  int32_t local_solver;  /* ddg_local_solver (default DDG_LOCAL_EXACT) */
+  double ssor_omega;     /* relaxation of DDG_LOCAL_SSOR, 0 < omega < 2 (default 1) */
+  int32_t ssor_sweeps;   /* symmetric sweeps of DDG_LOCAL_SSOR, >= 1 (default 1) */
 } ddg_options;
 
 typedef struct {
@@ -133,7 +145,7 @@ void ddg_default_options(ddg_options* opt);
  * Build the two-level preconditioner (Sections 4 and 6).
  *   n, row_ptr[n+1], col_idx[nnz], val[nnz]  host; full symmetric CSR, sorted columns,
  *                                             positive diagonal (checked).
- *   k, F[n*k]        host; generating vectors, column-major (column j at F + j*n).
+ *   k, F[n*k]        host; generating vectors, column-major (column j at F + j*n), k <= 80.
  *                    k = 0 disables the coarse grid.
  *   part[n]          host; non-overlapping subdomain id of each unknown, in [0, n_parts);
  *                    every subdomain non-empty.
@@ -200,7 +212,7 @@ typedef struct {
   const int64_t* row_ptr;   /* n+1 */
   const int32_t* col_idx;   /* row_ptr[n], local column ids */
   const double* val;
-  int32_t k;                /* generating vectors (<= 32); may differ between systems */
+  int32_t k;                /* generating vectors (<= 80); may differ between systems */
   const double* F;          /* n x k column-major */
   const int32_t* part;      /* n, ids in [0, n_parts) */
   int32_t n_parts;

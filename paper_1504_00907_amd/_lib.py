@@ -26,6 +26,7 @@ SCHEDULE = {"auto": 0, "colours": 1, "queue": 2}
 BC = {"dirichlet": 0, "x0": 1}
 CG_VARIANT = {"fr": 0, "pr": 1}
 MATRIX_FORMAT = {"auto": 0, "csr": 1}
+LOCAL_SOLVER = {"exact": 0, "ssor": 1}
 MATRIX_FORMAT_NAME = {1: "csr", 2: "dia"}
 
 
@@ -34,7 +35,8 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
         ("rank_tol", C.c_double), ("tile", C.c_int32), ("block_target", C.c_int32),
         ("check_every", C.c_int32), ("schedule", C.c_int32), ("cg_variant", C.c_int32),
-        ("stream", C.c_void_p), ("matrix_format", C.c_int32),
+        ("stream", C.c_void_p), ("matrix_format", C.c_int32), ("local_solver", C.c_int32),
+        ("ssor_omega", C.c_double), ("ssor_sweeps", C.c_int32),
     ]
 
 

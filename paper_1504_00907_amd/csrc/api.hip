@@ -133,6 +133,13 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
       }
       int64_t nnz_rows = 0;
       for (int64_t t = r0; t < r1; ++t) nnz_rows += rp[S.set_idx[t] + 1] - rp[S.set_idx[t]];
+      if (h.ssor) {
+        // SSOR: residual read, set index, e read-modify-write once; per relaxation of a
+        // row (2 per sweep) its row pointer, local entries (column + value), diagonal and
+        // place in the colour order; the iterate itself stays on chip
+        fb = 0;
+        cpl = 2 * (int64_t)h.opt.ssor_sweeps * (ni * (8 + 8 + 4) + h.ss_nnz_sub[i] * 12);
+      }
       bytes += fb + cpl + ni * (8 + 4 + 16);
       resid0 += ni * (4 + 8 + 8);
       // a gathered row from the diagonals reads its diagonal and both sides' entries
@@ -176,7 +183,7 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
   h.info.iter_bytes = sweep + coarse + cg + n * 8;
   h.info.tile = S.tile;
   h.info.schedule = h.flow_ok ? DDG_SCHEDULE_QUEUE : DDG_SCHEDULE_COLOURS;
-  h.info.factor_bytes = S.fac_elems * es;
+  h.info.factor_bytes = h.ssor ? 0 : S.fac_elems * es;
   h.info.coarse_bytes = h.nc ? ntiles * 64 * 64 * 8 : 0;
 }
 
@@ -210,6 +217,66 @@ void check_err_flag(Handle& h, const char* what) {
   }
 }
 
+// Local CSR, diagonal positions and local colouring of every A_i for SSOR
+// smoothing (integers only): colour(r) is the smallest colour not taken by a
+// coupled local row r' < r, and the rows of a subdomain are listed colour by
+// colour, ascending within a colour.
+void build_ssor(Handle& h, const int64_t* rp, const int32_t* ci) {
+  const Symbolic& S = h.S;
+  const int64_t tot = S.set_ptr[S.n_parts];
+  std::vector<int64_t> ptr((size_t)tot + 1, 0), pos, dpos((size_t)tot, -1);
+  std::vector<int32_t> col, perm((size_t)tot), cptr((size_t)S.n_parts + 1, 0), coff;
+  std::vector<int32_t> loc((size_t)S.n, -1), colour;
+  h.ss_nnz_sub.assign(S.n_parts, 0);
+  for (int32_t i = 0; i < S.n_parts; ++i) {
+    const int64_t r0 = S.set_ptr[i], r1 = S.set_ptr[i + 1];
+    const int32_t ni = (int32_t)(r1 - r0);
+    for (int64_t t = r0; t < r1; ++t) loc[S.set_idx[t]] = (int32_t)(t - r0);
+    colour.assign(ni, -1);
+    int32_t ncol = 0;
+    std::vector<char> used;
+    for (int64_t t = r0; t < r1; ++t) {
+      const int32_t g = S.set_idx[t], r = (int32_t)(t - r0);
+      used.assign((size_t)ncol + 1, 0);
+      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+        const int32_t l = loc[ci[e]];
+        if (l < 0) continue;
+        col.push_back(l);
+        pos.push_back(e);
+        if (l == r) dpos[(size_t)t] = e;
+        if (l < r) used[(size_t)colour[l]] = 1;
+      }
+      int32_t c = 0;
+      while (used[(size_t)c]) ++c;
+      colour[r] = c;
+      ncol = std::max(ncol, c + 1);
+      ptr[(size_t)t + 1] = (int64_t)col.size();
+      DDG_REQUIRE(dpos[(size_t)t] >= 0, DDG_ERR_INVALID_ARG, "row without a stored diagonal");
+    }
+    h.ss_nnz_sub[i] = ptr[(size_t)r1] - ptr[(size_t)r0];
+    cptr[i] = (int32_t)coff.size();
+    int32_t k = 0;
+    for (int32_t c = 0; c < ncol; ++c) {
+      coff.push_back(k);
+      for (int32_t r = 0; r < ni; ++r)
+        if (colour[r] == c) perm[(size_t)(r0 + k++)] = r;
+    }
+    coff.push_back(k);
+    for (int64_t t = r0; t < r1; ++t) loc[S.set_idx[t]] = -1;
+  }
+  cptr[S.n_parts] = (int32_t)coff.size();
+  hipStream_t s = h.stream;
+  h.ss_ptr.upload(ptr, s);
+  h.ss_col.upload(col, s);
+  h.ss_pos.upload(pos, s);
+  h.ss_dpos.upload(dpos, s);
+  h.ss_perm.upload(perm, s);
+  h.ss_cptr.upload(cptr, s);
+  h.ss_coff.upload(coff, s);
+  h.ss_val.alloc(std::max<size_t>(1, pos.size()) * sizeof(double));
+  h.ss_diag.alloc((size_t)std::max<int64_t>(1, tot) * sizeof(double));
+}
+
 void numeric_setup(Handle& h) {
   hipEvent_t e0, e1;
   DDG_HIP(hipEventCreate(&e0));
@@ -228,7 +295,14 @@ void numeric_setup(Handle& h) {
     DDG_HIP(hipEventCreateWithFlags(&ec, hipEventDisableTiming));
     DDG_HIP(hipEventRecord(eg, h.stream));
   }
-  launch_local_factor(h, h.stream);
+  if (h.ssor) {
+    launch_gather(h.ss_pos.as<int64_t>(), h.val.as<double>(), h.ss_val.as<double>(),
+                  (int64_t)(h.ss_pos.bytes / sizeof(int64_t)), h.stream);
+    launch_gather(h.ss_dpos.as<int64_t>(), h.val.as<double>(), h.ss_diag.as<double>(), h.S.set_ptr[h.S.n_parts],
+                  h.stream);
+  } else {
+    launch_local_factor(h, h.stream);
+  }
   if (h.nc > 0 && !h.three_level) {
     DDG_HIP(hipStreamWaitEvent(h.side, eg, 0));
     launch_coarse_invert(h, h.side);
@@ -263,11 +337,13 @@ void numeric_setup(Handle& h) {
 }
 
 // Diagonal storage is possible when no system's rows have more than kDiaMax
-// distinct positive column offsets and the rows are short (one lane per row).
+// distinct positive column offsets (up to 13-point stencils); the row dots then
+// take one lane per row.
 void plan_dia(Handle& h, const int64_t* rp, const int32_t* ci) {
   h.dia_possible = false;
   h.dia_ok = false;
-  if (h.opt.matrix_format == DDG_MATRIX_CSR || h.lpr != 1) return;
+  if (h.opt.matrix_format == DDG_MATRIX_CSR || std::getenv("DDG_ROW_LANES")) return;
+  if (h.S.nnz > (2 * kDiaMax + 1) * h.S.n) return;
   std::vector<DiaSys> sys((size_t)h.nb);
   for (int32_t b = 0; b < h.nb; ++b) {
     DiaSys& d = sys[b];
@@ -297,6 +373,7 @@ void plan_dia(Handle& h, const int64_t* rp, const int32_t* ci) {
   h.dia_diag.alloc((size_t)h.S.n * sizeof(double));
   h.dia_up.alloc((size_t)h.dia_nd * h.S.n * sizeof(double));
   h.dia_possible = true;
+  h.lpr = 1;
 }
 
 // Durations of the profiled local-solve launches.  A launch enqueued by CG
@@ -381,12 +458,18 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   DDG_REQUIRE(h->opt.rtol >= 0.0 && h->opt.rank_tol >= 0.0, DDG_ERR_INVALID_ARG, "negative tolerance");
   DDG_REQUIRE(h->opt.cg_variant == DDG_CG_FLETCHER_REEVES || h->opt.cg_variant == DDG_CG_POLAK_RIBIERE,
               DDG_ERR_INVALID_ARG, "cg_variant must be a ddg_cg_variant value");
+  DDG_REQUIRE(h->opt.local_solver == DDG_LOCAL_EXACT || h->opt.local_solver == DDG_LOCAL_SSOR,
+              DDG_ERR_INVALID_ARG, "local_solver must be a ddg_local_solver value");
+  h->ssor = h->opt.local_solver == DDG_LOCAL_SSOR;
+  if (h->ssor)
+    DDG_REQUIRE(h->opt.ssor_omega > 0.0 && h->opt.ssor_omega < 2.0 && h->opt.ssor_sweeps >= 1, DDG_ERR_INVALID_ARG,
+                "SSOR needs 0 < ssor_omega < 2 and ssor_sweeps >= 1");
   h->stream = static_cast<hipStream_t>(h->opt.stream);
   h->k = k;
   h->nb = (int32_t)seg_off.size() - 1;
   h->seg_off = seg_off;
   h->sub_off = sub_off;
-  DDG_REQUIRE(k <= 32, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
+  DDG_REQUIRE(k <= kMaxGen, DDG_ERR_UNSUPPORTED, "at most 80 generating vectors");
   if (k > 0)
     for (int64_t t = 0; t < n * (int64_t)k; ++t)
       DDG_REQUIRE(std::isfinite(F[t]), DDG_ERR_INVALID_ARG, "non-finite generating vectors");
@@ -468,7 +551,9 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   // differs in its bits (diagonal storage check)
   h->err_flag.alloc(8 * sizeof(int32_t));
   DDG_HIP(hipMemsetAsync(h->err_flag.p, 0, 8 * sizeof(int32_t), s));
-  h->fac.alloc((size_t)S.fac_elems * storage_size(h->opt.precision));
+  // (SSOR smoothing stores no local factors)
+  h->fac.alloc(h->ssor ? 16 : (size_t)S.fac_elems * storage_size(h->opt.precision));
+  if (h->ssor) build_ssor(*h, row_ptr, col_idx);
   // coarse basis (depends only on F and the partition)
   h->kcnt.assign(n_parts, 0);
   h->koff.assign(n_parts + 1, 0);
@@ -543,6 +628,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   DDG_REQUIRE(h->opt.schedule >= DDG_SCHEDULE_AUTO && h->opt.schedule <= DDG_SCHEDULE_QUEUE,
               DDG_ERR_INVALID_ARG, "schedule must be a ddg_schedule value");
   h->flow_ok = h->opt.schedule == DDG_SCHEDULE_QUEUE;
+  DDG_REQUIRE(!(h->flow_ok && h->ssor), DDG_ERR_UNSUPPORTED, "SSOR smoothing runs with the colour launches only");
   if (h->flow_ok) {
     const int32_t C = S.n_colours;
     for (int dir = 0; dir < 2; ++dir) {
@@ -574,7 +660,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   }
   h->rch = 4 * 256 / h->lpr;
   h->nch = std::max<int32_t>(1, (S.max_own + h->rch - 1) / h->rch);
-  if (h->nc > 0) h->rpart.alloc((size_t)n_parts * h->nch * 32 * sizeof(double));
+  if (h->nc > 0) h->rpart.alloc((size_t)n_parts * h->nch * kslots(k) * sizeof(double));
   // CG workspace
   h->r.alloc((size_t)n * sizeof(double));
   h->p.alloc((size_t)n * sizeof(double));
@@ -798,6 +884,9 @@ void ddg_default_options(ddg_options* opt) {
   opt->schedule = DDG_SCHEDULE_AUTO;
   opt->cg_variant = DDG_CG_FLETCHER_REEVES;
   opt->matrix_format = DDG_MATRIX_AUTO;
+  opt->local_solver = DDG_LOCAL_EXACT;
+  opt->ssor_omega = 1.0;
+  opt->ssor_sweeps = 1;
   opt->stream = nullptr;
 }
 
@@ -886,6 +975,7 @@ int ddg_setup_three_level(ddg_handle* out, int64_t n, const int64_t* row_ptr, co
     in->opt.tile = 0;
     in->opt.block_target = 0;
     in->opt.schedule = DDG_SCHEDULE_COLOURS;
+    in->opt.local_solver = DDG_LOCAL_EXACT;
     try {
       setup_impl(*in, nc, rp0.data(), ci0.data(), v0.data(), k, F0c.data(), part_c.data(), n_parts0, overlap,
                  {0, nc}, {0, n_parts0});

@@ -120,6 +120,11 @@ struct Symbolic {
   std::vector<int32_t> sl_lo_col, sl_up_col;     // local column of each entry
 };
 
+// Most generating vectors per system (degree 10 in 2D has 66); the coarse kernels
+// keep per-thread column arrays of 32 entries, or of kMaxGen when k > 32.
+constexpr int kMaxGen = 80;
+inline int32_t kslots(int32_t k) { return k <= 32 ? 32 : kMaxGen; }
+
 // Couplings per row and direction that the sweep keeps in registers; wider rows use
 // the sliced layout.
 constexpr int kCplRegs = 2;
@@ -234,6 +239,14 @@ struct Handle {
   mutable int32_t flow_seq = 0;      // flow launches so far
   int64_t flow_bytes[2] = {0, 0};    // algorithmic bytes of one flow launch per direction
   DevBuf bres;                       // local residuals of one colour's expanded sets
+  // SSOR local smoothing (DDG_LOCAL_SSOR): the local CSR of every A_i over its set
+  // rows (per set row t: entries [ss_ptr[t], ss_ptr[t+1]) with local columns and their
+  // positions in A's values), the diagonal's position per set row, and per subdomain
+  // its local rows sorted by local colour (ss_perm, at the subdomain's set offset) with
+  // the colour offsets ss_coff[ss_cptr[i] .. ss_cptr[i+1]] (relative to the set offset)
+  bool ssor = false;
+  DevBuf ss_ptr, ss_col, ss_pos, ss_val, ss_dpos, ss_diag, ss_perm, ss_cptr, ss_coff;
+  std::vector<int64_t> ss_nnz_sub;   // local entries per subdomain (byte accounting)
   // diagonal storage of A (DiaView): possible when every system's entries lie on at
   // most kDiaMax offset pairs; in use while the values are also symmetric bit for bit
   bool dia_possible = false, dia_ok = false;

@@ -19,13 +19,13 @@ namespace ddg {
 namespace {
 
 constexpr int kRThreads = 256;
-constexpr int kMaxK = 32;
 
 // Partial restriction over one chunk of the own rows of subdomain i (workgroup
 // (c, i) takes rows [own_ptr[i] + c rch, ... + rch)), L lanes per CSR row:
 //   rpart[i, c, m] = sum_{g in chunk} Q[g, m] (r - A e)_g,   m < kcnt[i]
 // (waves in order after a butterfly per wave); empty chunks write zeros.
-template <int L>
+// KM: capacity of the per-thread column arrays and stride of rpart (kslots(k)).
+template <int L, int KM>
 __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr,
     const int32_t* __restrict__ own_idx, const int32_t* __restrict__ kcnt, const double* __restrict__ Q, int kq,
@@ -33,11 +33,11 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     DiaView D, const double* __restrict__ r, const double* __restrict__ e, int rch, double* __restrict__ rpart) {
   const int i = blockIdx.y, c = blockIdx.x;
   if (st && st[sub_inst[i]].done) return;
-  __shared__ double red[kRThreads / 64][kMaxK];
+  __shared__ double red[kRThreads / 64][KM];
   const int ki = kcnt[i];
-  double acc[kMaxK];
+  double acc[KM];
 #pragma unroll
-  for (int m = 0; m < kMaxK; ++m) acc[m] = 0.0;
+  for (int m = 0; m < KM; ++m) acc[m] = 0.0;
   const int64_t t0 = own_ptr[i] + (int64_t)c * rch;
   const int64_t t1 = min(own_ptr[i + 1], t0 + rch);
   const int jl = threadIdx.x & (L - 1);
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
         if (g[u] < 0) continue;
         const double* qg = Q + (int64_t)g[u] * kq;
 #pragma unroll
-        for (int m = 0; m < kMaxK; ++m)
+        for (int m = 0; m < KM; ++m)
           if (m < ki) acc[m] += qg[m] * sv[u];
       }
     }
@@ -75,14 +75,14 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
       if (jl == 0) {
         const double* qg = Q + (int64_t)g * kq;
 #pragma unroll
-        for (int m = 0; m < kMaxK; ++m)
+        for (int m = 0; m < KM; ++m)
           if (m < ki) acc[m] += qg[m] * s;
       }
     }
   }
   const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int m = 0; m < kMaxK; ++m) {
+  for (int m = 0; m < KM; ++m) {
     if (m < ki) {
       double v = wave_sum(acc[m]);
       if ((threadIdx.x & 63) == 0) red[wv][m] = v;
@@ -93,23 +93,23 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kRThreads / 64; ++w) s += red[w][threadIdx.x];
-    rpart[((int64_t)i * gridDim.x + c) * kMaxK + threadIdx.x] = s;
+    rpart[((int64_t)i * gridDim.x + c) * KM + threadIdx.x] = s;
   }
 }
 
 // b0[koff[i] + m] = sum over the nch chunks of subdomain i, in chunk order
 __global__ void k_coarse_restrict_sum(const CgState* st, const int32_t* __restrict__ sub_inst,
                                       const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
-                                      const double* __restrict__ rpart, int nch, int n_parts,
+                                      const double* __restrict__ rpart, int nch, int n_parts, int KM,
                                       double* __restrict__ b0) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(id / kMaxK), m = (int)(id % kMaxK);
+  const int i = (int)(id / KM), m = (int)(id % KM);
   if (i >= n_parts) return;
   if (st && st[sub_inst[i]].done) return;
   if (m >= kcnt[i]) return;
-  const double* p = rpart + (int64_t)i * nch * kMaxK + m;
+  const double* p = rpart + (int64_t)i * nch * KM + m;
   double s = 0.0;
-  for (int c = 0; c < nch; ++c) s += p[(int64_t)c * kMaxK];
+  for (int c = 0; c < nch; ++c) s += p[(int64_t)c * KM];
   b0[koff[i] + m] = s;
 }
 
@@ -156,7 +156,8 @@ __global__ void k_coarse_sum(const CgState* st, const int32_t* __restrict__ trow
   y[row] = s;
 }
 
-__global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ sub_inst,
+template <int KM>
+__global__ void __launch_bounds__(256) k_coarse_prolong(const CgState* st, const int32_t* __restrict__ sub_inst,
                                  const int32_t* __restrict__ part,
                                  const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
                                  const double* __restrict__ Q, int kq, const double* __restrict__ y,
@@ -166,16 +167,16 @@ __global__ void k_coarse_prolong(const CgState* st, const int32_t* __restrict__ 
   // the row of Q (stride kq) is requested before the subdomain's count and offset
   // are known, so its loads do not wait behind that chain of lookups
   const double* qg = Q + g * kq;
-  double q[kMaxK];
+  double q[KM];
 #pragma unroll
-  for (int m = 0; m < kMaxK; ++m) q[m] = m < kq ? qg[m] : 0.0;
+  for (int m = 0; m < KM; ++m) q[m] = m < kq ? qg[m] : 0.0;
   const int i = part[g];
   if (st && st[sub_inst[i]].done) return;
   const int ki = kcnt[i];
   const double* yi = y + koff[i];
   double s = 0.0;
 #pragma unroll
-  for (int m = 0; m < kMaxK; ++m)
+  for (int m = 0; m < KM; ++m)
     if (m < ki) s += q[m] * yi[m];
   e[g] += s;
 }
@@ -212,24 +213,23 @@ void launch_restrict_columns(Handle& h, double* F0, hipStream_t s) {
 void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                   const CgState* st, hipStream_t s, bool residual);
 
-void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s) {
-  if (h.nc == 0) return;
+template <int KM>
+void launch_coarse_k(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s) {
   const Symbolic& S = h.S;
-  DDG_REQUIRE(h.k <= kMaxK, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
   double* b0 = h.ws.cy;             // padded to whole tiles, zero beyond each block
   double* y = b0 + h.nc_pad;
   const int32_t* sub_inst = h.sub_inst.as<int32_t>();
   DDG_REQUIRE(h.rch * h.lpr == 4 * kRThreads, DDG_ERR_HIP, "internal: restriction chunking");
   with_lanes(h.lpr, [&](auto Lc) {
     constexpr int L = decltype(Lc)::value;
-    hipLaunchKernelGGL(k_coarse_restrict<L>, dim3((unsigned)h.nch, (unsigned)S.n_parts), dim3(kRThreads), 0, s, st,
+    hipLaunchKernelGGL((k_coarse_restrict<L, KM>), dim3((unsigned)h.nch, (unsigned)S.n_parts), dim3(kRThreads), 0, s, st,
                        sub_inst, h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
                        h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(),
                        dia_view(h), r, e, h.rch, h.ws.rpart);
   });
-  hipLaunchKernelGGL(k_coarse_restrict_sum, dim3((unsigned)(((int64_t)S.n_parts * kMaxK + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL(k_coarse_restrict_sum, dim3((unsigned)(((int64_t)S.n_parts * KM + 255) / 256)), dim3(256), 0,
                      s, st, sub_inst, h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(), h.ws.rpart, h.nch,
-                     S.n_parts, b0);
+                     S.n_parts, KM, b0);
   if (h.inner) {
     // three levels: y = M0^{-1} b0, one application of the coarse level's two-level
     // preconditioner (its kernels skip work once this handle's system has stopped)
@@ -244,10 +244,17 @@ void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hip
                      h.trow_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
                      rowpart, colpart, h.nc_pad, y);
   }
-  hipLaunchKernelGGL(k_coarse_prolong, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st, sub_inst,
+  hipLaunchKernelGGL(k_coarse_prolong<KM>, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st, sub_inst,
                      h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
                      h.Q.as<double>(), h.k, y, e, S.n);
   DDG_HIP(hipGetLastError());
+}
+
+void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s) {
+  if (h.nc == 0) return;
+  DDG_REQUIRE(h.k <= kMaxGen, DDG_ERR_UNSUPPORTED, "at most 80 generating vectors");
+  if (h.k <= 32) launch_coarse_k<32>(h, r, e, st, s);
+  else launch_coarse_k<kMaxGen>(h, r, e, st, s);
 }
 
 // Attaches an event pair to the next local-solve dispatch for the scope's lifetime.

@@ -18,7 +18,6 @@ namespace ddg {
 
 namespace {
 
-constexpr int kMaxKq = 32;
 
 // Error record: [0] = code (0 none), [1] = subdomain, [2] = block, [3] = local row
 __device__ inline void record_error(int32_t* err, int code, int sub, int blk, int row) {
@@ -30,22 +29,21 @@ __device__ inline void record_error(int32_t* err, int code, int sub, int blk, in
 }
 
 // Sum `cnt` per-thread values across a 256-thread workgroup; results in out[0..cnt).
-template <int NT>
-__device__ inline void multi_sum(double (&acc)[kMaxKq], int cnt, double* red /*[NT/64][kMaxKq]*/,
-                                 double* out) {
+template <int NT, int KM>
+__device__ inline void multi_sum(double (&acc)[KM], int cnt, double* red /*[NT/64][KM]*/, double* out) {
   const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int m = 0; m < kMaxKq; ++m) {
+  for (int m = 0; m < KM; ++m) {
     if (m < cnt) {
       double v = wave_sum(acc[m]);
-      if ((threadIdx.x & 63) == 0) red[wv * kMaxKq + m] = v;
+      if ((threadIdx.x & 63) == 0) red[wv * KM + m] = v;
     }
   }
   __syncthreads();
   if (threadIdx.x < cnt) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) s += red[w * kMaxKq + threadIdx.x];
+    for (int w = 0; w < NT / 64; ++w) s += red[w * KM + threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
@@ -56,13 +54,15 @@ __device__ inline void multi_sum(double (&acc)[kMaxKq], int cnt, double* red /*[
 
 constexpr int kQrThreads = 256;
 
+// KM: capacity of the per-thread column arrays (32, or 80 for up to 80 generating vectors)
+template <int KM>
 __global__ void __launch_bounds__(kQrThreads) k_coarse_qr(
     const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
     const double* __restrict__ F, int64_t n, int k, double rank_tol, double* __restrict__ work,
     double* __restrict__ Q, int32_t* __restrict__ kcnt, int32_t* __restrict__ err) {
-  __shared__ double red[(kQrThreads / 64) * kMaxKq];
-  __shared__ double sums[kMaxKq];
-  __shared__ int used[kMaxKq];
+  __shared__ double red[(kQrThreads / 64) * KM];
+  __shared__ double sums[KM];
+  __shared__ int used[KM];
   __shared__ int pick;
   __shared__ double pick_norm, r11;
   const int i = blockIdx.x;
@@ -75,23 +75,23 @@ __global__ void __launch_bounds__(kQrThreads) k_coarse_qr(
     for (int j = 0; j < k; ++j) V[(int64_t)j * ni + r] = F[(int64_t)j * n + g];
     for (int j = 0; j < k; ++j) Q[(int64_t)g * k + j] = 0.0;
   }
-  if (tid < kMaxKq) used[tid] = 0;
+  if (tid < KM) used[tid] = 0;
   __syncthreads();
   int kept = 0;
-  double acc[kMaxKq];
+  double acc[KM];
   for (int s = 0; s < k; ++s) {
     // residual norms of the unused columns
 #pragma unroll
-    for (int m = 0; m < kMaxKq; ++m) acc[m] = 0.0;
+    for (int m = 0; m < KM; ++m) acc[m] = 0.0;
     for (int r = tid; r < ni; r += kQrThreads) {
 #pragma unroll
-      for (int m = 0; m < kMaxKq; ++m)
+      for (int m = 0; m < KM; ++m)
         if (m < k) {
           double v = V[(int64_t)m * ni + r];
           acc[m] += v * v;
         }
     }
-    multi_sum<kQrThreads>(acc, k, red, sums);
+    multi_sum<kQrThreads, KM>(acc, k, red, sums);
     if (tid == 0) {
       int best = -1;
       double bn = -1.0;
@@ -116,15 +116,15 @@ __global__ void __launch_bounds__(kQrThreads) k_coarse_qr(
     // re-orthogonalise against the kept basis vectors
     if (kept > 0) {
 #pragma unroll
-      for (int m = 0; m < kMaxKq; ++m) acc[m] = 0.0;
+      for (int m = 0; m < KM; ++m) acc[m] = 0.0;
       for (int r = tid; r < ni; r += kQrThreads) {
         const int g = own_idx[base + r];
         const double v = vp[r];
 #pragma unroll
-        for (int m = 0; m < kMaxKq; ++m)
+        for (int m = 0; m < KM; ++m)
           if (m < kept) acc[m] += Q[(int64_t)g * k + m] * v;
       }
-      multi_sum<kQrThreads>(acc, kept, red, sums);
+      multi_sum<kQrThreads, KM>(acc, kept, red, sums);
       for (int r = tid; r < ni; r += kQrThreads) {
         const int g = own_idx[base + r];
         double v = vp[r];
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kQrThreads) k_coarse_qr(
     }
     acc[0] = 0.0;
     for (int r = tid; r < ni; r += kQrThreads) acc[0] += vp[r] * vp[r];
-    multi_sum<kQrThreads>(acc, 1, red, sums);
+    multi_sum<kQrThreads, KM>(acc, 1, red, sums);
     const double inv = 1.0 / sqrt(sums[0]);
     for (int r = tid; r < ni; r += kQrThreads) {
       const int g = own_idx[base + r];
@@ -146,14 +146,14 @@ __global__ void __launch_bounds__(kQrThreads) k_coarse_qr(
     __syncthreads();
     // modified Gram-Schmidt: project the new direction out of the unused columns
 #pragma unroll
-    for (int m = 0; m < kMaxKq; ++m) acc[m] = 0.0;
+    for (int m = 0; m < KM; ++m) acc[m] = 0.0;
     for (int r = tid; r < ni; r += kQrThreads) {
       const double qv = vp[r];
 #pragma unroll
-      for (int m = 0; m < kMaxKq; ++m)
+      for (int m = 0; m < KM; ++m)
         if (m < k && m != jp && !used[m]) acc[m] += qv * V[(int64_t)m * ni + r];
     }
-    multi_sum<kQrThreads>(acc, k, red, sums);
+    multi_sum<kQrThreads, KM>(acc, k, red, sums);
     for (int r = tid; r < ni; r += kQrThreads) {
       const double qv = vp[r];
       for (int m = 0; m < k; ++m)
@@ -179,9 +179,11 @@ typedef double gal_d4 __attribute__((ext_vector_type(4)));
 // The rows of Omega_i are taken in chunks: W[r, (s, b)] = (A Q_j)[g_r, b] for a
 // group of neighbours s is formed in LDS from the sparse rows, then the dense
 // contraction Q_i^T W runs on the FP64 matrix cores (v_mfma_f64_16x16x4: the
-// k <= 32 coarse columns of subdomain i are one or two 16-row tiles, each wave
+// k <= 80 coarse columns of subdomain i are up to five 16-row tiles, each wave
 // owns 16-column slabs of the group's (s, b) columns, the chunk rows are the
 // reduction dimension).
+// MT row tiles of 16 coarse columns (2 for k <= 32, 5 for k <= 80), SL column slabs per wave.
+template <int MT, int SL>
 __global__ void __launch_bounds__(kGalThreads) k_galerkin(
     const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
     const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr_idx,
@@ -191,7 +193,6 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
     const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ cblk_off,
     const int32_t* __restrict__ cblk_n, const int64_t* __restrict__ a0_off, double* __restrict__ A0) {
   __shared__ double lds[kGalLds / 8];
-  constexpr int SL = 4;                     // slabs per wave (per row tile)
   const int i = blockIdx.x;
   // the block row of subdomain i lies in the dense coarse block of its system
   const int sys = sub_inst[i];
@@ -204,8 +205,8 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
   const int ki = kcnt[i];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int mt_n = kq > 16 ? 2 : 1;         // row tiles of the k coarse columns of i
-  const int slabs_max = 4 * (mt_n == 1 ? SL : SL / 2);
+  const int mt_n = (kq + 15) / 16;          // row tiles of the k coarse columns of i (<= MT)
+  const int slabs_max = MT == 2 ? 4 * (mt_n == 1 ? SL : SL / 2) : 4 * SL;
   const int gmax = max(1, (slabs_max * 16) / kq);
   for (int g0 = 0; g0 < nnb; g0 += gmax) {
     const int gs = min(gmax, nnb - g0);
@@ -214,9 +215,9 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
     ch = min(64, ch) & ~3;
     double* Wc = lds;               // [ch][ncol]
     double* Qc = lds + ch * ncol;   // [ch][kq]
-    gal_d4 acc[2][SL];
+    gal_d4 acc[MT][SL];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int q = 0; q < SL; ++q) acc[m][q] = gal_d4{0.0, 0.0, 0.0, 0.0};
     for (int r0 = 0; r0 < ni; r0 += ch) {
@@ -249,9 +250,9 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
       __syncthreads();
       for (int k0 = 0; k0 < rows4; k0 += 4) {
         const int r = k0 + lk;
-        double af[2];
+        double af[MT];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
+        for (int m = 0; m < MT; ++m) {
           const int a = m * 16 + li;
           af[m] = (m < mt_n && a < kq) ? Qc[r * kq + a] : 0.0;
         }
@@ -260,14 +261,14 @@ __global__ void __launch_bounds__(kGalThreads) k_galerkin(
           const int col = (q * 4 + wave) * 16 + li;
           const double bf = col < ncol ? Wc[r * ncol + col] : 0.0;
 #pragma unroll
-          for (int m = 0; m < 2; ++m)
+          for (int m = 0; m < MT; ++m)
             if (m < mt_n) acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m], bf, acc[m][q], 0, 0, 0);
         }
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < MT; ++m) {
       if (m >= mt_n) continue;
 #pragma unroll
       for (int q = 0; q < SL; ++q) {
@@ -961,10 +962,11 @@ void launch_factor_p(Handle& h, hipStream_t s) {
 
 void launch_coarse_basis(Handle& h, hipStream_t s) {
   const Symbolic& S = h.S;
-  DDG_REQUIRE(h.k <= kMaxKq, DDG_ERR_UNSUPPORTED, "at most 32 generating vectors");
+  DDG_REQUIRE(h.k <= kMaxGen, DDG_ERR_UNSUPPORTED, "at most 80 generating vectors");
   DevBuf work;
   work.alloc((size_t)S.n * h.k * sizeof(double));
-  hipLaunchKernelGGL(k_coarse_qr, dim3(S.n_parts), dim3(kQrThreads), 0, s, h.own_ptr.as<int64_t>(),
+  auto kern = h.k <= 32 ? k_coarse_qr<32> : k_coarse_qr<kMaxGen>;
+  hipLaunchKernelGGL(kern, dim3(S.n_parts), dim3(kQrThreads), 0, s, h.own_ptr.as<int64_t>(),
                      h.own_idx.as<int32_t>(), h.F.as<double>(), S.n, h.k, h.opt.rank_tol,
                      work.as<double>(), h.Q.as<double>(), h.kcnt_d.as<int32_t>(), h.err_flag.as<int32_t>());
   DDG_HIP(hipGetLastError());
@@ -974,7 +976,8 @@ void launch_coarse_basis(Handle& h, hipStream_t s) {
 void launch_galerkin(Handle& h, hipStream_t s) {
   const Symbolic& S = h.S;
   DDG_HIP(hipMemsetAsync(h.A0.p, 0, (size_t)h.a0_off[h.nb] * sizeof(double), s));
-  hipLaunchKernelGGL(k_galerkin, dim3(S.n_parts), dim3(kGalThreads), 0, s, h.own_ptr.as<int64_t>(),
+  auto kern = h.k <= 32 ? k_galerkin<2, 4> : k_galerkin<5, 2>;
+  hipLaunchKernelGGL(kern, dim3(S.n_parts), dim3(kGalThreads), 0, s, h.own_ptr.as<int64_t>(),
                      h.own_idx.as<int32_t>(), h.nbr_ptr.as<int32_t>(), h.nbr_idx.as<int32_t>(),
                      h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
                      h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(),

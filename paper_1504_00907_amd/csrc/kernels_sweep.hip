@@ -835,9 +835,100 @@ void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, boo
 
 }  // namespace
 
+namespace {
+
+// SSOR smoothing of the subdomains of one colour (DDG_LOCAL_SSOR, Section 7's
+// inexact variant): one workgroup per subdomain, the local right-hand side
+// b = (r - A e)[set] (the local-residual kernel's output) and the iterate x kept
+// on chip.  Each relaxation x_r += omega (b_r - (A_i x)_r) / a_rr covers the rows
+// of one local colour at once (they are not coupled), colours ascending then
+// descending, `sweeps` times from x = 0; then e[set] += x.
+constexpr int kSsorThreads = 512;
+
+__global__ void __launch_bounds__(kSsorThreads) k_ssor(
+    const int32_t* __restrict__ subs, const int64_t* __restrict__ set_ptr, const int32_t* __restrict__ set_idx,
+    const int64_t* __restrict__ ss_ptr, const int32_t* __restrict__ ss_col, const double* __restrict__ ss_val,
+    const double* __restrict__ ss_diag, const int32_t* __restrict__ ss_perm, const int32_t* __restrict__ ss_cptr,
+    const int32_t* __restrict__ ss_coff, const double* __restrict__ bres, double* __restrict__ e,
+    const CgState* st, const int32_t* __restrict__ sub_inst, double omega, int sweeps, int ld) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* x = reinterpret_cast<double*>(smem_raw);
+  double* b = x + ld;
+  const int sub = subs[blockIdx.x];
+  if (st && st[sub_inst[sub]].done) return;
+  const int64_t s0 = set_ptr[sub];
+  const int ni = (int)(set_ptr[sub + 1] - s0);
+  for (int j = threadIdx.x; j < ni; j += kSsorThreads) {
+    x[j] = 0.0;
+    b[j] = bres[s0 + j];
+  }
+  __syncthreads();
+  const int c0 = ss_cptr[sub];
+  const int nc = ss_cptr[sub + 1] - c0 - 1;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int q = 0; q < 2 * nc; ++q) {
+      const int c = q < nc ? q : 2 * nc - 1 - q;
+      const int t1 = ss_coff[c0 + c + 1];
+      for (int t = ss_coff[c0 + c] + threadIdx.x; t < t1; t += kSsorThreads) {
+        const int rl = ss_perm[s0 + t];
+        const int64_t g = s0 + rl;
+        double acc = b[rl];
+        for (int64_t k = ss_ptr[g]; k < ss_ptr[g + 1]; ++k) acc -= ss_val[k] * x[ss_col[k]];
+        x[rl] += omega * acc / ss_diag[g];
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = threadIdx.x; j < ni; j += kSsorThreads) e[set_idx[s0 + j]] += x[j];
+}
+
+// One colour phase with SSOR smoothing: its local-residual kernel, or its smoothing.
+void launch_ssor_phase(const Handle& h, int colour, const double* r, double* e, bool e_zero, const CgState* st,
+                       hipStream_t s, bool residual) {
+  const Symbolic& S = h.S;
+  const int nsub = S.colour_ptr[colour + 1] - S.colour_ptr[colour];
+  if (nsub == 0) return;
+  const int32_t* subs = h.colour_subs.as<int32_t>() + S.colour_ptr[colour];
+  if (residual) {
+    with_lanes(h.lpr, [&](auto Lc) {
+      constexpr int L = decltype(Lc)::value;
+      hipLaunchKernelGGL(k_local_residual<L>, dim3((unsigned)(((int64_t)S.max_set * L + 255) / 256), (unsigned)nsub),
+                         dim3(256), 0, s, st, h.sub_inst.as<int32_t>(), subs, h.set_ptr.as<int64_t>(),
+                         h.set_idx.as<int32_t>(), h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(),
+                         dia_view(h), r, e, e_zero ? 1 : 0, h.ws.bres);
+    });
+    DDG_HIP(hipGetLastError());
+    return;
+  }
+  const int ld = (S.max_set + 1) & ~1;
+  const size_t lds = (size_t)2 * ld * sizeof(double);
+  DDG_REQUIRE(lds + 1024 <= (size_t)h.dev_lds_limit, DDG_ERR_UNSUPPORTED,
+              "expanded set too large for on-chip SSOR smoothing (" + std::to_string(S.max_set) + " rows)");
+  if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)k_ssor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (h.kev0)
+    hipExtLaunchKernelGGL(k_ssor, dim3((unsigned)nsub), dim3(kSsorThreads), (uint32_t)lds, s, h.kev0, h.kev1, 0u,
+                          subs, h.set_ptr.as<int64_t>(), h.set_idx.as<int32_t>(), h.ss_ptr.as<int64_t>(),
+                          h.ss_col.as<int32_t>(), h.ss_val.as<double>(), h.ss_diag.as<double>(),
+                          h.ss_perm.as<int32_t>(), h.ss_cptr.as<int32_t>(), h.ss_coff.as<int32_t>(), h.ws.bres, e, st,
+                          h.sub_inst.as<int32_t>(), h.opt.ssor_omega, h.opt.ssor_sweeps, ld);
+  else
+    hipLaunchKernelGGL(k_ssor, dim3((unsigned)nsub), dim3(kSsorThreads), lds, s, subs, h.set_ptr.as<int64_t>(),
+                       h.set_idx.as<int32_t>(), h.ss_ptr.as<int64_t>(), h.ss_col.as<int32_t>(),
+                       h.ss_val.as<double>(), h.ss_diag.as<double>(), h.ss_perm.as<int32_t>(),
+                       h.ss_cptr.as<int32_t>(), h.ss_coff.as<int32_t>(), h.ws.bres, e, st, h.sub_inst.as<int32_t>(),
+                       h.opt.ssor_omega, h.opt.ssor_sweeps, ld);
+  DDG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
 // residual = true: launch only the local-residual kernel of the colour; false: the local solves.
 void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool e_zero,
                   const CgState* st, hipStream_t s, bool res) {
+  if (h.ssor) {
+    launch_ssor_phase(h, colour, r, e, e_zero, st, s, res);
+    return;
+  }
   switch (h.opt.precision) {
     case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, colour, r, e, e_zero, st, s, res, -1); break;
     case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, colour, r, e, e_zero, st, s, res, -1); break;

@@ -79,7 +79,7 @@ extern "C" int ddg_apply_precond_noalloc(ddg_handle hd, const double* r_dev, dou
     const Symbolic& S = h->S;
     const bool coarse = h->nc > 0;
     const size_t b_bres = round256((size_t)S.set_ptr[S.n_parts] * sizeof(double));
-    const size_t b_rpart = coarse ? round256((size_t)S.n_parts * h->nch * 32 * sizeof(double)) : 0;
+    const size_t b_rpart = coarse ? round256((size_t)S.n_parts * h->nch * kslots(h->k) * sizeof(double)) : 0;
     const size_t b_cy = coarse ? round256((size_t)2 * h->nc_pad * sizeof(double)) : 0;
     const size_t b_cpart = coarse ? round256((size_t)2 * h->ntiles * 64 * sizeof(double)) : 0;
     const size_t need = b_bres + b_rpart + b_cy + b_cpart;
