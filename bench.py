@@ -368,7 +368,8 @@ def biharmonic(m: int, boxes: int, overlap: int, ps, steps: int):
                "frac_iters": fin(rep["frac_iters"]), "kappa_estimate": fin(rep["kappa"]),
                "iter_bound": rep["iter_bound"], "status": info["status_name"],
                "ms_per_solve": ms, "true_rel_res": true_res, "setup_s": setup_s,
-               "matrix_format": _lib_format(hi)}
+               "matrix_format": _lib_format(hi), "coarse_refine": hi["coarse_refine"],
+               "coarse_inverse_err": hi["coarse_inverse_err"]}
         out["per_p"].append(rec)
         log(f"biharmonic p={p}: k {rec['k']}, N_c {hi['n_coarse']}, iters {info['iters']}, {ms:.1f} ms/solve, "
             f"true res {true_res:.2e}")
@@ -644,7 +645,7 @@ def main():
     ap.add_argument("--no-biharmonic", action="store_true", help="skip the biharmonic high-p leg")
     ap.add_argument("--biharmonic-m", type=int, default=1000)
     ap.add_argument("--biharmonic-boxes", type=int, default=8)
-    ap.add_argument("--biharmonic-p", default="1,2,3,4,6")
+    ap.add_argument("--biharmonic-p", default="1,2,3,4,6,8,10")
     ap.add_argument("--no-materials", action="store_true", help="skip the two-material leg")
     ap.add_argument("--no-inexact", action="store_true", help="skip the SSOR local smoothing leg")
     ap.add_argument("--adjoint-only", action="store_true",

@@ -136,6 +136,11 @@ typedef struct {
   int32_t matrix_format;   /* storage the row dots read: DDG_MATRIX_CSR or DDG_MATRIX_DIA */
   int32_t levels;          /* 1 (no coarse space), 2, or 3 (ddg_setup_three_level) */
   int32_t n_coarsest;      /* unknowns of the coarsest level (N_c with two levels) */
+  int32_t coarse_refine;   /* refinement steps y += X (b0 - A0 y) of every coarse solve (0 when the
+                              explicit inverse X is accurate to working precision) */
+  double coarse_inverse_err; /* estimate of the spectral radius of I - X A0 (largest
+                              ||(I - X A0) v|| / ||v|| over eight normalised power steps from a fixed
+                              pseudo-random v), at the last setup or refactor, worst system */
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */

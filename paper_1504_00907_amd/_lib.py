@@ -49,6 +49,7 @@ class Info(C.Structure):
         ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("schedule", C.c_int32),
         ("envelope_elems", C.c_int64), ("set_rows", C.c_int64), ("nbhd_rows", C.c_int64),
         ("matrix_format", C.c_int32), ("levels", C.c_int32), ("n_coarsest", C.c_int32),
+        ("coarse_refine", C.c_int32), ("coarse_inverse_err", C.c_double),
     ]
 
     def as_dict(self) -> dict:

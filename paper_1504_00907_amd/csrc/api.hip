@@ -311,6 +311,25 @@ void numeric_setup(Handle& h) {
   }
   if (eg) (void)hipEventDestroy(eg);
   if (ec) (void)hipEventDestroy(ec);
+  if (h.nc > 0 && !h.three_level) {
+    // accuracy of the explicit coarse inverse X: e estimates the spectral radius of
+    // I - X A0; when it is not at working precision (ill-conditioned A0, e.g. the
+    // biharmonic operator at large sizes), each coarse solve takes iterative-refinement
+    // steps y += X (b0 - A0 y), which reduce the error by e per step and keep the coarse
+    // operator symmetric (after s steps it is (I - (I - X A0)^{s+1}) A0^{-1})
+    const double e = measure_coarse_inverse(h, h.stream);
+    h.coarse_inv_err = e;
+    int32_t steps = 0;
+    if (!(e <= 1e-12)) {
+      DDG_REQUIRE(e < 0.5, DDG_ERR_NOT_SPD,
+                  "coarse inverse too inaccurate to refine (||v - X A0 v|| / ||v|| = " + std::to_string(e) + ")");
+      steps = (int32_t)std::ceil(std::log(1e-13) / std::log(e)) - 1;
+      steps = std::max(1, std::min(4, steps));
+      if (!h.cref.p) h.cref.alloc((size_t)2 * h.nc_pad * sizeof(double));
+    }
+    h.coarse_refine = steps;
+    h.ws.cref = h.cref.p ? h.cref.as<double>() : nullptr;
+  }
   if (h.inner) {
     // the coarse level's values from the new A0, then its own factorisation
     launch_gather(h.a0_pos.as<int64_t>(), h.A0.as<double>(), h.inner->val.as<double>(), h.inner->S.nnz, h.stream);
@@ -334,6 +353,8 @@ void numeric_setup(Handle& h) {
     h.dia_ok = bad == 0;
   }
   h.info.matrix_format = h.dia_ok ? DDG_MATRIX_DIA : DDG_MATRIX_CSR;
+  h.info.coarse_refine = h.coarse_refine;
+  h.info.coarse_inverse_err = h.coarse_inv_err;
 }
 
 // Diagonal storage is possible when no system's rows have more than kDiaMax

@@ -176,6 +176,7 @@ struct PrecondWs {
   double* rpart = nullptr;  // coarse restriction partials (n_parts x nch x 32)
   double* cy = nullptr;     // coarse right-hand side then solution (2 x nc_pad); zero padding
   double* cpart = nullptr;  // coarse GEMV row and column partials (2 x ntiles x 64)
+  double* cref = nullptr;   // coarse refinement residual and correction (2 x nc_pad; refinement only)
 };
 
 // ---------------------------------------------------------------------------
@@ -271,6 +272,12 @@ struct Handle {
   DevBuf A0;              // dense coarse blocks, one per system (kept for export)
   DevBuf A0inv_t;         // tiled lower inverses, float64, tile 64
   DevBuf cinv, cwork, cgd;   // coarse inverse: copy of A0 being inverted, recursion workspace, group tables
+  // iterative refinement of the coarse solve, y += A0^{-1}_approx (b0 - A0 y), for coarse
+  // matrices whose explicit inverse is not accurate to working precision; the step count
+  // is chosen at every refactor from the measured ||v - X A0 v|| / ||v||
+  int32_t coarse_refine = 0;
+  double coarse_inv_err = 0.0;
+  DevBuf cref, cerr;
   hipStream_t side = nullptr;  // second stream: the coarse inverse runs beside the local factorisation
   DevBuf fac;             // local factor tiles (storage precision)
   // batched local factorisation: item schedule (built once per handle) and scratch
@@ -394,6 +401,8 @@ void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgS
 void launch_coarse_basis(Handle& h, hipStream_t s);
 void launch_galerkin(Handle& h, hipStream_t s);
 void launch_coarse_invert(Handle& h, hipStream_t s);
+// max over systems of ||v - X A0 v|| / ||v|| for a fixed pseudo-random v (X the packed inverse)
+double measure_coarse_inverse(Handle& h, hipStream_t s);
 // F0 = R0 F (nc_pad x k column-major, zero padding) from the device copy of F
 void launch_restrict_columns(Handle& h, double* F0, hipStream_t s);
 void launch_local_factor(Handle& h, hipStream_t s);

@@ -9,8 +9,7 @@
 // CG state and returns when that system has stopped, so whole iterations can
 // be enqueued ahead of the host's convergence checks and converged systems of
 // a batch drop out of every launch.
-#include "common.hpp"
-#include "device_util.hpp"
+#include "cg_device.hpp"
 
 namespace ddg {
 
@@ -29,13 +28,6 @@ __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, int
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) d[i] = s[i];
 }
-
-struct SegMap {
-  const int32_t* seg;   // system of each workgroup
-  const int64_t* lo;    // first row
-  const int64_t* hi;    // end row
-  const int32_t* ptr;   // nb+1: partials of system b are [ptr[b], ptr[b+1])
-};
 
 // Row-dot kernels take L lanes per CSR row (row_dot_l): a workgroup covers
 // kThreads / L rows per pass and lane 0 of each group stores the row's result.
@@ -92,243 +84,73 @@ __global__ void k_dia_check(const int64_t* __restrict__ rp, const int32_t* __res
   }
 }
 
-// x = 0, r = f, partial f.f
+// One workgroup per row chunk (SegMap) or per system; the bodies are in cg_device.hpp.
 __global__ void k_cg_init(SegMap m, const double* __restrict__ f, double* __restrict__ x,
                           double* __restrict__ r, double* __restrict__ part) {
-  __shared__ double red[kThreads / 64];
-  double acc = 0.0;
-  const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-    double fi = f[i];
-    x[i] = 0.0;
-    r[i] = fi;
-    acc += fi * fi;
-  }
-  double s = block_sum<kThreads>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  d_cg_init(m, blockIdx.x, f, x, r, part);
 }
-
-__device__ inline uint64_t device_clock() { return wall_clock64(); }
-
-// Per-system history of the CG coefficients and residuals (for the Lanczos
-// estimates and the fractional iteration count of Section 7): system b owns
-// hist[b * 3 * (max_iter + 1) ...], as alpha[j] (j = 0..iters-1), then
-// beta[j] (j = 0..iters-2), then ||r_j||^2 (j = 0..iters).
-struct Hist {
-  double* base;
-  int64_t stride;  // max_iter + 1
-  __device__ double* alpha(int b) const { return base + (int64_t)b * 3 * stride; }
-  __device__ double* beta(int b) const { return base + ((int64_t)b * 3 + 1) * stride; }
-  __device__ double* rr(int b) const { return base + ((int64_t)b * 3 + 2) * stride; }
-};
 
 __global__ void k_cg_init_scalar(CgState* stb, SegMap m, const double* __restrict__ part, double rtol,
                                  int max_iter, Hist hist) {
-  __shared__ double red[kThreads / 64];
-  const int b = blockIdx.x;
-  CgState* st = stb + b;
-  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
-  if (threadIdx.x == 0) {
-    hist.rr(b)[0] = s;
-    st->iters = 0;
-    st->max_iter = max_iter;
-    st->status = DDG_OK;
-    st->done = 0;
-    st->fnorm = sqrt(s);
-    st->rr = s;
-    st->tol2 = rtol * rtol * s;
-    st->rho = st->alpha = st->beta = st->pq = 0.0;
-    st->true_rr = 0.0;
-    st->t_start = device_clock();
-    st->t_done = 0;
-    if (!isfinite(s)) {
-      st->status = DDG_ERR_INVALID_ARG;
-      st->done = 1;
-    } else if (s == 0.0) {
-      st->done = 1;
-    }
-    if (st->done) st->t_done = st->t_start;
-  }
+  d_cg_init_scalar(stb, m, blockIdx.x, part, rtol, max_iter, hist);
 }
 
-// p = z, partial r.z
 __global__ void k_copy_dot(const CgState* stb, SegMap m, const double* __restrict__ r,
                            const double* __restrict__ z, double* __restrict__ p,
                            double* __restrict__ part) {
   if (stb[m.seg[blockIdx.x]].done) return;
-  __shared__ double red[kThreads / 64];
-  double acc = 0.0;
-  const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-    double zi = z[i];
-    p[i] = zi;
-    acc += r[i] * zi;
-  }
-  double s = block_sum<kThreads>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  d_copy_dot(m, blockIdx.x, r, z, p, part);
 }
 
-__device__ inline void stop(CgState* st, int32_t status) {
-  st->status = status;
-  st->done = 1;
-  st->t_done = device_clock();
-}
-
-// rho' = r^T z from the partials; beta = rho' / rho (Fletcher-Reeves), or with
-// the z^T q partials (part2 non-null) the Polak-Ribiere value
-// z^T (r - r_prev) / rho = -alpha z^T q / rho, since r - r_prev = -alpha q.
 __global__ void k_rho_scalar(CgState* stb, SegMap m, const double* __restrict__ part,
                              const double* __restrict__ part2, int first, Hist hist) {
-  const int b = blockIdx.x;
-  CgState* st = stb + b;
-  if (st->done) return;
-  __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
-  double zq = 0.0;
-  if (part2) zq = sum_partials<kThreads>(part2 + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
-  if (threadIdx.x == 0) {
-    if (!(s > 0.0) || !isfinite(s)) {
-      stop(st, DDG_ERR_BREAKDOWN);
-      return;
-    }
-    if (first) {
-      st->rho = s;
-    } else {
-      const double beta = part2 ? -st->alpha * zq / st->rho : s / st->rho;
-      if (!isfinite(beta)) {
-        stop(st, DDG_ERR_BREAKDOWN);
-        return;
-      }
-      st->beta = beta;
-      st->rho = s;
-      hist.beta(b)[st->iters - 1] = beta;
-    }
-  }
+  if (stb[blockIdx.x].done) return;
+  d_rho_scalar(stb, m, blockIdx.x, part, part2, first, hist);
 }
 
-// q = A p, partial p.q
 template <int L>
 __global__ void k_spmv_dot(const CgState* stb, SegMap m, const int64_t* __restrict__ rp,
                            const int32_t* __restrict__ ci, const double* __restrict__ v, DiaView D,
                            const double* __restrict__ p, double* __restrict__ q,
                            double* __restrict__ part) {
   if (stb[m.seg[blockIdx.x]].done) return;
-  __shared__ double red[kThreads / 64];
-  double acc = 0.0;
-  const int64_t hi = m.hi[blockIdx.x];
-  const int j = threadIdx.x & (L - 1);
-  if (L == 1 && D.diag) {
-    const DiaSys& sy = D.sys[m.seg[blockIdx.x]];
-    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-      const double qi = dia_row_dot(D, sy, p, i);
-      q[i] = qi;
-      acc += p[i] * qi;
-    }
-  } else {
-    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x / L; i < hi; i += kThreads / L) {
-      const double qi = row_dot_l<L>(rp, ci, v, p, i, j);
-      if (j == 0) {
-        q[i] = qi;
-        acc += p[i] * qi;
-      }
-    }
-  }
-  double s = block_sum<kThreads>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  d_spmv_dot<L>(m, blockIdx.x, rp, ci, v, D, p, q, part);
 }
 
 __global__ void k_alpha_scalar(CgState* stb, SegMap m, const double* __restrict__ part, Hist hist) {
-  const int b = blockIdx.x;
-  CgState* st = stb + b;
-  if (st->done) return;
-  __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
-  if (threadIdx.x == 0) {
-    st->pq = s;
-    if (!(s > 0.0) || !isfinite(s)) {
-      stop(st, DDG_ERR_BREAKDOWN);
-      return;
-    }
-    st->alpha = st->rho / s;
-    hist.alpha(b)[st->iters] = st->alpha;
-  }
+  if (stb[blockIdx.x].done) return;
+  d_alpha_scalar(stb, m, blockIdx.x, part, hist);
 }
 
-// x += alpha p, r -= alpha q, partial r.r
 __global__ void k_axpy2_dot(const CgState* stb, SegMap m, double* __restrict__ x, double* __restrict__ r,
                             const double* __restrict__ p, const double* __restrict__ q,
                             double* __restrict__ part) {
   const CgState* st = stb + m.seg[blockIdx.x];
   if (st->done) return;
-  __shared__ double red[kThreads / 64];
-  const double a = st->alpha;
-  double acc = 0.0;
-  const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-    x[i] += a * p[i];
-    double ri = r[i] - a * q[i];
-    r[i] = ri;
-    acc += ri * ri;
-  }
-  double s = block_sum<kThreads>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  d_axpy2_dot(st, m, blockIdx.x, x, r, p, q, part);
 }
 
 __global__ void k_conv_scalar(CgState* stb, SegMap m, const double* __restrict__ part, Hist hist) {
-  const int b = blockIdx.x;
-  CgState* st = stb + b;
-  if (st->done) return;
-  __shared__ double red[kThreads / 64];
-  double s = sum_partials<kThreads>(part + m.ptr[b], m.ptr[b + 1] - m.ptr[b], red);
-  if (threadIdx.x == 0) {
-    st->rr = s;
-    st->iters += 1;
-    hist.rr(b)[st->iters] = s;
-    if (!isfinite(s)) stop(st, DDG_ERR_BREAKDOWN);
-    else if (s <= st->tol2) stop(st, DDG_OK);
-    else if (st->iters >= st->max_iter) stop(st, DDG_ERR_NO_CONVERGENCE);
-  }
+  if (stb[blockIdx.x].done) return;
+  d_conv_scalar(stb, m, blockIdx.x, part, hist);
 }
 
-// partial r.z (after the preconditioner)
 __global__ void k_dot(const CgState* stb, SegMap m, const double* __restrict__ a, const double* __restrict__ b,
                       double* __restrict__ part) {
   if (stb[m.seg[blockIdx.x]].done) return;
-  __shared__ double red[kThreads / 64];
-  double acc = 0.0;
-  const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) acc += a[i] * b[i];
-  double s = block_sum<kThreads>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  d_dot(m, blockIdx.x, a, b, part);
 }
 
-// partials r.z and z.q in one pass (Polak-Ribiere direction update)
 __global__ void k_dot2(const CgState* stb, SegMap m, const double* __restrict__ r, const double* __restrict__ z,
                        const double* __restrict__ q, double* __restrict__ part, double* __restrict__ part2) {
   if (stb[m.seg[blockIdx.x]].done) return;
-  __shared__ double red[kThreads / 64];
-  double a1 = 0.0, a2 = 0.0;
-  const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) {
-    const double zi = z[i];
-    a1 += r[i] * zi;
-    a2 += zi * q[i];
-  }
-  double s1 = block_sum<kThreads>(a1, red);
-  double s2 = block_sum<kThreads>(a2, red);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = s1;
-    part2[blockIdx.x] = s2;
-  }
+  d_dot2(m, blockIdx.x, r, z, q, part, part2);
 }
 
-// p = z + beta p
 __global__ void k_xpby(const CgState* stb, SegMap m, const double* __restrict__ z, double* __restrict__ p) {
   const CgState* st = stb + m.seg[blockIdx.x];
   if (st->done) return;
-  const double b = st->beta;
-  const int64_t hi = m.hi[blockIdx.x];
-  for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < hi; i += kThreads) p[i] = z[i] + b * p[i];
+  d_xpby(st, m, blockIdx.x, z, p);
 }
 
 // partial ||f - A x||^2 (always runs)

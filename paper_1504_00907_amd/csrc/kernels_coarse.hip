@@ -11,20 +11,12 @@
 // independent systems A0 is block diagonal: system b owns the padded coarse
 // rows [cblk_off[b], cblk_off[b+1]) and the tiles [tile_base[b], tile_base[b+1])
 // of its own inverse; kernels skip the work of systems that have stopped.
-#include "common.hpp"
-#include "symv_tile.hpp"
+#include "coarse_device.hpp"
 
 namespace ddg {
 
 namespace {
 
-constexpr int kRThreads = 256;
-
-// Partial restriction over one chunk of the own rows of subdomain i (workgroup
-// (c, i) takes rows [own_ptr[i] + c rch, ... + rch)), L lanes per CSR row:
-//   rpart[i, c, m] = sum_{g in chunk} Q[g, m] (r - A e)_g,   m < kcnt[i]
-// (waves in order after a butterfly per wave); empty chunks write zeros.
-// KM: capacity of the per-thread column arrays and stride of rpart (kslots(k)).
 template <int L, int KM>
 __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr,
@@ -33,68 +25,7 @@ __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     DiaView D, const double* __restrict__ r, const double* __restrict__ e, int rch, double* __restrict__ rpart) {
   const int i = blockIdx.y, c = blockIdx.x;
   if (st && st[sub_inst[i]].done) return;
-  __shared__ double red[kRThreads / 64][KM];
-  const int ki = kcnt[i];
-  double acc[KM];
-#pragma unroll
-  for (int m = 0; m < KM; ++m) acc[m] = 0.0;
-  const int64_t t0 = own_ptr[i] + (int64_t)c * rch;
-  const int64_t t1 = min(own_ptr[i + 1], t0 + rch);
-  const int jl = threadIdx.x & (L - 1);
-  if constexpr (L == 1) {
-    // a thread's rows t, t + 256, ... four at a time: each stage's loads (row index,
-    // row pointers, entries, e) go out for all four rows together; the rows are
-    // still added in the same order
-    constexpr int U = 4;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += (int64_t)U * kRThreads) {
-      int g[U];
-      double sv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) g[u] = t + u * kRThreads < t1 ? own_idx[t + u * kRThreads] : -1;
-      if (D.diag) {
-        const DiaSys& sy = D.sys[sub_inst[i]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) sv[u] = g[u] >= 0 ? dia_row_sub(D, sy, e, g[u], r[g[u]]) : 0.0;
-      } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u) sv[u] = g[u] >= 0 ? row_sub(rp, ci, val, e, g[u], r[g[u]]) : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (g[u] < 0) continue;
-        const double* qg = Q + (int64_t)g[u] * kq;
-#pragma unroll
-        for (int m = 0; m < KM; ++m)
-          if (m < ki) acc[m] += qg[m] * sv[u];
-      }
-    }
-  } else {
-    for (int64_t t = t0 + threadIdx.x / L; t < t1; t += kRThreads / L) {
-      const int g = own_idx[t];
-      const double s = r[g] - row_dot_l<L>(rp, ci, val, e, g, jl);
-      if (jl == 0) {
-        const double* qg = Q + (int64_t)g * kq;
-#pragma unroll
-        for (int m = 0; m < KM; ++m)
-          if (m < ki) acc[m] += qg[m] * s;
-      }
-    }
-  }
-  const int wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int m = 0; m < KM; ++m) {
-    if (m < ki) {
-      double v = wave_sum(acc[m]);
-      if ((threadIdx.x & 63) == 0) red[wv][m] = v;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < ki) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kRThreads / 64; ++w) s += red[w][threadIdx.x];
-    rpart[((int64_t)i * gridDim.x + c) * KM + threadIdx.x] = s;
-  }
+  d_coarse_restrict<L, KM>(i, c, gridDim.x, sub_inst, own_ptr, own_idx, kcnt, Q, kq, rp, ci, val, D, r, e, rch, rpart);
 }
 
 // b0[koff[i] + m] = sum over the nch chunks of subdomain i, in chunk order
@@ -106,11 +37,7 @@ __global__ void k_coarse_restrict_sum(const CgState* st, const int32_t* __restri
   const int i = (int)(id / KM), m = (int)(id % KM);
   if (i >= n_parts) return;
   if (st && st[sub_inst[i]].done) return;
-  if (m >= kcnt[i]) return;
-  const double* p = rpart + (int64_t)i * nch * KM + m;
-  double s = 0.0;
-  for (int c = 0; c < nch; ++c) s += p[(int64_t)c * KM];
-  b0[koff[i] + m] = s;
+  d_coarse_restrict_sum_entry(i, m, kcnt, koff, rpart, nch, KM, b0);
 }
 
 // one wave per 64x64 float64 tile: row and column partials into per-tile slots
@@ -121,18 +48,11 @@ __global__ void __launch_bounds__(256) k_coarse_symv(const CgState* st, const in
                                                      const double* __restrict__ x,
                                                      double* __restrict__ rowpart,
                                                      double* __restrict__ colpart) {
-  constexpr int T = 64;
-  using G = TileGeom<double, T>;
-  const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const int b = tile_inst[t];
   if (st && st[b].done) return;
-  int I, J;
-  tile_ij((int)(t - tile_base[b]), I, J);
-  double m[G::SS];
-  load_subtile<double, T>(tiles + t * T * T, lane, m);
-  symv_tile_slots<double, double, T>(m, I, J, x + cblk_off[b], rowpart + t * T, colpart + t * T, lane, true);
+  d_coarse_symv_tile(t, b, tile_base, cblk_off, tiles, x, rowpart, colpart);
 }
 
 // y over the padded coarse rows; trow_inst gives the system of each 64-row tile row
@@ -140,20 +60,11 @@ __global__ void k_coarse_sum(const CgState* st, const int32_t* __restrict__ trow
                              const int64_t* __restrict__ tile_base, const int64_t* __restrict__ cblk_off,
                              const double* __restrict__ rowpart, const double* __restrict__ colpart,
                              int64_t nc_pad, double* __restrict__ y) {
-  constexpr int T = 64;
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= nc_pad) return;
-  const int b = trow_inst[row / T];
+  const int b = trow_inst[row / 64];
   if (st && st[b].done) return;
-  const int64_t lr = row - cblk_off[b];
-  const int I = (int)(lr / T), rr = (int)(lr % T);
-  const int ntr = (int)((cblk_off[b + 1] - cblk_off[b]) / T);
-  const double* rp = rowpart + tile_base[b] * T;
-  const double* cp = colpart + tile_base[b] * T;
-  double s = 0.0;
-  for (int J = 0; J <= I; ++J) s += rp[((int64_t)I * (I + 1) / 2 + J) * T + rr];
-  for (int J = I + 1; J < ntr; ++J) s += cp[((int64_t)J * (J + 1) / 2 + I) * T + rr];
-  y[row] = s;
+  d_coarse_sum_row(row, b, tile_base, cblk_off, rowpart, colpart, y);
 }
 
 template <int KM>
@@ -164,21 +75,7 @@ __global__ void __launch_bounds__(256) k_coarse_prolong(const CgState* st, const
                                  double* __restrict__ e, int64_t n) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  // the row of Q (stride kq) is requested before the subdomain's count and offset
-  // are known, so its loads do not wait behind that chain of lookups
-  const double* qg = Q + g * kq;
-  double q[KM];
-#pragma unroll
-  for (int m = 0; m < KM; ++m) q[m] = m < kq ? qg[m] : 0.0;
-  const int i = part[g];
-  if (st && st[sub_inst[i]].done) return;
-  const int ki = kcnt[i];
-  const double* yi = y + koff[i];
-  double s = 0.0;
-#pragma unroll
-  for (int m = 0; m < KM; ++m)
-    if (m < ki) s += q[m] * yi[m];
-  e[g] += s;
+  d_coarse_prolong_row<KM>(g, st, sub_inst, part, kcnt, koff, Q, kq, y, e);
 }
 
 // F0[koff[i] + j, c] = sum over the own rows g of subdomain i of Q[g, j] F[g, c]
@@ -200,7 +97,144 @@ __global__ void k_restrict_columns(const int64_t* __restrict__ own_ptr, const in
   }
 }
 
+// t[row] = b[row] - (A0 y)[row] over the padded coarse rows (one wave per row, the
+// columns of the row's system in lane order then a butterfly); 0 on padding rows
+__global__ void __launch_bounds__(256) k_a0_resid(const CgState* st, const int32_t* __restrict__ trow_inst,
+                                                  const int64_t* __restrict__ cblk_off,
+                                                  const int32_t* __restrict__ cblk_n, const int64_t* __restrict__ a0_off,
+                                                  const double* __restrict__ A0, const double* __restrict__ b,
+                                                  const double* __restrict__ y, int64_t nc_pad,
+                                                  double* __restrict__ t) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nc_pad) return;
+  const int sys = trow_inst[row / 64];
+  if (st && st[sys].done) return;
+  const int64_t c0 = cblk_off[sys], N = cblk_n[sys], lr = row - c0;
+  double s = 0.0;
+  if (lr < N) {
+    const double* a = A0 + a0_off[sys] + lr * N;
+    for (int64_t j = lane; j < N; j += 64) s += a[j] * y[c0 + j];
+  }
+  s = wave_sum(s);
+  if (lane == 0) t[row] = lr < N ? b[row] - s : 0.0;
+}
+
+// y += dy over the padded coarse rows
+__global__ void k_coarse_add(const CgState* st, const int32_t* __restrict__ trow_inst, const double* __restrict__ dy,
+                             int64_t nc_pad, double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nc_pad) return;
+  if (st && st[trow_inst[row / 64]].done) return;
+  y[row] += dy[row];
+}
+
+// v[row] = a fixed pseudo-random value in [-1, 1) (integer hash of the row), 0 on padding rows
+__global__ void k_coarse_probe(const int32_t* __restrict__ trow_inst, const int64_t* __restrict__ cblk_off,
+                               const int32_t* __restrict__ cblk_n, int64_t nc_pad, double* __restrict__ v) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nc_pad) return;
+  const int sys = trow_inst[row / 64];
+  uint64_t z = (uint64_t)row * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  v[row] = row - cblk_off[sys] < cblk_n[sys] ? (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0 : 0.0;
+}
+
+// per system: out[2b] = ||v + u||^2, out[2b+1] = ||v||^2 over its coarse rows (u = -X A0 v)
+__global__ void k_coarse_err(const int64_t* __restrict__ cblk_off, const int32_t* __restrict__ cblk_n,
+                             const double* __restrict__ v, const double* __restrict__ u, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const int64_t c0 = cblk_off[b];
+  double a = 0.0, c = 0.0;
+  for (int64_t r = threadIdx.x; r < cblk_n[b]; r += 256) {
+    const double d = v[c0 + r] + u[c0 + r];
+    a += d * d;
+    c += v[c0 + r] * v[c0 + r];
+  }
+  const double sa = block_sum<256>(a, red);
+  const double sc = block_sum<256>(c, red);
+  if (threadIdx.x == 0) {
+    out[2 * b] = sa;
+    out[2 * b + 1] = sc;
+  }
+}
+
+// power-iteration step: v = (v + u) / ||v + u|| per system (u = -X A0 v; out from k_coarse_err)
+__global__ void k_coarse_next(const int32_t* __restrict__ trow_inst, const int64_t* __restrict__ cblk_off,
+                              const int32_t* __restrict__ cblk_n, int64_t nc_pad, const double* __restrict__ out,
+                              const double* __restrict__ u, double* __restrict__ v) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nc_pad) return;
+  const int sys = trow_inst[row / 64];
+  const double nn = out[2 * sys];
+  v[row] = row - cblk_off[sys] < cblk_n[sys] && nn > 0.0 ? (v[row] + u[row]) / sqrt(nn) : 0.0;
+}
+
+// y = X b with the packed inverse tiles (row and column slots, then the fixed-order sum)
+void coarse_symv(Handle& h, const CgState* st, const double* b, double* y, hipStream_t s) {
+  double* rowpart = h.ws.cpart;
+  double* colpart = rowpart + h.ntiles * 64;
+  hipLaunchKernelGGL(k_coarse_symv, dim3((unsigned)((h.ntiles + 3) / 4)), dim3(256), 0, s, st,
+                     h.tile_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
+                     h.A0inv_t.as<double>(), h.ntiles, b, rowpart, colpart);
+  hipLaunchKernelGGL(k_coarse_sum, dim3((unsigned)((h.nc_pad + 255) / 256)), dim3(256), 0, s, st,
+                     h.trow_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
+                     rowpart, colpart, h.nc_pad, y);
+}
+
+// t = b - A0 y on the padded coarse rows
+void coarse_resid(Handle& h, const CgState* st, const double* b, const double* y, double* t, hipStream_t s) {
+  hipLaunchKernelGGL(k_a0_resid, dim3((unsigned)((h.nc_pad + 3) / 4)), dim3(256), 0, s, st,
+                     h.trow_inst.as<int32_t>(), h.cblk_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(),
+                     h.a0_off_d.as<int64_t>(), h.A0.as<double>(), b, y, h.nc_pad, t);
+}
+
 }  // namespace
+
+// Estimate of the spectral radius of I - X A0 (X the explicit coarse inverse), the
+// factor by which each refinement step reduces the coarse error: the largest
+// ||(I - X A0) v|| / ||v|| over a few normalised power-iteration steps from a fixed
+// pseudo-random start, worst system.  NaN when X or A0 holds non-finite values.
+double measure_coarse_inverse(Handle& h, hipStream_t s) {
+  if (h.nc == 0 || h.three_level) return 0.0;
+  if (!h.cerr.p) h.cerr.alloc((size_t)(3 * h.nc_pad + 2 * h.nb) * sizeof(double));
+  double* v = h.cerr.as<double>();
+  double* t = v + h.nc_pad;
+  double* u = t + h.nc_pad;
+  double* out = u + h.nc_pad;
+  const unsigned g = (unsigned)((h.nc_pad + 255) / 256);
+  hipLaunchKernelGGL(k_coarse_probe, dim3(g), dim3(256), 0, s, h.trow_inst.as<int32_t>(), h.cblk_off_d.as<int64_t>(),
+                     h.cblk_n_d.as<int32_t>(), h.nc_pad, v);
+  PrecondWs keep = h.ws;
+  if (!h.ws.cpart) h.ws.cpart = h.cpart.as<double>();
+  constexpr int kPowerSteps = 8;
+  std::vector<double> hv((size_t)2 * h.nb);
+  double worst = 0.0;
+  for (int it = 0; it < kPowerSteps; ++it) {
+    if (it > 0)
+      hipLaunchKernelGGL(k_coarse_next, dim3(g), dim3(256), 0, s, h.trow_inst.as<int32_t>(),
+                         h.cblk_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.nc_pad, out, u, v);
+    launch_fill(u, 0.0, h.nc_pad, s);
+    coarse_resid(h, nullptr, u, v, t, s);   // t = 0 - A0 v
+    // u = X t = -X A0 v (the handle's own partial slots; no solve is running)
+    coarse_symv(h, nullptr, t, u, s);
+    hipLaunchKernelGGL(k_coarse_err, dim3((unsigned)h.nb), dim3(256), 0, s, h.cblk_off_d.as<int64_t>(),
+                       h.cblk_n_d.as<int32_t>(), v, u, out);
+    DDG_HIP(hipMemcpyAsync(hv.data(), out, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DDG_HIP(hipStreamSynchronize(s));
+    for (int32_t b = 0; b < h.nb; ++b) {
+      if (!(hv[2 * b + 1] > 0)) continue;
+      const double e = std::sqrt(hv[2 * b] / hv[2 * b + 1]);
+      if (!(e <= worst)) worst = e;   // keeps a NaN
+    }
+    if (!(worst <= 1e-12) || std::isnan(worst)) break;
+  }
+  h.ws = keep;
+  return worst;
+}
 
 void launch_restrict_columns(Handle& h, double* F0, hipStream_t s) {
   launch_fill(F0, 0.0, h.nc_pad * h.k, s);
@@ -235,14 +269,16 @@ void launch_coarse_k(Handle& h, const double* r, double* e, const CgState* st, h
     // preconditioner (its kernels skip work once this handle's system has stopped)
     launch_precond(*h.inner, b0, y, -1, false, s, st);
   } else {
-  double* rowpart = h.ws.cpart;
-  double* colpart = rowpart + h.ntiles * 64;
-  hipLaunchKernelGGL(k_coarse_symv, dim3((unsigned)((h.ntiles + 3) / 4)), dim3(256), 0, s, st,
-                     h.tile_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
-                     h.A0inv_t.as<double>(), h.ntiles, b0, rowpart, colpart);
-  hipLaunchKernelGGL(k_coarse_sum, dim3((unsigned)((h.nc_pad + 255) / 256)), dim3(256), 0, s, st,
-                     h.trow_inst.as<int32_t>(), h.tile_base_d.as<int64_t>(), h.cblk_off_d.as<int64_t>(),
-                     rowpart, colpart, h.nc_pad, y);
+    coarse_symv(h, st, b0, y, s);
+    // refinement steps y += X (b0 - A0 y) when the explicit inverse is inaccurate
+    for (int32_t j = 0; j < h.coarse_refine; ++j) {
+      double* t = h.ws.cref;
+      double* dy = t + h.nc_pad;
+      coarse_resid(h, st, b0, y, t, s);
+      coarse_symv(h, st, t, dy, s);
+      hipLaunchKernelGGL(k_coarse_add, dim3((unsigned)((h.nc_pad + 255) / 256)), dim3(256), 0, s, st,
+                         h.trow_inst.as<int32_t>(), dy, h.nc_pad, y);
+    }
   }
   hipLaunchKernelGGL(k_coarse_prolong<KM>, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st, sub_inst,
                      h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),

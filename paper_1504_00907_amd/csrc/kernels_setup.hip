@@ -726,6 +726,30 @@ __global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid,
   gemm_tile(g, i0, j0);
 }
 
+// X[lo:hi, lo:hi] = (X + X^T) / 2 for every item (clipped to its order).  The
+// recursive inverse forms the Schur complement D - C W and the update
+// X11 - X12 W^T, whose two triangles differ by rounding, and Gauss-Jordan leaves
+// are not exactly symmetric either.  Used as they are in the next step, that
+// asymmetry grows from node to node and from level to level when the operator is
+// ill-conditioned or the level couplings amplify (||X C|| > 1: the 13-point
+// biharmonic operator), so every leaf, Schur complement and updated block is made
+// exactly symmetric before it is used.
+__global__ void __launch_bounds__(256) k_bsym(BInv bi, int lo, int hi) {
+  const int q = blockIdx.x;
+  const int b = bi.n[q];
+  if (lo >= b) return;
+  const int w = min(hi, b) - lo;
+  double* X = bi.scratch + bi.off[q] + (int64_t)lo * b + lo;
+  const int64_t total = (int64_t)w * w;
+  for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
+    const int i = (int)(idx / w), j = (int)(idx % w);
+    if (i <= j) continue;
+    const double v = 0.5 * (X[(int64_t)i * b + j] + X[(int64_t)j * b + i]);
+    X[(int64_t)i * b + j] = v;
+    X[(int64_t)j * b + i] = v;
+  }
+}
+
 // X21 = X12^T for every item
 __global__ void k_btranspose(BInv bi, int lo, int mid, int hi) {
   const int q = blockIdx.z;
@@ -757,10 +781,19 @@ int64_t binv_work_need(int lo, int hi, int64_t woff) {
   return std::max(next, std::max(binv_work_need(lo, m, next), binv_work_need(m, hi, next)));
 }
 
+void bsym(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi) {
+  const int64_t n = hi - lo;
+  hipLaunchKernelGGL(k_bsym, dim3(cnt, (unsigned)std::min<int64_t>(1024, (n * n + 255) / 256)), dim3(256), 0, s, bi,
+                     lo, hi);
+}
+
+// Inverse of X[lo:hi, lo:hi] in place (the items' blocks past their order are
+// skipped), symmetric on return.
 void binv_node(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi, int64_t woff, int32_t* err) {
   const int n = hi - lo;
   if (n <= kCNB) {
     hipLaunchKernelGGL(k_bleaf, dim3(cnt), dim3(kPivThreads), 0, s, bi, lo, hi, err);
+    bsym(s, bi, cnt, lo, hi);
     return;
   }
   const int m = lo + kCNB * ((n + 2 * kCNB - 1) / (2 * kCNB));
@@ -770,11 +803,13 @@ void binv_node(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi, int6
   binv_node(s, bi, cnt, lo, m, next, err);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n2), dim3(256), 0, s, bi, 0, lo, m, hi, woff, n2);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n2, n2), dim3(256), 0, s, bi, 1, lo, m, hi, woff, n2);
+  bsym(s, bi, cnt, m, hi);
   binv_node(s, bi, cnt, m, hi, next, err);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n2), dim3(256), 0, s, bi, 2, lo, m, hi, woff, n2);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n1), dim3(256), 0, s, bi, 3, lo, m, hi, woff, n2);
   hipLaunchKernelGGL(k_btranspose, dim3((unsigned)((n2 + 31) / 32), (unsigned)((n1 + 31) / 32), cnt), dim3(256), 0,
                      s, bi, lo, m, hi);
+  bsym(s, bi, cnt, lo, m);
 }
 
 // Schedule of the batched factorisation: groups of subdomains whose scratch

@@ -695,14 +695,14 @@ namespace {
 // flow_dir < 0: one colour phase (its local-residual kernel when `residual`, else its
 // local solves); flow_dir = 0 / 1: the whole ascending / descending sweep as one
 // persistent launch.
+// The local-solve arguments of one launch and its dynamic LDS size (on-chip plan:
+// w (set), tv and the phase accumulator (one level each), then the per-tile slots
+// of up to slot_tiles tiles, whole rounds of NW * TPW tiles).
 template <class FT, class AT, int T, int NW, int TPW, bool SL>
-void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                      const CgState* st, hipStream_t s, bool residual, int flow_dir) {
+size_t build_sweep_args(const Handle& h, const int32_t* subs, int nsub, const double* r, double* e, bool e_zero,
+                        const CgState* st, SweepArgs& a) {
   const Symbolic& S = h.S;
-  const int nsub = flow_dir >= 0 ? S.n_parts : S.colour_ptr[colour + 1] - S.colour_ptr[colour];
-  if (nsub == 0) return;
-  SweepArgs a;
-  a.subs = h.colour_subs.as<int32_t>() + (flow_dir >= 0 ? 0 : S.colour_ptr[colour]);
+  a.subs = subs;
   a.nsub = nsub;
   a.twisted = h.twisted_ok ? 1 : 0;
   a.set_ptr = h.set_ptr.as<int64_t>();
@@ -761,7 +761,18 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   a.slot_tiles = (int32_t)std::min<int64_t>(cap, need_tiles);
   DDG_REQUIRE(a.slot_tiles >= round_tiles, DDG_ERR_UNSUPPORTED,
               "local problem too large for on-chip storage (" + std::to_string(fixed) + " bytes before slots)");
-  const size_t lds = (size_t)(fixed + per_tile * a.slot_tiles);
+  return (size_t)(fixed + per_tile * a.slot_tiles);
+}
+
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
+void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, bool e_zero,
+                      const CgState* st, hipStream_t s, bool residual, int flow_dir) {
+  const Symbolic& S = h.S;
+  const int nsub = flow_dir >= 0 ? S.n_parts : S.colour_ptr[colour + 1] - S.colour_ptr[colour];
+  if (nsub == 0) return;
+  SweepArgs a;
+  const size_t lds = build_sweep_args<FT, AT, T, NW, TPW, SL>(
+      h, h.colour_subs.as<int32_t>() + (flow_dir >= 0 ? 0 : S.colour_ptr[colour]), nsub, r, e, e_zero, st, a);
   if (flow_dir >= 0) {
     auto fk = k_sweep_flow<FT, AT, T, NW, TPW, SL>;
     if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -82,7 +82,8 @@ extern "C" int ddg_apply_precond_noalloc(ddg_handle hd, const double* r_dev, dou
     const size_t b_rpart = coarse ? round256((size_t)S.n_parts * h->nch * kslots(h->k) * sizeof(double)) : 0;
     const size_t b_cy = coarse ? round256((size_t)2 * h->nc_pad * sizeof(double)) : 0;
     const size_t b_cpart = coarse ? round256((size_t)2 * h->ntiles * 64 * sizeof(double)) : 0;
-    const size_t need = b_bres + b_rpart + b_cy + b_cpart;
+    const size_t b_cref = coarse && h->coarse_refine > 0 ? round256((size_t)2 * h->nc_pad * sizeof(double)) : 0;
+    const size_t need = b_bres + b_rpart + b_cy + b_cpart + b_cref;
     DDG_REQUIRE(need <= kScratchBytes, DDG_ERR_UNSUPPORTED,
                 "this handle needs " + std::to_string(need) +
                     " bytes of scratch; the allocation-free entry point holds at most " +
@@ -94,6 +95,7 @@ extern "C" int ddg_apply_precond_noalloc(ddg_handle hd, const double* r_dev, dou
       ws.rpart = reinterpret_cast<double*>(base + b_bres);
       ws.cy = reinterpret_cast<double*>(base + b_bres + b_rpart);
       ws.cpart = reinterpret_cast<double*>(base + b_bres + b_rpart + b_cy);
+      if (b_cref) ws.cref = reinterpret_cast<double*>(base + b_bres + b_rpart + b_cy + b_cpart);
       launch_fill(ws.cy, 0.0, 2 * h->nc_pad, h->stream);
     }
     WsSwap swap(*h, ws);
