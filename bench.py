@@ -419,7 +419,7 @@ def _batch_instance(arg):
     return (P.A.row_ptr, P.A.col_idx, P.A.val, np.asfortranarray(P.F), P.part, P.n_parts), P.f
 
 
-def batched(count: int, precision: str, steps: int, warmup: int):
+def batched(count: int, precision: str, steps: int, warmup: int, persistent_leg: bool = True):
     """Batched leg: `count` independent 2D diffusion systems in one handle.
 
     Side lengths L ~ U{128..512} (seeded), L x L cells, kappa = exp(z) with z
@@ -427,7 +427,9 @@ def batched(count: int, precision: str, steps: int, warmup: int):
     (m = round(L/32) per axis), overlap 2, p = 3 (10 monomials), rtol 1e-8.
     The launch shape (tile edge, level merge target) comes from the library's
     autotuner on a sample of the batch.  Reports solves/s over the whole batch
-    and the per-system device time to convergence (p50/p99).
+    and the per-system device time to convergence (p50/p99), for the colour
+    launches (systems in lockstep) and for the persistent schedule (one launch,
+    systems advancing and stopping independently).
     """
     import multiprocessing as mp
 
@@ -459,6 +461,7 @@ def batched(count: int, precision: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = b.info()
+    persist_probs = probs if persistent_leg else None
     del probs
     log(f"batched: setup {setup_s:.1f} s (device numeric {info['setup_ms']:.0f} ms)")
     u = torch.empty_like(f)
@@ -488,10 +491,43 @@ def batched(count: int, precision: str, steps: int, warmup: int):
     its = np.array([i["iters"] for i in infos])
     tres = np.array([i["true_rel_res"] for i in infos])
     ok = all(i["status"] == 0 for i in infos)
+    u_colours = u.clone()
     b.close()
     log(f"batched: {ms:.1f} ms per batch solve, {count * 1e3 / ms:.1f} solves/s, iters {its.min()}..{its.max()}, "
         f"sweep kernel {sweep_gbs:.0f} GB/s")
+    # the same batch with the persistent schedule: one launch per batch solve, every
+    # system advancing through its own CG steps from a device task ring
+    persistent = None
+    if persist_probs is not None:
+        t0 = time.perf_counter()
+        bp = DDGBatchSolver(persist_probs, 2, precision=precision, rtol=1e-8, tile=tile, block_target=bt,
+                            schedule="persistent")
+        torch.cuda.synchronize()
+        psetup_s = time.perf_counter() - t0
+        up = torch.empty_like(f)
+        for _ in range(warmup):
+            bp.solve(f, up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, pinfos = bp.solve(f, up)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) * 1e3 / steps
+        pper = np.array([i["solve_ms"] for i in pinfos])
+        pits = np.array([i["iters"] for i in pinfos])
+        same = bool(torch.equal(up, u_colours))
+        bp.close()
+        log(f"batched persistent: {pms:.1f} ms per batch solve, {count * 1e3 / pms:.1f} solves/s, per-system "
+            f"p50 {np.percentile(pper, 50):.1f} ms p99 {np.percentile(pper, 99):.1f} ms, same u as colour launches: {same}")
+        persistent = {"ms_per_batch": pms, "solves_per_s": count * 1e3 / pms,
+                      "system_ms_p50": float(np.percentile(pper, 50)),
+                      "system_ms_p99": float(np.percentile(pper, 99)),
+                      "system_ms_min": float(pper.min()), "system_ms_max": float(pper.max()),
+                      "iters_min": int(pits.min()), "iters_max": int(pits.max()),
+                      "all_converged": all(i["status"] == 0 for i in pinfos),
+                      "same_u_as_colour_launches": same, "setup_s": psetup_s}
     return {
+        "persistent": persistent,
         "workload": f"batch{count}_diffusion2d_L128-512_kappa_lognormal",
         "systems": count, "n_total": int(f.numel()), "subdomains": int(info["n_parts"]), "overlap": 2, "p": 3,
         "precision": precision, "rtol": 1e-8, "steps": steps,

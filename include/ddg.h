@@ -62,9 +62,18 @@ typedef enum {
   DDG_SCHEDULE_AUTO = 0,     /* the library's choice: currently COLOURS, measured as fast or faster
                                 on every workload tried */
   DDG_SCHEDULE_COLOURS = 1,  /* one launch per colour phase, each preceded by a local-residual launch */
-  DDG_SCHEDULE_QUEUE = 2     /* one launch per sweep direction: (subdomain, chain) tasks taken from a
+  DDG_SCHEDULE_QUEUE = 2,    /* one launch per sweep direction: (subdomain, chain) tasks taken from a
                                 device queue in sweep order, each waiting only for the earlier
                                 subdomains whose sets meet its neighbourhood */
+  DDG_SCHEDULE_PERSISTENT = 3 /* ddg_solve runs the whole PCG of every system of the handle in one
+                                launch: workgroups take (system, step, chunk or subdomain) tasks from
+                                a device ring, and the last task of a step enqueues that system's
+                                next step, so the systems of a batch advance and stop independently
+                                (per-system solve_ms of ddg_solve_batched then differ).  Same results
+                                bit for bit as COLOURS with one workgroup per subdomain.  Needs exact
+                                local solves, two levels, at most 32 generating vectors and an
+                                explicit coarse inverse accurate without refinement (else
+                                DDG_ERR_UNSUPPORTED); ddg_apply_precond keeps the colour launches. */
 } ddg_schedule;
 
 /* Direction update of CG (Sections 1 and 7 use CG; the paper does not fix the

@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "mixed": 1, "bf16": 2}
 EXPORT_COLOURS, EXPORT_SET_PTR, EXPORT_SET_IDX, EXPORT_KCOUNTS, EXPORT_A0, EXPORT_Q, EXPORT_BLOCKS = range(7)
 
 
-SCHEDULE = {"auto": 0, "colours": 1, "queue": 2}
+SCHEDULE = {"auto": 0, "colours": 1, "queue": 2, "persistent": 3}
 BC = {"dirichlet": 0, "x0": 1}
 CG_VARIANT = {"fr": 0, "pr": 1}
 MATRIX_FORMAT = {"auto": 0, "csr": 1}

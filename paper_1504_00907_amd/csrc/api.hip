@@ -182,7 +182,7 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
   const int64_t cg = nnzb + 2 * n * 8 + 6 * n * 8 + 4 * n * 8 + 3 * n * 8;
   h.info.iter_bytes = sweep + coarse + cg + n * 8;
   h.info.tile = S.tile;
-  h.info.schedule = h.flow_ok ? DDG_SCHEDULE_QUEUE : DDG_SCHEDULE_COLOURS;
+  h.info.schedule = h.persist ? DDG_SCHEDULE_PERSISTENT : h.flow_ok ? DDG_SCHEDULE_QUEUE : DDG_SCHEDULE_COLOURS;
   h.info.factor_bytes = h.ssor ? 0 : S.fac_elems * es;
   h.info.coarse_bytes = h.nc ? ntiles * 64 * 64 * 8 : 0;
 }
@@ -646,7 +646,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   // sweep over a device task queue (each task forms its own residual rows) on request;
   // the automatic choice is the colour launches (measured: 21.7 vs 21.9 ms at 128^3
   // FP32, 123 vs 139 ms for the batch of 256)
-  DDG_REQUIRE(h->opt.schedule >= DDG_SCHEDULE_AUTO && h->opt.schedule <= DDG_SCHEDULE_QUEUE,
+  DDG_REQUIRE(h->opt.schedule >= DDG_SCHEDULE_AUTO && h->opt.schedule <= DDG_SCHEDULE_PERSISTENT,
               DDG_ERR_INVALID_ARG, "schedule must be a ddg_schedule value");
   h->flow_ok = h->opt.schedule == DDG_SCHEDULE_QUEUE;
   DDG_REQUIRE(!(h->flow_ok && h->ssor), DDG_ERR_UNSUPPORTED, "SSOR smoothing runs with the colour launches only");
@@ -695,6 +695,8 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->ws.rpart = h->nc > 0 ? h->rpart.as<double>() : nullptr;
   h->ws.cy = h->nc > 0 ? h->cy.as<double>() : nullptr;
   h->ws.cpart = h->nc > 0 && !h->three_level ? h->cpart.as<double>() : nullptr;
+  h->persist = h->opt.schedule == DDG_SCHEDULE_PERSISTENT;
+  if (h->persist) prepare_persist(*h, s);
   numeric_setup(*h);
   account_bytes(*h, row_ptr, col_idx);
   h->info.n_coarse = (int32_t)h->nc;
@@ -1091,13 +1093,17 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     double* x = u_dev;
     double* z = h->z.as<double>();
     const size_t sb = (size_t)h->nb * sizeof(CgState);
-    launch_cg_init(*h, f_dev, x, s);
-    h->cur_tag = 0;
-    launch_precond(*h, h->r.as<double>(), z, -1, true, s);
-    launch_cg_start(*h, s);
     const int chunk = h->opt.check_every;
     int enqueued = 0;
-    while (true) {
+    if (h->persist) {
+      launch_persist(*h, f_dev, x, s);
+    } else {
+      launch_cg_init(*h, f_dev, x, s);
+      h->cur_tag = 0;
+      launch_precond(*h, h->r.as<double>(), z, -1, true, s);
+      launch_cg_start(*h, s);
+    }
+    while (!h->persist) {
       for (int t = 0; t < chunk; ++t) {
         launch_cg_step_a(*h, x, s);
         h->cur_tag = enqueued + t + 1;  // the preconditioner of iteration enqueued + t + 1

@@ -23,7 +23,7 @@ __device__ inline void d_coarse_restrict(int i, int c, int nch, const int32_t* _
                                          const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
                                          const int32_t* __restrict__ kcnt, const double* __restrict__ Q, int kq,
                                          const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                         const double* __restrict__ val, const DiaView& D,
+                                         const double* __restrict__ val, const DiaView D,
                                          const double* __restrict__ r, const double* __restrict__ e, int rch,
                                          double* __restrict__ rpart) {
   __shared__ double red[kRThreads / 64][KM];

@@ -255,6 +255,13 @@ struct Handle {
   std::vector<DiaSys> dia_sys_h;
   DevBuf dia_sys, dia_diag, dia_up;
   PrecondWs ws;                      // the buffers the preconditioner's kernels use (see PrecondWs)
+  // persistent batched solve (DDG_SCHEDULE_PERSISTENT): per (system, colour) subdomain
+  // lists, the subdomain offsets of the systems, the initial ring words and per-system
+  // states, the per-system states and counts in use, the control words and the ring
+  bool persist = false;
+  DevBuf ps_ptr, ps_sub, ps_suboff, ps_init, ps_sys0, ps_sys, ps_cnt, ps_ctl, ps_ring;
+  int32_t ps_ninit = 0;
+  int64_t ps_omax = 0;               // most tasks outstanding at once (sum over systems of the largest phase)
   int32_t device = 0;                // HIP device current at setup
   int32_t xch_ld = 0;
   bool twisted_ok = false;
@@ -396,6 +403,8 @@ void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool 
                     hipStream_t s, const CgState* guard = nullptr);
 // one sweep direction (0: colours ascending, 1: descending) as a persistent launch
 void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s);
+void prepare_persist(Handle& h, hipStream_t s);
+void launch_persist(Handle& h, const double* f, double* x, hipStream_t s);
 
 // setup numerics
 void launch_coarse_basis(Handle& h, hipStream_t s);

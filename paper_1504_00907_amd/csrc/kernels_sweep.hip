@@ -29,6 +29,8 @@
 
 #include <hip/hip_ext.h>
 
+#include "cg_device.hpp"
+#include "coarse_device.hpp"
 #include "common.hpp"
 #include "symv_tile.hpp"
 
@@ -817,31 +819,47 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
   DDG_HIP(hipGetLastError());
 }
 
-template <class FT, class AT, bool SL>
-void launch_sweep_l(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                    const CgState* st, hipStream_t s, bool res, int fd) {
-  // (waves, tiles per wave per round) keep the register ring within 128 VGPRs at 16 waves
-  // or 256 at 8 waves, without spills (the sliced path's prefetched couplings take a
-  // few registers of their own)
-  switch (h.S.tile) {
-    case 16: launch_sweep_cfg<FT, AT, 16, 4, 4, SL>(h, colour, r, e, e_zero, st, s, res, fd); break;
+// The local-solve launch shapes: (waves, tiles per wave per round) keep the register
+// ring within 128 VGPRs at 16 waves or 256 at 8 waves, without spills (the sliced
+// path's prefetched couplings take a few registers of their own).  fn is called with
+// a SweepCfg of the handle's factor precision, coupling layout and tile edge.
+template <class FT_, class AT_, int T_, int NW_, int TPW_, bool SL_>
+struct SweepCfg {
+  using FT = FT_;
+  using AT = AT_;
+  static constexpr int T = T_, NW = NW_, TPW = TPW_;
+  static constexpr bool SL = SL_;
+};
+
+template <class FT, class AT, bool SL, class Fn>
+void with_cfg_tile(int tile, Fn&& fn) {
+  switch (tile) {
+    case 16: fn(SweepCfg<FT, AT, 16, 4, 4, SL>{}); break;
     case 32:
-      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 32, 8, 4, SL>(h, colour, r, e, e_zero, st, s, res, fd);
-      else if constexpr (SL) launch_sweep_cfg<FT, AT, 32, 8, 7, SL>(h, colour, r, e, e_zero, st, s, res, fd);
-      else launch_sweep_cfg<FT, AT, 32, 8, 8, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      if constexpr (sizeof(FT) == 8) fn(SweepCfg<FT, AT, 32, 8, 4, SL>{});
+      else if constexpr (SL) fn(SweepCfg<FT, AT, 32, 8, 7, SL>{});
+      else fn(SweepCfg<FT, AT, 32, 8, 8, SL>{});
       break;
     default:
-      if constexpr (sizeof(FT) == 8) launch_sweep_cfg<FT, AT, 64, 8, 1, SL>(h, colour, r, e, e_zero, st, s, res, fd);
-      else launch_sweep_cfg<FT, AT, 64, 8, 2, SL>(h, colour, r, e, e_zero, st, s, res, fd);
+      if constexpr (sizeof(FT) == 8) fn(SweepCfg<FT, AT, 64, 8, 1, SL>{});
+      else fn(SweepCfg<FT, AT, 64, 8, 2, SL>{});
       break;
   }
 }
 
-template <class FT, class AT>
-void launch_sweep_p(const Handle& h, int colour, const double* r, double* e, bool e_zero,
-                    const CgState* st, hipStream_t s, bool res, int fd) {
-  if (h.S.sliced) launch_sweep_l<FT, AT, true>(h, colour, r, e, e_zero, st, s, res, fd);
-  else launch_sweep_l<FT, AT, false>(h, colour, r, e, e_zero, st, s, res, fd);
+template <class FT, class AT, class Fn>
+void with_cfg_layout(const Handle& h, Fn&& fn) {
+  if (h.S.sliced) with_cfg_tile<FT, AT, true>(h.S.tile, fn);
+  else with_cfg_tile<FT, AT, false>(h.S.tile, fn);
+}
+
+template <class Fn>
+void with_sweep_cfg(const Handle& h, Fn&& fn) {
+  switch (h.opt.precision) {
+    case DDG_MIXED_FP32: with_cfg_layout<float, float>(h, fn); break;
+    case DDG_MIXED_BF16: with_cfg_layout<__hip_bfloat16, float>(h, fn); break;
+    default: with_cfg_layout<double, double>(h, fn); break;
+  }
 }
 
 }  // namespace
@@ -940,21 +958,518 @@ void launch_sweep(const Handle& h, int colour, const double* r, double* e, bool 
     launch_ssor_phase(h, colour, r, e, e_zero, st, s, res);
     return;
   }
-  switch (h.opt.precision) {
-    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, colour, r, e, e_zero, st, s, res, -1); break;
-    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, colour, r, e, e_zero, st, s, res, -1); break;
-    default: launch_sweep_p<double, double>(h, colour, r, e, e_zero, st, s, res, -1); break;
-  }
+  with_sweep_cfg(h, [&](auto c) {
+    using C = decltype(c);
+    launch_sweep_cfg<typename C::FT, typename C::AT, C::T, C::NW, C::TPW, C::SL>(h, colour, r, e, e_zero, st, s,
+                                                                                 res, -1);
+  });
 }
 
 // dir 0: the ascending sweep (e is zero on entry); 1: the descending sweep.
 void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s) {
   DDG_REQUIRE(h.flow_ok, DDG_ERR_HIP, "internal: persistent sweep not prepared");
-  switch (h.opt.precision) {
-    case DDG_MIXED_FP32: launch_sweep_p<float, float>(h, 0, r, e, dir == 0, st, s, false, dir); break;
-    case DDG_MIXED_BF16: launch_sweep_p<__hip_bfloat16, float>(h, 0, r, e, dir == 0, st, s, false, dir); break;
-    default: launch_sweep_p<double, double>(h, 0, r, e, dir == 0, st, s, false, dir); break;
+  with_sweep_cfg(h, [&](auto c) {
+    using C = decltype(c);
+    launch_sweep_cfg<typename C::FT, typename C::AT, C::T, C::NW, C::TPW, C::SL>(h, 0, r, e, dir == 0, st, s, false,
+                                                                                 dir);
+  });
+}
+
+
+// ---------------------------------------------------------------------------
+// Persistent batched solve (DDG_SCHEDULE_PERSISTENT): the whole PCG of every
+// system of the handle in one launch.  Workgroups take tasks from a device ring
+// in order.  A task is one chunk of rows, one subdomain's local solve, one
+// restriction chunk, a group of coarse tiles or one system's scalar step.  Each
+// system walks its own sequence of phases, the steps of the one-launch-per-step
+// driver in the same order: e = 0, the colours of the pre-sweep, restriction,
+// coarse solve, prolongation, the colours of the post-sweep, r.z, rho and beta,
+// the direction update, q = A p with p.q, alpha, the x and r update with r.r,
+// the convergence test.  The workgroup that finishes the last task of a phase
+// enqueues the next phase of that system, so systems advance and stop
+// independently.  Every task runs the device body of the per-step kernels on
+// the same data and rows, so every value is the same bit for bit.  No task
+// waits for another task: a workgroup only waits for the ring slot it claimed to
+// be published (bounded by a wall-clock limit), and it leaves once every system
+// has stopped.
+namespace {
+
+enum PTask : int32_t {
+  PT_EXIT = 0, PT_INIT, PT_INIT_S, PT_ZERO, PT_SWEEP_F, PT_RESTRICT, PT_RSUM, PT_SYMV, PT_CSUM, PT_PROLONG,
+  PT_SWEEP_B, PT_DOT, PT_RHO, PT_XPBY, PT_SPMV, PT_ALPHA, PT_AXPY, PT_CONV
+};
+
+// A ring slot is one 64-bit word, written and read whole: kind (5 bits), aux (7: the
+// colour of a sweep task, the first-iteration flag of r.z and rho), system (16),
+// task index within the phase (21), and the lap of the ring position (15), which
+// tells a published slot from the one of the previous lap.  Empty slots hold ~0.
+constexpr int kPsTagShift = 49;
+constexpr uint64_t kPsTagMask = 0x7FFF;
+constexpr int kPsRowsPerTask = 256;   // coarse entries or rows per summation task
+
+__host__ __device__ inline uint64_t ps_word(int kind, int aux, int sys, int idx, uint64_t lap) {
+  return (uint64_t)kind | ((uint64_t)aux << 5) | ((uint64_t)sys << 12) | ((uint64_t)idx << 28) |
+         ((lap & kPsTagMask) << kPsTagShift);
+}
+
+struct PSys {
+  int32_t phase;    // PTask of the running phase
+  int32_t colour;   // colour of a sweep phase
+  int32_t count;    // tasks of the running phase
+  int32_t first;    // 1 until the first r.z and rho have run
+};
+
+struct PsCtl {
+  unsigned long long head;   // next ring position to claim
+  unsigned long long tail;   // next ring position to allocate
+  int32_t all_done;          // every system has stopped (or the launch gave up)
+  int32_t remaining;         // systems still running
+};
+
+struct PersistArgs {
+  uint64_t* ring;
+  uint64_t mask;
+  int32_t log2size;
+  PsCtl* ctl;
+  PSys* sys;
+  int32_t* cnt;              // per system: finished tasks of the running phase
+  int32_t* err;
+  uint64_t wait_ticks;       // wall-clock limit of one wait for a slot
+  // CG
+  CgState* st;
+  SegMap m;
+  Hist hist;
+  double rtol;
+  int32_t max_iter;
+  int32_t pr;                // Polak-Ribiere direction update
+  const double* f;
+  double *x, *r, *p, *q, *z;
+  double *part, *part2;
+  const int64_t* rp;
+  const int32_t* ci;
+  const double* val;
+  DiaView D;
+  int32_t lpr;
+  // sweeps: per (system, colour) subdomain lists
+  const int32_t* ps_ptr;     // nb * C + 1
+  const int32_t* ps_sub;
+  int32_t C;
+  // coarse correction
+  int32_t has_coarse;
+  const int32_t* sub_off;    // nb + 1
+  const int32_t* sub_inst;
+  const int64_t* own_ptr;
+  const int32_t* own_idx;
+  const int32_t* kcnt;
+  const int64_t* koff;
+  const int32_t* part_id;    // subdomain of every row
+  const double* Q;
+  int32_t kq;
+  int32_t nch, rch;
+  double* rpart;
+  double* b0;
+  double* y;
+  const int64_t* tile_base;
+  const int64_t* cblk_off;
+  const int32_t* cblk_n;
+  const double* tiles;
+  double *rowpart, *colpart;
+};
+
+template <class Fn>
+__device__ inline void with_lanes_dev(int L, Fn&& f) {
+  switch (L) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
   }
+}
+
+// tasks of phase ph (colour c) of system b; NW tiles per coarse-GEMV task
+__host__ __device__ inline int32_t ps_count(int ph, int c, int chunks, const int32_t* ps_ptr, int b, int C,
+                                            int nsub, int nch, int64_t ntiles, int64_t crows, int NW) {
+  switch (ph) {
+    case PT_INIT: case PT_ZERO: case PT_PROLONG: case PT_DOT: case PT_XPBY: case PT_SPMV: case PT_AXPY:
+      return chunks;
+    case PT_SWEEP_F: case PT_SWEEP_B: return ps_ptr[b * C + c + 1] - ps_ptr[b * C + c];
+    case PT_RESTRICT: return nsub * nch;
+    case PT_RSUM: return (nsub * 32 + kPsRowsPerTask - 1) / kPsRowsPerTask;
+    case PT_SYMV: return (int32_t)((ntiles + NW - 1) / NW);
+    case PT_CSUM: return (int32_t)((crows + kPsRowsPerTask - 1) / kPsRowsPerTask);
+    default: return 1;
+  }
+}
+
+template <int NW>
+__device__ inline int32_t p_count(const PersistArgs& P, int b, int ph, int c) {
+  return ps_count(ph, c, P.m.ptr[b + 1] - P.m.ptr[b], P.ps_ptr, b, P.C, P.sub_off[b + 1] - P.sub_off[b], P.nch,
+                  P.has_coarse ? P.tile_base[b + 1] - P.tile_base[b] : 0,
+                  P.has_coarse ? P.cblk_off[b + 1] - P.cblk_off[b] : 0, NW);
+}
+
+// The phase after (ph, c) of system b, skipping phases without tasks; PT_EXIT once
+// the system has stopped.  first: the first r.z (after the first preconditioner).
+template <int NW>
+__device__ inline void p_next(const PersistArgs& P, int b, int& ph, int& c, int first) {
+  const bool coarse = P.has_coarse && P.cblk_n[b] > 0;
+  const bool done = P.st[b].done != 0;
+  for (;;) {
+    switch (ph) {
+      case PT_INIT: ph = PT_INIT_S; break;
+      case PT_INIT_S: ph = done ? PT_EXIT : PT_ZERO; break;
+      case PT_ZERO: ph = PT_SWEEP_F; c = 0; break;
+      case PT_SWEEP_F:
+        if (c + 1 < P.C) ++c;
+        else if (coarse) ph = PT_RESTRICT;
+        else { ph = PT_SWEEP_B; c = P.C - 1; }
+        break;
+      case PT_RESTRICT: ph = PT_RSUM; break;
+      case PT_RSUM: ph = PT_SYMV; break;
+      case PT_SYMV: ph = PT_CSUM; break;
+      case PT_CSUM: ph = PT_PROLONG; break;
+      case PT_PROLONG: ph = PT_SWEEP_B; c = P.C - 1; break;
+      case PT_SWEEP_B:
+        if (c > 0) --c;
+        else ph = PT_DOT;
+        break;
+      case PT_DOT: ph = PT_RHO; break;
+      case PT_RHO: ph = done ? PT_EXIT : (first ? PT_SPMV : PT_XPBY); break;
+      case PT_XPBY: ph = PT_SPMV; break;
+      case PT_SPMV: ph = PT_ALPHA; break;
+      case PT_ALPHA: ph = done ? PT_EXIT : PT_AXPY; break;
+      case PT_AXPY: ph = PT_CONV; break;
+      case PT_CONV: ph = done ? PT_EXIT : PT_ZERO; break;
+      default: ph = PT_EXIT; break;
+    }
+    if (ph == PT_EXIT || p_count<NW>(P, b, ph, c) > 0) return;
+  }
+}
+
+// At least two waves per SIMD: the task bodies together would otherwise take every
+// register of the SIMD at the 256-thread shape and leave one workgroup per CU (no
+// reference to the by-value arguments may reach a body that is not inlined, or they
+// are copied to private memory).
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
+__global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs P) {
+  constexpr int NT = NW * 64;
+  __shared__ int32_t s_task[5];
+  __shared__ int32_t s_next[4];
+  __shared__ unsigned long long s_base;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      const unsigned long long pos = atomicAdd(&P.ctl->head, 1ull);
+      const uint64_t want = (pos >> P.log2size) & kPsTagMask;
+      const uint64_t* sl = P.ring + (pos & P.mask);
+      int kind = PT_EXIT;
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      for (int spin = 1;; ++spin) {
+        const uint64_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((v >> kPsTagShift) == want) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          wait_vm();
+          kind = (int)(v & 31);
+          const int b = (int)((v >> 12) & 0xFFFF);
+          s_task[1] = b;
+          s_task[2] = (int)((v >> 28) & 0x1FFFFF);
+          s_task[3] = (int)((v >> 5) & 127);
+          // the phase's task count, read while this task is unfinished: the last
+          // finisher replaces it only after every task of the phase has counted itself
+          s_task[4] = __hip_atomic_load(&P.sys[b].count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        if (__hip_atomic_load(&P.ctl->all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(2);
+        if ((spin & 255) == 0 && (uint64_t)wall_clock64() - t0 > P.wait_ticks) {
+          if (atomicCAS(P.err, 0, DDG_ERR_HIP) == 0) {
+            P.err[1] = -1;
+            P.err[2] = -10;
+          }
+          __hip_atomic_store(&P.ctl->all_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      s_task[0] = kind;
+    }
+    __syncthreads();
+    const int kind = s_task[0], b = s_task[1], idx = s_task[2], aux = s_task[3], need = s_task[4];
+    __syncthreads();
+    if (kind == PT_EXIT) return;
+    const int g = P.m.ptr[b] + idx;   // chunk of rows (chunk tasks)
+    switch (kind) {
+      case PT_INIT: d_cg_init(P.m, g, P.f, P.x, P.r, P.part); break;
+      case PT_INIT_S: d_cg_init_scalar(P.st, P.m, b, P.part, P.rtol, P.max_iter, P.hist); break;
+      case PT_ZERO: d_zero(P.m, g, P.z); break;
+      case PT_SWEEP_F:
+      case PT_SWEEP_B: {
+        const int sub = P.ps_sub[P.ps_ptr[b * P.C + aux] + idx];
+        sweep_task<FT, AT, T, NW, TPW, SL, true>(a, sub, 0, sub, kind == PT_SWEEP_F && aux == 0);
+        break;
+      }
+      case PT_RESTRICT: {
+        const int i = P.sub_off[b] + idx / P.nch, c = idx % P.nch;
+        with_lanes_dev(P.lpr, [&](auto Lc) {
+          constexpr int L = decltype(Lc)::value;
+          d_coarse_restrict<L, 32>(i, c, P.nch, P.sub_inst, P.own_ptr, P.own_idx, P.kcnt, P.Q, P.kq, P.rp, P.ci,
+                                   P.val, P.D, P.r, P.z, P.rch, P.rpart);
+        });
+        break;
+      }
+      case PT_RSUM: {
+        const int i0 = P.sub_off[b], ne = (P.sub_off[b + 1] - i0) * 32;
+        const int e = idx * kPsRowsPerTask + tid;
+        if (tid < kPsRowsPerTask && e < ne) d_coarse_restrict_sum_entry(i0 + e / 32, e % 32, P.kcnt, P.koff, P.rpart, P.nch, 32, P.b0);
+        break;
+      }
+      case PT_SYMV: {
+        const int64_t t = P.tile_base[b] + (int64_t)idx * NW + (tid >> 6);
+        if (t < P.tile_base[b + 1]) d_coarse_symv_tile(t, b, P.tile_base, P.cblk_off, P.tiles, P.b0, P.rowpart, P.colpart);
+        break;
+      }
+      case PT_CSUM: {
+        const int64_t row = P.cblk_off[b] + (int64_t)idx * kPsRowsPerTask + tid;
+        if (tid < kPsRowsPerTask && row < P.cblk_off[b + 1])
+          d_coarse_sum_row(row, b, P.tile_base, P.cblk_off, P.rowpart, P.colpart, P.y);
+        break;
+      }
+      case PT_PROLONG:
+        for (int64_t row = P.m.lo[g] + tid; row < P.m.hi[g]; row += NT)
+          d_coarse_prolong_row<32>(row, nullptr, P.sub_inst, P.part_id, P.kcnt, P.koff, P.Q, P.kq, P.y, P.z);
+        break;
+      case PT_DOT:
+        if (aux) d_copy_dot(P.m, g, P.r, P.z, P.p, P.part);
+        else if (P.pr) d_dot2(P.m, g, P.r, P.z, P.q, P.part, P.part2);
+        else d_dot(P.m, g, P.r, P.z, P.part);
+        break;
+      case PT_RHO: d_rho_scalar(P.st, P.m, b, P.part, P.pr && !aux ? P.part2 : nullptr, aux, P.hist); break;
+      case PT_XPBY: d_xpby(P.st + b, P.m, g, P.z, P.p); break;
+      case PT_SPMV:
+        with_lanes_dev(P.lpr, [&](auto Lc) {
+          constexpr int L = decltype(Lc)::value;
+          d_spmv_dot<L>(P.m, g, P.rp, P.ci, P.val, P.D, P.p, P.q, P.part);
+        });
+        break;
+      case PT_ALPHA: d_alpha_scalar(P.st, P.m, b, P.part, P.hist); break;
+      case PT_AXPY: d_axpy2_dot(P.st + b, P.m, g, P.x, P.r, P.p, P.q, P.part); break;
+      case PT_CONV: d_conv_scalar(P.st, P.m, b, P.part, P.hist); break;
+      default: break;
+    }
+    // completion: publish this task's stores and count it; the last task of the
+    // phase moves its system on
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      wait_vm();
+      const int32_t finished = __hip_atomic_fetch_add(P.cnt + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+      int n_next = 0;
+      if (finished == need) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        wait_vm();
+        PSys s = P.sys[b];
+        int ph = s.phase, c = s.colour;
+        const int first = s.first;
+        p_next<NW>(P, b, ph, c, first);
+        if (s.phase == PT_RHO) s.first = 0;
+        if (ph == PT_EXIT) {
+          if (__hip_atomic_fetch_add(&P.ctl->remaining, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1)
+            __hip_atomic_store(&P.ctl->all_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          n_next = p_count<NW>(P, b, ph, c);
+          s.phase = ph;
+          s.colour = c;
+          s.count = n_next;
+          P.sys[b] = s;
+          __hip_atomic_store(P.cnt + b, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // the state is in memory before any task of the next phase can be claimed
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          wait_vm();
+          s_base = atomicAdd(&P.ctl->tail, (unsigned long long)n_next);
+          s_next[1] = ph;
+          s_next[2] = (ph == PT_SWEEP_F || ph == PT_SWEEP_B) ? c : ((ph == PT_DOT || ph == PT_RHO) ? first : 0);
+        }
+      }
+      s_next[0] = n_next;
+    }
+    __syncthreads();
+    const int n_next = s_next[0];
+    if (n_next > 0) {
+      const int ph = s_next[1], aux2 = s_next[2];
+      const unsigned long long base = s_base;
+      for (int t = tid; t < n_next; t += NT) {
+        const unsigned long long pos = base + (unsigned long long)t;
+        __hip_atomic_store(P.ring + (pos & P.mask), ps_word(ph, aux2, b, t, pos >> P.log2size), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ring reset: the initial tasks (PT_INIT of every system) at the first positions,
+// every other slot empty; the per-system states and counts from their initial values
+__global__ void k_persist_reset(uint64_t* __restrict__ ring, int64_t size, const uint64_t* __restrict__ init,
+                                int32_t n_init, PSys* __restrict__ sys, const PSys* __restrict__ sys0,
+                                int32_t* __restrict__ cnt, int32_t nb, PsCtl* __restrict__ ctl) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < size) ring[i] = i < n_init ? init[i] : ~0ull;
+  if (i < nb) {
+    sys[i] = sys0[i];
+    cnt[i] = 0;
+  }
+  if (i == 0) {
+    ctl->head = 0;
+    ctl->tail = (unsigned long long)n_init;
+    ctl->all_done = 0;
+    ctl->remaining = nb;
+  }
+}
+
+template <class FT, class AT, int T, int NW, int TPW, bool SL>
+void launch_persist_cfg(Handle& h, const double* f, double* x, hipStream_t s) {
+  const Symbolic& S = h.S;
+  SweepArgs a;
+  const size_t lds = build_sweep_args<FT, AT, T, NW, TPW, SL>(h, h.colour_subs.as<int32_t>(), S.n_parts,
+                                                              h.r.as<double>(), h.z.as<double>(), false, nullptr, a);
+  auto kern = k_persist<FT, AT, T, NW, TPW, SL>;
+  if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int occ = 0;
+  DDG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, NW * 64, lds));
+  const int64_t grid = (int64_t)h.n_cu * std::max(1, occ);
+  // ring: at least twice the most tasks that can be outstanding at once plus the grid
+  // (a slot is reused only after the whole ring has been claimed since), a power of two
+  int32_t lg = 10;
+  while (((int64_t)1 << lg) < 2 * (h.ps_omax + grid)) ++lg;
+  DDG_REQUIRE(lg <= 30, DDG_ERR_UNSUPPORTED, "persistent schedule: too many tasks");
+  const int64_t size = (int64_t)1 << lg;
+  if (h.ps_ring.bytes < (size_t)size * sizeof(uint64_t)) h.ps_ring.alloc((size_t)size * sizeof(uint64_t));
+  hipLaunchKernelGGL(k_persist_reset, dim3((unsigned)((std::max<int64_t>(size, h.nb) + 255) / 256)), dim3(256), 0, s,
+                     h.ps_ring.as<uint64_t>(), size, h.ps_init.as<uint64_t>(), h.ps_ninit, h.ps_sys.as<PSys>(),
+                     h.ps_sys0.as<PSys>(), h.ps_cnt.as<int32_t>(), h.nb, h.ps_ctl.as<PsCtl>());
+  PersistArgs P{};
+  P.ring = h.ps_ring.as<uint64_t>();
+  P.mask = (uint64_t)size - 1;
+  P.log2size = lg;
+  P.ctl = h.ps_ctl.as<PsCtl>();
+  P.sys = h.ps_sys.as<PSys>();
+  P.cnt = h.ps_cnt.as<int32_t>();
+  P.err = h.err_flag.as<int32_t>();
+  P.wait_ticks = (uint64_t)h.clock_khz * 30000ull;   // 30 s
+  P.st = h.cstate.as<CgState>();
+  P.m = SegMap{h.wg_seg.as<int32_t>(), h.wg_lo.as<int64_t>(), h.wg_hi.as<int64_t>(), h.seg_wg_ptr_d.as<int32_t>()};
+  P.hist = Hist{h.hist.as<double>(), (int64_t)h.opt.max_iter + 1};
+  P.rtol = h.opt.rtol;
+  P.max_iter = h.opt.max_iter;
+  P.pr = h.opt.cg_variant == DDG_CG_POLAK_RIBIERE ? 1 : 0;
+  P.f = f;
+  P.x = x;
+  P.r = h.r.as<double>();
+  P.p = h.p.as<double>();
+  P.q = h.q.as<double>();
+  P.z = h.z.as<double>();
+  P.part = h.part_sums.as<double>();
+  P.part2 = P.part + h.n_partials;
+  P.rp = h.rowptr.as<int64_t>();
+  P.ci = h.col.as<int32_t>();
+  P.val = h.val.as<double>();
+  P.D = dia_view(h);
+  P.lpr = h.lpr;
+  P.ps_ptr = h.ps_ptr.as<int32_t>();
+  P.ps_sub = h.ps_sub.as<int32_t>();
+  P.C = S.n_colours;
+  P.has_coarse = h.nc > 0 ? 1 : 0;
+  P.sub_off = h.ps_suboff.as<int32_t>();
+  P.sub_inst = h.sub_inst.as<int32_t>();
+  if (h.nc > 0) {
+    P.own_ptr = h.own_ptr.as<int64_t>();
+    P.own_idx = h.own_idx.as<int32_t>();
+    P.kcnt = h.kcnt_d.as<int32_t>();
+    P.koff = h.koff_d.as<int64_t>();
+    P.part_id = h.part.as<int32_t>();
+    P.Q = h.Q.as<double>();
+    P.kq = h.k;
+    P.nch = h.nch;
+    P.rch = h.rch;
+    P.rpart = h.ws.rpart;
+    P.b0 = h.ws.cy;
+    P.y = h.ws.cy + h.nc_pad;
+    P.tile_base = h.tile_base_d.as<int64_t>();
+    P.cblk_off = h.cblk_off_d.as<int64_t>();
+    P.cblk_n = h.cblk_n_d.as<int32_t>();
+    P.tiles = h.A0inv_t.as<double>();
+    P.rowpart = h.ws.cpart;
+    P.colpart = h.ws.cpart + h.ntiles * 64;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NW * 64), lds, s, a, P);
+  DDG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// Host tables of the persistent schedule (per system and colour, its subdomains in
+// the colour lists' order; the initial ring words and states; the most tasks that
+// can be outstanding at once).
+void prepare_persist(Handle& h, hipStream_t s) {
+  const Symbolic& S = h.S;
+  const int32_t nb = h.nb, C = S.n_colours;
+  DDG_REQUIRE(!h.three_level && !h.ssor && h.k <= 32, DDG_ERR_UNSUPPORTED,
+              "persistent schedule: needs exact local solves, two levels and at most 32 generating vectors");
+  DDG_REQUIRE(C < 128 && nb < 65536, DDG_ERR_UNSUPPORTED, "persistent schedule: at most 127 colours and 65535 systems");
+  std::vector<int32_t> sub_sys(S.n_parts);
+  for (int32_t b = 0; b < nb; ++b)
+    for (int32_t i = h.sub_off[b]; i < h.sub_off[b + 1]; ++i) sub_sys[i] = b;
+  std::vector<std::vector<int32_t>> lists((size_t)nb * C);
+  for (int32_t c = 0; c < C; ++c)
+    for (int32_t t = S.colour_ptr[c]; t < S.colour_ptr[c + 1]; ++t) {
+      const int32_t sub = S.colour_subs[t];
+      lists[(size_t)sub_sys[sub] * C + c].push_back(sub);
+    }
+  std::vector<int32_t> ptr((size_t)nb * C + 1, 0), subs;
+  subs.reserve(S.n_parts);
+  for (size_t q = 0; q < lists.size(); ++q) {
+    subs.insert(subs.end(), lists[q].begin(), lists[q].end());
+    ptr[q + 1] = (int32_t)subs.size();
+  }
+  std::vector<uint64_t> init;
+  std::vector<PSys> sys0(nb);
+  int64_t omax = 0;
+  for (int32_t b = 0; b < nb; ++b) {
+    const int32_t chunks = h.seg_wg_ptr[b + 1] - h.seg_wg_ptr[b];
+    const int32_t nsub = h.sub_off[b + 1] - h.sub_off[b];
+    const int64_t ntiles = h.nc > 0 ? h.tile_base[b + 1] - h.tile_base[b] : 0;
+    const int64_t crows = h.nc > 0 ? h.cblk_off[b + 1] - h.cblk_off[b] : 0;
+    int32_t most = 0;
+    for (int ph = PT_INIT; ph <= PT_CONV; ++ph)
+      for (int c = 0; c < ((ph == PT_SWEEP_F || ph == PT_SWEEP_B) ? C : 1); ++c)
+        most = std::max(most, ps_count(ph, c, chunks, ptr.data(), b, C, nsub, h.nch, ntiles, crows, 4));
+    DDG_REQUIRE(most < (1 << 21), DDG_ERR_UNSUPPORTED, "persistent schedule: more than 2^21 tasks in one phase");
+    omax += most;
+    for (int32_t t = 0; t < chunks; ++t) init.push_back(ps_word(PT_INIT, 0, b, t, 0));
+    sys0[b] = PSys{PT_INIT, 0, chunks, 1};
+  }
+  h.ps_omax = omax;
+  h.ps_ninit = (int32_t)init.size();
+  h.ps_ptr.upload(ptr, s);
+  h.ps_sub.upload(subs, s);
+  h.ps_suboff.upload(h.sub_off, s);
+  h.ps_init.upload(init, s);
+  h.ps_sys0.upload(sys0, s);
+  h.ps_sys.alloc((size_t)nb * sizeof(PSys));
+  h.ps_cnt.alloc((size_t)nb * sizeof(int32_t));
+  h.ps_ctl.alloc(sizeof(PsCtl));
+}
+
+// The whole solve of every system in one launch (schedule DDG_SCHEDULE_PERSISTENT).
+void launch_persist(Handle& h, const double* f, double* x, hipStream_t s) {
+  DDG_REQUIRE(h.persist, DDG_ERR_HIP, "internal: persistent schedule not prepared");
+  DDG_REQUIRE(h.coarse_refine == 0, DDG_ERR_UNSUPPORTED,
+              "persistent schedule: the coarse inverse needs refinement steps (ill-conditioned A0)");
+  with_sweep_cfg(h, [&](auto c) {
+    using Cf = decltype(c);
+    launch_persist_cfg<typename Cf::FT, typename Cf::AT, Cf::T, Cf::NW, Cf::TPW, Cf::SL>(h, f, x, s);
+  });
 }
 
 }  // namespace ddg
