@@ -71,6 +71,30 @@ def profiled_traffic(kernel: str, precision: str, tile: int):
         return None
 
 
+def profiled_mfma():
+    """Setup GEMM rates on the FP64 matrix cores from the committed rocprofv3 summary
+    (128^3 workload), or None when kernels_setup.hip changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "setup_mfma_diffusion3d_128.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        for tok in line.split():
+            if "=" in tok:
+                k, v = tok.split("=", 1)
+                kv[k] = v
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_1504_00907_amd/csrc/kernels_setup.hip"), "rb").read())
+    if kv.get("src_sha256_16") != h.hexdigest()[:16]:
+        return None
+    out = {"peak": 78.6, "unit": "TFLOP/s", "source": "profiles/setup_mfma_diffusion3d_128.md"}
+    for name in ("bgemm", "galerkin"):
+        fl, t = float(kv[f"{name}_flops"]), float(kv[f"{name}_s"])
+        out[f"k_{name}"] = {"flops": fl, "seconds": t, "achieved": round(fl / t / 1e12, 2),
+                            "frac": round(fl / t / 1e12 / 78.6, 4)}
+    return out
+
+
 def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -973,6 +997,7 @@ def main():
         "tuned": tuned,
         "other_schedule": alt,
         "roofline": roofline,
+        "setup_mfma": profiled_mfma() if args.side == 128 and args.box == 16 else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
