@@ -735,18 +735,42 @@ __global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid,
 // biharmonic operator), so every leaf, Schur complement and updated block is made
 // exactly symmetric before it is used.
 __global__ void __launch_bounds__(256) k_bsym(BInv bi, int lo, int hi) {
+  // 32 x 32 tile pairs (I, J), I >= J, staged through LDS so that both the tile and
+  // its mirror are read and written along rows (coalesced)
   const int q = blockIdx.x;
   const int b = bi.n[q];
   if (lo >= b) return;
   const int w = min(hi, b) - lo;
   double* X = bi.scratch + bi.off[q] + (int64_t)lo * b + lo;
-  const int64_t total = (int64_t)w * w;
-  for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
-    const int i = (int)(idx / w), j = (int)(idx % w);
-    if (i <= j) continue;
-    const double v = 0.5 * (X[(int64_t)i * b + j] + X[(int64_t)j * b + i]);
-    X[(int64_t)i * b + j] = v;
-    X[(int64_t)j * b + i] = v;
+  const int nt = (w + 31) / 32;
+  const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
+  __shared__ double ta[32][33], tb[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t pr = blockIdx.y; pr < npairs; pr += gridDim.y) {
+    int I, J;
+    tile_ij((int)pr, I, J);   // I >= J
+    const int r0 = I * 32, c0 = J * 32;
+    for (int r = ty; r < 32; r += 8) {
+      const int gr = r0 + r, gc = c0 + tx;
+      ta[r][tx] = (gr < w && gc < w) ? X[(int64_t)gr * b + gc] : 0.0;   // tile (I, J)
+      const int mr = c0 + r, mc = r0 + tx;
+      tb[r][tx] = (mr < w && mc < w) ? X[(int64_t)mr * b + mc] : 0.0;   // tile (J, I)
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      // (I, J)[r][c] and (J, I)[c][r] are the same pair of entries
+      const int gr = r0 + r, gc = c0 + tx;
+      if (gr < w && gc < w && gr > gc) {
+        const double v = 0.5 * (ta[r][tx] + tb[tx][r]);
+        X[(int64_t)gr * b + gc] = v;
+      }
+      const int mr = c0 + r, mc = r0 + tx;
+      if (mr < w && mc < w && mc > mr) {
+        const double v = 0.5 * (ta[tx][r] + tb[r][tx]);
+        X[(int64_t)mr * b + mc] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -782,8 +806,8 @@ int64_t binv_work_need(int lo, int hi, int64_t woff) {
 }
 
 void bsym(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi) {
-  const int64_t n = hi - lo;
-  hipLaunchKernelGGL(k_bsym, dim3(cnt, (unsigned)std::min<int64_t>(1024, (n * n + 255) / 256)), dim3(256), 0, s, bi,
+  const int64_t nt = (hi - lo + 31) / 32;
+  hipLaunchKernelGGL(k_bsym, dim3(cnt, (unsigned)std::min<int64_t>(1024, nt * (nt + 1) / 2)), dim3(256), 0, s, bi,
                      lo, hi);
 }
 
