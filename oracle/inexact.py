@@ -15,7 +15,8 @@ the order of the rows, nor the inner tolerance; the readings taken here:
   within a colour the order does not matter.  A symmetric smoother keeps the
   preconditioner symmetric under the reversed post-sweep;
 * coarse solve: CG on A0 from zero, preconditioned by the zero-fill incomplete
-  Cholesky factor of A0 on its block pattern (subdomain couplings), stopped at
+  Cholesky factor of A0 on its block pattern (every entry of the blocks of coupled
+  subdomains, a structural pattern: zero values inside it stay in it), stopped at
   a relative residual ``ic_tol`` or after ``ic_maxit`` iterations.  This makes
   the preconditioner depend on its input, so the outer CG uses the
   Polak-Ribiere direction update.
@@ -151,10 +152,12 @@ class InexactDDGOracle(DDGOracle):
         self.coarse_solver = coarse_solver
         if self.coarse and coarse_solver == "ic_cg":
             adj = subdomain_adjacency(self.A, self.part, self.n_parts)
-            # the block pattern of A0: unknowns of coupled subdomains
+            # the block pattern of A0 (unknowns of coupled subdomains), kept structurally:
+            # an entry of a coupled block belongs to the pattern even when its value is 0
             owner = np.repeat(np.arange(self.n_parts), self.k_counts)
-            mask = adj[owner][:, owner].toarray() > 0
-            self.A0s = sp.csr_matrix(np.where(mask, self.A0, 0.0))
+            self.block_mask = adj[owner][:, owner].toarray() > 0
+            r, c = np.nonzero(self.block_mask)
+            self.A0s = sp.csr_matrix((self.A0[r, c], (r, c)), shape=self.A0.shape)
             self.L0 = ic0(self.A0s)
             self.ic_tol = ic_tol
             self.ic_maxit = ic_maxit

@@ -16,6 +16,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import DDGOracle
+from oracle.ddg import subdomain_adjacency
 from oracle.inexact import InexactDDGOracle, SSORLocal, ic0, ic_pcg, local_colouring
 from workloads import box_partition, cell_coords, diffusion_cc, monomials, seed_rng
 
@@ -84,11 +85,16 @@ def test_ic0_properties_and_coarse_cg():
     A, F, part, n_parts, overlap = tiny3d(L=10, boxes=2, p=2)
     o = InexactDDGOracle(A, F, part, n_parts, overlap, coarse_solver="ic_cg", ic_tol=1e-13, ic_maxit=500)
     L0 = o.L0.toarray()
-    # zero fill: L has entries only where the lower triangle of A0's pattern does
-    assert np.all((L0 != 0) <= np.tril(o.A0s.toarray() != 0))
+    # the pattern is the block pattern of coupled subdomains (structural)
+    adj = subdomain_adjacency(A, part, n_parts).toarray() > 0
+    owner = np.repeat(np.arange(n_parts), o.k_counts)
+    pat = adj[owner][:, owner]
+    assert np.array_equal(pat, o.block_mask) and not pat.all()
+    # zero fill: L has entries only in the lower triangle of that pattern, and L L^T
+    # reproduces A0 on it
+    assert np.all((L0 != 0) <= np.tril(pat))
     LLt = L0 @ L0.T
-    pat = o.A0s.toarray() != 0
-    assert np.allclose(LLt[pat], o.A0s.toarray()[pat], rtol=0, atol=1e-12 * np.abs(o.A0).max())
+    assert np.allclose(LLt[pat], o.A0[pat], rtol=0, atol=1e-12 * np.abs(o.A0).max())
     b = seed_rng(63, 0).standard_normal(o.A0.shape[0])
     y = ic_pcg(o.A0s, o.L0, b, 1e-13, 500)
     assert np.linalg.norm(y - np.linalg.solve(o.A0, b)) <= 1e-11 * np.linalg.norm(y)
@@ -104,3 +110,16 @@ def test_inexact_pcg_converges_with_more_iterations():
                                       ic_tol=1e-4).pcg(f, 1e-10, variant="pr")
     assert info2["status"] == "ok"
     assert np.linalg.norm(x2 - x) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_ic0_on_a_full_block_pattern_is_the_cholesky_factor():
+    """Two coupled subdomains: the block pattern of A0 is the whole matrix, so the
+    zero-fill incomplete factor is the complete Cholesky factor (numpy's)."""
+    L = 6
+    kappa = np.exp(seed_rng(65, 1).standard_normal((L, L, L)))
+    A = diffusion_cc(kappa).to_scipy()
+    part = box_partition((L, L, L), (2, 1, 1))
+    o = InexactDDGOracle(A, monomials(cell_coords((L, L, L)), 2), part, 2, 1, coarse_solver="ic_cg")
+    assert o.block_mask.all()
+    C = np.linalg.cholesky(o.A0)
+    assert np.allclose(o.L0.toarray(), C, rtol=0, atol=1e-13 * np.abs(C).max())
