@@ -104,6 +104,19 @@ typedef enum {
                            (ascending local index); FP64; no local factors are stored */
 } ddg_local_solver;
 
+/* How the coarse problem A0 y = b0 is solved in every preconditioner application. */
+typedef enum {
+  DDG_COARSE_INVERSE = 0,  /* exactly (Section 4): the explicit inverse of A0 formed at setup, applied
+                              as a tiled FP64 GEMV (with refinement steps when A0 is ill-conditioned) */
+  DDG_COARSE_IC_CG = 1     /* inexactly (Section 7, the timed 3D runs): CG on A0 from zero,
+                              preconditioned by the zero-fill incomplete Cholesky factor of A0 on its
+                              block pattern (every entry of the blocks of coupled subdomains), stopped
+                              at ||r|| <= ic_tol ||b0|| or after ic_maxit iterations.  The
+                              preconditioner then depends on its input: use DDG_CG_POLAK_RIBIERE.
+                              One workgroup per system runs the whole inner solve; the triangular
+                              solves go level by level over the block pattern. */
+} ddg_coarse_solver;
+
 typedef struct {
   int32_t precision;   /* ddg_precision */
   int32_t max_iter;    /* CG iteration cap (default 1000, Section 7) */
@@ -119,6 +132,9 @@ typedef struct {
   int32_t local_solver;  /* ddg_local_solver (default DDG_LOCAL_EXACT) */
   double ssor_omega;     /* relaxation of DDG_LOCAL_SSOR, 0 < omega < 2 (default 1) */
   int32_t ssor_sweeps;   /* symmetric sweeps of DDG_LOCAL_SSOR, >= 1 (default 1) */
+  int32_t coarse_solver; /* ddg_coarse_solver (default DDG_COARSE_INVERSE) */
+  double ic_tol;         /* relative residual of the DDG_COARSE_IC_CG inner solve, >= 0 (default 1e-6) */
+  int32_t ic_maxit;      /* inner iteration cap of DDG_COARSE_IC_CG, >= 1 (default 200) */
 } ddg_options;
 
 typedef struct {
@@ -150,6 +166,9 @@ typedef struct {
   double coarse_inverse_err; /* estimate of the spectral radius of I - X A0 (largest
                               ||(I - X A0) v|| / ||v|| over eight normalised power steps from a fixed
                               pseudo-random v), at the last setup or refactor, worst system */
+  int32_t coarse_solver;   /* ddg_coarse_solver in use */
+  int32_t coarse_iters;    /* DDG_COARSE_IC_CG: inner CG iterations summed over the last solve's
+                              coarse solves (worst system); 0 otherwise */
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */

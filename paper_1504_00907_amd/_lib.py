@@ -27,6 +27,7 @@ BC = {"dirichlet": 0, "x0": 1}
 CG_VARIANT = {"fr": 0, "pr": 1}
 MATRIX_FORMAT = {"auto": 0, "csr": 1}
 LOCAL_SOLVER = {"exact": 0, "ssor": 1}
+COARSE_SOLVER = {"inverse": 0, "ic_cg": 1}
 MATRIX_FORMAT_NAME = {1: "csr", 2: "dia"}
 
 
@@ -36,7 +37,8 @@ class Options(C.Structure):
         ("rank_tol", C.c_double), ("tile", C.c_int32), ("block_target", C.c_int32),
         ("check_every", C.c_int32), ("schedule", C.c_int32), ("cg_variant", C.c_int32),
         ("stream", C.c_void_p), ("matrix_format", C.c_int32), ("local_solver", C.c_int32),
-        ("ssor_omega", C.c_double), ("ssor_sweeps", C.c_int32),
+        ("ssor_omega", C.c_double), ("ssor_sweeps", C.c_int32), ("coarse_solver", C.c_int32),
+        ("ic_tol", C.c_double), ("ic_maxit", C.c_int32),
     ]
 
 
@@ -49,7 +51,8 @@ class Info(C.Structure):
         ("sweep_bytes", C.c_int64), ("iter_bytes", C.c_int64), ("tile", C.c_int32), ("schedule", C.c_int32),
         ("envelope_elems", C.c_int64), ("set_rows", C.c_int64), ("nbhd_rows", C.c_int64),
         ("matrix_format", C.c_int32), ("levels", C.c_int32), ("n_coarsest", C.c_int32),
-        ("coarse_refine", C.c_int32), ("coarse_inverse_err", C.c_double),
+        ("coarse_refine", C.c_int32), ("coarse_inverse_err", C.c_double), ("coarse_solver", C.c_int32),
+        ("coarse_iters", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -174,8 +174,9 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
   const int64_t n = S.n, nnzb = h.dia_ok ? n * 8 * (1 + (int64_t)h.dia_nd) : S.nnz * 12 + (n + 1) * 8;
   const int64_t ntiles = h.ntiles;
   // coarse: restrict (residual SpMV + Q), tiled inverse GEMV, prolong (Q, e rmw)
-  // (the dense inverse's tiles, or one application of the coarse level's preconditioner)
-  const int64_t core = h.inner ? h.inner->apply_bytes : ntiles * 64 * 64 * 8;
+  // (the dense inverse's tiles, or one application of the coarse level's preconditioner;
+  // the inexact coarse solve's bytes depend on its inner iteration count: not counted)
+  const int64_t core = h.inner ? h.inner->apply_bytes : h.ic ? 0 : ntiles * 64 * 64 * 8;
   const int64_t coarse = h.nc ? (nnzb + 3 * n * 8 + n * h.k * 8 + core + n * h.k * 8 + 16 * n) : 0;
   h.apply_bytes = sweep + coarse;
   // CG: SpMV (p, q), x/r/p/q update, two dots, p update
@@ -184,7 +185,7 @@ void account_bytes(Handle& h, const int64_t* rp, const int32_t* ci) {
   h.info.tile = S.tile;
   h.info.schedule = h.persist ? DDG_SCHEDULE_PERSISTENT : h.flow_ok ? DDG_SCHEDULE_QUEUE : DDG_SCHEDULE_COLOURS;
   h.info.factor_bytes = h.ssor ? 0 : S.fac_elems * es;
-  h.info.coarse_bytes = h.nc ? ntiles * 64 * 64 * 8 : 0;
+  h.info.coarse_bytes = h.nc && !h.ic ? ntiles * 64 * 64 * 8 : 0;
 }
 
 void check_err_flag(Handle& h, const char* what) {
@@ -196,6 +197,7 @@ void check_err_flag(Handle& h, const char* what) {
     if (e[0] == DDG_ERR_RANK) m += "every generating vector vanishes on subdomain " + std::to_string(e[1]);
     else if (e[0] == DDG_ERR_HIP && e[2] == -8) m += "sweep task of subdomain " + std::to_string(e[1]) + " timed out waiting for a dependency";
     else if (e[0] == DDG_ERR_HIP && e[2] == -9) m += "sweep task queue out of step";
+    else if (e[0] == DDG_ERR_HIP && e[2] == -10) m += "persistent solve: a workgroup waited too long for its next task";
     else if (e[0] == DDG_ERR_HIP) m += "workgroup handoff timed out in subdomain " + std::to_string(e[1]);
     else if (e[1] < 0) m += "coarse pivot " + std::to_string(e[3]) + " not positive (A0 not SPD)";
     else m += "local pivot not positive in subdomain " + std::to_string(e[1]) + " block " + std::to_string(e[2]) +
@@ -305,13 +307,14 @@ void numeric_setup(Handle& h) {
   }
   if (h.nc > 0 && !h.three_level) {
     DDG_HIP(hipStreamWaitEvent(h.side, eg, 0));
-    launch_coarse_invert(h, h.side);
+    if (h.ic) launch_ic_factor(h, h.side);
+    else launch_coarse_invert(h, h.side);
     DDG_HIP(hipEventRecord(ec, h.side));
     DDG_HIP(hipStreamWaitEvent(h.stream, ec, 0));
   }
   if (eg) (void)hipEventDestroy(eg);
   if (ec) (void)hipEventDestroy(ec);
-  if (h.nc > 0 && !h.three_level) {
+  if (h.nc > 0 && !h.three_level && !h.ic) {
     // accuracy of the explicit coarse inverse X: e estimates the spectral radius of
     // I - X A0; when it is not at working precision (ill-conditioned A0, e.g. the
     // biharmonic operator at large sizes), each coarse solve takes iterative-refinement
@@ -355,6 +358,7 @@ void numeric_setup(Handle& h) {
   h.info.matrix_format = h.dia_ok ? DDG_MATRIX_DIA : DDG_MATRIX_CSR;
   h.info.coarse_refine = h.coarse_refine;
   h.info.coarse_inverse_err = h.coarse_inv_err;
+  h.info.coarse_solver = h.ic ? DDG_COARSE_IC_CG : DDG_COARSE_INVERSE;
 }
 
 // Diagonal storage is possible when no system's rows have more than kDiaMax
@@ -481,6 +485,15 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
               DDG_ERR_INVALID_ARG, "cg_variant must be a ddg_cg_variant value");
   DDG_REQUIRE(h->opt.local_solver == DDG_LOCAL_EXACT || h->opt.local_solver == DDG_LOCAL_SSOR,
               DDG_ERR_INVALID_ARG, "local_solver must be a ddg_local_solver value");
+  DDG_REQUIRE(h->opt.coarse_solver == DDG_COARSE_INVERSE || h->opt.coarse_solver == DDG_COARSE_IC_CG,
+              DDG_ERR_INVALID_ARG, "coarse_solver must be a ddg_coarse_solver value");
+  h->ic = h->opt.coarse_solver == DDG_COARSE_IC_CG;
+  if (h->ic) {
+    DDG_REQUIRE(h->opt.ic_tol >= 0.0 && h->opt.ic_maxit >= 1, DDG_ERR_INVALID_ARG,
+                "the incomplete Cholesky coarse solve needs ic_tol >= 0 and ic_maxit >= 1");
+    DDG_REQUIRE(!h->three_level, DDG_ERR_UNSUPPORTED,
+                "the three-level cycle replaces the coarse solve; use DDG_COARSE_INVERSE with it");
+  }
   h->ssor = h->opt.local_solver == DDG_LOCAL_SSOR;
   if (h->ssor)
     DDG_REQUIRE(h->opt.ssor_omega > 0.0 && h->opt.ssor_omega < 2.0 && h->opt.ssor_sweeps >= 1, DDG_ERR_INVALID_ARG,
@@ -628,10 +641,10 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     h->tile_inst.upload(tinst, s);
     h->trow_inst.upload(rinst, s);
     h->A0.alloc((size_t)h->a0_off[h->nb] * sizeof(double));
-    if (!h->three_level) h->A0inv_t.alloc((size_t)h->ntiles * 64 * 64 * sizeof(double));
+    if (!h->three_level && !h->ic) h->A0inv_t.alloc((size_t)h->ntiles * 64 * 64 * sizeof(double));
     h->cy.alloc((size_t)2 * h->nc_pad * sizeof(double));
     DDG_HIP(hipMemsetAsync(h->cy.p, 0, (size_t)2 * h->nc_pad * sizeof(double), s));
-    if (!h->three_level) h->cpart.alloc((size_t)2 * h->ntiles * 64 * sizeof(double));
+    if (!h->three_level && !h->ic) h->cpart.alloc((size_t)2 * h->ntiles * 64 * sizeof(double));
   }
   // row-dot kernels: lanes per CSR row; the coarse restriction runs four passes of
   // its workgroup per chunk of own rows
@@ -694,7 +707,8 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   h->ws.bres = h->bres.as<double>();
   h->ws.rpart = h->nc > 0 ? h->rpart.as<double>() : nullptr;
   h->ws.cy = h->nc > 0 ? h->cy.as<double>() : nullptr;
-  h->ws.cpart = h->nc > 0 && !h->three_level ? h->cpart.as<double>() : nullptr;
+  h->ws.cpart = h->nc > 0 && !h->three_level && !h->ic ? h->cpart.as<double>() : nullptr;
+  if (h->ic && h->nc > 0) prepare_ic(*h, s);
   h->persist = h->opt.schedule == DDG_SCHEDULE_PERSISTENT;
   if (h->persist) prepare_persist(*h, s);
   numeric_setup(*h);
@@ -910,6 +924,9 @@ void ddg_default_options(ddg_options* opt) {
   opt->local_solver = DDG_LOCAL_EXACT;
   opt->ssor_omega = 1.0;
   opt->ssor_sweeps = 1;
+  opt->coarse_solver = DDG_COARSE_INVERSE;
+  opt->ic_tol = 1e-6;
+  opt->ic_maxit = 200;
   opt->stream = nullptr;
 }
 
@@ -1095,6 +1112,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     const size_t sb = (size_t)h->nb * sizeof(CgState);
     const int chunk = h->opt.check_every;
     int enqueued = 0;
+    if (h->ic && h->nc > 0) DDG_HIP(hipMemsetAsync(h->ic_it.p, 0, (size_t)h->nb * sizeof(int32_t), s));
     if (h->persist) {
       launch_persist(*h, f_dev, x, s);
     } else {
@@ -1127,6 +1145,11 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     if (h->inner) check_err_flag(*h->inner, "solve (coarse level)");
     DDG_HIP(hipMemcpyAsync(h->h_state, h->cstate.p, sb, hipMemcpyDeviceToHost, s));
     DDG_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> ic_it((size_t)h->nb, 0);
+    if (h->ic && h->nc > 0) {
+      DDG_HIP(hipMemcpyAsync(ic_it.data(), h->ic_it.p, ic_it.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      DDG_HIP(hipStreamSynchronize(s));
+    }
     float ms = 0.f;
     DDG_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -1145,6 +1168,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
       si.n_coarse = h->cblk_n[b];
       si.n_parts = h->sub_off[b + 1] - h->sub_off[b];
       si.solve_ms = st.t_done >= st.t_start ? (double)(st.t_done - st.t_start) / h->clock_khz : 0.0;
+      si.coarse_iters = ic_it[b];
       if (status == DDG_OK && st.status != DDG_OK) status = st.status;
       iters = std::max(iters, st.iters);
       rel = std::max(rel, si.rel_res);
@@ -1155,6 +1179,7 @@ int ddg_solve(ddg_handle hd, const double* f_dev, double* u_dev, ddg_info* info)
     h->info.rel_res = rel;
     h->info.true_rel_res = trel;
     h->info.solve_ms = ms;
+    h->info.coarse_iters = ic_it.empty() ? 0 : *std::max_element(ic_it.begin(), ic_it.end());
     if (info) *info = h->info;
     if (status != DDG_OK) {
       const char* what = status == DDG_ERR_NO_CONVERGENCE ? "maximum iterations reached"

@@ -284,6 +284,13 @@ struct Handle {
   // is chosen at every refactor from the measured ||v - X A0 v|| / ||v||
   int32_t coarse_refine = 0;
   double coarse_inv_err = 0.0;
+  // inexact coarse solve (DDG_COARSE_IC_CG): the incomplete Cholesky factor in A0's
+  // layout, the inverses of its diagonal blocks, the inner CG's work vectors, the
+  // level schedule of the triangular solves (per system levels, rows by level, the
+  // subdomain of every coarse row), factorisation marks, inner iteration counts and
+  // the subdomain offsets of the systems
+  bool ic = false;
+  DevBuf icL, icD, icw, ic_sys_lvl, ic_lvl_ptr, ic_lvl_rows, ic_row_sub, ic_mark, ic_it, ic_suboff;
   DevBuf cref, cerr;
   hipStream_t side = nullptr;  // second stream: the coarse inverse runs beside the local factorisation
   DevBuf fac;             // local factor tiles (storage precision)
@@ -404,6 +411,9 @@ void launch_precond(Handle& h, const double* r, double* e, int32_t stages, bool 
 // one sweep direction (0: colours ascending, 1: descending) as a persistent launch
 void launch_sweep_flow(Handle& h, int dir, const double* r, double* e, const CgState* st, hipStream_t s);
 void prepare_persist(Handle& h, hipStream_t s);
+void prepare_ic(Handle& h, hipStream_t s);
+void launch_ic_factor(Handle& h, hipStream_t s);
+void launch_ic_solve(Handle& h, const CgState* st, const double* b0, double* y, hipStream_t s);
 void launch_persist(Handle& h, const double* f, double* x, hipStream_t s);
 
 // setup numerics

@@ -268,6 +268,9 @@ void launch_coarse_k(Handle& h, const double* r, double* e, const CgState* st, h
     // three levels: y = M0^{-1} b0, one application of the coarse level's two-level
     // preconditioner (its kernels skip work once this handle's system has stopped)
     launch_precond(*h.inner, b0, y, -1, false, s, st);
+  } else if (h.ic) {
+    // inexact coarse solve: incomplete-Cholesky-preconditioned CG on A0 y = b0
+    launch_ic_solve(h, st, b0, y, s);
   } else {
     coarse_symv(h, st, b0, y, s);
     // refinement steps y += X (b0 - A0 y) when the explicit inverse is inaccurate

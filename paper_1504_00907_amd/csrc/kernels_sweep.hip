@@ -1414,8 +1414,9 @@ void launch_persist_cfg(Handle& h, const double* f, double* x, hipStream_t s) {
 void prepare_persist(Handle& h, hipStream_t s) {
   const Symbolic& S = h.S;
   const int32_t nb = h.nb, C = S.n_colours;
-  DDG_REQUIRE(!h.three_level && !h.ssor && h.k <= 32, DDG_ERR_UNSUPPORTED,
-              "persistent schedule: needs exact local solves, two levels and at most 32 generating vectors");
+  DDG_REQUIRE(!h.three_level && !h.ssor && !h.ic && h.k <= 32, DDG_ERR_UNSUPPORTED,
+              "persistent schedule: needs exact local solves, the explicit coarse inverse, two levels and at "
+              "most 32 generating vectors");
   DDG_REQUIRE(C < 128 && nb < 65536, DDG_ERR_UNSUPPORTED, "persistent schedule: at most 127 colours and 65535 systems");
   std::vector<int32_t> sub_sys(S.n_parts);
   for (int32_t b = 0; b < nb; ++b)

@@ -29,7 +29,7 @@ def _dev(t: torch.Tensor, n: int, name: str) -> int:
 
 def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, stream,
              schedule="auto", cg_variant="fr", matrix_format="auto", local_solver="exact", ssor_omega=1.0,
-             ssor_sweeps=1):
+             ssor_sweeps=1, coarse_solver="inverse", ic_tol=1e-6, ic_maxit=200):
     opt = Options()
     lib.ddg_default_options(C.byref(opt))
     opt.precision = _lib.PRECISION[precision]
@@ -45,6 +45,9 @@ def _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check
     opt.local_solver = _lib.LOCAL_SOLVER[local_solver]
     opt.ssor_omega = float(ssor_omega)
     opt.ssor_sweeps = int(ssor_sweeps)
+    opt.coarse_solver = _lib.COARSE_SOLVER[coarse_solver]
+    opt.ic_tol = float(ic_tol)
+    opt.ic_maxit = int(ic_maxit)
     opt.stream = C.c_void_p(stream.cuda_stream)
     return opt
 
@@ -57,7 +60,8 @@ class DDGSolver:
                  rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0, check_every: int = 4,
                  stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto", cg_variant: str = "fr",
                  matrix_format: str = "auto", part0=None, n_parts0: int = 0, local_solver: str = "exact",
-                 ssor_omega: float = 1.0, ssor_sweeps: int = 1):
+                 ssor_omega: float = 1.0, ssor_sweeps: int = 1, coarse_solver: str = "inverse",
+                 ic_tol: float = 1e-6, ic_maxit: int = 200):
         """``part0`` (coarse subdomain of every subdomain, ``n_parts0`` of them) selects
         the three-level V-cycle (``ddg_setup_three_level``)."""
         lib = _lib.load()
@@ -82,7 +86,8 @@ class DDGSolver:
             raise ValueError("F must have n rows")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
-                       schedule, cg_variant, matrix_format, local_solver, ssor_omega, ssor_sweeps)
+                       schedule, cg_variant, matrix_format, local_solver, ssor_omega, ssor_sweeps,
+                       coarse_solver, ic_tol, ic_maxit)
         self.precision = precision
         h = C.c_void_p()
         if part0 is None:

@@ -71,3 +71,79 @@ def test_ssor_option_errors():
             DDGSolver.from_problem(P, local_solver="ssor", **kw)
     with pytest.raises(Exception, match="UNSUPPORTED"):
         DDGSolver.from_problem(P, local_solver="ssor", schedule="queue")
+
+
+# --- incomplete-Cholesky-preconditioned CG coarse solve (DDG_COARSE_IC_CG) ---
+
+IC_CASES = [("cfg1", 3), ("cfg1", 12), ("3d12", 5), ("3d14x10x12", 20)]
+
+
+@pytest.mark.parametrize("name,m", IC_CASES, ids=[f"{c[0]}_m{c[1]}" for c in IC_CASES])
+def test_ic_coarse_correction_matches_oracle(name, m):
+    """m inner iterations (ic_tol = 0): the coarse correction of one application
+    (stage C+1 minus stage C) equals R0^T y with y from the oracle's incomplete
+    Cholesky factor and PCG on the same restricted residual."""
+    from oracle.inexact import ic_pcg
+    P = problem(name)
+    o = InexactDDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap, coarse_solver="ic_cg", ic_tol=0.0, ic_maxit=m)
+    s = DDGSolver.from_problem(P, rtol=P.rtol, coarse_solver="ic_cg", ic_tol=0.0, ic_maxit=m)
+    inf = s.info()
+    assert inf["coarse_solver"] == 1 and inf["coarse_bytes"] == 0 and inf["n_coarse"] == o.n_coarse
+    C = inf["n_colours"]
+    r = np.random.default_rng(m).standard_normal(P.n)
+    eC = host(s.apply_stages(dev(r), C))
+    d = host(s.apply_stages(dev(r), C + 1)) - eC
+    b0 = o.R0 @ (r - P.A.to_scipy() @ eC)
+    do = o.R0.T @ ic_pcg(o.A0s, o.L0, b0, 0.0, m)
+    err = rel(d, do)
+    print(f"ic coarse {name} m={m}: rel err {err:.2e}", flush=True)
+    assert err <= 1e-10
+    s.close()
+
+
+def test_ic_coarse_solve_converges_to_the_exact_coarse_solve():
+    """With a tight inner tolerance the inexact coarse correction is the exact one
+    (the explicit-inverse handle's) to that tolerance."""
+    P = problem("3d12")
+    C = None
+    r = np.random.default_rng(3).standard_normal(P.n)
+    out = []
+    for kw in (dict(coarse_solver="ic_cg", ic_tol=1e-13, ic_maxit=500), dict()):
+        s = DDGSolver.from_problem(P, rtol=P.rtol, **kw)
+        C = s.info()["n_colours"]
+        eC = host(s.apply_stages(dev(r), C))
+        out.append(host(s.apply_stages(dev(r), C + 1)) - eC)
+        s.close()
+    assert rel(out[0], out[1]) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["cfg1", "3d12"])
+def test_ssor_and_ic_coarse_solve_against_inexact_oracle(name):
+    """Section 7's timed variant: SSOR local smoothing and the IC-CG coarse solve
+    (inner tolerance 1e-6), Polak-Ribiere outer CG.  One application matches the
+    oracle's (inner stopping may fall one iteration apart at the threshold: the bar
+    is ten times the inner tolerance); the solve reaches the tolerance on the true
+    residual within one iteration of the oracle's count."""
+    P = problem(name)
+    o = InexactDDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap, omega=1.0, sweeps=1, coarse_solver="ic_cg",
+                         ic_tol=1e-6, ic_maxit=200)
+    s = DDGSolver.from_problem(P, rtol=P.rtol, local_solver="ssor", coarse_solver="ic_cg", ic_tol=1e-6,
+                               ic_maxit=200, cg_variant="pr")
+    r = np.random.default_rng(11).standard_normal(P.n)
+    assert rel(host(s.apply_precond(dev(r))), o.apply(r)) <= 1e-5
+    u, inf = s.solve(dev(P.f))
+    x, it, _ = o.pcg(P.f, P.rtol, variant="pr")
+    tr = np.linalg.norm(P.f - P.A.to_scipy() @ host(u)) / np.linalg.norm(P.f)
+    print(f"ssor + ic-cg {name}: iters gpu {inf['iters']} oracle {it}, inner iterations {inf['coarse_iters']}, "
+          f"true res {tr:.2e}", flush=True)
+    assert inf["status"] == 0 and abs(inf["iters"] - it) <= 1 and tr <= P.rtol * 1.05
+    assert inf["coarse_iters"] > 0
+    s.close()
+
+
+def test_ic_coarse_solve_options():
+    P = cfg1()
+    with pytest.raises(Exception, match="INVALID_ARG"):
+        DDGSolver.from_problem(P, coarse_solver="ic_cg", ic_maxit=0)
+    with pytest.raises(Exception, match="UNSUPPORTED"):
+        DDGSolver.from_problem(P, coarse_solver="ic_cg", schedule="persistent")
