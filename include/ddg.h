@@ -68,8 +68,10 @@ typedef enum {
   DDG_SCHEDULE_PERSISTENT = 3 /* ddg_solve runs the whole PCG of every system of the handle in one
                                 launch: workgroups take (system, step, chunk or subdomain) tasks from
                                 a device ring, and the last task of a step enqueues that system's
-                                next step, so the systems of a batch advance and stop independently
-                                (per-system solve_ms of ddg_solve_batched then differ).  Same results
+                                next step, so the systems of a batch advance and stop independently.
+                                Systems start smallest first, enough at once for about eight subdomains
+                                per CU; each stopped system hands its place to the next (per-system
+                                solve_ms counts from a system's start).  Same results
                                 bit for bit as COLOURS with one workgroup per subdomain.  Needs exact
                                 local solves, two levels, at most 32 generating vectors and an
                                 explicit coarse inverse accurate without refinement (else

@@ -259,8 +259,9 @@ struct Handle {
   // lists, the subdomain offsets of the systems, the initial ring words and per-system
   // states, the per-system states and counts in use, the control words and the ring
   bool persist = false;
-  DevBuf ps_ptr, ps_sub, ps_suboff, ps_init, ps_sys0, ps_sys, ps_cnt, ps_ctl, ps_ring;
+  DevBuf ps_ptr, ps_sub, ps_suboff, ps_init, ps_sys0, ps_sys, ps_cnt, ps_ctl, ps_ring, ps_order;
   int32_t ps_ninit = 0;
+  int32_t ps_admit = 0;              // systems started at launch (admission order: smallest first)
   int64_t ps_omax = 0;               // most tasks outstanding at once (sum over systems of the largest phase)
   int32_t device = 0;                // HIP device current at setup
   int32_t xch_ld = 0;

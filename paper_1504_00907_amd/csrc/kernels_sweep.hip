@@ -1023,7 +1023,8 @@ struct PsCtl {
   unsigned long long head;   // next ring position to claim
   unsigned long long tail;   // next ring position to allocate
   int32_t all_done;          // every system has stopped (or the launch gave up)
-  int32_t remaining;         // systems still running
+  int32_t remaining;         // systems not yet stopped
+  int32_t next_sys;          // position in the admission order of the next system to start
 };
 
 struct PersistArgs {
@@ -1031,6 +1032,8 @@ struct PersistArgs {
   uint64_t mask;
   int32_t log2size;
   PsCtl* ctl;
+  const int32_t* order;      // admission order of the systems (smallest first)
+  int32_t nb;
   PSys* sys;
   int32_t* cnt;              // per system: finished tasks of the running phase
   int32_t* err;
@@ -1276,6 +1279,16 @@ __global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs
         if (ph == PT_EXIT) {
           if (__hip_atomic_fetch_add(&P.ctl->remaining, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1)
             __hip_atomic_store(&P.ctl->all_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // the stopped system's place goes to the next system in the admission order
+          const int q = __hip_atomic_fetch_add(&P.ctl->next_sys, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (q < P.nb) {
+            const int b2 = P.order[q];
+            n_next = P.m.ptr[b2 + 1] - P.m.ptr[b2];   // its first phase (PT_INIT, state from the reset)
+            s_base = atomicAdd(&P.ctl->tail, (unsigned long long)n_next);
+            s_next[1] = PT_INIT;
+            s_next[2] = 0;
+            s_next[3] = b2;
+          }
         } else {
           n_next = p_count<NW>(P, b, ph, c);
           s.phase = ph;
@@ -1289,6 +1302,7 @@ __global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs
           s_base = atomicAdd(&P.ctl->tail, (unsigned long long)n_next);
           s_next[1] = ph;
           s_next[2] = (ph == PT_SWEEP_F || ph == PT_SWEEP_B) ? c : ((ph == PT_DOT || ph == PT_RHO) ? first : 0);
+          s_next[3] = b;
         }
       }
       s_next[0] = n_next;
@@ -1296,11 +1310,11 @@ __global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs
     __syncthreads();
     const int n_next = s_next[0];
     if (n_next > 0) {
-      const int ph = s_next[1], aux2 = s_next[2];
+      const int ph = s_next[1], aux2 = s_next[2], tb = s_next[3];
       const unsigned long long base = s_base;
       for (int t = tid; t < n_next; t += NT) {
         const unsigned long long pos = base + (unsigned long long)t;
-        __hip_atomic_store(P.ring + (pos & P.mask), ps_word(ph, aux2, b, t, pos >> P.log2size), __ATOMIC_RELAXED,
+        __hip_atomic_store(P.ring + (pos & P.mask), ps_word(ph, aux2, tb, t, pos >> P.log2size), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -1312,7 +1326,7 @@ __global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs
 // every other slot empty; the per-system states and counts from their initial values
 __global__ void k_persist_reset(uint64_t* __restrict__ ring, int64_t size, const uint64_t* __restrict__ init,
                                 int32_t n_init, PSys* __restrict__ sys, const PSys* __restrict__ sys0,
-                                int32_t* __restrict__ cnt, int32_t nb, PsCtl* __restrict__ ctl) {
+                                int32_t* __restrict__ cnt, int32_t nb, int32_t n_admit, PsCtl* __restrict__ ctl) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < size) ring[i] = i < n_init ? init[i] : ~0ull;
   if (i < nb) {
@@ -1324,6 +1338,7 @@ __global__ void k_persist_reset(uint64_t* __restrict__ ring, int64_t size, const
     ctl->tail = (unsigned long long)n_init;
     ctl->all_done = 0;
     ctl->remaining = nb;
+    ctl->next_sys = n_admit;
   }
 }
 
@@ -1347,12 +1362,14 @@ void launch_persist_cfg(Handle& h, const double* f, double* x, hipStream_t s) {
   if (h.ps_ring.bytes < (size_t)size * sizeof(uint64_t)) h.ps_ring.alloc((size_t)size * sizeof(uint64_t));
   hipLaunchKernelGGL(k_persist_reset, dim3((unsigned)((std::max<int64_t>(size, h.nb) + 255) / 256)), dim3(256), 0, s,
                      h.ps_ring.as<uint64_t>(), size, h.ps_init.as<uint64_t>(), h.ps_ninit, h.ps_sys.as<PSys>(),
-                     h.ps_sys0.as<PSys>(), h.ps_cnt.as<int32_t>(), h.nb, h.ps_ctl.as<PsCtl>());
+                     h.ps_sys0.as<PSys>(), h.ps_cnt.as<int32_t>(), h.nb, h.ps_admit, h.ps_ctl.as<PsCtl>());
   PersistArgs P{};
   P.ring = h.ps_ring.as<uint64_t>();
   P.mask = (uint64_t)size - 1;
   P.log2size = lg;
   P.ctl = h.ps_ctl.as<PsCtl>();
+  P.order = h.ps_order.as<int32_t>();
+  P.nb = h.nb;
   P.sys = h.ps_sys.as<PSys>();
   P.cnt = h.ps_cnt.as<int32_t>();
   P.err = h.err_flag.as<int32_t>();
@@ -1433,6 +1450,16 @@ void prepare_persist(Handle& h, hipStream_t s) {
     subs.insert(subs.end(), lists[q].begin(), lists[q].end());
     ptr[q + 1] = (int32_t)subs.size();
   }
+  // admission: systems start smallest first; enough of them at once for about eight
+  // subdomains per CU, and each stopped system hands its place to the next one
+  std::vector<int32_t> order(nb);
+  for (int32_t b = 0; b < nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return h.seg_off[x + 1] - h.seg_off[x] < h.seg_off[y + 1] - h.seg_off[y];
+  });
+  int32_t admit = 0;
+  for (int64_t subs = 0; admit < nb && subs < 8 * (int64_t)h.n_cu; ++admit)
+    subs += h.sub_off[order[admit] + 1] - h.sub_off[order[admit]];
   std::vector<uint64_t> init;
   std::vector<PSys> sys0(nb);
   int64_t omax = 0;
@@ -1447,11 +1474,16 @@ void prepare_persist(Handle& h, hipStream_t s) {
         most = std::max(most, ps_count(ph, c, chunks, ptr.data(), b, C, nsub, h.nch, ntiles, crows, 4));
     DDG_REQUIRE(most < (1 << 21), DDG_ERR_UNSUPPORTED, "persistent schedule: more than 2^21 tasks in one phase");
     omax += most;
-    for (int32_t t = 0; t < chunks; ++t) init.push_back(ps_word(PT_INIT, 0, b, t, 0));
     sys0[b] = PSys{PT_INIT, 0, chunks, 1};
+  }
+  for (int32_t q = 0; q < admit; ++q) {
+    const int32_t b = order[q];
+    for (int32_t t = 0; t < h.seg_wg_ptr[b + 1] - h.seg_wg_ptr[b]; ++t) init.push_back(ps_word(PT_INIT, 0, b, t, 0));
   }
   h.ps_omax = omax;
   h.ps_ninit = (int32_t)init.size();
+  h.ps_admit = admit;
+  h.ps_order.upload(order, s);
   h.ps_ptr.upload(ptr, s);
   h.ps_sub.upload(subs, s);
   h.ps_suboff.upload(h.sub_off, s);
