@@ -553,6 +553,13 @@ struct GemmArgs {
   int64_t ldc;
   int32_t M, N, K;
   double alpha, beta;
+  // epilogue: 0 plain; 1 symmetric result (M = N): the tile's entries on and below the
+  // diagonal are formed and the ones below it also written to their mirror, so C
+  // comes out exactly symmetric (the caller runs only tiles with i0 >= j0); 2 also
+  // writes the transpose into D (ldd)
+  int32_t mode;
+  double* D;
+  int64_t ldd;
 };
 
 // C = beta C + alpha A op(B) on 64 x 64 output tiles on the FP64 matrix cores: each of
@@ -565,8 +572,12 @@ struct GemmArgs {
 __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
   constexpr int UC = 32;
   constexpr int PER = 64 * UC / 256;  // elements of each operand chunk per thread
-  __shared__ double As[64][UC + 1];
-  __shared__ double Bs[UC][64 + 1];
+  // the operand chunks, and after the reduction the output tile for the mirrored or
+  // transposed stores
+  __shared__ double smem[64 * (UC + 1) + UC * (64 + 1)];
+  double (*As)[UC + 1] = reinterpret_cast<double (*)[UC + 1]>(smem);
+  double (*Bs)[64 + 1] = reinterpret_cast<double (*)[64 + 1]>(smem + 64 * (UC + 1));
+  double (*Cs)[64 + 1] = reinterpret_cast<double (*)[64 + 1]>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
@@ -630,12 +641,29 @@ __device__ inline void gemm_tile(const GemmArgs& g, int64_t i0, int64_t j0) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + wr + x * 16 + 4 * r + lk;
-        const int64_t j = j0 + wc + y * 16 + li;
-        if (i >= g.M || j >= g.N) continue;
+        const int li_ = wr + x * 16 + 4 * r + lk, lj_ = wc + y * 16 + li;
+        const int64_t i = i0 + li_;
+        const int64_t j = j0 + lj_;
+        if (i >= g.M || j >= g.N || (g.mode == 1 && j > i)) continue;
         double* c = g.C + i * g.ldc + j;
-        *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * acc[x][y][r];
+        const double v = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * acc[x][y][r];
+        *c = v;
+        if (g.mode != 0) Cs[li_][lj_] = v;
       }
+  if (g.mode == 0) return;
+  // mirrored (mode 1: C[j][i], below the diagonal only) or transposed (mode 2:
+  // D[j][i]) stores, rows of the stored matrix along the threads
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int lj_ = idx >> 6, li_ = idx & 63;
+    const int64_t i = i0 + li_, j = j0 + lj_;
+    if (i >= g.M || j >= g.N) continue;
+    if (g.mode == 1) {
+      if (i > j) g.C[j * g.ldc + i] = Cs[li_][lj_];
+    } else {
+      g.D[j * g.ldd + i] = Cs[li_][lj_];
+    }
+  }
 }
 
 // tile t of the packed inverses (system tile_inst[t]); zero beyond the block's order
@@ -693,14 +721,28 @@ __global__ void __launch_bounds__(kPivThreads) k_bleaf(BInv bi, int lo, int hi, 
     for (int j = 0; j < 4; ++j) m[i][j] = (r0 + i < w && c0 + j < w) ? X[(int64_t)(r0 + i) * b + c0 + j] : 0.0;
   if (bi.err_sub) gj_regs(m, w, err, bi.err_sub[q], bi.err_blk[q], lo);
   else gj_regs(m, w, err, -1, bi.err_blk ? bi.err_blk[q] : q, lo);
+  // the inverse made exactly symmetric, (X + X^T) / 2 with the entry below the
+  // diagonal first, through LDS
+  __shared__ double sm[64][65];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (r0 + i < w && c0 + j < w) X[(int64_t)(r0 + i) * b + c0 + j] = m[i][j];
+    for (int j = 0; j < 4; ++j) sm[r0 + i][c0 + j] = m[i][j];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + i, c = c0 + j;
+      if (r >= w || c >= w) continue;
+      const double v = r > c ? 0.5 * (sm[r][c] + sm[c][r]) : r < c ? 0.5 * (sm[c][r] + sm[r][c]) : sm[r][r];
+      X[(int64_t)r * b + c] = v;
+    }
 }
 
-// op 0: W = X11 X12; 1: X22 -= X21 W; 2: X12 = -W X22; 3: X11 -= X12 W^T
+// op 0: W = X11 X12; 1: X22 -= X21 W (the Schur complement, formed on and below the
+// diagonal and mirrored); 2: X12 = -W X22, with X21 = X12^T; 3: X11 -= X12 W^T
+// (formed on and below the diagonal and mirrored)
 __global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid, int hi, int64_t woff, int ldw) {
   const int q = blockIdx.z;
   const int b = bi.n[q];
@@ -716,84 +758,25 @@ __global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid,
   double* X22 = X + (int64_t)m * b + m;
   GemmArgs g;
   switch (op) {
-    case 0: g = GemmArgs{X11, b, X12, b, 0, W, ldw, n1, n2, n1, 1.0, 0.0}; break;
-    case 1: g = GemmArgs{X21, b, W, ldw, 0, X22, b, n2, n2, n1, -1.0, 1.0}; break;
-    case 2: g = GemmArgs{W, ldw, X22, b, 0, X12, b, n1, n2, n2, -1.0, 0.0}; break;
-    default: g = GemmArgs{X12, b, W, ldw, 1, X11, b, n1, n1, n2, -1.0, 1.0}; break;
+    case 0: g = GemmArgs{X11, b, X12, b, 0, W, ldw, n1, n2, n1, 1.0, 0.0, 0, nullptr, 0}; break;
+    case 1: g = GemmArgs{X21, b, W, ldw, 0, X22, b, n2, n2, n1, -1.0, 1.0, 1, nullptr, 0}; break;
+    case 2: g = GemmArgs{W, ldw, X22, b, 0, X12, b, n1, n2, n2, -1.0, 0.0, 2, X21, b}; break;
+    default: g = GemmArgs{X12, b, W, ldw, 1, X11, b, n1, n1, n2, -1.0, 1.0, 1, nullptr, 0}; break;
   }
   const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
   if (i0 >= g.M || j0 >= g.N) return;
+  if (g.mode == 1 && j0 > i0) return;   // symmetric results: lower tiles only
   gemm_tile(g, i0, j0);
 }
 
-// X[lo:hi, lo:hi] = (X + X^T) / 2 for every item (clipped to its order).  The
-// recursive inverse forms the Schur complement D - C W and the update
-// X11 - X12 W^T, whose two triangles differ by rounding, and Gauss-Jordan leaves
-// are not exactly symmetric either.  Used as they are in the next step, that
+// Symmetry.  The recursive inverse forms the Schur complement D - C W and the update
+// X11 - X12 W^T, whose two triangles would differ by rounding, and Gauss-Jordan
+// leaves are not exactly symmetric either.  Used as they are in the next step, that
 // asymmetry grows from node to node and from level to level when the operator is
 // ill-conditioned or the level couplings amplify (||X C|| > 1: the 13-point
-// biharmonic operator), so every leaf, Schur complement and updated block is made
-// exactly symmetric before it is used.
-__global__ void __launch_bounds__(256) k_bsym(BInv bi, int lo, int hi) {
-  // 32 x 32 tile pairs (I, J), I >= J, staged through LDS so that both the tile and
-  // its mirror are read and written along rows (coalesced)
-  const int q = blockIdx.x;
-  const int b = bi.n[q];
-  if (lo >= b) return;
-  const int w = min(hi, b) - lo;
-  double* X = bi.scratch + bi.off[q] + (int64_t)lo * b + lo;
-  const int nt = (w + 31) / 32;
-  const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
-  __shared__ double ta[32][33], tb[32][33];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int64_t pr = blockIdx.y; pr < npairs; pr += gridDim.y) {
-    int I, J;
-    tile_ij((int)pr, I, J);   // I >= J
-    const int r0 = I * 32, c0 = J * 32;
-    for (int r = ty; r < 32; r += 8) {
-      const int gr = r0 + r, gc = c0 + tx;
-      ta[r][tx] = (gr < w && gc < w) ? X[(int64_t)gr * b + gc] : 0.0;   // tile (I, J)
-      const int mr = c0 + r, mc = r0 + tx;
-      tb[r][tx] = (mr < w && mc < w) ? X[(int64_t)mr * b + mc] : 0.0;   // tile (J, I)
-    }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-      // (I, J)[r][c] and (J, I)[c][r] are the same pair of entries
-      const int gr = r0 + r, gc = c0 + tx;
-      if (gr < w && gc < w && gr > gc) {
-        const double v = 0.5 * (ta[r][tx] + tb[tx][r]);
-        X[(int64_t)gr * b + gc] = v;
-      }
-      const int mr = c0 + r, mc = r0 + tx;
-      if (mr < w && mc < w && mc > mr) {
-        const double v = 0.5 * (ta[tx][r] + tb[r][tx]);
-        X[(int64_t)mr * b + mc] = v;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// X21 = X12^T for every item
-__global__ void k_btranspose(BInv bi, int lo, int mid, int hi) {
-  const int q = blockIdx.z;
-  const int b = bi.n[q];
-  if (lo >= b) return;
-  const int m = min(mid, b), h = min(hi, b);
-  const int n1 = m - lo, n2 = h - m;
-  if (n2 <= 0) return;
-  double* X = bi.scratch + bi.off[q];
-  const double* src = X + (int64_t)lo * b + m;
-  double* dst = X + (int64_t)m * b + lo;
-  __shared__ double t[32][33];
-  const int bi0 = blockIdx.y * 32, bj = blockIdx.x * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8)
-    if (bi0 + r < n1 && bj + tx < n2) t[r][tx] = src[(int64_t)(bi0 + r) * b + bj + tx];
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8)
-    if (bj + r < n2 && bi0 + tx < n1) dst[(int64_t)(bj + r) * b + bi0 + tx] = t[tx][r];
-}
+// biharmonic operator).  So every leaf is made exactly symmetric ((X + X^T) / 2,
+// in k_bleaf), and the two symmetric updates are formed on and below the diagonal
+// only and mirrored (k_bgemm ops 1 and 3).
 
 // Workspace elements per item that binv_node(lo = 0, hi = n) touches: W of a node
 // sits at the node's stack offset and spans n1 x n2 (leading dimension n2).
@@ -805,19 +788,12 @@ int64_t binv_work_need(int lo, int hi, int64_t woff) {
   return std::max(next, std::max(binv_work_need(lo, m, next), binv_work_need(m, hi, next)));
 }
 
-void bsym(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi) {
-  const int64_t nt = (hi - lo + 31) / 32;
-  hipLaunchKernelGGL(k_bsym, dim3(cnt, (unsigned)std::min<int64_t>(1024, nt * (nt + 1) / 2)), dim3(256), 0, s, bi,
-                     lo, hi);
-}
-
 // Inverse of X[lo:hi, lo:hi] in place (the items' blocks past their order are
 // skipped), symmetric on return.
 void binv_node(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi, int64_t woff, int32_t* err) {
   const int n = hi - lo;
   if (n <= kCNB) {
     hipLaunchKernelGGL(k_bleaf, dim3(cnt), dim3(kPivThreads), 0, s, bi, lo, hi, err);
-    bsym(s, bi, cnt, lo, hi);
     return;
   }
   const int m = lo + kCNB * ((n + 2 * kCNB - 1) / (2 * kCNB));
@@ -827,13 +803,9 @@ void binv_node(hipStream_t s, const BInv& bi, unsigned cnt, int lo, int hi, int6
   binv_node(s, bi, cnt, lo, m, next, err);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n2), dim3(256), 0, s, bi, 0, lo, m, hi, woff, n2);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n2, n2), dim3(256), 0, s, bi, 1, lo, m, hi, woff, n2);
-  bsym(s, bi, cnt, m, hi);
   binv_node(s, bi, cnt, m, hi, next, err);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n2), dim3(256), 0, s, bi, 2, lo, m, hi, woff, n2);
   hipLaunchKernelGGL(k_bgemm, gemm_grid(n1, n1), dim3(256), 0, s, bi, 3, lo, m, hi, woff, n2);
-  hipLaunchKernelGGL(k_btranspose, dim3((unsigned)((n2 + 31) / 32), (unsigned)((n1 + 31) / 32), cnt), dim3(256), 0,
-                     s, bi, lo, m, hi);
-  bsym(s, bi, cnt, lo, m);
 }
 
 // Schedule of the batched factorisation: groups of subdomains whose scratch
