@@ -767,8 +767,9 @@ def main():
                                                    args.elasticity_block_target)}), flush=True)
         return
     if args.adjoint_only:
-        print(json.dumps({"fwd_adjoint": fwd_adjoint(args.adjoint_side, args.precision, max(1, args.steps), 1)}),
-              flush=True)
+        adj = fwd_adjoint(args.adjoint_side, args.precision, max(1, args.steps), 1)
+        adj.pop("_grad", None)
+        print(json.dumps({"fwd_adjoint": adj}), flush=True)
         return
     log(f"generating workload {args.side}^3, boxes {args.box}^3")
     P = cfg2(side=args.side, box=args.box)

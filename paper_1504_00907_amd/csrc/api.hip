@@ -27,6 +27,7 @@ Handle::~Handle() {
   delete inner;
   for (auto ev : ev_pool) (void)hipEventDestroy(ev);
   if (h_state) (void)hipHostFree(h_state);
+  if (h_cerr) (void)hipHostFree(h_cerr);
   if (side) (void)hipStreamDestroy(side);
 }
 
@@ -297,6 +298,19 @@ void numeric_setup(Handle& h) {
     DDG_HIP(hipEventCreateWithFlags(&ec, hipEventDisableTiming));
     DDG_HIP(hipEventRecord(eg, h.stream));
   }
+  // the coarse chain (inverse and its accuracy measurement, or the incomplete factor)
+  // is enqueued first on the side stream: it is the longer one, and its host code
+  // never waits, so the local factorisation's launches follow at once
+  if (h.nc > 0 && !h.three_level) {
+    DDG_HIP(hipStreamWaitEvent(h.side, eg, 0));
+    if (h.ic) {
+      launch_ic_factor(h, h.side);
+    } else {
+      launch_coarse_invert(h, h.side);
+      launch_coarse_measure(h, h.side);
+    }
+    DDG_HIP(hipEventRecord(ec, h.side));
+  }
   if (h.ssor) {
     launch_gather(h.ss_pos.as<int64_t>(), h.val.as<double>(), h.ss_val.as<double>(),
                   (int64_t)(h.ss_pos.bytes / sizeof(int64_t)), h.stream);
@@ -305,34 +319,9 @@ void numeric_setup(Handle& h) {
   } else {
     launch_local_factor(h, h.stream);
   }
-  if (h.nc > 0 && !h.three_level) {
-    DDG_HIP(hipStreamWaitEvent(h.side, eg, 0));
-    if (h.ic) launch_ic_factor(h, h.side);
-    else launch_coarse_invert(h, h.side);
-    DDG_HIP(hipEventRecord(ec, h.side));
-    DDG_HIP(hipStreamWaitEvent(h.stream, ec, 0));
-  }
+  if (h.nc > 0 && !h.three_level) DDG_HIP(hipStreamWaitEvent(h.stream, ec, 0));
   if (eg) (void)hipEventDestroy(eg);
   if (ec) (void)hipEventDestroy(ec);
-  if (h.nc > 0 && !h.three_level && !h.ic) {
-    // accuracy of the explicit coarse inverse X: e estimates the spectral radius of
-    // I - X A0; when it is not at working precision (ill-conditioned A0, e.g. the
-    // biharmonic operator at large sizes), each coarse solve takes iterative-refinement
-    // steps y += X (b0 - A0 y), which reduce the error by e per step and keep the coarse
-    // operator symmetric (after s steps it is (I - (I - X A0)^{s+1}) A0^{-1})
-    const double e = measure_coarse_inverse(h, h.stream);
-    h.coarse_inv_err = e;
-    int32_t steps = 0;
-    if (!(e <= 1e-12)) {
-      DDG_REQUIRE(e < 0.5, DDG_ERR_NOT_SPD,
-                  "coarse inverse too inaccurate to refine (||v - X A0 v|| / ||v|| = " + std::to_string(e) + ")");
-      steps = (int32_t)std::ceil(std::log(1e-13) / std::log(e)) - 1;
-      steps = std::max(1, std::min(4, steps));
-      if (!h.cref.p) h.cref.alloc((size_t)2 * h.nc_pad * sizeof(double));
-    }
-    h.coarse_refine = steps;
-    h.ws.cref = h.cref.p ? h.cref.as<double>() : nullptr;
-  }
   if (h.inner) {
     // the coarse level's values from the new A0, then its own factorisation
     launch_gather(h.a0_pos.as<int64_t>(), h.A0.as<double>(), h.inner->val.as<double>(), h.inner->S.nnz, h.stream);
@@ -346,6 +335,25 @@ void numeric_setup(Handle& h) {
   (void)hipEventDestroy(e1);
   h.info.setup_ms = ms;
   check_err_flag(h, "numeric factorisation");
+  if (h.nc > 0 && !h.three_level && !h.ic) {
+    // accuracy of the explicit coarse inverse X: e estimates the spectral radius of
+    // I - X A0; when it is not at working precision (ill-conditioned A0, e.g. the
+    // biharmonic operator at large sizes), each coarse solve takes iterative-refinement
+    // steps y += X (b0 - A0 y), which reduce the error by e per step and keep the coarse
+    // operator symmetric (after s steps it is (I - (I - X A0)^{s+1}) A0^{-1})
+    const double e = finish_coarse_measure(h);
+    h.coarse_inv_err = e;
+    int32_t steps = 0;
+    if (!(e <= 1e-12)) {
+      DDG_REQUIRE(e < 0.5, DDG_ERR_NOT_SPD,
+                  "coarse inverse too inaccurate to refine (||v - X A0 v|| / ||v|| = " + std::to_string(e) + ")");
+      steps = (int32_t)std::ceil(std::log(1e-13) / std::log(e)) - 1;
+      steps = std::max(1, std::min(4, steps));
+      if (!h.cref.p) h.cref.alloc((size_t)2 * h.nc_pad * sizeof(double));
+    }
+    h.coarse_refine = steps;
+    h.ws.cref = h.cref.p ? h.cref.as<double>() : nullptr;
+  }
   if (h.dia_possible) {
     // the diagonals represent A only when its values are symmetric bit for bit;
     // otherwise the row dots read the CSR rows (until a refactor makes them so)

@@ -280,6 +280,12 @@ struct Handle {
   DevBuf A0;              // dense coarse blocks, one per system (kept for export)
   DevBuf A0inv_t;         // tiled lower inverses, float64, tile 64
   DevBuf cinv, cwork, cgd;   // coarse inverse: copy of A0 being inverted, recursion workspace, group tables
+  struct CoarseGroup {
+    int32_t first, count, nfirst;   // items [first, first + count) of the tables, the largest order
+    int64_t need;                   // workspace elements per item
+  };
+  std::vector<CoarseGroup> cinv_groups;   // built once per handle
+  int32_t cinv_items = 0;
   // iterative refinement of the coarse solve, y += A0^{-1}_approx (b0 - A0 y), for coarse
   // matrices whose explicit inverse is not accurate to working precision; the step count
   // is chosen at every refactor from the measured ||v - X A0 v|| / ||v||
@@ -293,6 +299,7 @@ struct Handle {
   bool ic = false;
   DevBuf icL, icD, icw, ic_sys_lvl, ic_lvl_ptr, ic_lvl_rows, ic_row_sub, ic_mark, ic_it, ic_suboff;
   DevBuf cref, cerr;
+  double* h_cerr = nullptr;   // pinned: the power steps' norms of the last measurement
   hipStream_t side = nullptr;  // second stream: the coarse inverse runs beside the local factorisation
   DevBuf fac;             // local factor tiles (storage precision)
   // batched local factorisation: item schedule (built once per handle) and scratch
@@ -422,7 +429,8 @@ void launch_coarse_basis(Handle& h, hipStream_t s);
 void launch_galerkin(Handle& h, hipStream_t s);
 void launch_coarse_invert(Handle& h, hipStream_t s);
 // max over systems of ||v - X A0 v|| / ||v|| for a fixed pseudo-random v (X the packed inverse)
-double measure_coarse_inverse(Handle& h, hipStream_t s);
+void launch_coarse_measure(Handle& h, hipStream_t s);
+double finish_coarse_measure(const Handle& h);
 // F0 = R0 F (nc_pad x k column-major, zero padding) from the device copy of F
 void launch_restrict_columns(Handle& h, double* F0, hipStream_t s);
 void launch_local_factor(Handle& h, hipStream_t s);

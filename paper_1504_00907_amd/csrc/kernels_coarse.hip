@@ -196,11 +196,17 @@ void coarse_resid(Handle& h, const CgState* st, const double* b, const double* y
 
 // Estimate of the spectral radius of I - X A0 (X the explicit coarse inverse), the
 // factor by which each refinement step reduces the coarse error: the largest
-// ||(I - X A0) v|| / ||v|| over a few normalised power-iteration steps from a fixed
-// pseudo-random start, worst system.  NaN when X or A0 holds non-finite values.
-double measure_coarse_inverse(Handle& h, hipStream_t s) {
-  if (h.nc == 0 || h.three_level) return 0.0;
-  if (!h.cerr.p) h.cerr.alloc((size_t)(3 * h.nc_pad + 2 * h.nb) * sizeof(double));
+// ||(I - X A0) v|| / ||v|| over kPowerSteps normalised power-iteration steps from a
+// fixed pseudo-random start, worst system.  The steps are enqueued on s with their
+// norms copied to pinned host memory; finish_coarse_measure reads them once the
+// stream has been synchronised.
+constexpr int kPowerSteps = 8;
+
+void launch_coarse_measure(Handle& h, hipStream_t s) {
+  if (h.nc == 0 || h.three_level || h.ic) return;
+  const size_t nout = (size_t)2 * h.nb * kPowerSteps;
+  if (!h.cerr.p) h.cerr.alloc(((size_t)3 * h.nc_pad + nout) * sizeof(double));
+  if (!h.h_cerr) DDG_HIP(hipHostMalloc((void**)&h.h_cerr, nout * sizeof(double), hipHostMallocDefault));
   double* v = h.cerr.as<double>();
   double* t = v + h.nc_pad;
   double* u = t + h.nc_pad;
@@ -210,29 +216,33 @@ double measure_coarse_inverse(Handle& h, hipStream_t s) {
                      h.cblk_n_d.as<int32_t>(), h.nc_pad, v);
   PrecondWs keep = h.ws;
   if (!h.ws.cpart) h.ws.cpart = h.cpart.as<double>();
-  constexpr int kPowerSteps = 8;
-  std::vector<double> hv((size_t)2 * h.nb);
-  double worst = 0.0;
   for (int it = 0; it < kPowerSteps; ++it) {
+    double* o = out + (size_t)2 * h.nb * it;
     if (it > 0)
       hipLaunchKernelGGL(k_coarse_next, dim3(g), dim3(256), 0, s, h.trow_inst.as<int32_t>(),
-                         h.cblk_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.nc_pad, out, u, v);
+                         h.cblk_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.nc_pad, o - 2 * h.nb, u, v);
     launch_fill(u, 0.0, h.nc_pad, s);
     coarse_resid(h, nullptr, u, v, t, s);   // t = 0 - A0 v
     // u = X t = -X A0 v (the handle's own partial slots; no solve is running)
     coarse_symv(h, nullptr, t, u, s);
     hipLaunchKernelGGL(k_coarse_err, dim3((unsigned)h.nb), dim3(256), 0, s, h.cblk_off_d.as<int64_t>(),
-                       h.cblk_n_d.as<int32_t>(), v, u, out);
-    DDG_HIP(hipMemcpyAsync(hv.data(), out, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    DDG_HIP(hipStreamSynchronize(s));
-    for (int32_t b = 0; b < h.nb; ++b) {
-      if (!(hv[2 * b + 1] > 0)) continue;
-      const double e = std::sqrt(hv[2 * b] / hv[2 * b + 1]);
-      if (!(e <= worst)) worst = e;   // keeps a NaN
-    }
-    if (!(worst <= 1e-12) || std::isnan(worst)) break;
+                       h.cblk_n_d.as<int32_t>(), v, u, o);
   }
   h.ws = keep;
+  DDG_HIP(hipMemcpyAsync(h.h_cerr, out, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+  DDG_HIP(hipGetLastError());
+}
+
+double finish_coarse_measure(const Handle& h) {
+  if (h.nc == 0 || h.three_level || h.ic || !h.h_cerr) return 0.0;
+  double worst = 0.0;
+  for (int it = 0; it < kPowerSteps; ++it)
+    for (int32_t b = 0; b < h.nb; ++b) {
+      const double* o = h.h_cerr + (size_t)2 * h.nb * it + 2 * b;
+      if (!(o[1] > 0)) continue;
+      const double e = std::sqrt(o[0] / o[1]);
+      if (!(e <= worst)) worst = e;   // keeps a NaN
+    }
   return worst;
 }
 

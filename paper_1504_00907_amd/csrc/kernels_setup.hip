@@ -1019,68 +1019,76 @@ void launch_galerkin(Handle& h, hipStream_t s) {
 
 void launch_coarse_invert(Handle& h, hipStream_t s) {
   const int64_t total = h.a0_off[h.nb];
-  int64_t nmax = 0;
-  for (int32_t b = 0; b < h.nb; ++b) nmax = std::max<int64_t>(nmax, h.cblk_n[b]);
   // the inverse is formed in a copy so that A0 stays available for export; the
   // buffers stay with the handle (freeing device memory would synchronise the device)
   DevBuf& inv = h.cinv;
   if (inv.bytes < (size_t)total * sizeof(double)) inv.alloc((size_t)total * sizeof(double));
   DDG_HIP(hipMemcpyAsync(inv.p, h.A0.p, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
-  // recursive inverse of every coarse block, one item per system: systems sorted by
-  // order and taken in groups whose workspace (the tree of the group's largest
-  // block, for every item) stays within a budget
-  std::vector<int32_t> order(h.nb);
-  for (int32_t b = 0; b < h.nb; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return h.cblk_n[x] > h.cblk_n[y]; });
-  const int64_t budget = ((int64_t)1 << 30) / 8;   // workspace elements (1 GiB)
-  const int64_t need0 = binv_work_need(0, (int)nmax, 0) + 64;
-  DevBuf& W = h.cwork;
-  DevBuf& gd = h.cgd;
-  const size_t wbytes = (size_t)std::max(need0, std::min<int64_t>(budget, need0 * h.nb)) * sizeof(double);
-  if (W.bytes < wbytes) W.alloc(wbytes);
-  const size_t gbytes = (size_t)h.nb * (sizeof(int64_t) + 2 * sizeof(int32_t));
-  if (gd.bytes < gbytes) gd.alloc(gbytes);
-  std::vector<int64_t> goff;
-  std::vector<int32_t> gn, gsys;
-  for (int32_t i0 = 0; i0 < h.nb;) {
-    const int32_t nfirst = h.cblk_n[order[i0]];
-    if (nfirst == 0) break;   // the remaining systems have no coarse space
-    const int64_t need = binv_work_need(0, nfirst, 0) + 64;
-    const int32_t cnt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(h.nb - i0, (int64_t)(W.bytes / 8) / need));
-    goff.assign(cnt, 0);
-    gn.assign(cnt, 0);
-    gsys.assign(cnt, 0);
-    for (int32_t q = 0; q < cnt; ++q) {
-      goff[q] = h.a0_off[order[i0 + q]];
-      gn[q] = h.cblk_n[order[i0 + q]];
-      gsys[q] = order[i0 + q];
+  if (h.cinv_groups.empty()) {
+    // recursive inverse of every coarse block, one item per system: systems sorted by
+    // order and taken in groups whose workspace (the tree of the group's largest
+    // block, for every item) stays within a budget.  The group tables depend only on
+    // the structure: built and uploaded once per handle, so a refactor enqueues the
+    // whole inverse without waiting on the host.
+    int64_t nmax = 0;
+    for (int32_t b = 0; b < h.nb; ++b) nmax = std::max<int64_t>(nmax, h.cblk_n[b]);
+    std::vector<int32_t> order(h.nb);
+    for (int32_t b = 0; b < h.nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return h.cblk_n[x] > h.cblk_n[y]; });
+    const int64_t budget = ((int64_t)1 << 30) / 8;   // workspace elements (1 GiB)
+    const int64_t need0 = binv_work_need(0, (int)nmax, 0) + 64;
+    const size_t wbytes = (size_t)std::max(need0, std::min<int64_t>(budget, need0 * h.nb)) * sizeof(double);
+    if (h.cwork.bytes < wbytes) h.cwork.alloc(wbytes);
+    std::vector<int64_t> goff;
+    std::vector<int32_t> gn, gsys;
+    for (int32_t i0 = 0; i0 < h.nb;) {
+      const int32_t nfirst = h.cblk_n[order[i0]];
+      if (nfirst == 0) break;   // the remaining systems have no coarse space
+      const int64_t need = binv_work_need(0, nfirst, 0) + 64;
+      const int32_t cnt =
+          (int32_t)std::max<int64_t>(1, std::min<int64_t>(h.nb - i0, (int64_t)(h.cwork.bytes / 8) / need));
+      h.cinv_groups.push_back(Handle::CoarseGroup{i0, cnt, nfirst, need});
+      for (int32_t q = 0; q < cnt; ++q) {
+        goff.push_back(h.a0_off[order[i0 + q]]);
+        gn.push_back(h.cblk_n[order[i0 + q]]);
+        gsys.push_back(order[i0 + q]);
+      }
+      i0 += cnt;
     }
-    int64_t* doff = gd.as<int64_t>();
-    int32_t* dn = reinterpret_cast<int32_t*>(doff + h.nb);
-    int32_t* dsys = dn + h.nb;
-    DDG_HIP(hipMemcpyAsync(doff, goff.data(), cnt * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DDG_HIP(hipMemcpyAsync(dn, gn.data(), cnt * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    DDG_HIP(hipMemcpyAsync(dsys, gsys.data(), cnt * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    const size_t m = goff.size();
+    h.cgd.alloc(std::max<size_t>(1, m) * (sizeof(int64_t) + 2 * sizeof(int32_t)));
+    if (m) {
+      int64_t* doff = h.cgd.as<int64_t>();
+      int32_t* dn = reinterpret_cast<int32_t*>(doff + m);
+      DDG_HIP(hipMemcpyAsync(doff, goff.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      DDG_HIP(hipMemcpyAsync(dn, gn.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      DDG_HIP(hipMemcpyAsync(dn + m, gsys.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      // (pageable sources: wait for the copies before the vectors go out of scope)
+      DDG_HIP(hipStreamSynchronize(s));
+    }
+    h.cinv_items = (int32_t)m;
+  }
+  const int64_t m = h.cinv_items;
+  int64_t* doff = h.cgd.as<int64_t>();
+  int32_t* dn = reinterpret_cast<int32_t*>(doff + m);
+  int32_t* dsys = dn + m;
+  for (const auto& gr : h.cinv_groups) {
     BInv bi;
     bi.scratch = inv.as<double>();
-    bi.off = doff;
-    bi.n = dn;
-    bi.W = W.as<double>();
-    bi.wstride = need;
+    bi.off = doff + gr.first;
+    bi.n = dn + gr.first;
+    bi.W = h.cwork.as<double>();
+    bi.wstride = gr.need;
     bi.woffs = nullptr;
     bi.err_sub = nullptr;
-    bi.err_blk = dsys;
-    binv_node(s, bi, (unsigned)cnt, 0, nfirst, 0, h.err_flag.as<int32_t>());
-    // the host arrays are reused by the next group: wait for this group's copies
-    DDG_HIP(hipStreamSynchronize(s));
-    i0 += cnt;
+    bi.err_blk = dsys + gr.first;
+    binv_node(s, bi, (unsigned)gr.count, 0, gr.nfirst, 0, h.err_flag.as<int32_t>());
   }
   const int64_t elems = h.ntiles * 64 * 64;
   hipLaunchKernelGGL(k_pack_coarse, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, inv.as<double>(),
                      h.a0_off_d.as<int64_t>(), h.cblk_n_d.as<int32_t>(), h.tile_inst.as<int32_t>(),
                      h.tile_base_d.as<int64_t>(), h.ntiles, h.A0inv_t.as<double>());
   DDG_HIP(hipGetLastError());
-  DDG_HIP(hipStreamSynchronize(s));
 }
 
 void launch_local_factor(Handle& h, hipStream_t s) {

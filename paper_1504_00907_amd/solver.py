@@ -275,14 +275,16 @@ class DDGBatchSolver(DDGSolver):
     def __init__(self, problems, overlap: int, precision: str = "fp64", rtol: float = 1e-8,
                  max_iter: int = 1000, rank_tol: float = 1e-10, tile: int = 0, block_target: int = 0,
                  check_every: int = 4, stream: Optional[torch.cuda.Stream] = None, schedule: str = "auto",
-                 cg_variant: str = "fr", matrix_format: str = "auto"):
+                 cg_variant: str = "fr", matrix_format: str = "auto", coarse_solver: str = "inverse",
+                 ic_tol: float = 1e-6, ic_maxit: int = 200):
         lib = _lib.load()
         self._lib = lib
         self.max_iter = int(max_iter)
         arr, keep = _problem_array(problems)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = _options(lib, precision, rtol, max_iter, rank_tol, tile, block_target, check_every, self.stream,
-                       schedule, cg_variant, matrix_format)
+                       schedule, cg_variant, matrix_format, coarse_solver=coarse_solver, ic_tol=ic_tol,
+                       ic_maxit=ic_maxit)
         self.precision = precision
         h = C.c_void_p()
         check(lib.ddg_setup_batched(C.byref(h), len(problems), arr, int(overlap), C.byref(opt)))

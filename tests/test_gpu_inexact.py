@@ -147,3 +147,29 @@ def test_ic_coarse_solve_options():
         DDGSolver.from_problem(P, coarse_solver="ic_cg", ic_maxit=0)
     with pytest.raises(Exception, match="UNSUPPORTED"):
         DDGSolver.from_problem(P, coarse_solver="ic_cg", schedule="persistent")
+
+
+def test_ic_coarse_solve_in_a_batch():
+    """Three uneven systems in one batched handle (2 x 2, 2 x 2 and 3 x 3 boxes: with a
+    single subdomain the pre-sweep is already exact and the restricted residual is
+    rounding noise): one workgroup per system runs its own inner CG; each system's
+    coarse correction matches its oracle's (m = 6)."""
+    from oracle.inexact import ic_pcg
+    from paper_1504_00907_amd import DDGBatchSolver
+    from workloads import cfg4_instance
+    m = 6
+    Ps = [cfg4_instance(300 + i, L, overlap=2, p=3, cell=16, rtol=1e-10) for i, L in enumerate((30, 37, 46))]
+    assert min(P.n_parts for P in Ps) >= 4
+    probs = [(P.A.row_ptr, P.A.col_idx, P.A.val, P.F, P.part, P.n_parts) for P in Ps]
+    b = DDGBatchSolver(probs, 2, coarse_solver="ic_cg", ic_tol=0.0, ic_maxit=m)
+    C = b.info()["n_colours"]
+    r = np.random.default_rng(5).standard_normal(b.n)
+    eC = host(b.apply_stages(dev(r), C))
+    d = host(b.apply_stages(dev(r), C + 1)) - eC
+    for i, P in enumerate(Ps):
+        o = InexactDDGOracle(P.A, P.F, P.part, P.n_parts, P.overlap, coarse_solver="ic_cg", ic_tol=0.0, ic_maxit=m)
+        sl = slice(b.row_off[i], b.row_off[i + 1])
+        b0 = o.R0 @ (r[sl] - P.A.to_scipy() @ eC[sl])
+        do = o.R0.T @ ic_pcg(o.A0s, o.L0, b0, 0.0, m)
+        assert rel(d[sl], do) <= 1e-10
+    b.close()

@@ -159,3 +159,22 @@ def test_persistent_unsupported_configurations():
     with pytest.raises(DDGError) as e:
         DDGSolver.from_problem(P, schedule="persistent", local_solver="ssor")
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_persistent_elasticity_matches_colour_launches(precision, monkeypatch):
+    """Q1 elasticity (about 78 entries per row): sliced level couplings and lane-group
+    row dots inside the persistent kernel; bit for bit the colour launches' results."""
+    from paper_1504_00907_amd import DDGSolver
+    from workloads.elasticity import elasticity_q1
+    monkeypatch.setenv("DDG_NO_TWIST", "1")
+    P = elasticity_q1(nel=10, part_dofs=(200, 500), min_dofs=200, sigma=1.0, rtol=1e-10)
+    out = {}
+    for schedule in ("persistent", "colours"):
+        s = DDGSolver.from_problem(P, precision=precision, rtol=P.rtol, schedule=schedule)
+        u, inf = s.solve(dev(P.f))
+        out[schedule] = (host(u), inf["iters"], inf["status"])
+        s.close()
+    say(f"   elasticity {precision}: iters {out['persistent'][1]} vs {out['colours'][1]}")
+    assert out["persistent"][1:] == out["colours"][1:]
+    assert np.array_equal(out["persistent"][0], out["colours"][0])
