@@ -268,7 +268,8 @@ def elasticity(nel: int, steps: int, tile: int = 0, block_target: int = 0):
         hinfo = s.info()
         rec = {"ms_per_solve": ms, "iters": info["iters"], "true_rel_res": true_res,
                "setup_s": setup_s, "setup_ms_device": hinfo["setup_ms"], "factor_bytes": hinfo["factor_bytes"],
-               "n_coarse": hinfo["n_coarse"], "colours": hinfo["n_colours"]}
+               "n_coarse": hinfo["n_coarse"], "colours": hinfo["n_colours"],
+               "sweep_groups": hinfo["sweep_groups"], "sweep_bytes": hinfo["sweep_bytes"]}
         if prec == "fp64":
             u64 = uh
         else:

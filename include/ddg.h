@@ -171,6 +171,8 @@ typedef struct {
   int32_t coarse_solver;   /* ddg_coarse_solver in use */
   int32_t coarse_iters;    /* DDG_COARSE_IC_CG: inner CG iterations summed over the last solve's
                               coarse solves (worst system); 0 otherwise */
+  int32_t sweep_groups;    /* largest number of workgroups that shared one chain of a local solve in
+                              any colour launch since setup (1: every chain ran in one workgroup) */
 } ddg_info;
 
 /* Fill *opt with defaults: FP64, max_iter 1000, rtol 1e-8, rank_tol 1e-10, automatic tiles. */

@@ -52,7 +52,7 @@ class Info(C.Structure):
         ("envelope_elems", C.c_int64), ("set_rows", C.c_int64), ("nbhd_rows", C.c_int64),
         ("matrix_format", C.c_int32), ("levels", C.c_int32), ("n_coarsest", C.c_int32),
         ("coarse_refine", C.c_int32), ("coarse_inverse_err", C.c_double), ("coarse_solver", C.c_int32),
-        ("coarse_iters", C.c_int32),
+        ("coarse_iters", C.c_int32), ("sweep_groups", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

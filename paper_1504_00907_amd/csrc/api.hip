@@ -199,6 +199,7 @@ void check_err_flag(Handle& h, const char* what) {
     else if (e[0] == DDG_ERR_HIP && e[2] == -8) m += "sweep task of subdomain " + std::to_string(e[1]) + " timed out waiting for a dependency";
     else if (e[0] == DDG_ERR_HIP && e[2] == -9) m += "sweep task queue out of step";
     else if (e[0] == DDG_ERR_HIP && e[2] == -10) m += "persistent solve: a workgroup waited too long for its next task";
+    else if (e[0] == DDG_ERR_HIP && e[2] == -11) m += "grouped sweep barrier timed out in subdomain " + std::to_string(e[1]);
     else if (e[0] == DDG_ERR_HIP) m += "workgroup handoff timed out in subdomain " + std::to_string(e[1]);
     else if (e[1] < 0) m += "coarse pivot " + std::to_string(e[3]) + " not positive (A0 not SPD)";
     else m += "local pivot not positive in subdomain " + std::to_string(e[1]) + " block " + std::to_string(e[2]) +
@@ -207,7 +208,11 @@ void check_err_flag(Handle& h, const char* what) {
     if (h.twisted_ok) {
       // a partner that arrived after its handoff wait gave up has raised its flag:
       // clear every flag so that the next launch's readers wait for fresh data
-      DDG_HIP(hipMemsetAsync(h.flags.p, 0, (size_t)h.S.n_parts * 2 * sizeof(int32_t), h.stream));
+      DDG_HIP(hipMemsetAsync(h.flags.p, 0, (size_t)h.S.n_parts * 2 * h.grp_max * sizeof(int32_t), h.stream));
+    }
+    if (h.grp_max > 1) {
+      // likewise the grouped sweep's barrier counts
+      DDG_HIP(hipMemsetAsync(h.gcnt.p, 0, (size_t)h.grp_slots * 2 * sizeof(int32_t), h.stream));
     }
     if (h.flow_ok) {
       // the task queue may be out of step after a failed sweep: start it afresh
@@ -583,10 +588,25 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
   for (int32_t c = 0; c < S.n_colours; ++c) max_nsub = std::max(max_nsub, S.colour_ptr[c + 1] - S.colour_ptr[c]);
   h->twisted_ok = (16 * ((max_nsub + 7) / 8) <= ncu) && std::getenv("DDG_NO_TWIST") == nullptr;
   h->xch_ld = ((S.max_blk + 63) / 64) * 64;
+  // grouped sweep: with the sliced coupling layout (wide levels), when a colour leaves
+  // CUs idle; DDG_SWEEP_GROUPS caps the group size (1 = off), DDG_SWEEP_SPLIT_ROUNDS
+  // sets the narrowest split level in rounds
+  if (S.sliced && h->opt.local_solver == DDG_LOCAL_EXACT) {
+    h->grp_max = kSweepGroupsMax;
+    if (const char* env = std::getenv("DDG_SWEEP_GROUPS")) h->grp_max = std::max(1, std::min(kSweepGroupsCap, std::atoi(env)));
+    h->grp_split = kSweepSplitRounds;
+    if (const char* env = std::getenv("DDG_SWEEP_SPLIT_ROUNDS")) h->grp_split = std::max(2, std::atoi(env));
+  }
+  if (h->grp_max > 1) {
+    h->grp_slots = max_nsub;
+    h->gx.alloc((size_t)max_nsub * 2 * 2 * h->grp_max * h->xch_ld * sizeof(double));
+    h->gcnt.alloc((size_t)max_nsub * 2 * sizeof(int32_t));
+    DDG_HIP(hipMemsetAsync(h->gcnt.p, 0, (size_t)max_nsub * 2 * sizeof(int32_t), s));
+  }
   if (h->twisted_ok) {
     h->xch.alloc((size_t)n_parts * 2 * h->xch_ld * sizeof(double));
-    h->flags.alloc((size_t)n_parts * 2 * sizeof(int32_t));
-    DDG_HIP(hipMemsetAsync(h->flags.p, 0, (size_t)n_parts * 2 * sizeof(int32_t), s));
+    h->flags.alloc((size_t)n_parts * 2 * h->grp_max * sizeof(int32_t));
+    DDG_HIP(hipMemsetAsync(h->flags.p, 0, (size_t)n_parts * 2 * h->grp_max * sizeof(int32_t), s));
   }
   h->bres.alloc((size_t)S.set_ptr[n_parts] * sizeof(double));
   // [0..3] setup/solve error (code, subdomain, block, pivot); [4] entries whose transpose
@@ -608,6 +628,7 @@ void setup_impl(Handle& hh, int64_t n, const int64_t* row_ptr, const int32_t* co
     h->kcnt_d.alloc((size_t)n_parts * sizeof(int32_t));
     launch_coarse_basis(*h, s);
     check_err_flag(*h, "coarse basis");
+    launch_q_own(*h, s);
     DDG_HIP(hipMemcpyAsync(h->kcnt.data(), h->kcnt_d.p, (size_t)n_parts * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s));
     DDG_HIP(hipStreamSynchronize(s));
@@ -1323,6 +1344,7 @@ int ddg_get_info(ddg_handle hd, ddg_info* info) {
     Handle* h = H(hd);
     DDG_REQUIRE(h && info, DDG_ERR_INVALID_ARG, "null argument");
     *info = h->info;
+    info->sweep_groups = h->grp_used;
   });
 }
 

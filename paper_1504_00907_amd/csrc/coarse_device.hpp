@@ -12,16 +12,25 @@ namespace ddg {
 
 constexpr int kRThreads = 256;
 
+// The basis as the solve reads it: row t of the own-row order (the rows of
+// subdomain 0, then of subdomain 1, ...; own_idx maps t to the global row),
+// column m < kq, in 64-row tiles stored column-major, so that the 64 lanes of a
+// wave reading one column of 64 consecutive own rows read 512 contiguous bytes.
+__host__ __device__ inline int64_t q_own_at(int64_t t, int m, int kq) {
+  return ((t >> 6) * kq + m) * 64 + (t & 63);
+}
+
 // Partial restriction over one chunk of the own rows of subdomain i (workgroup
 // (c, i) takes rows [own_ptr[i] + c rch, ... + rch)), L lanes per CSR row:
 //   rpart[i, c, m] = sum_{g in chunk} Q[g, m] (r - A e)_g,   m < kcnt[i]
+// with the basis read from the own-row layout Qo (q_own_at)
 // (waves in order after a butterfly per wave); empty chunks write zeros.
 // KM: capacity of the per-thread column arrays and stride of rpart (kslots(k)).
 // (the first kRThreads threads of the workgroup do the work; any others join the barrier)
 template <int L, int KM>
 __device__ inline void d_coarse_restrict(int i, int c, int nch, const int32_t* __restrict__ sub_inst,
                                          const int64_t* __restrict__ own_ptr, const int32_t* __restrict__ own_idx,
-                                         const int32_t* __restrict__ kcnt, const double* __restrict__ Q, int kq,
+                                         const int32_t* __restrict__ kcnt, const double* __restrict__ Qo, int kq,
                                          const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                          const double* __restrict__ val, const DiaView D,
                                          const double* __restrict__ r, const double* __restrict__ e, int rch,
@@ -55,10 +64,10 @@ __device__ inline void d_coarse_restrict(int i, int c, int nch, const int32_t* _
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (g[u] < 0) continue;
-        const double* qg = Q + (int64_t)g[u] * kq;
+        const double* qt = Qo + q_own_at(t + u * kRThreads, 0, kq);
 #pragma unroll
         for (int m = 0; m < KM; ++m)
-          if (m < ki) acc[m] += qg[m] * sv[u];
+          if (m < ki) acc[m] += qt[m * 64] * sv[u];
       }
     }
   } else {
@@ -66,10 +75,10 @@ __device__ inline void d_coarse_restrict(int i, int c, int nch, const int32_t* _
       const int g = own_idx[t];
       const double s = r[g] - row_dot_l<L>(rp, ci, val, e, g, jl);
       if (jl == 0) {
-        const double* qg = Q + (int64_t)g * kq;
+        const double* qt = Qo + q_own_at(t, 0, kq);
 #pragma unroll
         for (int m = 0; m < KM; ++m)
-          if (m < ki) acc[m] += qg[m] * s;
+          if (m < ki) acc[m] += qt[m * 64] * s;
       }
     }
   }
@@ -132,18 +141,20 @@ __device__ inline void d_coarse_sum_row(int64_t row, int b, const int64_t* __res
   y[row] = s;
 }
 
-// e[g] += sum_m Q[g, m] y[koff[part g] + m]
+// e[g] += sum_m Q[g, m] y[koff[part g] + m] for the row g at position t of the
+// own-row order (g = own_idx[t])
 template <int KM>
-__device__ inline void d_coarse_prolong_row(int64_t g, const CgState* st, const int32_t* __restrict__ sub_inst,
-                                            const int32_t* __restrict__ part, const int32_t* __restrict__ kcnt,
-                                            const int64_t* __restrict__ koff, const double* __restrict__ Q, int kq,
-                                            const double* __restrict__ y, double* __restrict__ e) {
-  // the row of Q (stride kq) is requested before the subdomain's count and offset
-  // are known, so its loads do not wait behind that chain of lookups
-  const double* qg = Q + g * kq;
+__device__ inline void d_coarse_prolong_row(int64_t g, int64_t t, const CgState* st,
+                                            const int32_t* __restrict__ sub_inst, const int32_t* __restrict__ part,
+                                            const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
+                                            const double* __restrict__ Qo, int kq, const double* __restrict__ y,
+                                            double* __restrict__ e) {
+  // the row of the basis is requested before the subdomain's count and offset are
+  // known, so its loads do not wait behind that chain of lookups
+  const double* qt = Qo + q_own_at(t, 0, kq);
   double q[KM];
 #pragma unroll
-  for (int m = 0; m < KM; ++m) q[m] = m < kq ? qg[m] : 0.0;
+  for (int m = 0; m < KM; ++m) q[m] = m < kq ? qt[m * 64] : 0.0;
   const int i = part[g];
   if (st && st[sub_inst[i]].done) return;
   const int ki = kcnt[i];

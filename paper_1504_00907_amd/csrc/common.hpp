@@ -123,6 +123,11 @@ struct Symbolic {
 // Most generating vectors per system (degree 10 in 2D has 66); the coarse kernels
 // keep per-thread column arrays of 32 entries, or of kMaxGen when k > 32.
 constexpr int kMaxGen = 80;
+// grouped sweep: workgroups per chain at most (default, and the most DDG_SWEEP_GROUPS
+// may ask for), narrowest split level in rounds
+constexpr int kSweepGroupsMax = 4;
+constexpr int kSweepGroupsCap = 8;
+constexpr int kSweepSplitRounds = 4;
 inline int32_t kslots(int32_t k) { return k <= 32 ? 32 : kMaxGen; }
 
 // Couplings per row and direction that the sweep keeps in registers; wider rows use
@@ -230,6 +235,7 @@ struct Handle {
   DevBuf sl_lo_off, sl_up_off, sl_lo_col, sl_up_col;
   DevBuf sl_lo_val, sl_up_val;                       // in the sweep's arithmetic type
   DevBuf xch, flags;                 // two-workgroup handoff buffers of the twisted sweep
+  DevBuf gx, gcnt;                   // grouped sweep: partial level sums and barrier counts
   // persistent sweep over a task queue (one launch per sweep direction): per
   // direction the subdomains in sweep order and each subdomain's earlier
   // conflicting subdomains; per subdomain a completion count; the queue counter
@@ -266,6 +272,12 @@ struct Handle {
   int32_t device = 0;                // HIP device current at setup
   int32_t xch_ld = 0;
   bool twisted_ok = false;
+  // grouped sweep (sliced layout): up to grp_max workgroups per chain, levels of at
+  // least grp_split rounds split between them; grp_max 1 = off
+  int32_t grp_max = 1;
+  int32_t grp_split = 0;
+  int32_t grp_slots = 0;             // subdomains per launch the buffers hold
+  mutable int32_t grp_used = 1;      // largest group size launched so far
   int32_t n_cu = 256;
   // three-level V-cycle: one application of the two-level method of A0 (coarse
   // partition of the subdomains, generating vectors F0 = R0 F, the same overlap)
@@ -276,6 +288,8 @@ struct Handle {
   int64_t apply_bytes = 0;           // algorithmic bytes of one preconditioner application
   DevBuf F;               // n x k column-major (setup input)
   DevBuf Q;               // n x k node-major orthonormal basis (zero-padded)
+  DevBuf Qo;              // the same basis in own-row order, 64-row tiles column-major (q_own_at)
+  DevBuf qpos;            // n: position of each row in the own-row order
   DevBuf kcnt_d, koff_d;
   DevBuf A0;              // dense coarse blocks, one per system (kept for export)
   DevBuf A0inv_t;         // tiled lower inverses, float64, tile 64
@@ -426,6 +440,7 @@ void launch_persist(Handle& h, const double* f, double* x, hipStream_t s);
 
 // setup numerics
 void launch_coarse_basis(Handle& h, hipStream_t s);
+void launch_q_own(Handle& h, hipStream_t s);   // Qo and qpos from Q
 void launch_galerkin(Handle& h, hipStream_t s);
 void launch_coarse_invert(Handle& h, hipStream_t s);
 // max over systems of ||v - X A0 v|| / ||v|| for a fixed pseudo-random v (X the packed inverse)

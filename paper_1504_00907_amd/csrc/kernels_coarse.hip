@@ -5,6 +5,7 @@
 //   b0[off_i + m] = sum_{g in Omega_i} Q[g, m] (r - A e)_g        (restrict)
 //   y = A0^{-1} b0                                                  (tiled symmetric GEMV)
 //   e_g += sum_m Q[g, m] y[off_{part g} + m]                        (prolong)
+// (restriction and prolongation read Q in the own-row layout q_own_at)
 // A0^{-1} is the explicit float64 inverse computed at setup; it is stored as
 // lower 64 x 64 tiles and applied with one wave per tile, writing fixed
 // per-tile partials that a second kernel sums in a fixed order.  With several
@@ -20,12 +21,12 @@ namespace {
 template <int L, int KM>
 __global__ void __launch_bounds__(kRThreads) k_coarse_restrict(
     const CgState* st, const int32_t* __restrict__ sub_inst, const int64_t* __restrict__ own_ptr,
-    const int32_t* __restrict__ own_idx, const int32_t* __restrict__ kcnt, const double* __restrict__ Q, int kq,
+    const int32_t* __restrict__ own_idx, const int32_t* __restrict__ kcnt, const double* __restrict__ Qo, int kq,
     const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ val,
     DiaView D, const double* __restrict__ r, const double* __restrict__ e, int rch, double* __restrict__ rpart) {
   const int i = blockIdx.y, c = blockIdx.x;
   if (st && st[sub_inst[i]].done) return;
-  d_coarse_restrict<L, KM>(i, c, gridDim.x, sub_inst, own_ptr, own_idx, kcnt, Q, kq, rp, ci, val, D, r, e, rch, rpart);
+  d_coarse_restrict<L, KM>(i, c, gridDim.x, sub_inst, own_ptr, own_idx, kcnt, Qo, kq, rp, ci, val, D, r, e, rch, rpart);
 }
 
 // b0[koff[i] + m] = sum over the nch chunks of subdomain i, in chunk order
@@ -67,15 +68,27 @@ __global__ void k_coarse_sum(const CgState* st, const int32_t* __restrict__ trow
   d_coarse_sum_row(row, b, tile_base, cblk_off, rowpart, colpart, y);
 }
 
+// one thread per row, in the own-row order (the basis reads are contiguous)
+// The basis in the own-row layout (q_own_at) and each row's position in the
+// own-row order, from the node-major basis of the setup.
+__global__ void k_q_own(const int32_t* __restrict__ own_idx, const double* __restrict__ Q, int64_t n, int k,
+                        double* __restrict__ Qo, int32_t* __restrict__ qpos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int g = own_idx[t];
+  qpos[g] = (int32_t)t;
+  for (int m = 0; m < k; ++m) Qo[q_own_at(t, m, k)] = Q[(int64_t)g * k + m];
+}
+
 template <int KM>
 __global__ void __launch_bounds__(256) k_coarse_prolong(const CgState* st, const int32_t* __restrict__ sub_inst,
-                                 const int32_t* __restrict__ part,
+                                 const int32_t* __restrict__ part, const int32_t* __restrict__ own_idx,
                                  const int32_t* __restrict__ kcnt, const int64_t* __restrict__ koff,
-                                 const double* __restrict__ Q, int kq, const double* __restrict__ y,
+                                 const double* __restrict__ Qo, int kq, const double* __restrict__ y,
                                  double* __restrict__ e, int64_t n) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  d_coarse_prolong_row<KM>(g, st, sub_inst, part, kcnt, koff, Q, kq, y, e);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  d_coarse_prolong_row<KM>(own_idx[t], t, st, sub_inst, part, kcnt, koff, Qo, kq, y, e);
 }
 
 // F0[koff[i] + j, c] = sum over the own rows g of subdomain i of Q[g, j] F[g, c]
@@ -246,6 +259,15 @@ double finish_coarse_measure(const Handle& h) {
   return worst;
 }
 
+void launch_q_own(Handle& h, hipStream_t s) {
+  const int64_t n = h.S.n;
+  h.Qo.alloc((size_t)((n + 63) / 64) * 64 * h.k * sizeof(double));
+  h.qpos.alloc((size_t)n * sizeof(int32_t));
+  hipLaunchKernelGGL(k_q_own, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h.own_idx.as<int32_t>(),
+                     h.Q.as<double>(), n, h.k, h.Qo.as<double>(), h.qpos.as<int32_t>());
+  DDG_HIP(hipGetLastError());
+}
+
 void launch_restrict_columns(Handle& h, double* F0, hipStream_t s) {
   launch_fill(F0, 0.0, h.nc_pad * h.k, s);
   hipLaunchKernelGGL(k_restrict_columns, dim3((unsigned)h.S.n_parts), dim3(256), 0, s, h.own_ptr.as<int64_t>(),
@@ -268,7 +290,7 @@ void launch_coarse_k(Handle& h, const double* r, double* e, const CgState* st, h
     constexpr int L = decltype(Lc)::value;
     hipLaunchKernelGGL((k_coarse_restrict<L, KM>), dim3((unsigned)h.nch, (unsigned)S.n_parts), dim3(kRThreads), 0, s, st,
                        sub_inst, h.own_ptr.as<int64_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(),
-                       h.Q.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(),
+                       h.Qo.as<double>(), h.k, h.rowptr.as<int64_t>(), h.col.as<int32_t>(), h.val.as<double>(),
                        dia_view(h), r, e, h.rch, h.ws.rpart);
   });
   hipLaunchKernelGGL(k_coarse_restrict_sum, dim3((unsigned)(((int64_t)S.n_parts * KM + 255) / 256)), dim3(256), 0,
@@ -294,8 +316,8 @@ void launch_coarse_k(Handle& h, const double* r, double* e, const CgState* st, h
     }
   }
   hipLaunchKernelGGL(k_coarse_prolong<KM>, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, st, sub_inst,
-                     h.part.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
-                     h.Q.as<double>(), h.k, y, e, S.n);
+                     h.part.as<int32_t>(), h.own_idx.as<int32_t>(), h.kcnt_d.as<int32_t>(), h.koff_d.as<int64_t>(),
+                     h.Qo.as<double>(), h.k, y, e, S.n);
   DDG_HIP(hipGetLastError());
 }
 

@@ -80,6 +80,11 @@ struct SweepArgs {
   int32_t* err;
   int32_t slot_tiles;   // tiles whose partial slots fit on chip (a multiple of one round); wider
                         // levels are reduced in phases of this many tiles into an accumulator
+  // grouped launch (several workgroups per chain, wide levels split between them)
+  int32_t groups;        // workgroups per chain (1 otherwise)
+  int32_t split_rounds;  // a level of at least this many rounds (>= 2) is split over the group
+  void* gx;              // per (slot, chain): 2 parities x groups x xch_ld partial level sums
+  int32_t* gcnt;         // per (slot, chain): barrier count
 };
 
 namespace {
@@ -146,44 +151,94 @@ __device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub) {
 // Publish the exchange buffer: every wave waits for its own stores to
 // complete (vmcnt 0), the barrier collects the waves, and thread 0 issues one
 // agent-scope release before raising the flag.
-__device__ inline void handoff_signal(int32_t* flag) {
+// (n flags: one per reading workgroup of a grouped launch)
+__device__ inline void handoff_signal(int32_t* flag, int n = 1) {
   wait_vm();
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     wait_vm();
-    __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = 0; i < n; ++i) __hip_atomic_store(flag + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// Barrier of the workgroups of one chain in a grouped launch: every wave waits for
+// its own stores, thread 0 makes an agent-scope release, counts the workgroup and
+// waits (bounded; also ended by an error another workgroup raised) until the count
+// reaches `target`, then makes an agent-scope acquire before the barrier lets the
+// other waves read.
+__device__ inline void group_barrier(int32_t* cnt, int target, int32_t* err, int sub) {
+  wait_vm();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    wait_vm();
+    __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (spins > kSpinLimit) {
+        if (atomicCAS(err, 0, DDG_ERR_HIP) == 0) {
+          err[1] = sub;
+          err[2] = -11;
+        }
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    wait_vm();
+  }
+  __syncthreads();
 }
 
 }  // namespace
 
 // c + sum_{q >= q0} val_q * w[col_q] over the entries of one row of a slice (lane
 // ln), in the order the entries are stored; the slice's entries are
-// [base + tab[sl], base + tab[sl + 1]).  The slice's width is the same for all
-// lanes of a wave, so the loads are coalesced and issued in unconditional groups
-// of kCplU.
-constexpr int kCplU = 8;
+// [base + tab[sl], base + tab[sl + 1]), 64 per entry index.  The slice's width is
+// the same for all lanes of a wave, so the loads are coalesced; they go out in
+// chunks of cpl_chunk<AT>() entries, the next chunk's before the current one is
+// used (two chunks in flight, one dependent round trip per chunk pair rather than
+// per chunk), and the last chunk is predicated rather than taken one entry at a
+// time.  (FP64 values take half-size chunks: the same registers as one FP32 chunk pair.)
+template <class AT>
+__host__ __device__ constexpr int cpl_chunk() { return sizeof(AT) == 8 ? 4 : 8; }
 // entries of the first row a thread owns in a level, prefetched one level ahead
 constexpr int kCplHead = 4;
 
 template <class AT>
 __device__ inline AT slice_dot(const int32_t* tab, int64_t base, const int32_t* __restrict__ col,
                                const AT* __restrict__ val, int sl, int ln, int q0, const AT* w, AT c) {
-  const int64_t o1 = base + tab[sl + 1];
-  int64_t o = base + tab[sl] + 64 * q0 + ln;
-  for (; o + (kCplU - 1) * 64 < o1; o += kCplU * 64) {
-    int cc[kCplU];
-    AT vv[kCplU];
+  constexpr int U = cpl_chunk<AT>();
+  const int n = ((tab[sl + 1] - tab[sl]) >> 6) - q0;   // entries left in the row
+  const int64_t o0 = base + tab[sl] + 64 * q0 + ln;
+  int cc[U], cn[U];
+  AT vv[U], vn[U];
+  auto load = [&](int i, int (&cx)[U], AT (&vx)[U]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < kCplU; ++u) {
-      cc[u] = col[o + u * 64];
-      vv[u] = val[o + u * 64];
+    for (int u = 0; u < U; ++u) {
+      const int q = i * U + u;
+      cx[u] = 0;
+      vx[u] = 0;
+      if (q < n) {
+        cx[u] = col[o0 + 64 * q];
+        vx[u] = val[o0 + 64 * q];
+      }
     }
+  };
+  if (n > 0) load(0, cc, vv);
+  for (int i = 0; i * U < n; ++i) {
+    if ((i + 1) * U < n) load(i + 1, cn, vn);
 #pragma unroll
-    for (int u = 0; u < kCplU; ++u) c += vv[u] * w[cc[u]];
+    for (int u = 0; u < U; ++u)
+      if (i * U + u < n) c += vv[u] * w[cc[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cc[u] = cn[u];
+      vv[u] = vn[u];
+    }
   }
-  for (; o < o1; o += 64) c += val[o] * w[col[o]];
   return c;
 }
 
@@ -195,9 +250,13 @@ constexpr int kMaxLevels = 96;   // levels per subdomain staged in LDS
 // registers, rows past the first NT of a level read the ELL arrays); SL = true:
 // the sliced coupling layout.  OWN_RES: the workgroup forms b = (r - A e) on its
 // own rows from the CSR rows of A (res_e_zero: e is zero there) instead of reading
-// the local-residual kernel's output.
-template <class FT, class AT, int T, int NW, int TPW, bool SL, bool OWN_RES>
-__device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs, bool res_e_zero) {
+// the local-residual kernel's output.  GRP: workgroup gi of the a.groups that share
+// the chain; a level of at least a.split_rounds rounds is split between them (each
+// sums the slots of its own rounds, the partial sums are exchanged through global
+// memory and added in workgroup order, so all of them hold the same level result);
+// a narrower level is computed whole by each of them.
+template <class FT, class AT, int T, int NW, int TPW, bool SL, bool OWN_RES, bool GRP = false>
+__device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs, bool res_e_zero, int gi = 0) {
   using G = TileGeom<FT, T>;
   constexpr int NT = NW * 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -205,6 +264,21 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   __shared__ int64_t lv_foff[kMaxLevels];
   __shared__ int32_t lv_slice[kMaxLevels];  // first slice of each level, relative to the subdomain's
   const int p = xs;
+  constexpr int NWT = NW * TPW;
+  const int NG = GRP ? a.groups : 1;   // workgroups of the chain
+  // this workgroup's rounds [rf, rl) of a level of ntl_ tiles (empty for some
+  // workgroups when a split level has fewer rounds than the group has workgroups)
+  auto rounds_of = [&](int ntl_, int& rf, int& rl) __attribute__((always_inline)) {
+    const int R = (ntl_ + NWT - 1) / NWT;
+    rf = 0;
+    rl = R;
+    if constexpr (GRP) {
+      if (R >= a.split_rounds) {
+        rf = R * gi / NG;
+        rl = R * (gi + 1) / NG;
+      }
+    }
+  };
   const int64_t s0 = a.set_ptr[sub];
   const int ni = (int)(a.set_ptr[sub + 1] - s0);
   const int ni_pad = (ni + 3) & ~3;
@@ -293,8 +367,20 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   constexpr bool cpl_regs = !SL;
   auto load_tile = [&](int k, int j) __attribute__((always_inline)) {
     const int ntl = tiles_for(lv_size[k], T);
-    const int t = j * NW + wave;
-    if (t < ntl) load_tile_at(k, t, tI[j], tJ[j], j);
+    if constexpr (GRP) {
+      // this workgroup's first tile of slot j at level k
+      int rf, rl;
+      rounds_of(ntl, rf, rl);
+      const int t = (rf * TPW + j) * NW + wave;
+      if (rf < rl && t < ntl) {
+        int I = tI[j], J = tJ[j];
+        if (rf > 0) tile_ij(t, I, J);
+        load_tile_at(k, t, I, J, j);
+      }
+    } else {
+      const int t = j * NW + wave;
+      if (t < ntl) load_tile_at(k, t, tI[j], tJ[j], j);
+    }
   };
   auto load_cpl = [&](int kind, int k) {
     if (!cpl_regs) return;
@@ -396,7 +482,14 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
   __syncthreads();
 
   double* xch = a.xch + (int64_t)p * 2 * a.xch_ld;
-  int32_t* flags = a.flags + 2 * p;
+  // handoff flags of the slot: [d * NG + i] for direction d (0: up to the top chain,
+  // 1: down to the bottom chain) and reading workgroup i
+  int32_t* flags = a.flags + 2 * p * NG;
+  // grouped launch: this chain's partial-sum buffers and barrier count, and the
+  // number of split levels passed so far
+  const int chain = 2 * p + (role == 2 ? 1 : 0);
+  int32_t* gcnt = GRP ? a.gcnt + chain : nullptr;
+  int nsplit = 0;
 
   for (int s = 0; s < ns; ++s) {
     int kind, k;
@@ -407,14 +500,14 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
     const int ntl = nt * (nt + 1) / 2;
     if (role == 1 && kind == MID && nB > 0) {
       // import t_{m+1} from the bottom chain
-      handoff_wait(flags + 0, a.err, sub);
+      handoff_wait(flags + gi, a.err, sub);
       const int bs1 = lv_start[m + 1], b1 = lv_size[m + 1];
       for (int jj = tid; jj < b1; jj += NT) w[bs1 + jj] = (AT)xch[jj];
       __syncthreads();
     }
     if (role == 2 && kind == BWD_LO && k == m + 1) {
       // import x_m from the top chain
-      handoff_wait(flags + 1, a.err, sub);
+      handoff_wait(flags + NG + gi, a.err, sub);
       const int bsm = lv_start[m], bm = lv_size[m];
       for (int jj = tid; jj < bm; jj += NT) w[bsm + jj] = (AT)xch[a.xch_ld + jj];
       __syncthreads();
@@ -472,13 +565,17 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
     // computations can interleave.  When a level fits in one round, each register
     // set is refilled with the next level's tile as soon as it has been used.
     const int rounds = (ntl + NW * TPW - 1) / (NW * TPW);
+    int rf = 0, rl = rounds;   // this workgroup's rounds
+    if constexpr (GRP) rounds_of(ntl, rf, rl);
+    const bool split = GRP && rounds >= a.split_rounds;
     const int phase_rounds = a.slot_tiles / (NW * TPW);
-    const bool phased = ntl > a.slot_tiles;
+    const bool phased = split || ntl > a.slot_tiles;
     int kind2 = 0, k2 = 0;
     const bool has_next = s + 1 < ns;
     if (has_next) decode_step(role, s + 1, K, m, kind2, k2);
-    for (int round = 0; round < rounds; ++round) {
-      const int t_phase = (round / phase_rounds) * phase_rounds * NW * TPW;  // first tile of the phase
+    for (int round = rf; round < rl; ++round) {
+      const int t_phase = GRP ? (rf + ((round - rf) / phase_rounds) * phase_rounds) * NW * TPW
+                              : (round / phase_rounds) * phase_rounds * NW * TPW;  // first tile of the phase
       int rI[TPW], rJ[TPW];
 #pragma unroll
       for (int j = 0; j < TPW; ++j) {
@@ -486,14 +583,14 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
         rJ[j] = tJ[j];
         if (round > 0) tile_ij((round * TPW + j) * NW + wave, rI[j], rJ[j]);
       }
-      if (round > 0) {
+      if (round > rf) {
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
           const int t = (round * TPW + j) * NW + wave;
           if (t < ntl) load_tile_at(k, t, rI[j], rJ[j], j);
         }
       }
-      const bool last = round + 1 == rounds;
+      const bool last = round + 1 == rl;
       if (last && has_next) {
         // the next step's couplings go out before its tiles
         load_cpl(kind2, k2);
@@ -508,57 +605,105 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
                                        slots + (int64_t)(2 * (t - t_phase) + 1) * T, lane, valid);
         if (last && has_next) load_tile(k2, j);
       }
-      if (phased && ((round + 1) % phase_rounds == 0 || last)) {
+      if (phased && ((round + 1 - rf) % phase_rounds == 0 || last)) {
         // fold this phase's slots into the accumulator, rows in a fixed tile order
         __syncthreads();
-        const int t_end = min(ntl, t_phase + phase_rounds * NW * TPW);
+        const int t_end = min(GRP ? min(ntl, rl * NW * TPW) : ntl, t_phase + phase_rounds * NW * TPW);
         for (int jj = tid; jj < b; jj += NT) {
           const AT part = sum_slots_range<AT, T, CD>(slots, nt, jj, t_phase, t_end);
-          acc[jj] = t_phase == 0 ? part : acc[jj] + part;
+          acc[jj] = t_phase == rf * NW * TPW ? part : acc[jj] + part;
         }
         __syncthreads();
       }
     }
-    __syncthreads();
-    for (int jj = tid; jj < b; jj += NT) {
-      const AT sum = phased ? acc[jj] : sum_slots<AT, T, CD>(slots, nt, jj);
-      if (fwd) w[bs + jj] = sum;
-      else w[bs + jj] -= sum;
+    if (GRP && rl == rf && has_next) {
+      // no round of this level here: the next step's couplings and tiles go out now
+      load_cpl(kind2, k2);
+      load_head(kind2, k2);
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) load_tile(k2, j);
     }
     __syncthreads();
-    if (role == 2 && kind == FWD_UP && k == m + 1) {
+    if (split) {
+      // the group's partial sums of this level (parity of the split count: a buffer
+      // is written again only after every workgroup has passed the next barrier,
+      // i.e. has read it), summed in workgroup order
+      AT* X = static_cast<AT*>(a.gx) + ((int64_t)chain * 2 + (nsplit & 1)) * NG * a.xch_ld;
+      for (int jj = tid; jj < b; jj += NT) X[(int64_t)gi * a.xch_ld + jj] = rl > rf ? acc[jj] : (AT)0;
+      ++nsplit;
+      group_barrier(gcnt, NG * nsplit, a.err, sub);
+      for (int jj = tid; jj < b; jj += NT) {
+        AT sum = X[jj];
+        for (int i = 1; i < NG; ++i) sum += X[(int64_t)i * a.xch_ld + jj];
+        if (fwd) w[bs + jj] = sum;
+        else w[bs + jj] -= sum;
+      }
+    } else {
+      for (int jj = tid; jj < b; jj += NT) {
+        const AT sum = phased ? acc[jj] : sum_slots<AT, T, CD>(slots, nt, jj);
+        if (fwd) w[bs + jj] = sum;
+        else w[bs + jj] -= sum;
+      }
+    }
+    __syncthreads();
+    // (in a grouped launch every workgroup of a chain holds the same values; the
+    // first one hands them over to every workgroup of the other chain)
+    if (role == 2 && kind == FWD_UP && k == m + 1 && gi == 0) {
       for (int jj = tid; jj < b; jj += NT) xch[jj] = (double)w[bs + jj];
-      handoff_signal(flags + 0);
+      handoff_signal(flags + 0, NG);
     }
-    if (role == 1 && kind == MID && nB > 0) {
+    if (role == 1 && kind == MID && nB > 0 && gi == 0) {
       for (int jj = tid; jj < b; jj += NT) xch[a.xch_ld + jj] = (double)w[bs + jj];
-      handoff_signal(flags + 1);
+      handoff_signal(flags + NG, NG);
     }
   }
 
-  // scatter-add the correction on the owned rows
+  // scatter-add the correction on the owned rows (in a grouped launch, every G-th
+  // block of NT rows by each workgroup)
   constexpr int GB = 4;
-  for (int j0 = r0 + tid; j0 < r1; j0 += NT * GB) {
+  const int gstride = GRP ? NG * NT : NT;
+  for (int j0 = r0 + (GRP ? gi * NT : 0) + tid; j0 < r1; j0 += gstride * GB) {
     int g[GB];
     double ev[GB];
 #pragma unroll
     for (int q = 0; q < GB; ++q) {
-      const int j = j0 + q * NT;
+      const int j = j0 + q * gstride;
       g[q] = j < r1 ? a.set_idx[s0 + j] : -1;
     }
 #pragma unroll
     for (int q = 0; q < GB; ++q) ev[q] = g[q] >= 0 ? a.e[g[q]] : 0.0;
 #pragma unroll
     for (int q = 0; q < GB; ++q)
-      if (g[q] >= 0) a.e[g[q]] = ev[q] + (double)w[j0 + q * NT];
+      if (g[q] >= 0) a.e[g[q]] = ev[q] + (double)w[j0 + q * gstride];
+  }
+  if constexpr (GRP) {
+    // the last workgroup of the chain to get here returns the count to zero for the
+    // next launch (every other one has passed all of its waits)
+    if (tid == 0 &&
+        __hip_atomic_fetch_add(gcnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == NG * (nsplit + 1) - 1)
+      __hip_atomic_store(gcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// One colour phase: workgroup per (subdomain, chain) of the colour.
-template <class FT, class AT, int T, int NW, int TPW, bool SL>
+// One colour phase: workgroup per (subdomain, chain) of the colour; GRP: a.groups
+// workgroups per chain, member i at i times the ungrouped grid (the same XCD when
+// the chains are twisted).
+template <class FT, class AT, int T, int NW, int TPW, bool SL, bool GRP = false>
 __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
-  int p, role;
-  if (a.twisted) {
+  int p, role, gi = 0;
+  if constexpr (GRP) {
+    const int per = a.twisted ? 16 * ((a.nsub + 7) / 8) : a.nsub;
+    gi = blockIdx.x / per;
+    const int bx = blockIdx.x - gi * per;
+    if (a.twisted) {
+      const int g = bx >> 4, w16 = bx & 15;
+      p = g * 8 + (w16 & 7);
+      role = (w16 < 8) ? 2 : 1;
+    } else {
+      p = bx;
+      role = 0;
+    }
+  } else if (a.twisted) {
     // pair (bottom, top) = (16g + i, 16g + i + 8): same XCD under round-robin dispatch,
     // bottom chain dispatched first
     const int g = blockIdx.x >> 4, w16 = blockIdx.x & 15;
@@ -573,7 +718,7 @@ __global__ void __launch_bounds__(NW * 64) k_sweep(SweepArgs a) {
   // both workgroups of a pair read the same flag (stable during the launch), so
   // they skip together and no handoff is left waiting
   if (a.st && a.st[a.sub_inst[sub]].done) return;
-  sweep_task<FT, AT, T, NW, TPW, SL, false>(a, sub, role, p, false);
+  sweep_task<FT, AT, T, NW, TPW, SL, false, GRP>(a, sub, role, p, false, gi);
 }
 
 // A whole sweep direction (every colour) as one launch over a task queue.  Tasks
@@ -745,6 +890,10 @@ size_t build_sweep_args(const Handle& h, const int32_t* subs, int nsub, const do
   a.flags = h.flags.as<int32_t>();
   a.xch_ld = h.xch_ld;
   a.err = h.err_flag.as<int32_t>();
+  a.groups = 1;
+  a.split_rounds = 1 << 30;
+  a.gx = h.gx.p;
+  a.gcnt = h.gcnt.as<int32_t>();
   const int ni_pad = (S.max_set + 3) & ~3;
   DDG_REQUIRE(S.max_blocks <= kMaxLevels, DDG_ERR_UNSUPPORTED, "more than 96 levels in a local problem");
   const int max_tiles = tiles_for(S.max_blk, T);
@@ -812,6 +961,28 @@ void launch_sweep_cfg(const Handle& h, int colour, const double* r, double* e, b
     return;
   }
   const unsigned grid = a.twisted ? (unsigned)(16 * ((nsub + 7) / 8)) : (unsigned)nsub;
+  if constexpr (SL) {
+    // grouped launch: when the colour leaves CUs idle and the local problems have
+    // levels of at least grp_split rounds, G workgroups per chain (every workgroup
+    // of the launch resident at once, one per CU)
+    const int max_rounds = (tiles_for(S.max_blk, T) + NW * TPW - 1) / (NW * TPW);
+    int G = 1;
+    if (h.grp_max > 1 && nsub <= h.grp_slots && max_rounds >= h.grp_split)
+      G = std::min(h.grp_max, h.n_cu / (int)grid);
+    if (G > 1) {
+      h.grp_used = std::max(h.grp_used, G);
+      a.groups = G;
+      a.split_rounds = h.grp_split;
+      auto gk = k_sweep<FT, AT, T, NW, TPW, SL, true>;
+      if (lds > 65536) DDG_HIP(hipFuncSetAttribute((const void*)gk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      if (h.kev0)
+        hipExtLaunchKernelGGL(gk, dim3(grid * G), dim3(NW * 64), (uint32_t)lds, s, h.kev0, h.kev1, 0u, a);
+      else
+        hipLaunchKernelGGL(gk, dim3(grid * G), dim3(NW * 64), lds, s, a);
+      DDG_HIP(hipGetLastError());
+      return;
+    }
+  }
   if (h.kev0)
     hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), (uint32_t)lds, s, h.kev0, h.kev1, 0u, a);
   else
@@ -1066,7 +1237,8 @@ struct PersistArgs {
   const int32_t* kcnt;
   const int64_t* koff;
   const int32_t* part_id;    // subdomain of every row
-  const double* Q;
+  const int32_t* qpos;       // position of every row in the own-row order
+  const double* Qo;          // the basis in the own-row layout (q_own_at)
   int32_t kq;
   int32_t nch, rch;
   double* rpart;
@@ -1215,7 +1387,7 @@ __global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs
         const int i = P.sub_off[b] + idx / P.nch, c = idx % P.nch;
         with_lanes_dev(P.lpr, [&](auto Lc) {
           constexpr int L = decltype(Lc)::value;
-          d_coarse_restrict<L, 32>(i, c, P.nch, P.sub_inst, P.own_ptr, P.own_idx, P.kcnt, P.Q, P.kq, P.rp, P.ci,
+          d_coarse_restrict<L, 32>(i, c, P.nch, P.sub_inst, P.own_ptr, P.own_idx, P.kcnt, P.Qo, P.kq, P.rp, P.ci,
                                    P.val, P.D, P.r, P.z, P.rch, P.rpart);
         });
         break;
@@ -1239,7 +1411,8 @@ __global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs
       }
       case PT_PROLONG:
         for (int64_t row = P.m.lo[g] + tid; row < P.m.hi[g]; row += NT)
-          d_coarse_prolong_row<32>(row, nullptr, P.sub_inst, P.part_id, P.kcnt, P.koff, P.Q, P.kq, P.y, P.z);
+          d_coarse_prolong_row<32>(row, P.qpos[row], nullptr, P.sub_inst, P.part_id, P.kcnt, P.koff, P.Qo, P.kq,
+                                   P.y, P.z);
         break;
       case PT_DOT:
         if (aux) d_copy_dot(P.m, g, P.r, P.z, P.p, P.part);
@@ -1405,7 +1578,8 @@ void launch_persist_cfg(Handle& h, const double* f, double* x, hipStream_t s) {
     P.kcnt = h.kcnt_d.as<int32_t>();
     P.koff = h.koff_d.as<int64_t>();
     P.part_id = h.part.as<int32_t>();
-    P.Q = h.Q.as<double>();
+    P.qpos = h.qpos.as<int32_t>();
+    P.Qo = h.Qo.as<double>();
     P.kq = h.k;
     P.nch = h.nch;
     P.rch = h.rch;

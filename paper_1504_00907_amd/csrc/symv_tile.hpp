@@ -263,11 +263,14 @@ __device__ inline AT group_reduce_scatter(AT (&v)[S], int c, bool& writer) {
 //                   contribution of the sub-tiles below the diagonal to the rows
 //                   of their columns).
 // x is indexed from the block's first row.  The slots are written, not
-// accumulated, so the final sum over tiles has a fixed order.
+// accumulated, so the final sum over tiles has a fixed order.  The work is
+// written as two phases: the lane's products, then the butterflies and stores.
+
+// Phase 1: the lane's row and column partial sums of its sub-tile.
 template <class FT, class AT, int T, bool CD = false>
-__device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I, int J,
-                                       const AT* __restrict__ x, AT* __restrict__ rowslot,
-                                       AT* __restrict__ colslot, int lane, bool valid) {
+__device__ inline void symv_tile_partials(const FT (&m)[TileGeom<FT, T>::SS], int I, int J,
+                                          const AT* __restrict__ x, int lane, AT (&rowp)[TileGeom<FT, T>::S],
+                                          AT (&colp)[TileGeom<FT, T>::S]) {
   using G = TileGeom<FT, T>;
   constexpr int S = G::S;
   const int p = lane_p(lane), q = lane_q(lane);
@@ -278,7 +281,6 @@ __device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I
   for (int j = 0; j < S; ++j) xr[j] = x[J * T + q * S + (j ^ pm)];
 #pragma unroll
   for (int i = 0; i < S; ++i) xc[i] = x[I * T + p * S + (i ^ qm)];
-  AT rowp[S], colp[S];
 #pragma unroll
   for (int i = 0; i < S; ++i) {
     rowp[i] = 0;
@@ -300,11 +302,31 @@ __device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I
       for (int j = 0; j < S; ++j) colp[j] = 0;
     }
   }
+}
+
+// Phase 2: butterflies over the lanes that share rows (columns) and the slot stores.
+template <class FT, class AT, int T, bool CD = false>
+__device__ inline void symv_tile_store(int I, int J, AT (&rowp)[TileGeom<FT, T>::S],
+                                       AT (&colp)[TileGeom<FT, T>::S], AT* __restrict__ rowslot,
+                                       AT* __restrict__ colslot, int lane, bool valid) {
+  using G = TileGeom<FT, T>;
+  constexpr int S = G::S;
+  const int p = lane_p(lane), q = lane_q(lane);
   bool w;
   AT rs = group_reduce_scatter<AT, S, G::LOGS, 8, 2, 1>(rowp, q, w);
   if (valid && w) rowslot[p * S + (q >> (3 - G::LOGS))] = rs;
   AT cs = group_reduce_scatter<AT, S, G::LOGS, 32, 16, 4>(colp, p, w);
   if (valid && (CD || I != J) && w) colslot[q * S + (p >> (3 - G::LOGS))] = cs;
+}
+
+template <class FT, class AT, int T, bool CD = false>
+__device__ inline void symv_tile_slots(const FT (&m)[TileGeom<FT, T>::SS], int I, int J,
+                                       const AT* __restrict__ x, AT* __restrict__ rowslot,
+                                       AT* __restrict__ colslot, int lane, bool valid) {
+  using G = TileGeom<FT, T>;
+  AT rowp[G::S], colp[G::S];
+  symv_tile_partials<FT, AT, T, CD>(m, I, J, x, lane, rowp, colp);
+  symv_tile_store<FT, AT, T, CD>(I, J, rowp, colp, rowslot, colslot, lane, valid);
 }
 
 // Tile (I, J) of linear index t in row-major lower order.
