@@ -1322,12 +1322,14 @@ __device__ inline void p_next(const PersistArgs& P, int b, int& ph, int& c, int 
   }
 }
 
-// At least two waves per SIMD: the task bodies together would otherwise take every
-// register of the SIMD at the 256-thread shape and leave one workgroup per CU (no
-// reference to the by-value arguments may reach a body that is not inlined, or they
-// are copied to private memory).
+// At least two waves per SIMD (three at tile edge 16): the task bodies together would
+// otherwise take every register of the SIMD at the 256-thread shape and leave one
+// workgroup per CU (no reference to the by-value arguments may reach a body that is
+// not inlined, or they are copied to private memory).  At edge 16 the third wave is
+// worth its spills (batch of 256: 206 -> 201 ms per solve); the wider tiles' sweep
+// bodies alone need more than a third of the register file.
 template <class FT, class AT, int T, int NW, int TPW, bool SL>
-__global__ void __launch_bounds__(NW * 64, 2) k_persist(SweepArgs a, PersistArgs P) {
+__global__ void __launch_bounds__(NW * 64, T == 16 ? 3 : 2) k_persist(SweepArgs a, PersistArgs P) {
   constexpr int NT = NW * 64;
   __shared__ int32_t s_task[5];
   __shared__ int32_t s_next[4];
