@@ -324,7 +324,10 @@ void launch_coarse_k(Handle& h, const double* r, double* e, const CgState* st, h
 void launch_coarse(Handle& h, const double* r, double* e, const CgState* st, hipStream_t s) {
   if (h.nc == 0) return;
   DDG_REQUIRE(h.k <= kMaxGen, DDG_ERR_UNSUPPORTED, "at most 80 generating vectors");
-  if (h.k <= 32) launch_coarse_k<32>(h, r, e, st, s);
+  // (the per-thread column arrays sized to the basis: fewer registers and predicated
+  // steps for small k; the partial-sum stride stays within the kslots(k) allocation)
+  if (h.k <= 16) launch_coarse_k<16>(h, r, e, st, s);
+  else if (h.k <= 32) launch_coarse_k<32>(h, r, e, st, s);
   else launch_coarse_k<kMaxGen>(h, r, e, st, s);
 }
 
