@@ -135,9 +135,28 @@ __device__ inline void d_coarse_sum_row(int64_t row, int b, const int64_t* __res
   const int ntr = (int)((cblk_off[b + 1] - cblk_off[b]) / T);
   const double* rp = rowpart + tile_base[b] * T;
   const double* cp = colpart + tile_base[b] * T;
+  // (the loads of eight terms go out together; the terms are added in order)
+  constexpr int U = 8;
   double s = 0.0;
-  for (int J = 0; J <= I; ++J) s += rp[((int64_t)I * (I + 1) / 2 + J) * T + rr];
-  for (int J = I + 1; J < ntr; ++J) s += cp[((int64_t)J * (J + 1) / 2 + I) * T + rr];
+  const double* r0 = rp + (int64_t)I * (I + 1) / 2 * T + rr;   // tile (I, J) at r0 + J T
+  int J = 0;
+  for (; J + U <= I + 1; J += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = r0[(int64_t)(J + u) * T];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; J <= I; ++J) s += r0[(int64_t)J * T];
+  J = I + 1;
+  for (; J + U <= ntr; J += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = cp[((int64_t)(J + u) * (J + u + 1) / 2 + I) * T + rr];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; J < ntr; ++J) s += cp[((int64_t)J * (J + 1) / 2 + I) * T + rr];
   y[row] = s;
 }
 
