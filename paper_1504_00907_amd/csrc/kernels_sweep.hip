@@ -85,6 +85,11 @@ struct SweepArgs {
   int32_t split_rounds;  // a level of at least this many rounds (>= 2) is split over the group
   void* gx;              // per (slot, chain): 2 parities x groups x xch_ld partial level sums
   int32_t* gcnt;         // per (slot, chain): barrier count
+  // bounded waits: polls before a wait gives up and raises the error flag, and a
+  // test switch that leaves waits unsatisfied (bit 0: the chain handoff is never
+  // signalled; bit 1: the first workgroup of a group never counts itself at a barrier)
+  int32_t spin_limit;
+  int32_t fault;
 };
 
 namespace {
@@ -128,12 +133,12 @@ __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // performs the agent-scope acquire (which invalidates this CU's vector cache and
 // the die's L2 lines); the barrier then orders every wave's reads of the exchange
 // buffer after it.  The reader clears the flag for the next launch.
-__device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub) {
+__device__ inline void handoff_wait(int32_t* flag, int32_t* err, int sub, int limit) {
   if (threadIdx.x == 0) {
     int spins = 0;
     while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
+      if (++spins > limit) {
         if (atomicCAS(err, 0, DDG_ERR_HIP) == 0) {
           err[1] = sub;
           err[2] = -7;
@@ -167,18 +172,18 @@ __device__ inline void handoff_signal(int32_t* flag, int n = 1) {
 // waits (bounded; also ended by an error another workgroup raised) until the count
 // reaches `target`, then makes an agent-scope acquire before the barrier lets the
 // other waves read.
-__device__ inline void group_barrier(int32_t* cnt, int target, int32_t* err, int sub) {
+__device__ inline void group_barrier(int32_t* cnt, int target, int32_t* err, int sub, int limit, bool count) {
   wait_vm();
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     wait_vm();
-    __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (count) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int spins = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if ((++spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      if (spins > kSpinLimit) {
+      if (spins > limit) {
         if (atomicCAS(err, 0, DDG_ERR_HIP) == 0) {
           err[1] = sub;
           err[2] = -11;
@@ -500,14 +505,14 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
     const int ntl = nt * (nt + 1) / 2;
     if (role == 1 && kind == MID && nB > 0) {
       // import t_{m+1} from the bottom chain
-      handoff_wait(flags + gi, a.err, sub);
+      handoff_wait(flags + gi, a.err, sub, a.spin_limit);
       const int bs1 = lv_start[m + 1], b1 = lv_size[m + 1];
       for (int jj = tid; jj < b1; jj += NT) w[bs1 + jj] = (AT)xch[jj];
       __syncthreads();
     }
     if (role == 2 && kind == BWD_LO && k == m + 1) {
       // import x_m from the top chain
-      handoff_wait(flags + NG + gi, a.err, sub);
+      handoff_wait(flags + NG + gi, a.err, sub, a.spin_limit);
       const int bsm = lv_start[m], bm = lv_size[m];
       for (int jj = tid; jj < bm; jj += NT) w[bsm + jj] = (AT)xch[a.xch_ld + jj];
       __syncthreads();
@@ -631,7 +636,7 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
       AT* X = static_cast<AT*>(a.gx) + ((int64_t)chain * 2 + (nsplit & 1)) * NG * a.xch_ld;
       for (int jj = tid; jj < b; jj += NT) X[(int64_t)gi * a.xch_ld + jj] = rl > rf ? acc[jj] : (AT)0;
       ++nsplit;
-      group_barrier(gcnt, NG * nsplit, a.err, sub);
+      group_barrier(gcnt, NG * nsplit, a.err, sub, a.spin_limit, !((a.fault & 2) && gi == 0));
       for (int jj = tid; jj < b; jj += NT) {
         AT sum = X[jj];
         for (int i = 1; i < NG; ++i) sum += X[(int64_t)i * a.xch_ld + jj];
@@ -650,11 +655,11 @@ __device__ inline void sweep_task(const SweepArgs& a, int sub, int role, int xs,
     // first one hands them over to every workgroup of the other chain)
     if (role == 2 && kind == FWD_UP && k == m + 1 && gi == 0) {
       for (int jj = tid; jj < b; jj += NT) xch[jj] = (double)w[bs + jj];
-      handoff_signal(flags + 0, NG);
+      if (!(a.fault & 1)) handoff_signal(flags + 0, NG);
     }
     if (role == 1 && kind == MID && nB > 0 && gi == 0) {
       for (int jj = tid; jj < b; jj += NT) xch[a.xch_ld + jj] = (double)w[bs + jj];
-      handoff_signal(flags + NG, NG);
+      if (!(a.fault & 1)) handoff_signal(flags + NG, NG);
     }
   }
 
@@ -892,6 +897,12 @@ size_t build_sweep_args(const Handle& h, const int32_t* subs, int nsub, const do
   a.err = h.err_flag.as<int32_t>();
   a.groups = 1;
   a.split_rounds = 1 << 30;
+  // DDG_SPIN_LIMIT / DDG_SWEEP_FAULT: shorter bounded waits and unsatisfied waits for
+  // the tests of the error paths (read at every launch, so a test can clear them)
+  a.spin_limit = kSpinLimit;
+  if (const char* env = std::getenv("DDG_SPIN_LIMIT")) a.spin_limit = std::max(16, std::atoi(env));
+  a.fault = 0;
+  if (const char* env = std::getenv("DDG_SWEEP_FAULT")) a.fault = std::atoi(env);
   a.gx = h.gx.p;
   a.gcnt = h.gcnt.as<int32_t>();
   const int ni_pad = (S.max_set + 3) & ~3;
