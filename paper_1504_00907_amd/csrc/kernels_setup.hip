@@ -742,8 +742,11 @@ __global__ void __launch_bounds__(kPivThreads) k_bleaf(BInv bi, int lo, int hi, 
 
 // op 0: W = X11 X12; 1: X22 -= X21 W (the Schur complement, formed on and below the
 // diagonal and mirrored); 2: X12 = -W X22, with X21 = X12^T; 3: X11 -= X12 W^T
-// (formed on and below the diagonal and mirrored)
-__global__ void __launch_bounds__(256) k_bgemm(BInv bi, int op, int lo, int mid, int hi, int64_t woff, int ldw) {
+// (formed on and below the diagonal and mirrored).
+// The occupancy hint makes the compiler keep the accumulators in VGPRs: 154 in all
+// instead of 160 VGPRs + 32 AGPRs, so three waves per SIMD fit where two did, and the
+// operand loads of more tiles overlap (the products are the same instructions).
+__global__ void __launch_bounds__(256, 2) k_bgemm(BInv bi, int op, int lo, int mid, int hi, int64_t woff, int ldw) {
   const int q = blockIdx.z;
   const int b = bi.n[q];
   if (lo >= b) return;
