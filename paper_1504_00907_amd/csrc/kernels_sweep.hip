@@ -1637,15 +1637,17 @@ void prepare_persist(Handle& h, hipStream_t s) {
     subs.insert(subs.end(), lists[q].begin(), lists[q].end());
     ptr[q + 1] = (int32_t)subs.size();
   }
-  // admission: systems start smallest first; enough of them at once for about eight
-  // subdomains per CU, and each stopped system hands its place to the next one
+  // admission: systems start smallest first; enough of them at once for about sixteen
+  // subdomains per CU (a system offers only its current colour's subdomains as sweep
+  // tasks, so fewer leave workgroups without work), and each stopped system hands its
+  // place to the next one
   std::vector<int32_t> order(nb);
   for (int32_t b = 0; b < nb; ++b) order[b] = b;
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
     return h.seg_off[x + 1] - h.seg_off[x] < h.seg_off[y + 1] - h.seg_off[y];
   });
   int32_t admit = 0;
-  for (int64_t subs = 0; admit < nb && subs < 8 * (int64_t)h.n_cu; ++admit)
+  for (int64_t subs = 0; admit < nb && subs < 16 * (int64_t)h.n_cu; ++admit)
     subs += h.sub_off[order[admit] + 1] - h.sub_off[order[admit]];
   std::vector<uint64_t> init;
   std::vector<PSys> sys0(nb);
