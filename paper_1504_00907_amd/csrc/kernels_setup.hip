@@ -364,6 +364,10 @@ __global__ void __launch_bounds__(256) k_fac_tm(FacArgs a) {
 }
 
 // S[r, :] = (add_d ? D_k[r, :] : S[r, :]) - sum_q c_q Tm[col_q - bsp, :]
+// A level that starts from D_k and has a coupled level writes 0 - acc first and then adds
+// D_k's few stored entries of each row (distinct columns: the input rows are strictly
+// increasing): (0 - acc) + d rounds as d - acc does, and S is written once instead of being
+// cleared, filled and read back.
 __global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
   const FacItem it = a.items[blockIdx.x];
   const int b = a.blk_size[it.cur];
@@ -373,7 +377,8 @@ __global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
   const int bs = a.blk_start[it.cur];
   const int64_t row0 = a.set_ptr[it.sub] + bs;
   double* S = a.scratch + it.s_off;
-  if (it.add_d) {
+  if (it.prev < 0) {
+    if (!it.add_d) return;
     for (int idx = threadIdx.x; idx < rows * b; idx += 256) S[(int64_t)(r0 + idx / b) * b + idx % b] = 0.0;
     __syncthreads();
     for (int r = threadIdx.x; r < rows; r += 256) {
@@ -381,9 +386,8 @@ __global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
       for (int64_t t = a.in_ptr[row]; t < a.in_ptr[row + 1]; ++t)
         S[(int64_t)(r0 + r) * b + (a.in_col[t] - bs)] = a.val[a.in_pos[t]];
     }
-    __syncthreads();
+    return;
   }
-  if (it.prev < 0) return;
   const int bsp = a.blk_start[it.prev];
   const int cc = it.use_up ? a.cu : a.cl;
   const int32_t* ccol = it.use_up ? a.up_col : a.lo_col;
@@ -397,7 +401,16 @@ __global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
       const int col = ccol[row * cc + q];
       if (col >= 0) acc += cval[row * cc + q] * Tm[(int64_t)(col - bsp) * b + c];
     }
-    S[(int64_t)r * b + c] -= acc;
+    double* sp = S + (int64_t)r * b + c;
+    if (it.add_d) *sp = 0.0 - acc;
+    else *sp -= acc;
+  }
+  if (!it.add_d) return;
+  __syncthreads();
+  for (int r = threadIdx.x; r < rows; r += 256) {
+    const int64_t row = row0 + r0 + r;
+    for (int64_t t = a.in_ptr[row]; t < a.in_ptr[row + 1]; ++t)
+      S[(int64_t)(r0 + r) * b + (a.in_col[t] - bs)] += a.val[a.in_pos[t]];
   }
 }
 
