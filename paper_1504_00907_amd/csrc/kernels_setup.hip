@@ -332,22 +332,16 @@ struct FacArgs {
   double* scratch;
   double* tm;
   void* fac;
-  int32_t frows;   // rows of the level per workgroup in the formation kernels
 };
 
-// Rows per workgroup in the formation kernels: k_fac_tm writes Tm in runs of that many
-// consecutive values, so stages whose widest level has at least kFacWideLevel rows take
-// kFacRowsWide (longer runs); narrower stages keep kFacRows (more workgroups per level).
-constexpr int kFacRows = 8;
-constexpr int kFacRowsWide = 32;
-constexpr int kFacWideLevel = 256;
+constexpr int kFacRows = 8;   // rows of the level per workgroup in the formation kernels
 
 // Tm[pp, r] = sum_q X_prev[pp, col_q - bsp] * c_q over the couplings (col_q, c_q) of row r
 __global__ void __launch_bounds__(256) k_fac_tm(FacArgs a) {
   const FacItem it = a.items[blockIdx.x];
   if (it.prev < 0) return;
   const int b = a.blk_size[it.cur];
-  const int r0 = blockIdx.y * a.frows;
+  const int r0 = blockIdx.y * kFacRows;
   if (r0 >= b) return;
   const int bp = a.blk_size[it.prev], bsp = a.blk_start[it.prev];
   const int64_t row0 = a.set_ptr[it.sub] + a.blk_start[it.cur];
@@ -356,7 +350,7 @@ __global__ void __launch_bounds__(256) k_fac_tm(FacArgs a) {
   const double* cval = it.use_up ? a.up_val : a.lo_val;
   const double* X = a.scratch + it.x_off;
   double* Tm = a.tm + it.t_off;
-  const int rows = min(a.frows, b - r0);
+  const int rows = min(kFacRows, b - r0);
   for (int idx = threadIdx.x; idx < bp * rows; idx += 256) {
     const int pp = idx / rows, r = r0 + idx % rows;
     const int64_t row = row0 + r;
@@ -377,9 +371,9 @@ __global__ void __launch_bounds__(256) k_fac_tm(FacArgs a) {
 __global__ void __launch_bounds__(256) k_fac_form(FacArgs a) {
   const FacItem it = a.items[blockIdx.x];
   const int b = a.blk_size[it.cur];
-  const int r0 = blockIdx.y * a.frows;
+  const int r0 = blockIdx.y * kFacRows;
   if (r0 >= b) return;
-  const int rows = min(a.frows, b - r0);
+  const int rows = min(kFacRows, b - r0);
   const int bs = a.blk_start[it.cur];
   const int64_t row0 = a.set_ptr[it.sub] + bs;
   double* S = a.scratch + it.s_off;
@@ -980,8 +974,7 @@ void launch_factor_t(Handle& h, hipStream_t s) {
   const FacItem* items = h.fac_items.as<FacItem>();
   for (const auto& st : h.fac_stages) {
     a.items = items + st.first;
-    a.frows = st.bmax >= kFacWideLevel ? kFacRowsWide : kFacRows;
-    const unsigned ny = (unsigned)((st.bmax + a.frows - 1) / a.frows);
+    const unsigned ny = (unsigned)((st.bmax + kFacRows - 1) / kFacRows);
     hipLaunchKernelGGL(k_fac_tm, dim3((unsigned)st.count, ny), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_fac_form, dim3((unsigned)st.count, ny), dim3(256), 0, s, a);
     if (!st.gj) continue;
